@@ -1,0 +1,614 @@
+/*
+ * FP64 CPU oracle for perceptual rasterization (Friston, Ritschel & Steed,
+ * "Perceptual Rasterization for Head-mounted Display Image Synthesis").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow definition that
+ * the GPU library is checked against.  Only the test suite, the smoke check
+ * and the benchmark's CPU-baseline leg may load it; the product path never
+ * does, and it shares no code with the GPU library.
+ *
+ * What it computes is the "correct, but slow" solution the paper names in
+ * Sec. 3 (every primitive tested against every pixel, then a z-test), with
+ * the ray-primitive models of Sec. 3.1:
+ *   - foveation (Sec. 3.1.1): the pixel grid lives in the foveated domain; a
+ *     pixel's display position is the unfoveated point of its centre;
+ *   - rolling (Sec. 3.1.2): the pixel's time is r(x) = x . d of its unit
+ *     display position;
+ *   - joint (Sec. 3.1.3): time taken from the unfoveated display position;
+ *   - intersection (Sec. 3.2, "Intersection"): the triangle is linearly
+ *     interpolated to the pixel's time in camera space and intersected with
+ *     the pixel's ray; the nearest hit wins;
+ *   - shading (Sec. 3.2, "Shading"): light direction interpolated to the
+ *     pixel's time, Lambert with one directional light.
+ * Plus the analytic gradient of an L2 image loss with visibility held fixed
+ * (an AI-systems form of the method; pinned by central differences).
+ *
+ * Everything is double precision; float32 inputs convert exactly.
+ *
+ * View parameter block (24 doubles), see ORC_* indices below:
+ *   width, height, pose0[6], pose1[6], fx, fy, cx, cy, znear,
+ *   fovea[2], alpha, roll_dir[2]
+ * A pose is a world->view rotation vector omega (3) then translation T (3):
+ *   P = R(omega) v + T.
+ * View space: x right, y up, +z forward.  NDC: x = fx X/Z + cx,
+ * y = fy Y/Z + cy.  Pixel (i, j), row 0 at the top, samples the foveated NDC
+ * point y = (2(i+1/2)/W - 1, 1 - 2(j+1/2)/H).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum {
+    ORC_W = 0, ORC_H = 1, ORC_POSE0 = 2, ORC_POSE1 = 8, ORC_FX = 14, ORC_FY = 15,
+    ORC_CX = 16, ORC_CY = 17, ORC_ZNEAR = 18, ORC_FOV = 19, ORC_ALPHA = 21,
+    ORC_ROLL = 22, ORC_NPARAM = 24
+};
+
+/* ------------------------------------------------------------------------- */
+/* small vector helpers                                                       */
+/* ------------------------------------------------------------------------- */
+static void cross3(const double a[3], const double b[3], double o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double a[3], const double b[3]) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+static double norm3(const double a[3]) { return sqrt(dot3(a, a)); }
+static void matvec(const double R[9], const double v[3], double o[3]) {
+    for (int r = 0; r < 3; ++r) o[r] = R[3 * r] * v[0] + R[3 * r + 1] * v[1] + R[3 * r + 2] * v[2];
+}
+static void matTvec(const double R[9], const double v[3], double o[3]) {
+    for (int c = 0; c < 3; ++c) o[c] = R[c] * v[0] + R[3 + c] * v[1] + R[6 + c] * v[2];
+}
+
+/* Rotation matrix of a rotation vector (Rodrigues' formula):
+ * R = I + sin(th)/th [w]x + (1 - cos(th))/th^2 [w]x^2, th = |w|. */
+void orc_rodrigues(const double w[3], double R[9]) {
+    double th = norm3(w);
+    double K[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
+    double K2[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k) s += K[3 * r + k] * K[3 * k + c];
+            K2[3 * r + c] = s;
+        }
+    double a, b;
+    if (th < 1e-8) {            /* series: sin(th)/th ~ 1 - th^2/6, (1-cos)/th^2 ~ 1/2 - th^2/24 */
+        a = 1.0 - th * th / 6.0;
+        b = 0.5 - th * th / 24.0;
+    } else {
+        a = sin(th) / th;
+        b = (1.0 - cos(th)) / (th * th);
+    }
+    for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0 ? 1.0 : 0.0) + a * K[i] + b * K2[i];
+}
+
+/* dR/dw_i for the rotation vector w (Gallego & Yezzi 2015, "A compact
+ * formula for the derivative of a 3-D rotation in exponential coordinates"):
+ *   dR/dw_i = ( w_i [w]x + [ w x ((I - R) e_i) ]x ) R / |w|^2,
+ * with the first-order expansion [e_i]x + ([e_i]x[w]x + [w]x[e_i]x)/2 near 0. */
+static void skew(const double v[3], double S[9]) {
+    S[0] = 0; S[1] = -v[2]; S[2] = v[1];
+    S[3] = v[2]; S[4] = 0; S[5] = -v[0];
+    S[6] = -v[1]; S[7] = v[0]; S[8] = 0;
+}
+static void matmul3(const double A[9], const double B[9], double C[9]) {
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k) s += A[3 * r + k] * B[3 * k + c];
+            C[3 * r + c] = s;
+        }
+}
+void orc_rodrigues_jac(const double w[3], double dR[27]) {
+    double th = norm3(w);
+    double R[9];
+    orc_rodrigues(w, R);
+    for (int i = 0; i < 3; ++i) {
+        double e[3] = {0, 0, 0};
+        e[i] = 1.0;
+        double Ei[9];
+        skew(e, Ei);
+        double *out = dR + 9 * i;
+        if (th < 1e-6) {
+            double W[9], A[9], B[9];
+            skew(w, W);
+            matmul3(Ei, W, A);
+            matmul3(W, Ei, B);
+            for (int k = 0; k < 9; ++k) out[k] = Ei[k] + 0.5 * (A[k] + B[k]);
+        } else {
+            double ImR_e[3], u[3], W[9], U[9], M[9];
+            for (int r = 0; r < 3; ++r) ImR_e[r] = e[r] - R[3 * r + i];
+            cross3(w, ImR_e, u);
+            skew(w, W);
+            skew(u, U);
+            for (int k = 0; k < 9; ++k) M[k] = (w[i] * W[k] + U[k]) / (th * th);
+            matmul3(M, R, out);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* ray-primitive models (Sec. 3.1)                                             */
+/* ------------------------------------------------------------------------- */
+
+/* Normalising radius of the foveation domain: distance from the fovea to the
+ * farthest corner of [-1,1]^2 (sqrt 2 for a central fovea). */
+double orc_fovea_radius(const double *vp) {
+    double best = 0;
+    for (int c = 0; c < 4; ++c) {
+        double dx = (c & 1 ? 1.0 : -1.0) - vp[ORC_FOV];
+        double dy = (c & 2 ? 1.0 : -1.0) - vp[ORC_FOV + 1];
+        double d = sqrt(dx * dx + dy * dy);
+        if (d > best) best = d;
+    }
+    return best;
+}
+
+/* Unfoveate (foveated NDC y -> display NDC x): radial power law about the
+ * fovea, display distance = R (rho/R)^alpha.  alpha = 1 is the identity
+ * (constant density, common rasterization). */
+void orc_unfoveate(const double *vp, const double y[2], double x[2]) {
+    double fx = vp[ORC_FOV], fy = vp[ORC_FOV + 1];
+    double dx = y[0] - fx, dy = y[1] - fy;
+    double rho = sqrt(dx * dx + dy * dy);
+    if (rho == 0.0) { x[0] = fx; x[1] = fy; return; }
+    double s = pow(rho / orc_fovea_radius(vp), vp[ORC_ALPHA] - 1.0);
+    x[0] = fx + dx * s;
+    x[1] = fy + dy * s;
+}
+
+/* Foveate (display NDC x -> foveated NDC y), the inverse power law. */
+void orc_foveate(const double *vp, const double x[2], double y[2]) {
+    double fx = vp[ORC_FOV], fy = vp[ORC_FOV + 1];
+    double dx = x[0] - fx, dy = x[1] - fy;
+    double rho = sqrt(dx * dx + dy * dy);
+    if (rho == 0.0) { y[0] = fx; y[1] = fy; return; }
+    double s = pow(rho / orc_fovea_radius(vp), 1.0 / vp[ORC_ALPHA] - 1.0);
+    y[0] = fx + dx * s;
+    y[1] = fy + dy * s;
+}
+
+/* Rolling function: unit display position (x+1)/2 dotted with the skew
+ * direction d, clamped to the frame [0, 1].  d = (0,0) gives t = 0. */
+double orc_pixel_time(const double *vp, const double x[2]) {
+    double t = vp[ORC_ROLL] * (x[0] + 1.0) * 0.5 + vp[ORC_ROLL + 1] * (x[1] + 1.0) * 0.5;
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    return t;
+}
+
+/* Per-pixel setup: foveated sample y, display point x, time t, ray r. */
+void orc_pixel_setup(const double *vp, int64_t pix, double y[2], double x[2], double *t, double r[3]) {
+    int W = (int)vp[ORC_W], H = (int)vp[ORC_H];
+    int64_t i = pix % W, j = pix / W;
+    y[0] = 2.0 * (i + 0.5) / W - 1.0;
+    y[1] = 1.0 - 2.0 * (j + 0.5) / H;
+    orc_unfoveate(vp, y, x);
+    *t = orc_pixel_time(vp, x);
+    r[0] = (x[0] - vp[ORC_CX]) / vp[ORC_FX];
+    r[1] = (x[1] - vp[ORC_CY]) / vp[ORC_FY];
+    r[2] = 1.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* camera-space vertices (vertex program, Sec. 3.2 "Bounding")                */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    double R0[9], T0[3], R1[9], T1[3];
+    double *Ps, *Pe;   /* [nv][3] view space at t0 / t1 */
+} orc_cam;
+
+static void cam_init(orc_cam *c, const double *vp, const double *v0, const double *v1, int nv) {
+    orc_rodrigues(vp + ORC_POSE0, c->R0);
+    orc_rodrigues(vp + ORC_POSE1, c->R1);
+    for (int k = 0; k < 3; ++k) { c->T0[k] = vp[ORC_POSE0 + 3 + k]; c->T1[k] = vp[ORC_POSE1 + 3 + k]; }
+    c->Ps = (double *)malloc(sizeof(double) * 3 * (size_t)nv);
+    c->Pe = (double *)malloc(sizeof(double) * 3 * (size_t)nv);
+    for (int v = 0; v < nv; ++v) {
+        matvec(c->R0, v0 + 3 * (size_t)v, c->Ps + 3 * (size_t)v);
+        matvec(c->R1, v1 + 3 * (size_t)v, c->Pe + 3 * (size_t)v);
+        for (int k = 0; k < 3; ++k) { c->Ps[3 * v + k] += c->T0[k]; c->Pe[3 * v + k] += c->T1[k]; }
+    }
+}
+static void cam_free(orc_cam *c) { free(c->Ps); free(c->Pe); }
+
+/* Triangle interpolated to time t (linear vertex motion in camera space). */
+static void tri_at(const orc_cam *c, const int32_t *tri, int64_t f, double t, double P[3][3]) {
+    for (int k = 0; k < 3; ++k) {
+        int64_t v = tri[3 * f + k];
+        for (int d = 0; d < 3; ++d) P[k][d] = (1.0 - t) * c->Ps[3 * v + d] + t * c->Pe[3 * v + d];
+    }
+}
+
+/* Ray-triangle test for a ray from the eye (origin) along r.
+ * e_k = r . (P_a x P_b), (a,b) = (k+1, k+2) mod 3; S = sum e_k;
+ * D = P_0 . (P_1 x P_2).  Hit iff S != 0, the e_k share a sign (zero allowed,
+ * two-sided), and the hit depth z = D/S is at least znear.
+ * Returns 1 on hit; fills z and the normalised edge magnitude
+ * ehat = min_k |e_k| / (|r| |P_a x P_b|) (sine of the ray / edge-plane angle). */
+static int ray_tri(const double P[3][3], const double r[3], double znear, double *z, double *ehat, double e[3]) {
+    double c[3][3];
+    for (int k = 0; k < 3; ++k) {
+        cross3(P[(k + 1) % 3], P[(k + 2) % 3], c[k]);
+        e[k] = dot3(r, c[k]);
+    }
+    double S = e[0] + e[1] + e[2];
+    double D = dot3(P[0], c[0]);
+    int pos = e[0] >= 0 && e[1] >= 0 && e[2] >= 0;
+    int neg = e[0] <= 0 && e[1] <= 0 && e[2] <= 0;
+    double rn = norm3(r);
+    double em = INFINITY;
+    for (int k = 0; k < 3; ++k) {
+        double cn = norm3(c[k]);
+        double v = cn > 0 ? fabs(e[k]) / (rn * cn) : 0.0;
+        if (v < em) em = v;
+    }
+    *ehat = em;
+    if (S == 0.0 || !(pos || neg)) { *z = INFINITY; return 0; }
+    *z = D / S;
+    return *z >= znear;
+}
+
+/* ------------------------------------------------------------------------- */
+/* public entry points                                                        */
+/* ------------------------------------------------------------------------- */
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+int orc_get_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Brute force render of the given pixels (pix == NULL: all W*H pixels).
+ * Per pixel: winner id (-1 = miss), its depth (+inf = miss) and ehat, and the
+ * runner-up (second in (depth, id) order) id and depth.  Exact depth ties go
+ * to the lower triangle index. */
+void orc_render(const double *vp, const double *v0, const double *v1, int nv, const int32_t *tri, int nt,
+                const int64_t *pix, int64_t npix, int32_t *out_id, double *out_z, double *out_ehat,
+                int32_t *out_id2, double *out_z2) {
+    orc_cam cam;
+    cam_init(&cam, vp, v0, v1, nv);
+    if (!pix) npix = (int64_t)vp[ORC_W] * (int64_t)vp[ORC_H];
+    double znear = vp[ORC_ZNEAR];
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < npix; ++q) {
+        int64_t p = pix ? pix[q] : q;
+        double y[2], x[2], t, r[3];
+        orc_pixel_setup(vp, p, y, x, &t, r);
+        double bz = INFINITY, bz2 = INFINITY, beh = 0;
+        int32_t bid = -1, bid2 = -1;
+        for (int f = 0; f < nt; ++f) {
+            double P[3][3], z, eh, e[3];
+            tri_at(&cam, tri, f, t, P);
+            if (!ray_tri(P, r, znear, &z, &eh, e)) continue;
+            if (z < bz) {            /* f > bid always, so equal z keeps the lower id */
+                bz2 = bz; bid2 = bid;
+                bz = z; bid = f; beh = eh;
+            } else if (z < bz2) {
+                bz2 = z; bid2 = f;
+            }
+        }
+        if (out_id) out_id[q] = bid;
+        if (out_z) out_z[q] = bz;
+        if (out_ehat) out_ehat[q] = bid >= 0 ? beh : INFINITY;
+        if (out_id2) out_id2[q] = bid2;
+        if (out_z2) out_z2[q] = bz2;
+    }
+    cam_free(&cam);
+}
+
+/* Evaluate one (pixel, triangle) pair: returns hit flag; out[0] = z (D/S, or
+ * +inf if no line hit), out[1] = ehat, out[2] = pixel time. */
+int orc_eval(const double *vp, const double *v0, const double *v1, int nv, const int32_t *tri, int nt,
+             int64_t pix, int f, double *out) {
+    (void)nt;
+    orc_cam cam;
+    cam_init(&cam, vp, v0, v1, nv);
+    double y[2], x[2], t, r[3], P[3][3], z, eh, e[3];
+    orc_pixel_setup(vp, pix, y, x, &t, r);
+    tri_at(&cam, tri, f, t, P);
+    int hit = ray_tri(P, r, vp[ORC_ZNEAR], &z, &eh, e);
+    out[0] = z;
+    out[1] = eh;
+    out[2] = t;
+    cam_free(&cam);
+    return hit;
+}
+
+/* Batched orc_eval over (pix[q], tri_ids[q]) pairs. */
+void orc_eval_many(const double *vp, const double *v0, const double *v1, int nv, const int32_t *tri, int nt,
+                   const int64_t *pix, const int32_t *fid, int64_t n, int32_t *hit, double *z, double *ehat) {
+    (void)nt;
+    orc_cam cam;
+    cam_init(&cam, vp, v0, v1, nv);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q) {
+        double y[2], x[2], t, r[3], P[3][3], zz, eh, e[3];
+        orc_pixel_setup(vp, pix[q], y, x, &t, r);
+        tri_at(&cam, tri, fid[q], t, P);
+        hit[q] = ray_tri(P, r, vp[ORC_ZNEAR], &zz, &eh, e);
+        z[q] = zz;
+        ehat[q] = eh;
+    }
+    cam_free(&cam);
+}
+
+/* Every (pixel, triangle) hit, occluded or not, over the given pixels.
+ * Writes up to cap pairs; returns the total count (may exceed cap). */
+int64_t orc_all_hits(const double *vp, const double *v0, const double *v1, int nv, const int32_t *tri, int nt,
+                     const int64_t *pix, int64_t npix, int64_t *out_pix, int32_t *out_tri, double *out_ehat,
+                     int64_t cap) {
+    orc_cam cam;
+    cam_init(&cam, vp, v0, v1, nv);
+    if (!pix) npix = (int64_t)vp[ORC_W] * (int64_t)vp[ORC_H];
+    int64_t count = 0;
+    for (int64_t q = 0; q < npix; ++q) {
+        int64_t p = pix ? pix[q] : q;
+        double y[2], x[2], t, r[3];
+        orc_pixel_setup(vp, p, y, x, &t, r);
+        for (int f = 0; f < nt; ++f) {
+            double P[3][3], z, eh, e[3];
+            tri_at(&cam, tri, f, t, P);
+            if (!ray_tri(P, r, vp[ORC_ZNEAR], &z, &eh, e)) continue;
+            if (count < cap) { out_pix[count] = p; out_tri[count] = f; out_ehat[count] = eh; }
+            ++count;
+        }
+    }
+    cam_free(&cam);
+    return count;
+}
+
+/* ------------------------------------------------------------------------- */
+/* rolling Lambert shading and its gradient (frozen visibility)              */
+/* ------------------------------------------------------------------------- */
+
+/* Shade one pixel whose visible triangle is f.  light = (l_w[3], k_a).
+ * n = face normal flipped to face the eye; l(t) = normalize((1-t) R0 l_w +
+ * t R1 l_w); albedo = barycentric (mu_k = e_k/S) blend of per-vertex albedo;
+ * c = albedo * (k_a + (1-k_a) max(0, n.l)). */
+static void shade_px(const orc_cam *cam, const double *vp, const int32_t *tri, const double *albedo,
+                     const double *light, int64_t p, int f, double c[3]) {
+    double y[2], x[2], t, r[3], P[3][3];
+    orc_pixel_setup(vp, p, y, x, &t, r);
+    tri_at(cam, tri, f, t, P);
+    double e[3], ck[3][3];
+    for (int k = 0; k < 3; ++k) {
+        cross3(P[(k + 1) % 3], P[(k + 2) % 3], ck[k]);
+        e[k] = dot3(r, ck[k]);
+    }
+    double S = e[0] + e[1] + e[2];
+    double N[3], e1[3], e2[3];
+    for (int d = 0; d < 3; ++d) { e1[d] = P[1][d] - P[0][d]; e2[d] = P[2][d] - P[0][d]; }
+    cross3(e1, e2, N);
+    double nn = norm3(N);
+    double n[3] = {N[0] / nn, N[1] / nn, N[2] / nn};
+    if (dot3(n, r) > 0) { n[0] = -n[0]; n[1] = -n[1]; n[2] = -n[2]; }
+    double l0[3], l1[3], L[3];
+    matvec(cam->R0, light, l0);
+    matvec(cam->R1, light, l1);
+    for (int d = 0; d < 3; ++d) L[d] = (1.0 - t) * l0[d] + t * l1[d];
+    double ln = norm3(L);
+    double ndl = dot3(n, L) / ln;
+    double s = light[3] + (1.0 - light[3]) * (ndl > 0 ? ndl : 0.0);
+    for (int ch = 0; ch < 3; ++ch) {
+        double a = 0;
+        for (int k = 0; k < 3; ++k) a += e[k] / S * albedo[3 * (size_t)tri[3 * f + k] + ch];
+        c[ch] = a * s;
+    }
+}
+
+/* Shade pixels given their (frozen) triangle ids; misses give 0. */
+void orc_shade(const double *vp, const double *v0, const double *v1, int nv, const int32_t *tri, int nt,
+               const double *albedo, const double *light, const int64_t *pix, int64_t npix,
+               const int32_t *ids, double *out_rgb) {
+    (void)nt;
+    orc_cam cam;
+    cam_init(&cam, vp, v0, v1, nv);
+    if (!pix) npix = (int64_t)vp[ORC_W] * (int64_t)vp[ORC_H];
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < npix; ++q) {
+        int64_t p = pix ? pix[q] : q;
+        double c[3] = {0, 0, 0};
+        if (ids[q] >= 0) shade_px(&cam, vp, tri, albedo, light, p, ids[q], c);
+        for (int ch = 0; ch < 3; ++ch) out_rgb[3 * q + ch] = c[ch];
+    }
+    cam_free(&cam);
+}
+
+/* L = sum over pixels and channels of (c - target)^2 with the full-image id
+ * buffer frozen (background contributes (0 - target)^2). */
+double orc_loss(const double *vp, const double *v0, const double *v1, int nv, const int32_t *tri, int nt,
+                const double *albedo, const double *light, const int32_t *ids, const double *target) {
+    (void)nt;
+    orc_cam cam;
+    cam_init(&cam, vp, v0, v1, nv);
+    int64_t npix = (int64_t)vp[ORC_W] * (int64_t)vp[ORC_H];
+    double L = 0;
+#pragma omp parallel for schedule(static) reduction(+ : L)
+    for (int64_t p = 0; p < npix; ++p) {
+        double c[3] = {0, 0, 0};
+        if (ids[p] >= 0) shade_px(&cam, vp, tri, albedo, light, p, ids[p], c);
+        for (int ch = 0; ch < 3; ++ch) {
+            double d = c[ch] - target[3 * p + ch];
+            L += d * d;
+        }
+    }
+    cam_free(&cam);
+    return L;
+}
+
+/* Analytic gradient of orc_loss by the chain rule through shading,
+ * barycentrics, the face normal, the rolling light, camera-space
+ * interpolation, the vertex transform and Rodrigues' formula.
+ * Outputs: gv0, gv1 [nv][3] (world vertex positions at t0 / t1),
+ * gpose0, gpose1 [6] (rotation vector then translation).  Returns L. */
+double orc_loss_grad(const double *vp, const double *v0, const double *v1, int nv, const int32_t *tri, int nt,
+                     const double *albedo, const double *light, const int32_t *ids, const double *target,
+                     double *gv0, double *gv1, double *gpose0, double *gpose1) {
+    (void)nt;
+    orc_cam cam;
+    cam_init(&cam, vp, v0, v1, nv);
+    int64_t npix = (int64_t)vp[ORC_W] * (int64_t)vp[ORC_H];
+    int nth = orc_get_threads();
+    /* per-thread accumulators: gradient w.r.t. camera-space start/end vertex
+     * positions, the rotation matrices (light term) and the loss */
+    double *gPs = (double *)calloc((size_t)nth * 3 * nv, sizeof(double));
+    double *gPe = (double *)calloc((size_t)nth * 3 * nv, sizeof(double));
+    double *gRl = (double *)calloc((size_t)nth * 18, sizeof(double));
+    double *Lt = (double *)calloc((size_t)nth, sizeof(double));
+    double lw0[3], lw1[3];
+    matvec(cam.R0, light, lw0);
+    matvec(cam.R1, light, lw1);
+    const double ka = light[3];
+#pragma omp parallel num_threads(nth)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *mPs = gPs + (size_t)tid * 3 * nv, *mPe = gPe + (size_t)tid * 3 * nv, *mR = gRl + 18 * tid;
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < npix; ++p) {
+            int f = ids[p];
+            double c[3] = {0, 0, 0};
+            if (f < 0) {
+                for (int ch = 0; ch < 3; ++ch) { double d = -target[3 * p + ch]; Lt[tid] += d * d; }
+                continue;
+            }
+            double y[2], x[2], t, r[3], P[3][3];
+            orc_pixel_setup(vp, p, y, x, &t, r);
+            tri_at(&cam, tri, f, t, P);
+            double ck[3][3], e[3];
+            for (int k = 0; k < 3; ++k) {
+                cross3(P[(k + 1) % 3], P[(k + 2) % 3], ck[k]);
+                e[k] = dot3(r, ck[k]);
+            }
+            double S = e[0] + e[1] + e[2];
+            double mu[3] = {e[0] / S, e[1] / S, e[2] / S};
+            double N[3] = {ck[0][0] + ck[1][0] + ck[2][0], ck[0][1] + ck[1][1] + ck[2][1],
+                           ck[0][2] + ck[1][2] + ck[2][2]};
+            double nn = norm3(N);
+            double m[3] = {N[0] / nn, N[1] / nn, N[2] / nn};
+            double sg = dot3(m, r) > 0 ? -1.0 : 1.0;
+            double n[3] = {sg * m[0], sg * m[1], sg * m[2]};
+            double Lw[3];
+            for (int d = 0; d < 3; ++d) Lw[d] = (1.0 - t) * lw0[d] + t * lw1[d];
+            double lnorm = norm3(Lw);
+            double l[3] = {Lw[0] / lnorm, Lw[1] / lnorm, Lw[2] / lnorm};
+            double ndl = dot3(n, l);
+            double s = ka + (1.0 - ka) * (ndl > 0 ? ndl : 0.0);
+            double a[3];
+            const int32_t *tv = tri + 3 * (size_t)f;
+            for (int ch = 0; ch < 3; ++ch) {
+                a[ch] = 0;
+                for (int k = 0; k < 3; ++k) a[ch] += mu[k] * albedo[3 * (size_t)tv[k] + ch];
+                c[ch] = a[ch] * s;
+            }
+            double gc[3];
+            for (int ch = 0; ch < 3; ++ch) {
+                double d = c[ch] - target[3 * p + ch];
+                Lt[tid] += d * d;
+                gc[ch] = 2.0 * d;
+            }
+            /* c = a s */
+            double gs = dot3(gc, a);
+            double ga[3] = {gc[0] * s, gc[1] * s, gc[2] * s};
+            /* a = sum_k mu_k albedo_k */
+            double gmu[3];
+            for (int k = 0; k < 3; ++k) gmu[k] = dot3(ga, albedo + 3 * (size_t)tv[k]);
+            /* s = ka + (1-ka) max(0, n.l) */
+            double gndl = ndl > 0 ? gs * (1.0 - ka) : 0.0;
+            double gn[3] = {gndl * l[0], gndl * l[1], gndl * l[2]};
+            double gl[3] = {gndl * n[0], gndl * n[1], gndl * n[2]};
+            /* n = sg N/|N| */
+            double gm[3] = {sg * gn[0], sg * gn[1], sg * gn[2]};
+            double mg = dot3(m, gm);
+            double gN[3];
+            for (int d = 0; d < 3; ++d) gN[d] = (gm[d] - m[d] * mg) / nn;
+            /* l = Lw/|Lw|, Lw = (1-t) R0 lw + t R1 lw */
+            double lg = dot3(l, gl);
+            double gLw[3];
+            for (int d = 0; d < 3; ++d) gLw[d] = (gl[d] - l[d] * lg) / lnorm;
+            for (int rr = 0; rr < 3; ++rr)
+                for (int cc = 0; cc < 3; ++cc) {
+                    mR[3 * rr + cc] += (1.0 - t) * gLw[rr] * light[cc];
+                    mR[9 + 3 * rr + cc] += t * gLw[rr] * light[cc];
+                }
+            /* mu_k = e_k / S */
+            double sm = gmu[0] * mu[0] + gmu[1] * mu[1] + gmu[2] * mu[2];
+            double ge[3];
+            for (int k = 0; k < 3; ++k) ge[k] = (gmu[k] - sm) / S;
+            /* e_k = r . c_k, N = sum_k c_k, c_k = P_a x P_b */
+            double gP[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            for (int k = 0; k < 3; ++k) {
+                double g[3];
+                for (int d = 0; d < 3; ++d) g[d] = ge[k] * r[d] + gN[d];
+                int ia = (k + 1) % 3, ib = (k + 2) % 3;
+                double ta[3], tb[3];
+                cross3(P[ib], g, ta);   /* d/dP_a of g.(P_a x P_b) = P_b x g */
+                cross3(g, P[ia], tb);   /* d/dP_b of g.(P_a x P_b) = g x P_a */
+                for (int d = 0; d < 3; ++d) { gP[ia][d] += ta[d]; gP[ib][d] += tb[d]; }
+            }
+            /* P_k = (1-t) Ps_k + t Pe_k */
+            for (int k = 0; k < 3; ++k)
+                for (int d = 0; d < 3; ++d) {
+                    mPs[3 * (size_t)tv[k] + d] += (1.0 - t) * gP[k][d];
+                    mPe[3 * (size_t)tv[k] + d] += t * gP[k][d];
+                }
+        }
+    }
+    /* reduce thread partials in thread order */
+    double L = 0;
+    for (int th = 0; th < nth; ++th) L += Lt[th];
+    for (int th = 1; th < nth; ++th) {
+        for (size_t i = 0; i < 3 * (size_t)nv; ++i) { gPs[i] += gPs[(size_t)th * 3 * nv + i]; gPe[i] += gPe[(size_t)th * 3 * nv + i]; }
+        for (int i = 0; i < 18; ++i) gRl[i] += gRl[18 * th + i];
+    }
+    /* Ps_v = R0 v0_v + T0 -> gv0 = R0^T gPs, gT0 = sum gPs, gR0 = sum gPs v0^T (+ light term) */
+    double gR0[9], gR1[9], gT0[3] = {0, 0, 0}, gT1[3] = {0, 0, 0};
+    for (int i = 0; i < 9; ++i) { gR0[i] = gRl[i]; gR1[i] = gRl[9 + i]; }
+    for (int v = 0; v < nv; ++v) {
+        const double *gs_ = gPs + 3 * (size_t)v, *ge_ = gPe + 3 * (size_t)v;
+        matTvec(cam.R0, gs_, gv0 + 3 * (size_t)v);
+        matTvec(cam.R1, ge_, gv1 + 3 * (size_t)v);
+        for (int rr = 0; rr < 3; ++rr) {
+            gT0[rr] += gs_[rr];
+            gT1[rr] += ge_[rr];
+            for (int cc = 0; cc < 3; ++cc) {
+                gR0[3 * rr + cc] += gs_[rr] * v0[3 * (size_t)v + cc];
+                gR1[3 * rr + cc] += ge_[rr] * v1[3 * (size_t)v + cc];
+            }
+        }
+    }
+    double J0[27], J1[27];
+    orc_rodrigues_jac(vp + ORC_POSE0, J0);
+    orc_rodrigues_jac(vp + ORC_POSE1, J1);
+    for (int i = 0; i < 3; ++i) {
+        double s0 = 0, s1 = 0;
+        for (int k = 0; k < 9; ++k) { s0 += gR0[k] * J0[9 * i + k]; s1 += gR1[k] * J1[9 * i + k]; }
+        gpose0[i] = s0;
+        gpose1[i] = s1;
+        gpose0[3 + i] = gT0[i];
+        gpose1[3 + i] = gT1[i];
+    }
+    free(gPs); free(gPe); free(gRl); free(Lt);
+    cam_free(&cam);
+    return L;
+}

@@ -1,0 +1,68 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each case copies oracle/pr_oracle.c, plants one plausible mistake (a dropped
+term, a wrong sign or index, a swapped operand), builds the copy with gcc and
+runs tests/test_oracle_pins.py against it; the pins must fail.  Runs on the
+CPU only.
+"""
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, 'oracle', 'pr_oracle.c')
+
+MUTANTS = {
+    'time_swapped_in_lerp': ('(1.0 - t) * c->Ps[3 * v + d] + t * c->Pe[3 * v + d]',
+                             't * c->Ps[3 * v + d] + (1.0 - t) * c->Pe[3 * v + d]'),
+    'rolling_time_unscaled': ('vp[ORC_ROLL] * (x[0] + 1.0) * 0.5', 'vp[ORC_ROLL] * (x[0] + 1.0)'),
+    'foveation_exponent': ('pow(rho / orc_fovea_radius(vp), vp[ORC_ALPHA] - 1.0)', 'pow(rho / orc_fovea_radius(vp), vp[ORC_ALPHA])'),
+    'foveation_radius_nearest_corner': ('if (d > best) best = d;', 'if (best == 0 || d < best) best = d;'),
+    'one_sided_inside_test': ('int neg = e[0] <= 0 && e[1] <= 0 && e[2] <= 0;', 'int neg = 0;'),
+    'depth_is_distance': ('*z = D / S;', '*z = D / S * norm3(r);'),
+    'pixel_centre_offset': ('y[0] = 2.0 * (i + 0.5) / W - 1.0;', 'y[0] = 2.0 * (i + 1.0) / W - 1.0;'),
+    'rows_not_flipped': ('y[1] = 1.0 - 2.0 * (j + 0.5) / H;', 'y[1] = 2.0 * (j + 0.5) / H - 1.0;'),
+    'tie_to_higher_index': ('if (z < bz) {', 'if (z <= bz) {'),
+    'rodrigues_transposed': ('double K[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};',
+                             'double K[9] = {0, w[2], -w[1], -w[2], 0, w[0], w[1], -w[0], 0};'),
+    'principal_point_sign': ('r[0] = (x[0] - vp[ORC_CX]) / vp[ORC_FX];', 'r[0] = (x[0] + vp[ORC_CX]) / vp[ORC_FX];'),
+    'ambient_not_scaled': ('double s = light[3] + (1.0 - light[3]) * (ndl > 0 ? ndl : 0.0);',
+                           'double s = light[3] + (ndl > 0 ? ndl : 0.0);'),
+    'light_not_rolling': ('for (int d = 0; d < 3; ++d) L[d] = (1.0 - t) * l0[d] + t * l1[d];',
+                          'for (int d = 0; d < 3; ++d) L[d] = l0[d];'),
+    'normal_not_flipped': ('if (dot3(n, r) > 0) { n[0] = -n[0]; n[1] = -n[1]; n[2] = -n[2]; }', ''),
+    'grad_end_weight': ('mPe[3 * (size_t)tv[k] + d] += t * gP[k][d];',
+                        'mPe[3 * (size_t)tv[k] + d] += (1.0 - t) * gP[k][d];'),
+    'grad_cross_order': ('cross3(P[ib], g, ta);', 'cross3(g, P[ib], ta);'),
+    'grad_light_weight': ('mR[9 + 3 * rr + cc] += t * gLw[rr] * light[cc];', 'mR[9 + 3 * rr + cc] += gLw[rr] * light[cc];'),
+    'grad_rotation_jacobian': ('for (int k = 0; k < 9; ++k) out[k] = Ei[k] + 0.5 * (A[k] + B[k]);',
+                               'for (int k = 0; k < 9; ++k) out[k] = Ei[k];'),
+    'grad_translation': ('gT0[rr] += gs_[rr];', 'gT0[rr] -= gs_[rr];'),
+}
+
+
+def _run(name, tmp):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f'{name}: pattern must occur exactly once'
+    d = os.path.join(tmp, name)
+    os.makedirs(d, exist_ok=True)
+    c = os.path.join(d, 'm.c')
+    so = os.path.join(d, 'm.so')
+    open(c, 'w').write(src.replace(old, new))
+    subprocess.check_call(['gcc', '-O2', '-fopenmp', '-fPIC', '-shared', '-std=c11', '-o', so, c, '-lm'])
+    env = dict(os.environ, PR_ORACLE_LIB=so, OMP_NUM_THREADS='2')
+    r = subprocess.run([sys.executable, '-m', 'pytest', '-x', '-q', '-p', 'no:cacheprovider',
+                        os.path.join(ROOT, 'tests', 'test_oracle_pins.py')],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return name, r.returncode
+
+
+def test_every_planted_mistake_fails_a_pin(tmp_path):
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        results = list(ex.map(lambda n: _run(n, str(tmp_path)), sorted(MUTANTS)))
+    survived = [n for n, rc in results if rc == 0]
+    assert not survived, f'mutants not caught by the pins: {survived}'
