@@ -1,0 +1,145 @@
+"""Benchmark: one step = one perceptual rasterization frame of the HMD
+workload (201,920 triangles, two eyes at 1512x1680, foveated alpha = 2,
+rolling, head yaw 120 deg/s + 0.5 m/s over an 11.1 ms frame): pr_bound ->
+pr_bin -> pr_raycast -> pr_shade for both eyes on one GPU.  Inputs are
+resident in HBM before timing starts.  Prints one JSON line.
+
+The CPU baseline is the FP64 brute-force oracle timed on a bounded sample of
+pixels of the same workload and extrapolated to a full frame."""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_TEST_MOVING = 48   # 3 edges x (6 FMA for c(t) + 2 FMA for r.c)
+FLOP_PER_TEST_STATIC = 12   # 3 edges x 2 FMA
+PEAK_FP32_TFLOPS = 157.3    # MI355X vector FP32 (packed FMA)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=50)
+    ap.add_argument('--warmup', type=int, default=5)
+    ap.add_argument('--tile', type=int, default=16)
+    ap.add_argument('--cpu-pixels', type=int, default=1024)
+    ap.add_argument('--no-cpu-baseline', action='store_true')
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({'error': 'this build runs on one GPU; --gpus above 1 is not supported'}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_1806_05385_amd import binding as B
+    from paper_1806_05385_amd.render import Renderer
+
+    torch.cuda.set_device(0)
+    sc = scenegen.make_hmd()
+    mesh = sc.meshes[0]
+    r = Renderer(sc.meshes, sc.views, tile=args.tile, light=sc.light_dir, ambient=sc.ambient)
+    r.frame(check=True)            # sizes the tile-list capacity
+    # one counting frame (not timed): ray-triangle tests and hits
+    r.flags = B.PR_FLAG_COUNT
+    r._prepare()
+    r.frame(check=True)
+    st = r.status()
+    tests, hits = int(st.tests), int(st.hits)
+    r.flags = 0
+    r._prepare()
+    r.frame(check=True)
+
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        r.frame(check=False)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for k in range(args.steps):
+        r.bound()
+        r.bin()
+        ev[k][0].record(stream)
+        r.raycast()
+        ev[k][1].record(stream)
+        r.shade(rgba8=True, rgb32=False)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    st = r.status()
+    assert not st.overflow
+    ms_step = t0.elapsed_time(t1) / args.steps
+    ray_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    ray_ms_avg = float(ray_ms.mean())
+
+    rolling = any(v.roll_dir[0] or v.roll_dir[1] for v in sc.views)
+    flop_test = FLOP_PER_TEST_MOVING if rolling else FLOP_PER_TEST_STATIC
+    achieved = tests * flop_test / (ray_ms_avg * 1e-3) / 1e12
+    traffic = None
+    tpath = os.path.join(ROOT, 'profiles', 'raycast_hmd_traffic.json')
+    if os.path.exists(tpath):
+        traffic = json.load(open(tpath)).get('bytes_per_launch')
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        view = sc.views[0]
+        pix = scenegen.sample_pixels(1234, view, args.cpu_pixels)
+        orc = oracle.Oracle(mesh, view)
+        threads = oracle.lib().orc_get_threads()
+        c0 = time.perf_counter()
+        orc.render(pix)
+        c1 = time.perf_counter()
+        px_total = sum(v.width * v.height for v in sc.views)
+        cpu_ms = (c1 - c0) / len(pix) * px_total * 1e3
+        cpu = {'value': round(cpu_ms, 1), 'unit': 'ms/frame', 'cores': threads, 'kind': 'oracle',
+               'sample': f'{len(pix)} pixels of eye 0 (half within 0.1 NDC of the fovea) x {mesh.nt} triangles, '
+                         f'FP64 brute force, {c1 - c0:.1f} s, extrapolated to {px_total} pixels'}
+
+    out = {
+        'metric': 'frame ms + ray-tri tests/s, fov+rolling 2x1512x1680 @200k tris; bwd/fwd',
+        'value': round(ms_step, 4),
+        'unit': 'ms/frame',
+        'n_gpus': 1,
+        'steps': args.steps,
+        'warmup': args.warmup,
+        'ms_per_step': round(ms_step, 4),
+        'higher_is_better': False,
+        'scaling': 'weak',
+        'vs_baseline': None,
+        'dtype': 'f32',
+        'data': 'synthetic (seeded displaced geodesic sphere + 500 boxes)',
+        'config': {'workload': 'hmd: 201,920 triangles, 2 eyes x 1512x1680, foveated (alpha 2) + rolling, '
+                               'head yaw 120 deg/s + 0.5 m/s, Lambert', 'triangles': int(mesh.nt),
+                   'views': len(sc.views), 'width': sc.views[0].width, 'height': sc.views[0].height,
+                   'tile': args.tile},
+        'frames_per_s': round(1e3 / ms_step, 1),
+        'raycast_ms': round(ray_ms_avg, 4),
+        'tests_per_frame': tests,
+        'tests_per_s': round(tests / (ray_ms_avg * 1e-3), 1),
+        'ste': round(hits / max(tests, 1), 4),
+        'pairs_per_frame': int(st.pairs_total),
+        'wall_s': round(wall, 3),
+        'roofline': {'bound': 'alu', 'achieved': round(achieved, 3), 'peak': PEAK_FP32_TFLOPS,
+                     'unit': 'TFLOP/s', 'frac': round(achieved / PEAK_FP32_TFLOPS, 4), 'traffic': traffic,
+                     'kernel': 'k_raycast', 'flop_per_test': flop_test,
+                     'frac_of_unpacked_peak': round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4)},
+        'cpu_baseline': cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == '__main__':
+    main()

@@ -1,0 +1,228 @@
+/*
+ * pr.h -- C ABI of the perceptual rasterization library (libpr.so, gfx950).
+ *
+ * Perceptual rasterization (Friston, Ritschel & Steed, "Perceptual
+ * Rasterization for Head-mounted Display Image Synthesis") renders, in one
+ * pass, an image that is both foveated (its pixel grid is magnified about a
+ * fovea point, Sec. 3.1.1) and rolling (each pixel is rendered at the time
+ * its display column is lit, Sec. 3.1.2; jointly Sec. 3.1.3).  Every triangle
+ * moves linearly in camera space between the frame's start and end
+ * (Sec. 3.1.2, third display property).  A conservative per-triangle pixel
+ * bound (Sec. 4) selects the pixels whose rays are intersected with the
+ * triangle at the pixel's own time (Sec. 3.2, "Intersection"); the nearest
+ * hit wins.  Shading interpolates the light to the pixel's time (Sec. 3.2,
+ * "Shading").
+ *
+ * The calls of one frame are, in order:
+ *   pr_bound    per-triangle camera-space transform, clipping/culling,
+ *               rolling time interval and foveated screen bound (Sec. 3.2
+ *               "Bounding", Sec. 4.1-4.3)
+ *   pr_bin      per-(triangle, tile) conservative test and tile lists
+ *               (replaces the fixed-function rasterisation of the bound)
+ *   pr_raycast  per-pixel ray at the pixel's foveated position and time,
+ *               ray-triangle test, nearest-depth resolve (Sec. 3.2)
+ *   pr_shade    rolling Lambert shading of the resolved ids (Sec. 3.2)
+ * and, for differentiable rendering,
+ *   pr_backward gradient of an image loss w.r.t. vertex positions and the
+ *               start/end camera poses with visibility held fixed.
+ *
+ * CONVENTIONS
+ *   World->view pose: rotation vector omega (3), translation T (3);
+ *   P = R(omega) v + T (Rodrigues).  View space: x right, y up, +z forward.
+ *   NDC of a view-space point: (fx X/Z + cx, fy Y/Z + cy).
+ *   Pixel (i, j) (row 0 at the top) samples the foveated NDC point
+ *   y = (2(i+1/2)/W - 1, 1 - 2(j+1/2)/H); its display point is
+ *   x = f + (y - f) (|y - f|/R)^(alpha-1) with f the fovea and R the distance
+ *   from f to the farthest image corner (power-law density, alpha = 1 is the
+ *   identity); its time is t = clamp(d . (x+1)/2, 0, 1) with d = roll_dir
+ *   ((0,0) = rolling off); its ray is ((x0-cx)/fx, (x1-cy)/fy, 1).
+ *   The triangle at time t has camera-space vertices
+ *   (1-t)(R0 v0 + T0) + t(R1 v1 + T1).  A pixel is covered when the ray
+ *   meets the triangle (inclusive edges, both faces) at depth z >= znear;
+ *   depth is camera-space z.  Among covered triangles the smallest
+ *   (depth, triangle index) pair wins.
+ *
+ * MEMORY AND OWNERSHIP
+ *   All array pointers inside pr_mesh and all output pointers are DEVICE
+ *   pointers on the current HIP device; the pr_mesh / pr_view / pr_light /
+ *   pr_tuning structs themselves live in host memory and are only read
+ *   during the call.  The caller owns every buffer, including one workspace
+ *   of pr_workspace_size() bytes (256-byte aligned) that carries state from
+ *   pr_bound to the later calls of the same frame.  The library allocates no
+ *   device memory in these calls.  Outputs are fully overwritten (misses:
+ *   id -1, depth +inf, rgba 0); gradient outputs are overwritten, not
+ *   accumulated.
+ *
+ * ORDERING
+ *   Every call only enqueues work on `stream` (a hipStream_t; NULL = the
+ *   default stream) and returns; nothing synchronises except
+ *   pr_status_read.  Calls are thread-safe; concurrent frames need their
+ *   own workspaces.
+ *
+ * ERRORS
+ *   Every call returns PR_OK (0) or a negative code.  Arguments are checked
+ *   before anything is enqueued; on an error nothing is launched.  Conditions
+ *   found on the device (tile-list capacity overflow, non-finite vertices)
+ *   are recorded in a status block inside the workspace and read with
+ *   pr_status_read.  After an overflow, pr_raycast writes misses for the
+ *   affected view; rerun with bin_capacity >= pr_status.pairs_required.
+ */
+#ifndef PR_H
+#define PR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PR_OK 0
+#define PR_ERR_INVALID (-1)     /* null pointer, bad size or parameter */
+#define PR_ERR_UNSUPPORTED (-2) /* valid but not implemented (e.g. tile size) */
+#define PR_ERR_WORKSPACE (-3)   /* workspace too small or misaligned */
+#define PR_ERR_HIP (-4)         /* a HIP runtime call failed */
+
+#define PR_MAX_VIEWS 64         /* views per call */
+
+/* A triangle mesh.  v0 / v1: float32 [nv][3] world positions at the frame's
+ * start / end (v1 may equal v0); tri: int32 [nt][3] vertex indices in
+ * [0, nv).  nt may be 0. */
+typedef struct pr_mesh {
+    const float *v0;
+    const float *v1;
+    const int32_t *tri;
+    int32_t nv;
+    int32_t nt;
+} pr_mesh;
+
+/* One view (eye, frame or batch entry).  width, height in pixels
+ * (1..16384); mesh indexes the pr_mesh array; pose0 / pose1 world->view at
+ * the frame's start / end; fx, fy non-zero; znear > 0; fovea in NDC;
+ * alpha >= 1 (1 = no foveation); roll_dir = d ((0,0) = rolling off). */
+typedef struct pr_view {
+    int32_t width, height, mesh, reserved;
+    float pose0[6];
+    float pose1[6];
+    float fx, fy, cx, cy, znear;
+    float fovea[2];
+    float alpha;
+    float roll_dir[2];
+} pr_view;
+
+/* Directional light: dir_world points towards the light (need not be unit);
+ * ambient = k_a in c = albedo (k_a + (1 - k_a) max(0, n.l)). */
+typedef struct pr_light {
+    float dir_world[3];
+    float ambient;
+} pr_light;
+
+/* tile: square tile side in pixels, one of 8, 16, 32.
+ * bin_capacity: (triangle, tile) pairs each view's tile lists can hold.
+ * flags: PR_FLAG_COUNT makes pr_raycast count ray-triangle tests and hits
+ * (sample test efficiency) into the status block. */
+typedef struct pr_tuning {
+    int32_t tile;
+    int32_t bin_capacity;
+    int32_t flags;
+    int32_t reserved;
+} pr_tuning;
+
+#define PR_FLAG_COUNT 1
+
+/* Device-side conditions of the last frame (all views). */
+typedef struct pr_status {
+    int32_t overflow;          /* 1 if some view's pairs exceeded bin_capacity */
+    int32_t nonfinite;         /* triangles with a non-finite vertex (culled) */
+    int64_t pairs_required;    /* largest pair count of any view */
+    int64_t pairs_total;       /* pairs over all views */
+    int64_t tests;             /* ray-triangle tests (PR_FLAG_COUNT) */
+    int64_t hits;              /* tests that passed (PR_FLAG_COUNT) */
+} pr_status;
+
+/* Bytes of workspace a frame with these meshes, views and tuning needs.
+ * Writes *bytes; returns PR_OK or PR_ERR_INVALID. */
+int pr_workspace_size(const pr_mesh *meshes, int nm, const pr_view *views, int nv,
+                      const pr_tuning *tuning, size_t *bytes);
+
+/* Per-triangle bound (Sec. 3.2 "Bounding", Sec. 4): camera-space vertices
+ * at start and end, near-plane clipping of the space-time triangle
+ * (Sec. 4.2.2), the interval of frame time in which the rolling scan can
+ * meet the triangle (Sec. 4.2.3-4.2.4, the scan catching up with each moving
+ * vertex solved exactly), the display-space box of the triangle over that
+ * interval and its conservative foveated image (Sec. 4.1, 4.3) as a tile
+ * rectangle.  Also writes each triangle's intersection record.  Resets the
+ * status block.  Reads the meshes; writes only the workspace. */
+int pr_bound(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
+             void *ws, size_t ws_bytes, void *stream);
+
+/* Tile binning: every (triangle, tile) pair of the triangle's rectangle is
+ * tested conservatively against the tile's display region over the tile's
+ * own time window; surviving pairs are compacted (wave ballot + prefix) and
+ * gathered into per-tile triangle lists.  Needs pr_bound first. */
+int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
+           void *ws, size_t ws_bytes, void *stream);
+
+/* Ray cast (Sec. 3.2 "Intersection"): per pixel, the ray at the pixel's
+ * foveated position and time against every triangle of its tile list;
+ * nearest (depth, id) wins.  tri_id[v]: int32 [H][W], depth[v]: float32
+ * [H][W] for view v (device).  Needs pr_bin first. */
+int pr_raycast(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
+               void *ws, size_t ws_bytes, int32_t *const *tri_id, float *const *depth, void *stream);
+
+/* Rolling Lambert shading (Sec. 3.2 "Shading"): light direction
+ * normalize((1-t) R0 l + t R1 l) at the pixel's time t, face normal turned
+ * towards the eye, per-vertex albedo (float32 [nv][3] per mesh) blended with
+ * the perspective-correct barycentrics of the hit.  rgba8[v] (uint8
+ * [H][W][4]) and rgb32[v] (float32 [H][W][3]) may each be NULL (or hold NULL
+ * entries).  Needs pr_bound of the same frame. */
+int pr_shade(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
+             void *ws, size_t ws_bytes, const int32_t *const *tri_id, const pr_light *light,
+             const float *const *albedo, uint8_t *const *rgba8, float *const *rgb32, void *stream);
+
+/* Gradient of a loss L(rgb32) with visibility fixed to tri_id: given
+ * dL/drgb[v] (float32 [H][W][3]), writes dL/dv0 and dL/dv1 (float32 [nv][3]
+ * per mesh, summed over the views that use the mesh) and dL/dpose0,
+ * dL/dpose1 (float32 [nv_views][6]: rotation vector then translation).
+ * Needs pr_bound of the same frame. */
+int pr_backward(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
+                void *ws, size_t ws_bytes, const int32_t *const *tri_id, const pr_light *light,
+                const float *const *albedo, const float *const *dl_drgb, float *const *dv0,
+                float *const *dv1, float *dpose0, float *dpose1, void *stream);
+
+/* Waits for `stream`, copies the workspace's status block into *out.
+ * Returns PR_OK, PR_ERR_INVALID or PR_ERR_HIP. */
+int pr_status_read(const void *ws, size_t ws_bytes, pr_status *out, void *stream);
+
+/* Static text for a return code. */
+const char *pr_status_string(int code);
+
+/* Copies one view's tile lists to host memory for inspection:
+ * offsets: int32 [tiles+1] (host), lists: int32 [cap] (host; may be NULL to
+ * query).  *ntiles receives the tile count, *npairs the list length.
+ * Synchronises `stream`.  Used by tests of the bound's conservativeness. */
+int pr_debug_tile_lists(const pr_mesh *meshes, int nm, const pr_view *views, int nv,
+                        const pr_tuning *tuning, const void *ws, size_t ws_bytes, int view,
+                        int32_t *offsets, int32_t *lists, int64_t cap, int32_t *ntiles,
+                        int64_t *npairs, void *stream);
+
+/* Host evaluation of the bound pieces, for CPU tests of their
+ * conservativeness without a GPU (the same code the kernels run).  `mesh`
+ * holds HOST pointers here.
+ * pr_host_time_interval: the frame-time window of triangle f in `view`;
+ *   returns 0 (culled: never visible), 1 (window t[0..1]) or 2 (the near
+ *   plane cuts the triangle; the window is the whole frame).
+ * pr_host_tile_rect: the triangle's inclusive tile rectangle
+ *   rect = {x0, y0, x1, y1}; returns 0 if culled, 1 otherwise.
+ * pr_host_tile_test: 1 if the pair (triangle f, tile (tx, ty)) survives
+ *   binning, 0 if it is rejected (or the triangle is culled). */
+int pr_host_time_interval(const pr_mesh *mesh, int32_t f, const pr_view *view, double *t);
+int pr_host_tile_rect(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t tile, int32_t *rect);
+int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t tile, int32_t tx,
+                      int32_t ty);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PR_H */

@@ -1,0 +1,428 @@
+// pr_geom.h -- bound geometry shared by the gfx950 kernels and the host
+// test hooks (compiled for both).  Everything here is double precision: it
+// runs once per triangle (bound) or once per (triangle, tile) pair (bin),
+// where the cost is small next to the per-pixel ray cast, and it must be
+// conservative: a pair may only be dropped when the triangle provably covers
+// no pixel centre of the tile at that pixel's own time.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "pr.h"
+
+#define PRG __host__ __device__ inline
+
+namespace prg {
+
+// Absolute slack (NDC units / frame-time units) added to every bound; far
+// above the double rounding of the computations it protects.
+constexpr double kSlackNdc = 1e-9;
+constexpr double kSlackTime = 1e-6;
+
+struct Geom {
+    double R0[9], T0[3], R1[9], T1[3];
+    double fx, fy, cx, cy, znear;
+    double fov[2], alpha, rad;   // fovea, exponent, normalising radius
+    double roll[2];
+    int W, H;
+    bool rolling;
+};
+
+PRG double dmin(double a, double b) { return a < b ? a : b; }
+PRG double dmax(double a, double b) { return a > b ? a : b; }
+PRG double clamp01(double t) { return t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t); }
+
+// Rotation matrix of a rotation vector (Rodrigues' formula).
+PRG void rodrigues(const float *wf, double R[9]) {
+    double w[3] = {wf[0], wf[1], wf[2]};
+    double th = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    double a, b;
+    if (th < 1e-8) {
+        a = 1.0 - th * th / 6.0;
+        b = 0.5 - th * th / 24.0;
+    } else {
+        a = sin(th) / th;
+        b = (1.0 - cos(th)) / (th * th);
+    }
+    // R = I + a K + b K^2, K = [w]x ; K^2 = w w^T - th^2 I
+    double K[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double k2 = w[r] * w[c] - (r == c ? th * th : 0.0);
+            R[3 * r + c] = (r == c ? 1.0 : 0.0) + a * K[3 * r + c] + b * k2;
+        }
+}
+
+// Distance from the fovea to the farthest image corner.
+PRG double fovea_radius(double f0, double f1) {
+    double ex = fabs(f0) + 1.0, ey = fabs(f1) + 1.0;
+    return sqrt(ex * ex + ey * ey);
+}
+
+PRG void make_geom(const pr_view &v, Geom &g) {
+    rodrigues(v.pose0, g.R0);
+    rodrigues(v.pose1, g.R1);
+    for (int k = 0; k < 3; ++k) {
+        g.T0[k] = v.pose0[3 + k];
+        g.T1[k] = v.pose1[3 + k];
+    }
+    g.fx = v.fx; g.fy = v.fy; g.cx = v.cx; g.cy = v.cy; g.znear = v.znear;
+    g.fov[0] = v.fovea[0]; g.fov[1] = v.fovea[1];
+    g.alpha = v.alpha;
+    g.rad = fovea_radius(g.fov[0], g.fov[1]);
+    g.roll[0] = v.roll_dir[0]; g.roll[1] = v.roll_dir[1];
+    g.rolling = (v.roll_dir[0] != 0.0f) || (v.roll_dir[1] != 0.0f);
+    g.W = v.width; g.H = v.height;
+}
+
+// Radial power map about the fovea: |m(x) - f| = R (|x - f| / R)^e.
+// e = alpha: foveated -> display (unfoveate); e = 1/alpha: display ->
+// foveated (foveate).
+PRG void radial_map(const Geom &g, double e, double x0, double x1, double &o0, double &o1) {
+    double d0 = x0 - g.fov[0], d1 = x1 - g.fov[1];
+    double rho = sqrt(d0 * d0 + d1 * d1);
+    if (rho == 0.0 || e == 1.0) { o0 = x0; o1 = x1; return; }
+    double s = pow(rho / g.rad, e - 1.0);
+    o0 = g.fov[0] + d0 * s;
+    o1 = g.fov[1] + d1 * s;
+}
+
+// Exact bounding box of a radial map of the rectangle [a0,a1] x [b0,b1].
+// Component k of the map is increasing in coordinate k; in the other
+// coordinate it depends only on the distance to the fovea: for e > 1 the
+// scale (rho/R)^(e-1) grows with distance, for e < 1 it shrinks.  So each
+// extreme sits on the matching rectangle side at the point nearest to or
+// farthest from the fovea's coordinate.
+PRG void radial_bbox(const Geom &g, double e, double a0, double a1, double b0, double b1, double out[4]) {
+    bool grows = e > 1.0;
+    auto nearest = [](double c, double lo, double hi) { return c < lo ? lo : (c > hi ? hi : c); };
+    auto farthest = [](double c, double lo, double hi) { return (c - lo) > (hi - c) ? lo : hi; };
+    double o0, o1, y;
+    // max of component 0: at x = a1
+    y = ((a1 - g.fov[0] >= 0) == grows) ? farthest(g.fov[1], b0, b1) : nearest(g.fov[1], b0, b1);
+    radial_map(g, e, a1, y, o0, o1);
+    out[1] = o0;
+    // min of component 0: at x = a0
+    y = ((a0 - g.fov[0] <= 0) == grows) ? farthest(g.fov[1], b0, b1) : nearest(g.fov[1], b0, b1);
+    radial_map(g, e, a0, y, o0, o1);
+    out[0] = o0;
+    // max of component 1: at y = b1
+    double x = ((b1 - g.fov[1] >= 0) == grows) ? farthest(g.fov[0], a0, a1) : nearest(g.fov[0], a0, a1);
+    radial_map(g, e, x, b1, o0, o1);
+    out[3] = o1;
+    x = ((b0 - g.fov[1] <= 0) == grows) ? farthest(g.fov[0], a0, a1) : nearest(g.fov[0], a0, a1);
+    radial_map(g, e, x, b0, o0, o1);
+    out[2] = o1;
+}
+
+// Camera-space start / end vertices of triangle f.  Returns false if an
+// index is out of range or a vertex is not finite.
+PRG bool load_tri(const float *v0, const float *v1, const int32_t *tri, int32_t nv, int32_t f, const Geom &g,
+                  double Ps[3][3], double Pe[3][3], int32_t idx[3]) {
+    bool ok = true;
+    for (int k = 0; k < 3; ++k) {
+        int32_t i = tri[3 * (int64_t)f + k];
+        if (i < 0 || i >= nv) { i = 0; ok = false; }
+        idx[k] = i;
+        double a[3] = {v0[3 * (int64_t)i], v0[3 * (int64_t)i + 1], v0[3 * (int64_t)i + 2]};
+        double b[3] = {v1[3 * (int64_t)i], v1[3 * (int64_t)i + 1], v1[3 * (int64_t)i + 2]};
+        for (int r = 0; r < 3; ++r) {
+            Ps[k][r] = g.R0[3 * r] * a[0] + g.R0[3 * r + 1] * a[1] + g.R0[3 * r + 2] * a[2] + g.T0[r];
+            Pe[k][r] = g.R1[3 * r] * b[0] + g.R1[3 * r + 1] * b[1] + g.R1[3 * r + 2] * b[2] + g.T1[r];
+            ok = ok && isfinite(Ps[k][r]) && isfinite(Pe[k][r]);
+        }
+    }
+    return ok;
+}
+
+// Unclamped unit scan time of the projection of camera-space point P,
+// multiplied by P.z: N(P) = d . ((fx X + (cx+1) Z)/2, (fy Y + (cy+1) Z)/2).
+PRG double scan_numer(const Geom &g, const double P[3]) {
+    return 0.5 * (g.roll[0] * (g.fx * P[0] + (g.cx + 1.0) * P[2]) + g.roll[1] * (g.fy * P[1] + (g.cy + 1.0) * P[2]));
+}
+
+// Real roots of a t^2 + b t + c in the open interval (0, 1).
+PRG int quad_roots01(double a, double b, double c, double r[2]) {
+    int n = 0;
+    double scale = fabs(a) + fabs(b) + fabs(c);
+    if (scale == 0.0) return 0;
+    if (fabs(a) <= 1e-14 * scale) {
+        if (b != 0.0) {
+            double t = -c / b;
+            if (t > 0.0 && t < 1.0) r[n++] = t;
+        }
+        return n;
+    }
+    double disc = b * b - 4.0 * a * c;
+    if (disc < 0.0) {
+        // a (near-)double root: keep the vertex of the parabola as a breakpoint
+        if (disc > -1e-12 * b * b) {
+            double t = -b / (2.0 * a);
+            if (t > 0.0 && t < 1.0) r[n++] = t;
+        }
+        return n;
+    }
+    double q = -0.5 * (b + (b >= 0 ? sqrt(disc) : -sqrt(disc)));
+    double t1 = q / a;
+    double t2 = q != 0.0 ? c / q : t1;
+    if (t1 > 0.0 && t1 < 1.0) r[n++] = t1;
+    if (t2 > 0.0 && t2 < 1.0 && t2 != t1) r[n++] = t2;
+    return n;
+}
+
+enum { kCulled = 0, kWindow = 1, kClipped = 2 };
+
+// Frame-time window in which the triangle can affect a pixel.
+//  kCulled : never (every space-time vertex behind the near plane, or the
+//            rolling scan never meets the triangle).
+//  kWindow : every vertex stays at Z >= znear through the frame; win is the
+//            exact set of times at which the scan line (the iso-time line of
+//            the display) crosses the projected triangle, padded.
+//  kClipped: the near plane cuts the space-time triangle; win is the whole
+//            frame (or [0,0] without rolling).
+// Without rolling every pixel is at t = 0, so win = [0, 0].
+//
+// Catch-up test (the scan "catching up" with a moving vertex): vertex k
+// projects to display time u_k(t) = N_k(t) / Z_k(t) with N_k, Z_k linear in
+// t, so u_k(t) - t has the sign of the quadratic h_k(t) = N_k(t) - t Z_k(t).
+// The scan at time t meets the triangle only if min_k h_k(t) <= 0 <=
+// max_k h_k(t) (the projected triangle's scan-time range contains t); at
+// t = 0 pixels with u <= 0 count, at t = 1 pixels with u >= 1.  Between the
+// roots of the h_k no sign changes, so testing each root and each gap's
+// midpoint gives the window exactly.
+PRG int time_window(const Geom &g, const double Ps[3][3], const double Pe[3][3], double win[2]) {
+    int n_in = 0, n_pts = g.rolling ? 6 : 3;
+    for (int k = 0; k < 3; ++k) {
+        n_in += Ps[k][2] >= g.znear;
+        if (g.rolling) n_in += Pe[k][2] >= g.znear;
+    }
+    if (n_in == 0) return kCulled;
+    if (n_in < n_pts) {
+        win[0] = 0.0;
+        win[1] = g.rolling ? 1.0 : 0.0;
+        return kClipped;
+    }
+    if (!g.rolling) {
+        win[0] = win[1] = 0.0;
+        return kWindow;
+    }
+    double hc[3][3];  // h_k = hc[k][0] + hc[k][1] t + hc[k][2] t^2
+    double bp[8];
+    int nb = 0;
+    bp[nb++] = 0.0;
+    bp[nb++] = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        double n0 = scan_numer(g, Ps[k]);
+        double n1 = scan_numer(g, Pe[k]) - n0;
+        double z0 = Ps[k][2], z1 = Pe[k][2] - Ps[k][2];
+        hc[k][0] = n0;
+        hc[k][1] = n1 - z0;
+        hc[k][2] = -z1;
+        double r[2];
+        int nr = quad_roots01(hc[k][2], hc[k][1], hc[k][0], r);
+        for (int i = 0; i < nr; ++i) bp[nb++] = r[i];
+    }
+    // sort breakpoints (at most 8)
+    for (int i = 1; i < nb; ++i) {
+        double v = bp[i];
+        int j = i - 1;
+        while (j >= 0 && bp[j] > v) { bp[j + 1] = bp[j]; --j; }
+        bp[j + 1] = v;
+    }
+    double lo = 2.0, hi = -1.0;
+    for (int i = 0; i < nb; ++i) {
+        // the breakpoint itself
+        double t = bp[i];
+        double hmin = 1e300, hmax = -1e300;
+        for (int k = 0; k < 3; ++k) {
+            double h = hc[k][0] + t * (hc[k][1] + t * hc[k][2]);
+            hmin = dmin(hmin, h);
+            hmax = dmax(hmax, h);
+        }
+        bool rel;
+        if (t == 0.0) rel = hmin <= 0.0;
+        else if (t == 1.0) rel = hmax >= 0.0;
+        else rel = hmin <= 0.0 && hmax >= 0.0;
+        if (rel) { lo = dmin(lo, t); hi = dmax(hi, t); }
+        // the gap to the next breakpoint
+        if (i + 1 < nb && bp[i + 1] > t) {
+            double m = 0.5 * (t + bp[i + 1]);
+            hmin = 1e300; hmax = -1e300;
+            for (int k = 0; k < 3; ++k) {
+                double h = hc[k][0] + m * (hc[k][1] + m * hc[k][2]);
+                hmin = dmin(hmin, h);
+                hmax = dmax(hmax, h);
+            }
+            if (hmin <= 0.0 && hmax >= 0.0) { lo = dmin(lo, t); hi = dmax(hi, bp[i + 1]); }
+        }
+    }
+    if (lo > hi) return kCulled;
+    win[0] = clamp01(lo - kSlackTime);
+    win[1] = clamp01(hi + kSlackTime);
+    return kWindow;
+}
+
+// Display-space (NDC) box of the triangle over [w0, w1].  kWindow: the box
+// of the six projected vertices at the window ends (linear motion keeps the
+// triangle inside the hull of its end positions, and projection of the
+// segments in front of the eye keeps that hull's image inside the hull of
+// the projected ends).  kClipped: the box of the projected part of the
+// space-time hull in front of the near plane: the end points at Z >= znear
+// and every end-point segment's crossing of Z = znear.
+PRG void display_box(const Geom &g, const double Ps[3][3], const double Pe[3][3], double w0, double w1,
+                     int kind, double box[4]) {
+    double pts[6][3];
+    int n = (w1 > w0) ? 6 : 3;
+    for (int k = 0; k < 3; ++k)
+        for (int r = 0; r < 3; ++r) {
+            pts[k][r] = (1.0 - w0) * Ps[k][r] + w0 * Pe[k][r];
+            pts[3 + k][r] = (1.0 - w1) * Ps[k][r] + w1 * Pe[k][r];
+        }
+    box[0] = box[2] = 1e300;
+    box[1] = box[3] = -1e300;
+    auto add = [&](const double *P) {
+        double x = g.fx * P[0] / P[2] + g.cx, y = g.fy * P[1] / P[2] + g.cy;
+        box[0] = dmin(box[0], x); box[1] = dmax(box[1], x);
+        box[2] = dmin(box[2], y); box[3] = dmax(box[3], y);
+    };
+    if (kind == kWindow) {
+        for (int i = 0; i < n; ++i) add(pts[i]);
+    } else {
+        for (int i = 0; i < n; ++i)
+            if (pts[i][2] >= g.znear) add(pts[i]);
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) {
+                bool ii = pts[i][2] >= g.znear, jj = pts[j][2] >= g.znear;
+                if (ii == jj) continue;
+                double s = (g.znear - pts[i][2]) / (pts[j][2] - pts[i][2]);
+                double q[3];
+                for (int r = 0; r < 3; ++r) q[r] = pts[i][r] + s * (pts[j][r] - pts[i][r]);
+                q[2] = g.znear;
+                add(q);
+            }
+    }
+    for (int k = 0; k < 4; ++k) {
+        double m = kSlackNdc * (1.0 + fabs(box[k]));
+        box[k] += (k & 1) ? m : -m;
+    }
+}
+
+// Range of pixel indices whose centre coordinate lies in [lo, hi] for an
+// axis with n pixels; returns false if none.  flip: row axis (NDC y up).
+PRG bool pixel_range(double lo, double hi, int n, bool flip, int &i0, int &i1) {
+    double a, b;
+    if (!flip) { a = (lo + 1.0) * 0.5 * n - 0.5; b = (hi + 1.0) * 0.5 * n - 0.5; }
+    else { a = (1.0 - hi) * 0.5 * n - 0.5; b = (1.0 - lo) * 0.5 * n - 0.5; }
+    a = dmax(a, 0.0);
+    b = dmin(b, (double)(n - 1));
+    if (!(a <= b)) return false;
+    i0 = (int)ceil(a - 1e-7);
+    i1 = (int)floor(b + 1e-7);
+    if (i0 < 0) i0 = 0;
+    if (i1 > n - 1) i1 = n - 1;
+    return i0 <= i1;
+}
+
+// Tile rectangle (inclusive tile coordinates) of a display box.  The box is
+// clipped to the display square (every pixel's display point lies in it),
+// mapped to the foveated domain with the exact box rule, and converted to
+// the pixel centres it contains.  Returns false if it covers no pixel centre.
+PRG bool tile_rect(const Geom &g, const double box[4], int tile, int rect[4]) {
+    double a0 = dmax(box[0], -1.0), a1 = dmin(box[1], 1.0);
+    double b0 = dmax(box[2], -1.0), b1 = dmin(box[3], 1.0);
+    if (!(a0 <= a1 && b0 <= b1)) return false;
+    double fb[4];
+    radial_bbox(g, 1.0 / g.alpha, a0, a1, b0, b1, fb);
+    for (int k = 0; k < 4; ++k) {
+        double m = kSlackNdc * (1.0 + fabs(fb[k]));
+        fb[k] += (k & 1) ? m : -m;
+    }
+    int i0, i1, j0, j1;
+    if (!pixel_range(fb[0], fb[1], g.W, false, i0, i1)) return false;
+    if (!pixel_range(fb[2], fb[3], g.H, true, j0, j1)) return false;
+    rect[0] = i0 / tile; rect[1] = j0 / tile; rect[2] = i1 / tile; rect[3] = j1 / tile;
+    return true;
+}
+
+// Display box of a tile's pixel centres and its frame-time window.
+PRG void tile_display(const Geom &g, int tile, int tx, int ty, double box[4], double tw[2]) {
+    int i0 = tx * tile, j0 = ty * tile;
+    int i1 = i0 + tile - 1, j1 = j0 + tile - 1;
+    if (i1 > g.W - 1) i1 = g.W - 1;
+    if (j1 > g.H - 1) j1 = g.H - 1;
+    double a0 = 2.0 * (i0 + 0.5) / g.W - 1.0, a1 = 2.0 * (i1 + 0.5) / g.W - 1.0;
+    double b0 = 1.0 - 2.0 * (j1 + 0.5) / g.H, b1 = 1.0 - 2.0 * (j0 + 0.5) / g.H;
+    radial_bbox(g, g.alpha, a0, a1, b0, b1, box);
+    for (int k = 0; k < 4; ++k) {
+        double m = kSlackNdc * (1.0 + fabs(box[k]));
+        box[k] += (k & 1) ? m : -m;
+    }
+    if (!g.rolling) { tw[0] = tw[1] = 0.0; return; }
+    double umin = 1e300, umax = -1e300;
+    for (int c = 0; c < 4; ++c) {
+        double x = box[c & 1], y = box[2 + (c >> 1)];
+        double u = 0.5 * (g.roll[0] * (x + 1.0) + g.roll[1] * (y + 1.0));
+        umin = dmin(umin, u);
+        umax = dmax(umax, u);
+    }
+    tw[0] = clamp01(umin - kSlackTime);
+    tw[1] = clamp01(umax + kSlackTime);
+}
+
+// Conservative test of one (triangle, tile) pair.  kWindow triangles: the
+// window is cut to the tile's own time window, the six projected end
+// vertices of that window bound the triangle's image over it, and a
+// separating-axis test (box axes and the edge normals of both end
+// triangles) against the tile's display box rejects the pair.  kClipped
+// triangles use their whole-frame display box.
+PRG bool tile_test(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double win[2],
+                   const double tri_box[4], int tile, int tx, int ty) {
+    double tb[4], tw[2];
+    tile_display(g, tile, tx, ty, tb, tw);
+    if (kind == kClipped)
+        return !(tri_box[1] < tb[0] || tri_box[0] > tb[1] || tri_box[3] < tb[2] || tri_box[2] > tb[3]);
+    double w0 = dmax(win[0], tw[0]), w1 = dmin(win[1], tw[1]);
+    if (w0 > w1) return false;
+    double q[6][2];
+    for (int k = 0; k < 3; ++k)
+        for (int e = 0; e < 2; ++e) {
+            double w = e ? w1 : w0;
+            double P[3];
+            for (int r = 0; r < 3; ++r) P[r] = (1.0 - w) * Ps[k][r] + w * Pe[k][r];
+            q[3 * e + k][0] = g.fx * P[0] / P[2] + g.cx;
+            q[3 * e + k][1] = g.fy * P[1] / P[2] + g.cy;
+        }
+    double big = 1.0;
+    for (int i = 0; i < 6; ++i) big = dmax(big, dmax(fabs(q[i][0]), fabs(q[i][1])));
+    // axes: x, y, and the three edge normals of each end triangle
+    for (int a = 0; a < 8; ++a) {
+        double n0, n1;
+        if (a == 0) { n0 = 1; n1 = 0; }
+        else if (a == 1) { n0 = 0; n1 = 1; }
+        else {
+            int e = (a - 2) / 3, k = (a - 2) % 3;
+            const double *p = q[3 * e + k], *r = q[3 * e + (k + 1) % 3];
+            n0 = -(r[1] - p[1]);
+            n1 = r[0] - p[0];
+        }
+        double pmin = 1e300, pmax = -1e300;
+        for (int i = 0; i < 6; ++i) {
+            double s = n0 * q[i][0] + n1 * q[i][1];
+            pmin = dmin(pmin, s);
+            pmax = dmax(pmax, s);
+        }
+        double bmin = 1e300, bmax = -1e300;
+        for (int c = 0; c < 4; ++c) {
+            double s = n0 * tb[c & 1] + n1 * tb[2 + (c >> 1)];
+            bmin = dmin(bmin, s);
+            bmax = dmax(bmax, s);
+        }
+        double m = 1e-12 * (fabs(n0) + fabs(n1)) * big;
+        if (pmax < bmin - m || pmin > bmax + m) return false;
+    }
+    return true;
+}
+
+}  // namespace prg

@@ -1,0 +1,560 @@
+// pr_kernels.hip -- gfx950 kernels of the perceptual rasterization hot path.
+//
+//   k_bound    one lane per triangle, FP64: camera-space vertices, near plane,
+//              rolling time window, foveated tile rectangle, FP32
+//              intersection record (Sec. 3.2 "Bounding", Sec. 4)
+//   k_bin      one block per 256 triangles: every (triangle, tile) candidate
+//              of the block's rectangles tested conservatively, survivors
+//              compacted with a wave ballot + mbcnt prefix and one atomic
+//              per wave
+//   k_scan_*   exclusive scan of per-tile counts (three phases)
+//   k_scatter  pairs -> per-tile triangle lists
+//   k_raycast  one block per tile: the tile's list staged through LDS in
+//              chunks, every pixel's ray (foveated position, rolling time)
+//              tested against every staged triangle, nearest packed
+//              (depth bits << 32 | id) kept in registers (Sec. 3.2
+//              "Intersection")
+//   k_shade    rolling Lambert shading of resolved ids (Sec. 3.2 "Shading")
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "pr_geom.h"
+#include "pr_kernels.h"
+
+namespace prk {
+
+// ---------------------------------------------------------------------------
+// wave / block helpers (wave64)
+// ---------------------------------------------------------------------------
+__device__ inline unsigned lanes_below(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ inline int wave_incl_scan(int v) {
+    int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int n = __shfl_up(v, o, 64);
+        if (lane >= o) v += n;
+    }
+    return v;
+}
+
+// Exclusive block scan for blockDim.x a multiple of 64 (<= 1024).
+__device__ inline int block_excl_scan(int v, int *lds, int &total) {
+    int lane = __lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int inc = wave_incl_scan(v);
+    if (lane == 63) lds[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        int w = threadIdx.x < nw ? lds[threadIdx.x] : 0;
+        int wi = wave_incl_scan(w);
+        if (threadIdx.x < nw) lds[32 + threadIdx.x] = wi - w;
+        if (threadIdx.x == nw - 1) lds[64] = wi;
+    }
+    __syncthreads();
+    int out = inc - v + lds[32 + wid];
+    total = lds[64];
+    __syncthreads();
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// small fills (used instead of hipMemsetAsync so the frame can be captured)
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// bound
+// ---------------------------------------------------------------------------
+__device__ inline void dcross(const double a[3], const double b[3], double o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ inline double ddot(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Camera-space light direction at the frame's start and end (one thread).
+__global__ void k_view_light(pr_view view, pr_light light, ViewBlock *__restrict__ vb) {
+    prg::Geom g;
+    prg::make_geom(view, g);
+    double l[3] = {light.dir_world[0], light.dir_world[1], light.dir_world[2]};
+    for (int r = 0; r < 3; ++r) {
+        vb->light0[r] = (float)(g.R0[3 * r] * l[0] + g.R0[3 * r + 1] * l[1] + g.R0[3 * r + 2] * l[2]);
+        vb->light1[r] = (float)(g.R1[3 * r] * l[0] + g.R1[3 * r + 1] * l[1] + g.R1[3 * r + 2] * l[2]);
+    }
+}
+
+template <bool ROLL>
+__global__ __launch_bounds__(256) void k_bound(pr_view view, pr_mesh mesh, int tile, float4 *__restrict__ rec,
+                                               TriBound *__restrict__ tb, DevStatus *__restrict__ st) {
+    prg::Geom g;
+    prg::make_geom(view, g);
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= mesh.nt) return;
+    double Ps[3][3], Pe[3][3];
+    int32_t idx[3];
+    bool ok = prg::load_tri(mesh.v0, mesh.v1, mesh.tri, mesh.nv, f, g, Ps, Pe, idx);
+    TriBound b;
+    b.rect[0] = 1; b.rect[1] = 1; b.rect[2] = 0; b.rect[3] = 0;
+    b.kind = prg::kCulled;
+    b.pad = 0;
+    for (int k = 0; k < 4; ++k) b.w[k] = 0.0;
+    if (!ok) {
+        atomicAdd(&st->nonfinite, 1);
+    } else {
+        double win[2];
+        int kind = prg::time_window(g, Ps, Pe, win);
+        if (kind != prg::kCulled) {
+            double box[4];
+            prg::display_box(g, Ps, Pe, win[0], win[1], kind, box);
+            int rect[4];
+            if (prg::tile_rect(g, box, tile, rect)) {
+                for (int k = 0; k < 4; ++k) b.rect[k] = rect[k];
+                b.kind = kind;
+                if (kind == prg::kWindow) { b.w[0] = win[0]; b.w[1] = win[1]; }
+                else for (int k = 0; k < 4; ++k) b.w[k] = box[k];
+            }
+        }
+    }
+    tb[f] = b;
+
+    // Intersection record.  Edge k joins vertices a = k+1, b = k+2.  Its
+    // plane normal is computed from the lower-indexed mesh vertex as
+    // P_lo x (P_hi - P_lo) and negated when a > b, so the two triangles
+    // sharing an edge hold exactly negated coefficients (watertight).
+    float out[32];
+    double A[3][3], B[3][3], C[3][3];
+    for (int k = 0; k < 3; ++k) {
+        int a = (k + 1) % 3, bb = (k + 2) % 3;
+        bool flip = idx[a] > idx[bb];
+        int lo = flip ? bb : a, hi = flip ? a : bb;
+        double s = flip ? -1.0 : 1.0;
+        double P0[3], dP[3], E0[3], dE[3];
+        for (int r = 0; r < 3; ++r) {
+            P0[r] = Ps[lo][r];
+            dP[r] = Pe[lo][r] - Ps[lo][r];
+            E0[r] = Ps[hi][r] - Ps[lo][r];
+            dE[r] = (Pe[hi][r] - Pe[lo][r]) - E0[r];
+        }
+        double t1[3], t2[3];
+        dcross(P0, E0, A[k]);
+        dcross(P0, dE, t1);
+        dcross(dP, E0, t2);
+        dcross(dP, dE, C[k]);
+        for (int r = 0; r < 3; ++r) {
+            A[k][r] *= s;
+            B[k][r] = s * (t1[r] + t2[r]);
+            C[k][r] *= s;
+        }
+    }
+    double dq[3];
+    for (int r = 0; r < 3; ++r) dq[r] = Pe[0][r] - Ps[0][r];
+    // D(t) = P0(t) . c_0(t), P0(t) = Ps0 + t dq
+    double d0 = ddot(Ps[0], A[0]);
+    double d1 = ddot(Ps[0], B[0]) + ddot(dq, A[0]);
+    double d2 = ddot(Ps[0], C[0]) + ddot(dq, B[0]);
+    double d3 = ddot(dq, C[0]);
+    if (!ok) { d0 = d1 = d2 = d3 = 0.0; }
+    if (ROLL) {
+        int n = 0;
+        for (int k = 0; k < 3; ++k) {
+            for (int r = 0; r < 3; ++r) out[n++] = (float)A[k][r];
+            for (int r = 0; r < 3; ++r) out[n++] = (float)B[k][r];
+            for (int r = 0; r < 3; ++r) out[n++] = (float)C[k][r];
+        }
+        out[27] = (float)d0; out[28] = (float)d1; out[29] = (float)d2; out[30] = (float)d3;
+        out[31] = __int_as_float(f);
+        float4 *dst = rec + (int64_t)f * kRecRoll;
+        for (int q = 0; q < kRecRoll; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+    } else {
+        int n = 0;
+        for (int k = 0; k < 3; ++k)
+            for (int r = 0; r < 3; ++r) out[n++] = (float)A[k][r];
+        out[9] = (float)d0;
+        out[10] = __int_as_float(f);
+        out[11] = 0.0f;
+        float4 *dst = rec + (int64_t)f * kRecStatic;
+        for (int q = 0; q < kRecStatic; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// bin
+// ---------------------------------------------------------------------------
+struct Pair {
+    int32_t tile, slot, tri;
+};
+
+__global__ __launch_bounds__(256) void k_bin(pr_view view, pr_mesh mesh, int tile, int tiles_x,
+                                             const TriBound *__restrict__ tb, uint32_t *__restrict__ tcount,
+                                             Pair *__restrict__ pairs, int64_t cap, uint32_t *__restrict__ cursor) {
+    __shared__ double s_P[256][18];
+    __shared__ double s_w[256][4];
+    __shared__ int s_rect[256][4];
+    __shared__ int s_kind[256];
+    __shared__ int s_pref[257];
+    __shared__ int s_tmp[72];
+    prg::Geom g;
+    prg::make_geom(view, g);
+    int f0 = blockIdx.x * 256;
+    int j = threadIdx.x;
+    int f = f0 + j;
+    int cnt = 0;
+    if (f < mesh.nt) {
+        TriBound b = tb[f];
+        if (b.kind != prg::kCulled && b.rect[0] <= b.rect[2] && b.rect[1] <= b.rect[3]) {
+            cnt = (b.rect[2] - b.rect[0] + 1) * (b.rect[3] - b.rect[1] + 1);
+            double Ps[3][3], Pe[3][3];
+            int32_t idx[3];
+            prg::load_tri(mesh.v0, mesh.v1, mesh.tri, mesh.nv, f, g, Ps, Pe, idx);
+            for (int k = 0; k < 3; ++k)
+                for (int r = 0; r < 3; ++r) {
+                    s_P[j][3 * k + r] = Ps[k][r];
+                    s_P[j][9 + 3 * k + r] = Pe[k][r];
+                }
+            for (int k = 0; k < 4; ++k) { s_rect[j][k] = b.rect[k]; s_w[j][k] = b.w[k]; }
+            s_kind[j] = b.kind;
+        }
+    }
+    int total;
+    int ex = block_excl_scan(cnt, s_tmp, total);
+    s_pref[j] = ex;
+    if (j == 255) s_pref[256] = total;
+    __syncthreads();
+    for (int c = j; c < total; c += 256) {
+        // triangle of candidate c: largest q with s_pref[q] <= c
+        int lo = 0, hi = 255;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (s_pref[mid] <= c) lo = mid; else hi = mid - 1;
+        }
+        int q = lo;
+        int local = c - s_pref[q];
+        int rw = s_rect[q][2] - s_rect[q][0] + 1;
+        int tx = s_rect[q][0] + local % rw, ty = s_rect[q][1] + local / rw;
+        double Ps[3][3], Pe[3][3];
+        for (int k = 0; k < 3; ++k)
+            for (int r = 0; r < 3; ++r) {
+                Ps[k][r] = s_P[q][3 * k + r];
+                Pe[k][r] = s_P[q][9 + 3 * k + r];
+            }
+        double w[4] = {s_w[q][0], s_w[q][1], s_w[q][2], s_w[q][3]};
+        bool pass = prg::tile_test(g, Ps, Pe, s_kind[q], w, w, tile, tx, ty);
+        unsigned long long m = __ballot(pass);
+        if (m) {
+            unsigned leader = __ffsll((unsigned long long)m) - 1;
+            unsigned base = 0;
+            if (__lane_id() == leader) base = atomicAdd(cursor, (unsigned)__popcll(m));
+            base = __shfl(base, leader, 64);
+            if (pass) {
+                unsigned i = base + lanes_below(m);
+                int t = ty * tiles_x + tx;
+                unsigned slot = atomicAdd(&tcount[t], 1u);
+                if ((int64_t)i < cap) pairs[i] = Pair{t, (int32_t)slot, f0 + q};
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of n uint32 counts (n < 2^31; totals fit in 32 bits)
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = 256 * kScanItems;
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict__ in, int n, uint32_t *__restrict__ part) {
+    __shared__ int s_tmp[72];
+    int base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) s += (int)in[base + k];
+    int total;
+    block_excl_scan(s, s_tmp, total);
+    if (threadIdx.x == 0) part[blockIdx.x] = (uint32_t)total;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_part(uint32_t *__restrict__ part, int nb) {
+    __shared__ int s_tmp[72];
+    int carry = 0;
+    for (int base = 0; base < nb; base += 1024) {
+        int i = base + threadIdx.x;
+        int v = i < nb ? (int)part[i] : 0;
+        int total;
+        int ex = block_excl_scan(v, s_tmp, total);
+        if (i < nb) part[i] = (uint32_t)(ex + carry);
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__ in, int n,
+                                                    const uint32_t *__restrict__ part, uint32_t *__restrict__ out) {
+    __shared__ int s_tmp[72];
+    int base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < n ? (int)in[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int ex = block_excl_scan(s, s_tmp, total) + (int)part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = (uint32_t)ex;
+        ex += v[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// scatter pairs into tile lists; flags overflow
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scatter(const Pair *__restrict__ pairs, const uint32_t *__restrict__ toff,
+                                                 int32_t *__restrict__ lists, int64_t cap, int view,
+                                                 DevStatus *__restrict__ st) {
+    uint32_t np = st->num_pairs[view];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicAdd(&st->pairs_total, (unsigned long long)np);
+        atomicMax(&st->pairs_required, (unsigned long long)np);
+        if ((int64_t)np > cap) {
+            st->view_overflow[view] = 1;
+            st->overflow = 1;
+        }
+    }
+    if ((int64_t)np > cap) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)np; i += (int64_t)gridDim.x * blockDim.x) {
+        Pair p = pairs[i];
+        lists[toff[p.tile] + p.slot] = p.tri;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ray cast
+// ---------------------------------------------------------------------------
+struct PixelConst {
+    float invW2, invH2;    // 2/W, 2/H
+    float fov0, fov1, invR, alpha;
+    float roll0, roll1;
+    float cx, cy, invfx, invfy;
+    float znear;
+    int W, H;
+    int mode;              // 0: alpha == 1, 1: alpha == 2, 2: general power
+};
+
+// Per-pixel setup: foveated sample -> display point (unfoveate) -> time ->
+// ray direction (rx, ry, 1).
+__device__ __forceinline__ void pixel_setup(const PixelConst &pc, int px, int py, float &t, float &rx, float &ry) {
+    float y0 = (float)(2 * px + 1) * (0.5f * pc.invW2) - 1.0f;
+    float y1 = 1.0f - (float)(2 * py + 1) * (0.5f * pc.invH2);
+    float d0 = y0 - pc.fov0, d1 = y1 - pc.fov1;
+    float s = 1.0f;
+    if (pc.mode != 0) {
+        float rho = sqrtf(d0 * d0 + d1 * d1);
+        s = pc.mode == 1 ? rho * pc.invR : (rho > 0.0f ? powf(rho * pc.invR, pc.alpha - 1.0f) : 0.0f);
+    }
+    float x0 = pc.fov0 + d0 * s, x1 = pc.fov1 + d1 * s;
+    float u = 0.5f * (pc.roll0 * (x0 + 1.0f) + pc.roll1 * (x1 + 1.0f));
+    t = fminf(fmaxf(u, 0.0f), 1.0f);
+    rx = (x0 - pc.cx) * pc.invfx;
+    ry = (x1 - pc.cy) * pc.invfy;
+}
+
+__device__ __forceinline__ float edge_roll(float ax, float ay, float az, float bx, float by, float bz, float cx,
+                                           float cy, float cz, float t, float rx, float ry) {
+    float ex = fmaf(t, fmaf(t, cx, bx), ax);
+    float ey = fmaf(t, fmaf(t, cy, by), ay);
+    float ez = fmaf(t, fmaf(t, cz, bz), az);
+    return fmaf(ry, ey, fmaf(rx, ex, ez));
+}
+
+template <bool ROLL, int TILE>
+struct RayCfg {
+    static constexpr int NT = TILE * TILE >= 256 ? 256 : 64;
+    static constexpr int PPL = TILE * TILE / NT;
+    static constexpr int RECW = ROLL ? kRecRoll : kRecStatic;
+    static constexpr int CHUNK = 64;
+};
+
+template <bool ROLL, int TILE, bool COUNT>
+__global__ __launch_bounds__((RayCfg<ROLL, TILE>::NT)) void k_raycast(
+    PixelConst pc, int tiles_x, const float4 *__restrict__ rec, const uint32_t *__restrict__ toff,
+    const int32_t *__restrict__ lists, int32_t *__restrict__ out_id, float *__restrict__ out_depth, int view,
+    DevStatus *__restrict__ st) {
+    using C = RayCfg<ROLL, TILE>;
+    __shared__ float4 s_rec[C::CHUNK * C::RECW];
+    const int tile = blockIdx.x;
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    float t[C::PPL], rx[C::PPL], ry[C::PPL];
+    unsigned long long best[C::PPL];
+    int nvalid = 0;
+#pragma unroll
+    for (int k = 0; k < C::PPL; ++k) {
+        int q = threadIdx.x + k * C::NT;
+        int px = tx * TILE + q % TILE, py = ty * TILE + q / TILE;
+        pixel_setup(pc, px, py, t[k], rx[k], ry[k]);
+        best[k] = ~0ull;
+        nvalid += (px < pc.W && py < pc.H);
+    }
+    const bool ovf = st->view_overflow[view] != 0;
+    int beg = 0, end = 0;
+    if (!ovf) {
+        beg = (int)toff[tile];
+        end = (int)toff[tile + 1];
+    }
+    unsigned hits = 0;
+    for (int base = beg; base < end; base += C::CHUNK) {
+        int n = min(C::CHUNK, end - base);
+        for (int i = threadIdx.x; i < n * C::RECW; i += C::NT) {
+            int r = i / C::RECW, c = i - r * C::RECW;
+            int f = lists[base + r];
+            s_rec[i] = rec[(int64_t)f * C::RECW + c];
+        }
+        __syncthreads();
+        for (int jj = 0; jj < n; ++jj) {
+            const float4 *R = s_rec + jj * C::RECW;
+            if (ROLL) {
+                float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4], r5 = R[5], r6 = R[6], r7 = R[7];
+#pragma unroll
+                for (int k = 0; k < C::PPL; ++k) {
+                    float e0 = edge_roll(r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, t[k], rx[k], ry[k]);
+                    float e1 = edge_roll(r2.y, r2.z, r2.w, r3.x, r3.y, r3.z, r3.w, r4.x, r4.y, t[k], rx[k], ry[k]);
+                    float e2 = edge_roll(r4.z, r4.w, r5.x, r5.y, r5.z, r5.w, r6.x, r6.y, r6.z, t[k], rx[k], ry[k]);
+                    float lo = fminf(fminf(e0, e1), e2), hi = fmaxf(fmaxf(e0, e1), e2);
+                    if (lo >= 0.0f || hi <= 0.0f) {
+                        float S = e0 + e1 + e2;
+                        float D = fmaf(t[k], fmaf(t[k], fmaf(t[k], r7.z, r7.y), r7.x), r6.w);
+                        float z = D * __builtin_amdgcn_rcpf(S);
+                        if (z >= pc.znear && z <= 3.0e38f) {
+                            unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | __float_as_uint(r7.w);
+                            best[k] = key < best[k] ? key : best[k];
+                            if (COUNT) ++hits;
+                        }
+                    }
+                }
+            } else {
+                float4 r0 = R[0], r1 = R[1], r2 = R[2];
+#pragma unroll
+                for (int k = 0; k < C::PPL; ++k) {
+                    float e0 = fmaf(ry[k], r0.y, fmaf(rx[k], r0.x, r0.z));
+                    float e1 = fmaf(ry[k], r1.x, fmaf(rx[k], r0.w, r1.y));
+                    float e2 = fmaf(ry[k], r1.w, fmaf(rx[k], r1.z, r2.x));
+                    float lo = fminf(fminf(e0, e1), e2), hi = fmaxf(fmaxf(e0, e1), e2);
+                    if (lo >= 0.0f || hi <= 0.0f) {
+                        float S = e0 + e1 + e2;
+                        float z = r2.y * __builtin_amdgcn_rcpf(S);
+                        if (z >= pc.znear && z <= 3.0e38f) {
+                            unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | __float_as_uint(r2.z);
+                            best[k] = key < best[k] ? key : best[k];
+                            if (COUNT) ++hits;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < C::PPL; ++k) {
+        int q = threadIdx.x + k * C::NT;
+        int px = tx * TILE + q % TILE, py = ty * TILE + q / TILE;
+        if (px < pc.W && py < pc.H) {
+            int64_t p = (int64_t)py * pc.W + px;
+            bool miss = best[k] == ~0ull;
+            out_id[p] = miss ? -1 : (int32_t)(uint32_t)(best[k] & 0xffffffffu);
+            out_depth[p] = miss ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(best[k] >> 32));
+        }
+    }
+    if (COUNT) {
+        // tests = list length x valid pixels of the tile; hits summed per wave
+        unsigned long long h = hits;
+        for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
+        int nv = nvalid;
+        for (int o = 32; o > 0; o >>= 1) nv += __shfl_xor(nv, o, 64);
+        if (__lane_id() == 0) {
+            atomicAdd(&st->hits, h);
+            atomicAdd(&st->tests, (unsigned long long)nv * (unsigned long long)(end - beg));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// shade
+// ---------------------------------------------------------------------------
+template <bool ROLL>
+__global__ __launch_bounds__(256) void k_shade(PixelConst pc, const float4 *__restrict__ rec,
+                                               const int32_t *__restrict__ ids, const int32_t *__restrict__ tri,
+                                               const float *__restrict__ albedo, const ViewBlock *__restrict__ vb,
+                                               float ambient, int nt, uint8_t *__restrict__ rgba8,
+                                               float *__restrict__ rgb32) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= (int64_t)pc.W * pc.H) return;
+    int id = ids[p];
+    if (id >= nt) id = -1;   // ids outside the mesh shade as misses
+    float c[3] = {0.0f, 0.0f, 0.0f};
+    if (id >= 0) {
+        int px = (int)(p % pc.W), py = (int)(p / pc.W);
+        float t, rx, ry;
+        pixel_setup(pc, px, py, t, rx, ry);
+        float ck[3][3];
+        if (ROLL) {
+            const float4 *R = rec + (int64_t)id * kRecRoll;
+            float v[27];
+            for (int q = 0; q < 7; ++q) {
+                float4 x = R[q];
+                if (4 * q < 27) v[4 * q] = x.x;
+                if (4 * q + 1 < 27) v[4 * q + 1] = x.y;
+                if (4 * q + 2 < 27) v[4 * q + 2] = x.z;
+                if (4 * q + 3 < 27) v[4 * q + 3] = x.w;
+            }
+            for (int k = 0; k < 3; ++k)
+                for (int r = 0; r < 3; ++r)
+                    ck[k][r] = fmaf(t, fmaf(t, v[9 * k + 6 + r], v[9 * k + 3 + r]), v[9 * k + r]);
+        } else {
+            const float4 *R = rec + (int64_t)id * kRecStatic;
+            float4 a = R[0], b = R[1], d = R[2];
+            float v[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, d.x};
+            for (int k = 0; k < 3; ++k)
+                for (int r = 0; r < 3; ++r) ck[k][r] = v[3 * k + r];
+        }
+        float e[3];
+        for (int k = 0; k < 3; ++k) e[k] = fmaf(ry, ck[k][1], fmaf(rx, ck[k][0], ck[k][2]));
+        float S = e[0] + e[1] + e[2];
+        float N[3];
+        for (int r = 0; r < 3; ++r) N[r] = ck[0][r] + ck[1][r] + ck[2][r];
+        float inn = rsqrtf(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+        float sg = (N[0] * rx + N[1] * ry + N[2]) > 0.0f ? -inn : inn;
+        float L[3];
+        for (int r = 0; r < 3; ++r) L[r] = fmaf(t, vb->light1[r] - vb->light0[r], vb->light0[r]);
+        float inl = rsqrtf(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
+        float ndl = sg * inl * (N[0] * L[0] + N[1] * L[1] + N[2] * L[2]);
+        float s = ambient + (1.0f - ambient) * fmaxf(ndl, 0.0f);
+        float invS = 1.0f / S;
+        for (int k = 0; k < 3; ++k) {
+            int v = tri[3 * (int64_t)id + k];
+            float mu = e[k] * invS;
+            for (int ch = 0; ch < 3; ++ch) c[ch] = fmaf(mu, albedo[3 * (int64_t)v + ch], c[ch]);
+        }
+        for (int ch = 0; ch < 3; ++ch) c[ch] *= s;
+    }
+    if (rgb32) {
+        rgb32[3 * p] = c[0];
+        rgb32[3 * p + 1] = c[1];
+        rgb32[3 * p + 2] = c[2];
+    }
+    if (rgba8) {
+        uchar4 o;
+        o.x = (uint8_t)floorf(fminf(fmaxf(c[0], 0.0f), 1.0f) * 255.0f + 0.5f);
+        o.y = (uint8_t)floorf(fminf(fmaxf(c[1], 0.0f), 1.0f) * 255.0f + 0.5f);
+        o.z = (uint8_t)floorf(fminf(fmaxf(c[2], 0.0f), 1.0f) * 255.0f + 0.5f);
+        o.w = id >= 0 ? 255 : 0;
+        reinterpret_cast<uchar4 *>(rgba8)[p] = o;
+    }
+}
+
+}  // namespace prk

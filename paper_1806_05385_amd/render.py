@@ -1,0 +1,152 @@
+"""Torch front end of libpr: device buffers and streams come from PyTorch,
+every computation runs in the library's kernels (include/pr.h)."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import binding as B
+
+
+@dataclass
+class DeviceMesh:
+    v0: torch.Tensor       # float32 [V, 3] (cuda)
+    v1: torch.Tensor       # float32 [V, 3]
+    tri: torch.Tensor      # int32 [T, 3]
+    albedo: torch.Tensor   # float32 [V, 3]
+
+    @staticmethod
+    def from_numpy(mesh, device='cuda') -> 'DeviceMesh':
+        def t(a, dt):
+            return torch.as_tensor(a, dtype=dt).contiguous().to(device)
+        return DeviceMesh(t(mesh.v0, torch.float32), t(mesh.v1, torch.float32), t(mesh.tri, torch.int32),
+                          t(mesh.albedo, torch.float32))
+
+    def pr(self) -> B.PrMesh:
+        m = B.PrMesh()
+        for name in ('v0', 'v1', 'tri'):
+            x = getattr(self, name)
+            assert x.is_cuda and x.is_contiguous(), name
+        m.v0, m.v1, m.tri = self.v0.data_ptr(), self.v1.data_ptr(), self.tri.data_ptr()
+        m.nv, m.nt = int(self.v0.shape[0]), int(self.tri.shape[0])
+        return m
+
+
+def _stream_handle() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Renderer:
+    """One frame pipeline over a fixed set of meshes and views.
+
+    ``frame()`` enqueues pr_bound, pr_bin, pr_raycast and (optionally)
+    pr_shade on the current torch stream and returns the output tensors.
+    The workspace is a torch uint8 tensor sized by pr_workspace_size; on a
+    tile-list overflow (checked only when ``check=True``) the capacity is
+    raised to what the device reported and the frame is run again."""
+
+    def __init__(self, meshes, views, tile: int = 16, bin_capacity: int = 0, light=None, ambient: float = 0.1,
+                 flags: int = 0, device='cuda'):
+        self.L = B.lib()
+        self.device = torch.device(device)
+        self.meshes = [m if isinstance(m, DeviceMesh) else DeviceMesh.from_numpy(m, device) for m in meshes]
+        self.views = list(views)
+        self.tile = tile
+        self.flags = flags
+        if not bin_capacity:
+            bin_capacity = max(1 << 16, 4 * sum(self.meshes[v.mesh].tri.shape[0] for v in self.views) // len(self.views))
+        self.cap = int(bin_capacity)
+        self.light = B.make_light(light if light is not None else (0.0, 0.0, -1.0), ambient)
+        self._prepare()
+        self.outputs = []
+        for v in self.views:
+            h, w = v.height, v.width
+            self.outputs.append(dict(
+                id=torch.empty((h, w), dtype=torch.int32, device=self.device),
+                depth=torch.empty((h, w), dtype=torch.float32, device=self.device),
+                rgba8=torch.empty((h, w, 4), dtype=torch.uint8, device=self.device),
+                rgb32=torch.empty((h, w, 3), dtype=torch.float32, device=self.device)))
+
+    def _prepare(self):
+        nm = len(self.meshes)
+        self.c_meshes = (B.PrMesh * nm)(*[m.pr() for m in self.meshes])
+        self.c_views = (B.PrView * len(self.views))(*[B.make_view(v) for v in self.views])
+        self.tuning = B.PrTuning(self.tile, self.cap, self.flags, 0)
+        size = ctypes.c_size_t(0)
+        B.check('pr_workspace_size', self.L.pr_workspace_size(self.c_meshes, nm, self.c_views, len(self.views),
+                                                              ctypes.byref(self.tuning), ctypes.byref(size)))
+        self.ws_bytes = size.value
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) & ~255
+
+    def _args(self):
+        return (self.c_meshes, len(self.meshes), self.c_views, len(self.views), ctypes.byref(self.tuning),
+                ctypes.c_void_p(self.ws_ptr), self.ws_bytes)
+
+    def bound(self):
+        B.check('pr_bound', self.L.pr_bound(*self._args(), ctypes.c_void_p(_stream_handle())))
+
+    def bin(self):
+        B.check('pr_bin', self.L.pr_bin(*self._args(), ctypes.c_void_p(_stream_handle())))
+
+    def raycast(self):
+        ids = B.ptr_array([o['id'].data_ptr() for o in self.outputs])
+        deps = B.ptr_array([o['depth'].data_ptr() for o in self.outputs])
+        B.check('pr_raycast', self.L.pr_raycast(*self._args(), ids, deps, ctypes.c_void_p(_stream_handle())))
+
+    def shade(self, rgba8: bool = True, rgb32: bool = True, ids=None):
+        idp = B.ptr_array([(ids[i] if ids is not None else o['id']).data_ptr() for i, o in enumerate(self.outputs)])
+        alb = B.ptr_array([m.albedo.data_ptr() for m in self.meshes])
+        o8 = B.ptr_array([o['rgba8'].data_ptr() for o in self.outputs]) if rgba8 else None
+        o32 = B.ptr_array([o['rgb32'].data_ptr() for o in self.outputs]) if rgb32 else None
+        B.check('pr_shade', self.L.pr_shade(*self._args(), idp, ctypes.byref(self.light), alb, o8, o32,
+                                            ctypes.c_void_p(_stream_handle())))
+
+    def status(self) -> B.PrStatus:
+        st = B.PrStatus()
+        B.check('pr_status_read', self.L.pr_status_read(ctypes.c_void_p(self.ws_ptr), self.ws_bytes,
+                                                        ctypes.byref(st), ctypes.c_void_p(_stream_handle())))
+        return st
+
+    def frame(self, shade: bool = True, check: bool = True):
+        for _ in range(4):
+            self.bound()
+            self.bin()
+            self.raycast()
+            if shade:
+                self.shade()
+            if not check:
+                break
+            st = self.status()
+            if not st.overflow:
+                break
+            self.cap = int(st.pairs_required * 1.25) + 1024
+            self._prepare()
+        return self.outputs
+
+    def tile_lists(self, view: int):
+        """(offsets [tiles+1], lists [pairs]) of one view, copied to the host."""
+        import numpy as np
+        ntiles = ctypes.c_int32(0)
+        npairs = ctypes.c_int64(0)
+        a = self._args()
+        B.check('pr_debug_tile_lists', self.L.pr_debug_tile_lists(*a[:5], *a[5:], view, None, None, 0,
+                                                                  ctypes.byref(ntiles), ctypes.byref(npairs),
+                                                                  ctypes.c_void_p(_stream_handle())))
+        off = np.empty(ntiles.value + 1, np.int32)
+        lst = np.empty(max(1, npairs.value), np.int32)
+        B.check('pr_debug_tile_lists', self.L.pr_debug_tile_lists(
+            *a[:5], *a[5:], view, off.ctypes.data_as(B.c_int32_p), lst.ctypes.data_as(B.c_int32_p),
+            lst.shape[0], ctypes.byref(ntiles), ctypes.byref(npairs), ctypes.c_void_p(_stream_handle())))
+        return off, lst[:npairs.value]
+
+
+def render_scene(scene, tile: int = 16, shade: bool = True, flags: int = 0, device='cuda'):
+    """Render a scenegen.Scene; returns (renderer, outputs)."""
+    r = Renderer(scene.meshes, scene.views, tile=tile, light=scene.light_dir, ambient=scene.ambient, flags=flags,
+                 device=device)
+    out = r.frame(shade=shade)
+    return r, out

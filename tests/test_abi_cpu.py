@@ -1,0 +1,95 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/pr.h declares, and rejects bad arguments before launching anything."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import scenegen
+from paper_1806_05385_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, 'include', 'pr.h')).read()
+    src = re.sub(r'/\*.*?\*/', '', src, flags=re.S)
+    return sorted(set(re.findall(r'\b(pr_\w+)\s*\(', src)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    L = B.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in B.SIGNATURES, f'{n} not bound in binding.SIGNATURES'
+    assert set(B.SIGNATURES) == set(names)
+
+
+def test_status_strings():
+    L = B.lib()
+    for code in (B.PR_OK, B.PR_ERR_INVALID, B.PR_ERR_UNSUPPORTED, B.PR_ERR_WORKSPACE, B.PR_ERR_HIP, -99):
+        assert L.pr_status_string(code)
+
+
+def _frame(tile=16, cap=1000, **view_kw):
+    sc = scenegen.make_tiny(n_tris=10, size=32)
+    m = sc.meshes[0]
+    mesh = B.host_mesh(m.v0, m.v1, m.tri)   # pointers are not dereferenced on these paths
+    meshes = (B.PrMesh * 1)(mesh)
+    v = sc.views[0]
+    for k, val in view_kw.items():
+        setattr(v, k, val)
+    views = (B.PrView * 1)(B.make_view(v))
+    tu = B.PrTuning(tile, cap, 0, 0)
+    return meshes, views, tu, sc
+
+
+def test_workspace_size_and_argument_checks():
+    L = B.lib()
+    meshes, views, tu, sc = _frame()
+    size = ctypes.c_size_t(0)
+    assert L.pr_workspace_size(meshes, 1, views, 1, ctypes.byref(tu), ctypes.byref(size)) == B.PR_OK
+    assert size.value > 10 * 128
+    big = ctypes.c_size_t(0)
+    tu2 = B.PrTuning(16, 100000, 0, 0)
+    assert L.pr_workspace_size(meshes, 1, views, 1, ctypes.byref(tu2), ctypes.byref(big)) == B.PR_OK
+    assert big.value >= size.value + (100000 - 1000) * 16
+    bad = [
+        dict(width=0), dict(height=20000), dict(mesh=3), dict(alpha=0.5), dict(znear=0.0), dict(fx=0.0),
+        dict(fovea=(1.5, 0.0)), dict(alpha=float('nan')),
+    ]
+    for kw in bad:
+        m, v, t, _ = _frame(**kw)
+        assert L.pr_workspace_size(m, 1, v, 1, ctypes.byref(t), ctypes.byref(size)) == B.PR_ERR_INVALID, kw
+    m, v, t, _ = _frame(tile=12)
+    assert L.pr_workspace_size(m, 1, v, 1, ctypes.byref(t), ctypes.byref(size)) == B.PR_ERR_UNSUPPORTED
+    m, v, t, _ = _frame(cap=0)
+    assert L.pr_workspace_size(m, 1, v, 1, ctypes.byref(t), ctypes.byref(size)) == B.PR_ERR_INVALID
+    assert L.pr_workspace_size(None, 1, views, 1, ctypes.byref(tu), ctypes.byref(size)) == B.PR_ERR_INVALID
+    assert L.pr_workspace_size(meshes, 1, views, 0, ctypes.byref(tu), ctypes.byref(size)) == B.PR_ERR_INVALID
+    assert L.pr_workspace_size(meshes, 1, views, 65, ctypes.byref(tu), ctypes.byref(size)) == B.PR_ERR_INVALID
+    nullmesh = (B.PrMesh * 1)(B.PrMesh(None, None, None, 5, 5))
+    assert L.pr_workspace_size(nullmesh, 1, views, 1, ctypes.byref(tu), ctypes.byref(size)) == B.PR_ERR_INVALID
+
+
+def test_calls_reject_bad_workspace_before_launch():
+    """Workspace and pointer checks run on the host before any HIP call, so
+    they answer the same with or without a GPU."""
+    L = B.lib()
+    meshes, views, tu, sc = _frame()
+    size = ctypes.c_size_t(0)
+    L.pr_workspace_size(meshes, 1, views, 1, ctypes.byref(tu), ctypes.byref(size))
+    args = (meshes, 1, views, 1, ctypes.byref(tu))
+    assert L.pr_bound(*args, None, size.value, None) == B.PR_ERR_WORKSPACE
+    assert L.pr_bound(*args, ctypes.c_void_p(256 * 1000 + 8), size.value, None) == B.PR_ERR_WORKSPACE
+    assert L.pr_bound(*args, ctypes.c_void_p(256 * 1000), size.value - 1, None) == B.PR_ERR_WORKSPACE
+    assert L.pr_bin(*args, None, size.value, None) == B.PR_ERR_WORKSPACE
+    assert L.pr_raycast(*args, ctypes.c_void_p(256 * 1000), size.value, None, None, None) == B.PR_ERR_INVALID
+    assert L.pr_shade(*args, ctypes.c_void_p(256 * 1000), size.value, None, None, None, None, None,
+                      None) == B.PR_ERR_INVALID
+    st = B.PrStatus()
+    assert L.pr_status_read(None, 1024, ctypes.byref(st), None) == B.PR_ERR_INVALID

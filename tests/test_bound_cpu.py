@@ -1,0 +1,177 @@
+"""Conservativeness of the bound on the CPU (no GPU needed).
+
+The library's bound code (pr_geom.h) is compiled for the host as well and
+exposed through pr_host_*.  Every (pixel, triangle) hit the FP64 oracle
+finds, occluded or not, must survive binning: the triangle's time window
+contains the pixel's time, its tile rectangle contains the pixel's tile and
+the per-(triangle, tile) test keeps the pair (Sec. 3.2: the bound must cover
+every pixel the triangle affects at any time).  The bound must also be
+useful: it rejects most candidate pairs of a scattered scene.
+"""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import oracle
+import scenegen
+from paper_1806_05385_amd import binding as B
+
+
+def _check_hits(scene, tile, max_pix=None, seed=0):
+    L = B.lib()
+    mesh, view = scene.meshes[0], scene.views[0]
+    W, H = view.width, view.height
+    pix = None
+    if max_pix is not None and W * H > max_pix:
+        pix = np.sort(np.random.default_rng(seed).choice(W * H, size=max_pix, replace=False))
+    orc = oracle.Oracle(mesh, view)
+    hp, ht, he = orc.all_hits(pix)
+    hm = B.host_mesh(mesh.v0, mesh.v1, mesh.tri)
+    pv = B.make_view(view)
+    win = np.empty(2)
+    rect = (ctypes.c_int32 * 4)()
+    cache = {}
+    missed = []
+    for p, f in zip(hp.tolist(), ht.tolist()):
+        if f not in cache:
+            kind = L.pr_host_time_interval(ctypes.byref(hm), f, ctypes.byref(pv),
+                                           win.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+            ok = L.pr_host_tile_rect(ctypes.byref(hm), f, ctypes.byref(pv), tile, rect)
+            cache[f] = (kind, win.copy(), tuple(rect) if ok == 1 else None)
+        kind, w, r = cache[f]
+        i, j = p % W, p // W
+        tx, ty = i // tile, j // tile
+        t = oracle.pixel_setup(view, p)[2]
+        ok = kind in (1, 2) and r is not None and r[0] <= tx <= r[2] and r[1] <= ty <= r[3]
+        ok = ok and (kind == 2 or w[0] <= t <= w[1])
+        ok = ok and L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), tile, tx, ty) == 1
+        if not ok:
+            missed.append((p, f, kind, tuple(w), r, t))
+    return len(hp), missed, cache
+
+
+@pytest.mark.parametrize('tile', [8, 16, 32])
+def test_tiny_static_foveated(tile):
+    sc = scenegen.make_tiny(n_tris=400, size=96)
+    n, missed, _ = _check_hits(sc, tile)
+    assert n > 1000
+    assert not missed, missed[:5]
+
+
+@pytest.mark.parametrize('alpha,roll,fovea', [(2.0, (1.0, 0.0), (0.1, -0.15)), (1.0, (1.0, 0.0), (0.0, 0.0)),
+                                              (3.0, (0.0, 0.9), (-0.2, 0.2)), (1.5, (1.0, 0.5), (0.05, 0.0)),
+                                              (2.0, (0.0, 0.0), (0.19, 0.19))])
+def test_moving_rolling_foveated(alpha, roll, fovea):
+    sc = scenegen.make_moving_soup(seed=21, n_tris=300, width=80, height=72, alpha=alpha, roll=roll,
+                                   yaw_deg_s=3000.0, obj_speed=40.0, fovea=fovea, side=(0.05, 0.6))
+    n, missed, _ = _check_hits(sc, 16)
+    assert n > 1000
+    assert not missed, missed[:5]
+
+
+def _quad_mesh(pts0, pts1=None):
+    v0 = np.asarray(pts0, np.float32)
+    v1 = v0.copy() if pts1 is None else np.asarray(pts1, np.float32)
+    tri = np.array([[0, 1, 2]], np.int32)
+    return scenegen.Mesh(v0, v1, tri, np.ones_like(v0))
+
+
+@pytest.mark.parametrize('case', ['over_fovea', 'screen_filling', 'near_crossing', 'behind_eye_vertex',
+                                  'sweeps_frame', 'offscreen_vertices', 'eye_in_plane'])
+def test_adversarial_triangles(case):
+    """Single triangles that stress the bound: covering the fovea, filling the
+    screen, crossing the near plane, a vertex behind the eye, sweeping the
+    whole display within one frame, vertices far off-screen, the eye in the
+    triangle's plane."""
+    T = {
+        'over_fovea': ([[-0.05, -0.05, 1.0], [0.06, -0.04, 1.0], [0.0, 0.07, 1.1]], None),
+        'screen_filling': ([[-9, -9, 2.0], [9, -9, 2.0], [0, 9, 2.5]], None),
+        'near_crossing': ([[-0.5, -0.4, 0.02], [0.6, -0.3, 1.5], [0.0, 0.5, 0.8]], None),
+        'behind_eye_vertex': ([[-0.5, -0.4, -1.0], [0.6, -0.3, 1.5], [0.1, 0.5, 0.8]], None),
+        'sweeps_frame': ([[-3.0, -0.2, 2.0], [-2.8, -0.1, 2.0], [-2.9, 0.2, 2.0]],
+                         [[3.0, -0.2, 2.0], [3.2, -0.1, 2.0], [3.1, 0.2, 2.0]]),
+        'offscreen_vertices': ([[-40, -1, 3.0], [40, -0.5, 3.0], [0.0, 30, 3.0]], None),
+        'eye_in_plane': ([[-1, 0.0, 1.0], [1, 0.0, 1.0], [0.0, 0.0, 3.0]], None),
+    }[case]
+    mesh = _quad_mesh(*T)
+    for roll in [(1.0, 0.0), (0.0, 0.0)]:
+        for pose in [np.zeros(6, np.float32), np.array([0.0, -0.3, 0.0, 0.01, 0.0, 0.0], np.float32)]:
+            view = scenegen.View(64, 64, np.zeros(6, np.float32), pose, fovea=(0.1, 0.05), alpha=2.0, roll_dir=roll)
+            sc = scenegen.Scene('adv', [mesh], [view])
+            n, missed, _ = _check_hits(sc, 8)
+            assert not missed, (case, roll, missed[:3])
+
+
+def test_bound_is_tight_enough_to_reject_pairs():
+    """Most candidate tiles of a moving, rolling, foveated soup are rejected
+    by the per-tile test or never enter a rectangle."""
+    L = B.lib()
+    sc = scenegen.make_moving_soup(seed=22, n_tris=200, width=128, height=128, alpha=2.0, roll=(1.0, 0.0),
+                                   side=(0.02, 0.2))
+    mesh, view = sc.meshes[0], sc.views[0]
+    hm = B.host_mesh(mesh.v0, mesh.v1, mesh.tri)
+    pv = B.make_view(view)
+    rect = (ctypes.c_int32 * 4)()
+    cand = kept = 0
+    for f in range(mesh.nt):
+        if L.pr_host_tile_rect(ctypes.byref(hm), f, ctypes.byref(pv), 8, rect) != 1:
+            continue
+        for ty in range(rect[1], rect[3] + 1):
+            for tx in range(rect[0], rect[2] + 1):
+                cand += 1
+                kept += L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), 8, tx, ty)
+    tiles = 16 * 16
+    assert cand < 0.1 * tiles * mesh.nt
+    assert kept <= cand
+
+
+def _brute_window(mesh, view, f, n=20001):
+    """Relevant frame times by dense sampling: times t at which the scan line
+    position u = d.(x+1)/2 = t lies within the projected triangle's u-range."""
+    R0 = Rotation.from_rotvec(view.pose0[:3].astype(np.float64)).as_matrix()
+    R1 = Rotation.from_rotvec(view.pose1[:3].astype(np.float64)).as_matrix()
+    Ps = mesh.v0[mesh.tri[f]].astype(np.float64) @ R0.T + view.pose0[3:]
+    Pe = mesh.v1[mesh.tri[f]].astype(np.float64) @ R1.T + view.pose1[3:]
+    t = np.linspace(0, 1, n)[:, None, None]
+    P = (1 - t) * Ps + t * Pe
+    x = view.fx * P[..., 0] / P[..., 2] + view.cx
+    y = view.fy * P[..., 1] / P[..., 2] + view.cy
+    u = 0.5 * (view.roll_dir[0] * (x + 1) + view.roll_dir[1] * (y + 1))
+    tt = t[:, 0, 0]
+    rel = (u.min(1) <= tt) & (u.max(1) >= tt)
+    rel[0] |= u[0].min() <= 0
+    rel[-1] |= u[-1].max() >= 1
+    if not rel.any():
+        return None
+    return tt[rel].min(), tt[rel].max()
+
+
+def test_time_window_matches_dense_sampling():
+    """Pin of the rolling-time window (scan catching up with each moving
+    vertex): it contains every sampled relevant time and is not wider than
+    the sampled set by more than the sampling step plus the padding."""
+    L = B.lib()
+    sc = scenegen.make_moving_soup(seed=23, n_tris=300, width=64, height=64, alpha=2.0, roll=(1.0, 0.0),
+                                   yaw_deg_s=6000.0, obj_speed=80.0, side=(0.05, 0.4), centre_lo=(-2, -1.5, 1.5))
+    mesh, view = sc.meshes[0], sc.views[0]
+    hm = B.host_mesh(mesh.v0, mesh.v1, mesh.tri)
+    pv = B.make_view(view)
+    w = np.empty(2)
+    n_win = n_narrow = 0
+    for f in range(mesh.nt):
+        kind = L.pr_host_time_interval(ctypes.byref(hm), f, ctypes.byref(pv),
+                                       w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        if kind == 2:
+            continue
+        b = _brute_window(mesh, view, f)
+        if b is None:
+            continue
+        assert kind == 1, f
+        n_win += 1
+        assert w[0] <= b[0] + 1e-12 and w[1] >= b[1] - 1e-12, (f, w, b)
+        assert w[0] >= b[0] - 1e-4 - 1e-6 and w[1] <= b[1] + 1e-4 + 1e-6, (f, w, b)
+        n_narrow += (w[1] - w[0]) < 0.5
+    assert n_win > 100 and n_narrow > 0.5 * n_win
