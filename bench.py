@@ -29,7 +29,7 @@ def main():
     ap.add_argument('--steps', type=int, default=50)
     ap.add_argument('--warmup', type=int, default=5)
     ap.add_argument('--tile', type=int, default=16)
-    ap.add_argument('--cpu-pixels', type=int, default=1024)
+    ap.add_argument('--cpu-pixels', type=int, default=49152)
     ap.add_argument('--no-cpu-baseline', action='store_true')
     args = ap.parse_args()
     if args.gpus != 1:

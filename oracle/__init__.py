@@ -65,7 +65,7 @@ def lib():
         L.orc_render.argtypes = [dp] + mesh + [lp, i64, ip, dp, dp, ip, dp]
         L.orc_eval.argtypes = [dp] + mesh + [i64, ctypes.c_int, dp]
         L.orc_eval.restype = ctypes.c_int
-        L.orc_eval_many.argtypes = [dp] + mesh + [lp, ip, i64, ip, dp, dp]
+        L.orc_eval_many.argtypes = [dp] + mesh + [lp, ip, i64, ip, dp, dp, dp]
         L.orc_all_hits.argtypes = [dp] + mesh + [lp, i64, lp, ip, dp, i64]
         L.orc_all_hits.restype = i64
         L.orc_shade.argtypes = [dp] + mesh + [dp, dp, lp, i64, ip, dp]
@@ -129,14 +129,18 @@ class Oracle:
                           _p(out['z2'], ctypes.c_double))
         return out
 
-    def eval_many(self, pix, fid):
+    def eval_many(self, pix, fid, with_cos: bool = False):
+        """Per (pixel, triangle): hit flag, depth, ehat (and |cos| of the
+        ray / normal angle with with_cos)."""
         pix = np.ascontiguousarray(pix, dtype=np.int64)
         fid = np.ascontiguousarray(fid, dtype=np.int32)
         n = len(pix)
-        hit, z, eh = np.empty(n, np.int32), np.empty(n), np.empty(n)
+        hit, z, eh, cs = np.empty(n, np.int32), np.empty(n), np.empty(n), np.empty(n)
         self.L.orc_eval_many(_p(self.vp, ctypes.c_double), *self._m(), _p(pix, ctypes.c_int64),
                              _p(fid, ctypes.c_int32), n, _p(hit, ctypes.c_int32), _p(z, ctypes.c_double),
-                             _p(eh, ctypes.c_double))
+                             _p(eh, ctypes.c_double), _p(cs, ctypes.c_double))
+        if with_cos:
+            return hit.astype(bool), z, eh, cs
         return hit.astype(bool), z, eh
 
     def all_hits(self, pix=None, cap: int = 1 << 24):

@@ -332,9 +332,12 @@ int orc_eval(const double *vp, const double *v0, const double *v1, int nv, const
     return hit;
 }
 
-/* Batched orc_eval over (pix[q], tri_ids[q]) pairs. */
+/* Batched orc_eval over (pix[q], tri_ids[q]) pairs.  cosinc (may be NULL):
+ * |cos| of the angle between the ray and the triangle's normal, which sets
+ * how strongly the hit depth reacts to a perturbation of the ray. */
 void orc_eval_many(const double *vp, const double *v0, const double *v1, int nv, const int32_t *tri, int nt,
-                   const int64_t *pix, const int32_t *fid, int64_t n, int32_t *hit, double *z, double *ehat) {
+                   const int64_t *pix, const int32_t *fid, int64_t n, int32_t *hit, double *z, double *ehat,
+                   double *cosinc) {
     (void)nt;
     orc_cam cam;
     cam_init(&cam, vp, v0, v1, nv);
@@ -346,6 +349,13 @@ void orc_eval_many(const double *vp, const double *v0, const double *v1, int nv,
         hit[q] = ray_tri(P, r, vp[ORC_ZNEAR], &zz, &eh, e);
         z[q] = zz;
         ehat[q] = eh;
+        if (cosinc) {
+            double e1[3], e2[3], N[3];
+            for (int d = 0; d < 3; ++d) { e1[d] = P[1][d] - P[0][d]; e2[d] = P[2][d] - P[0][d]; }
+            cross3(e1, e2, N);
+            double nn = norm3(N) * norm3(r);
+            cosinc[q] = nn > 0 ? fabs(dot3(N, r)) / nn : 0.0;
+        }
     }
     cam_free(&cam);
 }

@@ -9,15 +9,19 @@
 namespace prk {
 
 // Intersection record of one triangle, written by the bound kernel.
-// Rolling views (float4 x 8): for edge k (opposite vertex k) the camera-
+// Rolling views (float4 x 11): for edge k (opposite vertex k) the camera-
 // space edge-plane normal c_k(t) = P_a(t) x P_b(t) = A_k + t B_k + t^2 C_k,
-// laid out A0 B0 C0 A1 B1 C1 A2 B2 C2 (27 floats), then the triple product
-// D(t) = P_0(t) . (P_1(t) x P_2(t)) = d0 + t d1 + t^2 d2 + t^3 d3, then the
-// triangle index (int bits).  The ray r = (rx, ry, 1) at time t gives
-// e_k = r . c_k(t); depth z = D(t) / sum_k e_k.
-// Non-rolling views (float4 x 3): A0 A1 A2 d0 id (t = 0).
-constexpr int kRecRoll = 8;
-constexpr int kRecStatic = 3;
+// laid out A0 B0 C0 A1 B1 C1 A2 B2 C2 (27 floats); the triple product
+// D(t) = P_0(t) . (P_1(t) x P_2(t)) = d0 + t d1 + t^2 d2 + t^3 d3; the face
+// normal N(t) = (P_1 - P_0) x (P_2 - P_0) = N0 + t N1 + t^2 N2; the
+// triangle index (int bits); 3 pad.  The ray r = (rx, ry, 1) at time t
+// passes edge k on the side sign(e_k), e_k = r . c_k(t); the hit depth is
+// z = D(t) / (r . N(t)).  N is stored separately although it equals
+// sum_k c_k: near grazing incidence r . N is much smaller than the edge
+// terms and their sum would lose it to cancellation in FP32.
+// Non-rolling views (float4 x 4, t = 0): A0 A1 A2 d0 N0 id pad pad.
+constexpr int kRecRoll = 11;
+constexpr int kRecStatic = 4;
 
 // Per-triangle bound (64 bytes).
 struct TriBound {

@@ -127,7 +127,6 @@ __global__ __launch_bounds__(256) void k_bound(pr_view view, pr_mesh mesh, int t
     // plane normal is computed from the lower-indexed mesh vertex as
     // P_lo x (P_hi - P_lo) and negated when a > b, so the two triangles
     // sharing an edge hold exactly negated coefficients (watertight).
-    float out[32];
     double A[3][3], B[3][3], C[3][3];
     for (int k = 0; k < 3; ++k) {
         int a = (k + 1) % 3, bb = (k + 2) % 3;
@@ -159,7 +158,24 @@ __global__ __launch_bounds__(256) void k_bound(pr_view view, pr_mesh mesh, int t
     double d1 = ddot(Ps[0], B[0]) + ddot(dq, A[0]);
     double d2 = ddot(Ps[0], C[0]) + ddot(dq, B[0]);
     double d3 = ddot(dq, C[0]);
-    if (!ok) { d0 = d1 = d2 = d3 = 0.0; }
+    // N(t) = E1(t) x E2(t), E_i(t) = (P_i - P_0)(t) linear in t
+    double E1[3], E2[3], dE1[3], dE2[3], N0[3], N1[3], N2[3], u1[3], u2[3];
+    for (int r = 0; r < 3; ++r) {
+        E1[r] = Ps[1][r] - Ps[0][r];
+        E2[r] = Ps[2][r] - Ps[0][r];
+        dE1[r] = (Pe[1][r] - Pe[0][r]) - E1[r];
+        dE2[r] = (Pe[2][r] - Pe[0][r]) - E2[r];
+    }
+    dcross(E1, E2, N0);
+    dcross(E1, dE2, u1);
+    dcross(dE1, E2, u2);
+    dcross(dE1, dE2, N2);
+    for (int r = 0; r < 3; ++r) N1[r] = u1[r] + u2[r];
+    if (!ok) {
+        d0 = d1 = d2 = d3 = 0.0;
+        for (int r = 0; r < 3; ++r) N0[r] = N1[r] = N2[r] = 0.0;
+    }
+    float out[44];
     if (ROLL) {
         int n = 0;
         for (int k = 0; k < 3; ++k) {
@@ -168,7 +184,13 @@ __global__ __launch_bounds__(256) void k_bound(pr_view view, pr_mesh mesh, int t
             for (int r = 0; r < 3; ++r) out[n++] = (float)C[k][r];
         }
         out[27] = (float)d0; out[28] = (float)d1; out[29] = (float)d2; out[30] = (float)d3;
-        out[31] = __int_as_float(f);
+        for (int r = 0; r < 3; ++r) {
+            out[31 + r] = (float)N0[r];
+            out[34 + r] = (float)N1[r];
+            out[37 + r] = (float)N2[r];
+        }
+        out[40] = __int_as_float(f);
+        out[41] = out[42] = out[43] = 0.0f;
         float4 *dst = rec + (int64_t)f * kRecRoll;
         for (int q = 0; q < kRecRoll; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
     } else {
@@ -176,8 +198,9 @@ __global__ __launch_bounds__(256) void k_bound(pr_view view, pr_mesh mesh, int t
         for (int k = 0; k < 3; ++k)
             for (int r = 0; r < 3; ++r) out[n++] = (float)A[k][r];
         out[9] = (float)d0;
-        out[10] = __int_as_float(f);
-        out[11] = 0.0f;
+        for (int r = 0; r < 3; ++r) out[10 + r] = (float)N0[r];
+        out[13] = __int_as_float(f);
+        out[14] = out[15] = 0.0f;
         float4 *dst = rec + (int64_t)f * kRecStatic;
         for (int q = 0; q < kRecStatic; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
     }
@@ -420,25 +443,39 @@ __global__ __launch_bounds__((RayCfg<ROLL, TILE>::NT)) void k_raycast(
             const float4 *R = s_rec + jj * C::RECW;
             if (ROLL) {
                 float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4], r5 = R[5], r6 = R[6], r7 = R[7];
+                bool pass[C::PPL];
+                bool any = false;
 #pragma unroll
                 for (int k = 0; k < C::PPL; ++k) {
                     float e0 = edge_roll(r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, t[k], rx[k], ry[k]);
                     float e1 = edge_roll(r2.y, r2.z, r2.w, r3.x, r3.y, r3.z, r3.w, r4.x, r4.y, t[k], rx[k], ry[k]);
                     float e2 = edge_roll(r4.z, r4.w, r5.x, r5.y, r5.z, r5.w, r6.x, r6.y, r6.z, t[k], rx[k], ry[k]);
                     float lo = fminf(fminf(e0, e1), e2), hi = fmaxf(fmaxf(e0, e1), e2);
-                    if (lo >= 0.0f || hi <= 0.0f) {
-                        float S = e0 + e1 + e2;
-                        float D = fmaf(t[k], fmaf(t[k], fmaf(t[k], r7.z, r7.y), r7.x), r6.w);
+                    pass[k] = lo >= 0.0f || hi <= 0.0f;
+                    any = any || pass[k];
+                }
+                if (any) {
+                    float4 r8 = R[8], r9 = R[9], r10 = R[10];
+#pragma unroll
+                    for (int k = 0; k < C::PPL; ++k) {
+                        if (!pass[k]) continue;
+                        float tk = t[k];
+                        // N(t): N0 = (r7.w, r8.x, r8.y), N1 = (r8.z, r8.w, r9.x), N2 = (r9.y, r9.z, r9.w)
+                        float nx = fmaf(tk, fmaf(tk, r9.y, r8.z), r7.w);
+                        float ny = fmaf(tk, fmaf(tk, r9.z, r8.w), r8.x);
+                        float nz = fmaf(tk, fmaf(tk, r9.w, r9.x), r8.y);
+                        float S = fmaf(ry[k], ny, fmaf(rx[k], nx, nz));
+                        float D = fmaf(tk, fmaf(tk, fmaf(tk, r7.z, r7.y), r7.x), r6.w);
                         float z = D * __builtin_amdgcn_rcpf(S);
                         if (z >= pc.znear && z <= 3.0e38f) {
-                            unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | __float_as_uint(r7.w);
+                            unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | __float_as_uint(r10.x);
                             best[k] = key < best[k] ? key : best[k];
                             if (COUNT) ++hits;
                         }
                     }
                 }
             } else {
-                float4 r0 = R[0], r1 = R[1], r2 = R[2];
+                float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3];
 #pragma unroll
                 for (int k = 0; k < C::PPL; ++k) {
                     float e0 = fmaf(ry[k], r0.y, fmaf(rx[k], r0.x, r0.z));
@@ -446,10 +483,11 @@ __global__ __launch_bounds__((RayCfg<ROLL, TILE>::NT)) void k_raycast(
                     float e2 = fmaf(ry[k], r1.w, fmaf(rx[k], r1.z, r2.x));
                     float lo = fminf(fminf(e0, e1), e2), hi = fmaxf(fmaxf(e0, e1), e2);
                     if (lo >= 0.0f || hi <= 0.0f) {
-                        float S = e0 + e1 + e2;
+                        // N0 = (r2.z, r2.w, r3.x), d0 = r2.y, id = r3.y
+                        float S = fmaf(ry[k], r2.w, fmaf(rx[k], r2.z, r3.x));
                         float z = r2.y * __builtin_amdgcn_rcpf(S);
                         if (z >= pc.znear && z <= 3.0e38f) {
-                            unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | __float_as_uint(r2.z);
+                            unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | __float_as_uint(r3.y);
                             best[k] = key < best[k] ? key : best[k];
                             if (COUNT) ++hits;
                         }
@@ -501,32 +539,29 @@ __global__ __launch_bounds__(256) void k_shade(PixelConst pc, const float4 *__re
         int px = (int)(p % pc.W), py = (int)(p / pc.W);
         float t, rx, ry;
         pixel_setup(pc, px, py, t, rx, ry);
-        float ck[3][3];
+        float ck[3][3], N[3];
         if (ROLL) {
             const float4 *R = rec + (int64_t)id * kRecRoll;
-            float v[27];
-            for (int q = 0; q < 7; ++q) {
+            float v[40];
+            for (int q = 0; q < 10; ++q) {
                 float4 x = R[q];
-                if (4 * q < 27) v[4 * q] = x.x;
-                if (4 * q + 1 < 27) v[4 * q + 1] = x.y;
-                if (4 * q + 2 < 27) v[4 * q + 2] = x.z;
-                if (4 * q + 3 < 27) v[4 * q + 3] = x.w;
+                v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
             }
             for (int k = 0; k < 3; ++k)
                 for (int r = 0; r < 3; ++r)
                     ck[k][r] = fmaf(t, fmaf(t, v[9 * k + 6 + r], v[9 * k + 3 + r]), v[9 * k + r]);
+            for (int r = 0; r < 3; ++r) N[r] = fmaf(t, fmaf(t, v[37 + r], v[34 + r]), v[31 + r]);
         } else {
             const float4 *R = rec + (int64_t)id * kRecStatic;
-            float4 a = R[0], b = R[1], d = R[2];
-            float v[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, d.x};
+            float4 a = R[0], b = R[1], d = R[2], e4 = R[3];
+            float v[13] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, d.x, d.y, d.z, d.w, e4.x};
             for (int k = 0; k < 3; ++k)
                 for (int r = 0; r < 3; ++r) ck[k][r] = v[3 * k + r];
+            for (int r = 0; r < 3; ++r) N[r] = v[10 + r];
         }
         float e[3];
         for (int k = 0; k < 3; ++k) e[k] = fmaf(ry, ck[k][1], fmaf(rx, ck[k][0], ck[k][2]));
         float S = e[0] + e[1] + e[2];
-        float N[3];
-        for (int r = 0; r < 3; ++r) N[r] = ck[0][r] + ck[1][r] + ck[2][r];
         float inn = rsqrtf(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
         float sg = (N[0] * rx + N[1] * ry + N[2]) > 0.0f ? -inn : inn;
         float L[3];

@@ -8,7 +8,10 @@ correct within the stated precision:
   * depth tie: the GPU chose the oracle's runner-up and the two depths agree
     to 1e-5 relative;
   * near plane: the winner's depth is within 1e-5 relative of znear.
-Depth must match to 1e-5 relative where the ids agree.
+Depth must match to 1e-5 relative where the ids agree, except at listed
+grazing pixels: when the ray meets the triangle's plane at an angle whose
+cosine is c, rounding the ray direction to FP32 alone (relative 2^-24)
+moves the depth by about 2^-24 / c, so there the bound is 16 * 2^-24 / c.
 """
 from __future__ import annotations
 
@@ -16,6 +19,8 @@ import numpy as np
 
 EHAT_TOL = 1e-6
 DEPTH_TOL = 1e-5
+EPS32 = 2.0 ** -24
+GRAZE_K = 16.0
 
 
 def compare(orc, o, gid, gdepth, pix, znear):
@@ -48,8 +53,20 @@ def compare(orc, o, gid, gdepth, pix, znear):
                 rep['near_plane'] += 1
                 continue
             rep['bad'].append((int(pix[q]), int(oid[q]), int(g[n])))
-    same = (oid == gid) & (oid >= 0)
+    same = np.nonzero((oid == gid) & (oid >= 0))[0]
     rel = np.abs(gdepth[same] - o['z'][same]) / o['z'][same]
+    rep['grazing'] = 0
+    rep['depth_bad'] = []
+    over = rel > DEPTH_TOL
+    if over.any():
+        q = same[over]
+        _, _, _, cs = orc.eval_many(pix[q], oid[q], with_cos=True)
+        for n, qq in enumerate(q):
+            if rel[over][n] <= GRAZE_K * EPS32 / max(cs[n], 1e-30):
+                rep['grazing'] += 1
+            else:
+                rep['depth_bad'].append((int(pix[qq]), int(oid[qq]), float(rel[over][n]), float(cs[n])))
+        rel = rel[~over]
     rep['depth_max_rel'] = float(rel.max()) if rel.size else 0.0
     miss = (oid == gid) & (oid < 0)
     rep['miss_depth_inf'] = bool(np.all(np.isinf(gdepth[miss]))) if miss.any() else True
@@ -59,6 +76,7 @@ def compare(orc, o, gid, gdepth, pix, znear):
 
 def assert_parity(rep, max_exempt_frac=0.01):
     assert not rep['bad'], f"{len(rep['bad'])} unexplained id mismatches, e.g. {rep['bad'][:5]}; {rep}"
+    assert not rep['depth_bad'], f"depth off at {len(rep['depth_bad'])} pixels, e.g. {rep['depth_bad'][:5]}"
     assert rep['depth_max_rel'] <= DEPTH_TOL, rep
     assert rep['miss_depth_inf'], rep
     assert rep['mismatch'] <= max_exempt_frac * rep['n'] + 5, rep

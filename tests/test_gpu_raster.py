@@ -34,7 +34,7 @@ def _full_parity(scene, tile=16, view=0):
     pix = np.arange(v.width * v.height)
     rep = compare(orc, o, out[view]['id'].ravel(), out[view]['depth'].ravel(), pix, v.znear)
     print(f"\n{scene.name} tile {tile}: {rep['hits']} hits, {rep['mismatch']} exempt mismatches "
-          f"(edge {rep['near_edge']}, tie {rep['depth_tie']}, near {rep['near_plane']}), "
+          f"(edge {rep['near_edge']}, tie {rep['depth_tie']}, near {rep['near_plane']}), grazing {rep['grazing']}, "
           f"depth max rel {rep['depth_max_rel']:.2e}", flush=True)
     assert_parity(rep)
     return r, out, orc, o
