@@ -64,8 +64,13 @@
  *   before anything is enqueued; on an error nothing is launched.  Conditions
  *   found on the device (tile-list capacity overflow, non-finite vertices)
  *   are recorded in a status block inside the workspace and read with
- *   pr_status_read.  After an overflow, pr_raycast writes misses for the
- *   affected view; rerun with bin_capacity >= pr_status.pairs_required.
+ *   pr_status_read.  After an overflow, pr_raycast writes misses for every
+ *   view; rerun with bin_capacity >= pr_status.pairs_required.
+ *
+ * All views of a call are processed together: each pass is one launch over
+ * the views laid end to end.  pr_bound writes the workspace's view table;
+ * the later calls of the frame must pass the same meshes, views and
+ * tuning.
  */
 #ifndef PR_H
 #define PR_H
@@ -132,10 +137,10 @@ typedef struct pr_tuning {
 
 /* Device-side conditions of the last frame (all views). */
 typedef struct pr_status {
-    int32_t overflow;          /* 1 if some view's pairs exceeded bin_capacity */
-    int32_t nonfinite;         /* triangles with a non-finite vertex (culled) */
-    int64_t pairs_required;    /* largest pair count of any view */
-    int64_t pairs_total;       /* pairs over all views */
+    int32_t overflow;          /* 1 if the frame's pairs exceeded bin_capacity */
+    int32_t nonfinite;         /* triangles with a bad index or non-finite vertex (culled) */
+    int64_t pairs_required;    /* pairs the frame needed (all views) */
+    int64_t pairs_total;       /* same, as counted */
     int64_t tests;             /* ray-triangle tests (PR_FLAG_COUNT) */
     int64_t hits;              /* tests that passed (PR_FLAG_COUNT) */
 } pr_status;

@@ -18,10 +18,14 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
-struct ViewLayout {
-    int tiles_x, tiles_y, ntiles, nparts, recw;
-    int64_t cap;
-    size_t rec, tb, vb, tcount, toff, part, pairs, lists;
+// Workspace: [status | view table | tile infos | records | triangle bounds |
+// tile counts | tile offsets | scan partials | pairs | lists], 256-aligned.
+struct Layout {
+    int nv;
+    ViewDev vd[PR_MAX_VIEWS];
+    int total_tiles, total_tri_blocks, total_pix_blocks, nparts;
+    int64_t cap, total_rec4, total_tris;
+    size_t table, tinfo, rec, tb, tcount, toff, part, pairs, lists, bytes;
 };
 
 bool finite_all(const float *p, int n) {
@@ -56,42 +60,6 @@ int check_args(const pr_mesh *meshes, int nm, const pr_view *views, int nv, cons
 
 bool rolling(const pr_view &v) { return v.roll_dir[0] != 0.0f || v.roll_dir[1] != 0.0f; }
 
-// Workspace: [status | view 0 | view 1 | ...], every buffer 256-aligned.
-int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tu, ViewLayout *L,
-           size_t *total) {
-    int rc = check_args(meshes, nm, views, nv, tu);
-    if (rc) return rc;
-    size_t off = up(sizeof(DevStatus));
-    for (int v = 0; v < nv; ++v) {
-        const pr_view &V = views[v];
-        const pr_mesh &M = meshes[V.mesh];
-        ViewLayout &l = L[v];
-        l.tiles_x = (V.width + tu->tile - 1) / tu->tile;
-        l.tiles_y = (V.height + tu->tile - 1) / tu->tile;
-        l.ntiles = l.tiles_x * l.tiles_y;
-        l.nparts = (l.ntiles + 1 + kScanBlock - 1) / kScanBlock;
-        l.recw = rolling(V) ? kRecRoll : kRecStatic;
-        l.cap = tu->bin_capacity;
-        size_t nt = (size_t)M.nt;
-        l.rec = off; off = up(off + nt * l.recw * sizeof(float4));
-        l.tb = off; off = up(off + nt * sizeof(TriBound));
-        l.vb = off; off = up(off + sizeof(ViewBlock));
-        l.tcount = off; off = up(off + ((size_t)l.ntiles + 1) * 4);
-        l.toff = off; off = up(off + ((size_t)l.ntiles + 1) * 4);
-        l.part = off; off = up(off + (size_t)l.nparts * 4);
-        l.pairs = off; off = up(off + (size_t)l.cap * sizeof(Pair));
-        l.lists = off; off = up(off + (size_t)l.cap * 4);
-    }
-    *total = off;
-    return PR_OK;
-}
-
-int check_ws(void *ws, size_t ws_bytes, size_t need) {
-    if (!ws || ((uintptr_t)ws & (kAlign - 1))) return PR_ERR_WORKSPACE;
-    if (ws_bytes < need) return PR_ERR_WORKSPACE;
-    return PR_OK;
-}
-
 PixelConst pixel_const(const pr_view &v) {
     PixelConst pc;
     pc.invW2 = (float)(2.0 / v.width);
@@ -114,6 +82,64 @@ PixelConst pixel_const(const pr_view &v) {
     return pc;
 }
 
+int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tu, Layout &L) {
+    int rc = check_args(meshes, nm, views, nv, tu);
+    if (rc) return rc;
+    L.nv = nv;
+    int64_t tiles = 0, tri_blocks = 0, pix_blocks = 0, rec4 = 0, tris = 0;
+    for (int v = 0; v < nv; ++v) {
+        const pr_view &V = views[v];
+        const pr_mesh &M = meshes[V.mesh];
+        ViewDev &d = L.vd[v];
+        memset(&d, 0, sizeof(d));
+        d.view = V;
+        d.mesh = M;
+        d.pc = pixel_const(V);
+        d.tile = tu->tile;
+        d.tiles_x = (V.width + tu->tile - 1) / tu->tile;
+        d.tiles_y = (V.height + tu->tile - 1) / tu->tile;
+        d.ntiles = d.tiles_x * d.tiles_y;
+        d.tile_base = (int32_t)tiles;
+        d.tri_block0 = (int32_t)tri_blocks;
+        d.pix_block0 = (int32_t)pix_blocks;
+        d.rolling = rolling(V) ? 1 : 0;
+        d.rec_w = d.rolling ? kRecRoll : kRecStatic;
+        d.rec_off = rec4;
+        d.tri_off = tris;
+        tiles += d.ntiles;
+        tri_blocks += (M.nt + 255) / 256;
+        pix_blocks += ((int64_t)V.width * V.height + 255) / 256;
+        rec4 += (int64_t)M.nt * d.rec_w;
+        tris += M.nt;
+    }
+    if (tiles + 1 > INT32_MAX / 2 || tri_blocks > INT32_MAX / 2 || pix_blocks > INT32_MAX / 2) return PR_ERR_INVALID;
+    L.total_tiles = (int)tiles;
+    L.total_tri_blocks = (int)tri_blocks;
+    L.total_pix_blocks = (int)pix_blocks;
+    L.nparts = (int)((tiles + 1 + kScanBlock - 1) / kScanBlock);
+    L.cap = tu->bin_capacity;
+    L.total_rec4 = rec4;
+    L.total_tris = tris;
+    size_t off = up(sizeof(DevStatus));
+    L.table = off; off = up(off + sizeof(ViewTable));
+    L.tinfo = off; off = up(off + (size_t)tiles * sizeof(TileInfo));
+    L.rec = off; off = up(off + (size_t)rec4 * sizeof(float4));
+    L.tb = off; off = up(off + (size_t)tris * sizeof(TriBound));
+    L.tcount = off; off = up(off + ((size_t)tiles + 1) * 4);
+    L.toff = off; off = up(off + ((size_t)tiles + 1) * 4);
+    L.part = off; off = up(off + (size_t)L.nparts * 4);
+    L.pairs = off; off = up(off + (size_t)L.cap * sizeof(Pair));
+    L.lists = off; off = up(off + (size_t)L.cap * 4);
+    L.bytes = off;
+    return PR_OK;
+}
+
+int check_ws(const void *ws, size_t ws_bytes, size_t need) {
+    if (!ws || ((uintptr_t)ws & (kAlign - 1))) return PR_ERR_WORKSPACE;
+    if (ws_bytes < need) return PR_ERR_WORKSPACE;
+    return PR_OK;
+}
+
 template <typename T>
 T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
 
@@ -126,35 +152,27 @@ void fill_u32(void *p, uint32_t v, int64_t n, hipStream_t s) {
 }
 
 #define PR_PREP()                                                         \
-    ViewLayout L[PR_MAX_VIEWS];                                           \
-    size_t need = 0;                                                      \
+    static thread_local Layout L;                                        \
     {                                                                     \
-        int rc_ = layout(meshes, nm, views, nv, tuning, L, &need);        \
+        int rc_ = layout(meshes, nm, views, nv, tuning, L);               \
         if (rc_) return rc_;                                              \
-        rc_ = check_ws(ws, ws_bytes, need);                               \
+        rc_ = check_ws(ws, ws_bytes, L.bytes);                            \
         if (rc_) return rc_;                                              \
     }                                                                     \
     hipStream_t s = (hipStream_t)stream;                                  \
-    DevStatus *st = at<DevStatus>(ws, 0);
+    DevStatus *st = at<DevStatus>(ws, 0);                                 \
+    ViewTable *T = at<ViewTable>(ws, L.table);
 
-template <bool ROLL, int TILE>
-void launch_raycast(int flags, const PixelConst &pc, const ViewLayout &l, void *ws, int32_t *id, float *depth, int v,
-                    DevStatus *st, hipStream_t s) {
-    using C = RayCfg<ROLL, TILE>;
+template <int TILE>
+void launch_raycast(int flags, const Layout &L, void *ws, const RayOut &out, DevStatus *st, ViewTable *T,
+                    hipStream_t s) {
+    using C = RayCfg<TILE>;
     if (flags & PR_FLAG_COUNT)
-        hipLaunchKernelGGL((k_raycast<ROLL, TILE, true>), dim3(l.ntiles), dim3(C::NT), 0, s, pc, l.tiles_x,
-                           at<float4>(ws, l.rec), at<uint32_t>(ws, l.toff), at<int32_t>(ws, l.lists), id, depth, v, st);
+        hipLaunchKernelGGL((k_raycast<TILE, true>), dim3(L.total_tiles), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
+                           at<uint32_t>(ws, L.toff), at<int32_t>(ws, L.lists), out, st);
     else
-        hipLaunchKernelGGL((k_raycast<ROLL, TILE, false>), dim3(l.ntiles), dim3(C::NT), 0, s, pc, l.tiles_x,
-                           at<float4>(ws, l.rec), at<uint32_t>(ws, l.toff), at<int32_t>(ws, l.lists), id, depth, v, st);
-}
-
-template <bool ROLL>
-void dispatch_raycast(int tile, int flags, const PixelConst &pc, const ViewLayout &l, void *ws, int32_t *id,
-                      float *depth, int v, DevStatus *st, hipStream_t s) {
-    if (tile == 8) launch_raycast<ROLL, 8>(flags, pc, l, ws, id, depth, v, st, s);
-    else if (tile == 16) launch_raycast<ROLL, 16>(flags, pc, l, ws, id, depth, v, st, s);
-    else launch_raycast<ROLL, 32>(flags, pc, l, ws, id, depth, v, st, s);
+        hipLaunchKernelGGL((k_raycast<TILE, false>), dim3(L.total_tiles), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
+                           at<uint32_t>(ws, L.toff), at<int32_t>(ws, L.lists), out, st);
 }
 
 }  // namespace
@@ -164,52 +182,53 @@ extern "C" {
 int pr_workspace_size(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
                       size_t *bytes) {
     if (!bytes) return PR_ERR_INVALID;
-    ViewLayout L[PR_MAX_VIEWS];
-    return layout(meshes, nm, views, nv, tuning, L, bytes);
+    static thread_local Layout L;
+    int rc = layout(meshes, nm, views, nv, tuning, L);
+    if (rc) return rc;
+    *bytes = L.bytes;
+    return PR_OK;
 }
 
 int pr_bound(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning, void *ws,
              size_t ws_bytes, void *stream) {
     PR_PREP();
     fill_u32(st, 0u, (int64_t)(sizeof(DevStatus) / 4), s);
-    for (int v = 0; v < nv; ++v) {
-        const pr_view &V = views[v];
-        const pr_mesh &M = meshes[V.mesh];
-        if (M.nt == 0) continue;
-        dim3 grid((M.nt + 255) / 256);
-        if (rolling(V))
-            hipLaunchKernelGGL(k_bound<true>, grid, dim3(256), 0, s, V, M, tuning->tile, at<float4>(ws, L[v].rec),
-                               at<TriBound>(ws, L[v].tb), st);
-        else
-            hipLaunchKernelGGL(k_bound<false>, grid, dim3(256), 0, s, V, M, tuning->tile, at<float4>(ws, L[v].rec),
-                               at<TriBound>(ws, L[v].tb), st);
+    for (int first = 0; first < nv; first += kViewsPerWrite) {
+        ViewPack p;
+        memset(&p, 0, sizeof(p));
+        p.first = first;
+        p.count = std::min(kViewsPerWrite, nv - first);
+        p.nv = nv;
+        p.total_tiles = L.total_tiles;
+        p.total_tri_blocks = L.total_tri_blocks;
+        p.total_pix_blocks = L.total_pix_blocks;
+        for (int i = 0; i < p.count; ++i) p.v[i] = L.vd[first + i];
+        hipLaunchKernelGGL(k_write_views, dim3(1), dim3(64), 0, s, p, T);
     }
+    if (L.total_tri_blocks > 0)
+        hipLaunchKernelGGL(k_bound, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec),
+                           at<TriBound>(ws, L.tb), st);
     return launched();
 }
 
 int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning, void *ws,
            size_t ws_bytes, void *stream) {
     PR_PREP();
-    for (int v = 0; v < nv; ++v) {
-        const pr_view &V = views[v];
-        const pr_mesh &M = meshes[V.mesh];
-        const ViewLayout &l = L[v];
-        fill_u32(at<void>(ws, l.tcount), 0u, (int64_t)l.ntiles + 1, s);
-        fill_u32(&st->num_pairs[v], 0u, 1, s);
-        if (M.nt > 0)
-            hipLaunchKernelGGL(k_bin, dim3((M.nt + 255) / 256), dim3(256), 0, s, V, M, tuning->tile, l.tiles_x,
-                               at<TriBound>(ws, l.tb), at<uint32_t>(ws, l.tcount), at<Pair>(ws, l.pairs), l.cap,
-                               &st->num_pairs[v]);
-        int n = l.ntiles + 1;
-        hipLaunchKernelGGL(k_scan_reduce, dim3(l.nparts), dim3(256), 0, s, at<uint32_t>(ws, l.tcount), n,
-                           at<uint32_t>(ws, l.part));
-        hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(1024), 0, s, at<uint32_t>(ws, l.part), l.nparts);
-        hipLaunchKernelGGL(k_scan_apply, dim3(l.nparts), dim3(256), 0, s, at<uint32_t>(ws, l.tcount), n,
-                           at<uint32_t>(ws, l.part), at<uint32_t>(ws, l.toff));
-        int sb = (int)std::min<int64_t>(std::max<int64_t>((l.cap + 255) / 256, 1), 2048);
-        hipLaunchKernelGGL(k_scatter, dim3(sb), dim3(256), 0, s, at<Pair>(ws, l.pairs), at<uint32_t>(ws, l.toff),
-                           at<int32_t>(ws, l.lists), l.cap, v, st);
-    }
+    fill_u32(at<void>(ws, L.tcount), 0u, (int64_t)L.total_tiles + 1, s);
+    fill_u32(&st->num_pairs, 0u, 1, s);
+    hipLaunchKernelGGL(k_tiles, dim3((L.total_tiles + 255) / 256), dim3(256), 0, s, T, at<TileInfo>(ws, L.tinfo));
+    if (L.total_tri_blocks > 0)
+        hipLaunchKernelGGL(k_bin, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<TriBound>(ws, L.tb),
+                           at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<Pair>(ws, L.pairs), L.cap, st);
+    int n = L.total_tiles + 1;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(L.nparts), dim3(256), 0, s, at<uint32_t>(ws, L.tcount), n,
+                       at<uint32_t>(ws, L.part));
+    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(1024), 0, s, at<uint32_t>(ws, L.part), L.nparts);
+    hipLaunchKernelGGL(k_scan_apply, dim3(L.nparts), dim3(256), 0, s, at<uint32_t>(ws, L.tcount), n,
+                       at<uint32_t>(ws, L.part), at<uint32_t>(ws, L.toff));
+    int sb = (int)std::min<int64_t>(std::max<int64_t>((L.cap + 255) / 256, 1), 2048);
+    hipLaunchKernelGGL(k_scatter, dim3(sb), dim3(256), 0, s, at<Pair>(ws, L.pairs), at<uint32_t>(ws, L.toff),
+                       at<int32_t>(ws, L.lists), L.cap, st);
     return launched();
 }
 
@@ -219,13 +238,15 @@ int pr_raycast(const pr_mesh *meshes, int nm, const pr_view *views, int nv, cons
     for (int v = 0; v < nv && v < PR_MAX_VIEWS; ++v)
         if (!tri_id[v] || !depth[v]) return PR_ERR_INVALID;
     PR_PREP();
+    RayOut out;
+    memset(&out, 0, sizeof(out));
     for (int v = 0; v < nv; ++v) {
-        PixelConst pc = pixel_const(views[v]);
-        if (rolling(views[v]))
-            dispatch_raycast<true>(tuning->tile, tuning->flags, pc, L[v], ws, tri_id[v], depth[v], v, st, s);
-        else
-            dispatch_raycast<false>(tuning->tile, tuning->flags, pc, L[v], ws, tri_id[v], depth[v], v, st, s);
+        out.id[v] = tri_id[v];
+        out.depth[v] = depth[v];
     }
+    if (tuning->tile == 8) launch_raycast<8>(tuning->flags, L, ws, out, st, T, s);
+    else if (tuning->tile == 16) launch_raycast<16>(tuning->flags, L, ws, out, st, T, s);
+    else launch_raycast<32>(tuning->flags, L, ws, out, st, T, s);
     return launched();
 }
 
@@ -238,26 +259,26 @@ int pr_shade(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const 
         return PR_ERR_INVALID;
     for (int v = 0; v < nv && v < PR_MAX_VIEWS; ++v)
         if (!tri_id[v]) return PR_ERR_INVALID;
-    for (int m = 0; m < nm; ++m)
-        if (meshes && meshes[m].nt > 0 && !albedo[m]) return PR_ERR_INVALID;
+    if (meshes)
+        for (int v = 0; v < nv && v < PR_MAX_VIEWS && views; ++v) {
+            int m = views[v].mesh;
+            if (m >= 0 && m < nm && meshes[m].nt > 0 && !albedo[m]) return PR_ERR_INVALID;
+        }
     PR_PREP();
+    ShadeIO io;
+    memset(&io, 0, sizeof(io));
+    bool any = false;
     for (int v = 0; v < nv; ++v) {
-        const pr_view &V = views[v];
-        const pr_mesh &M = meshes[V.mesh];
-        PixelConst pc = pixel_const(V);
-        int64_t np = (int64_t)V.width * V.height;
-        uint8_t *o8 = rgba8 ? rgba8[v] : nullptr;
-        float *o32 = rgb32 ? rgb32[v] : nullptr;
-        if (!o8 && !o32) continue;
-        dim3 grid((unsigned)((np + 255) / 256));
-        hipLaunchKernelGGL(k_view_light, dim3(1), dim3(1), 0, s, V, *light, at<ViewBlock>(ws, L[v].vb));
-        if (rolling(V))
-            hipLaunchKernelGGL(k_shade<true>, grid, dim3(256), 0, s, pc, at<float4>(ws, L[v].rec), tri_id[v], M.tri,
-                               albedo[V.mesh], at<ViewBlock>(ws, L[v].vb), light->ambient, M.nt, o8, o32);
-        else
-            hipLaunchKernelGGL(k_shade<false>, grid, dim3(256), 0, s, pc, at<float4>(ws, L[v].rec), tri_id[v], M.tri,
-                               albedo[V.mesh], at<ViewBlock>(ws, L[v].vb), light->ambient, M.nt, o8, o32);
+        io.id[v] = tri_id[v];
+        io.rgba8[v] = rgba8 ? rgba8[v] : nullptr;
+        io.rgb32[v] = rgb32 ? rgb32[v] : nullptr;
+        io.albedo[v] = albedo[views[v].mesh];
+        any = any || io.rgba8[v] || io.rgb32[v];
     }
+    if (!any) return PR_OK;
+    hipLaunchKernelGGL(k_view_light, dim3(1), dim3(64), 0, s, T, *light);
+    hipLaunchKernelGGL(k_shade, dim3(L.total_pix_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec), io,
+                       light->ambient);
     return launched();
 }
 
@@ -303,19 +324,28 @@ int pr_debug_tile_lists(const pr_mesh *meshes, int nm, const pr_view *views, int
     if (!ntiles || !npairs || view < 0 || view >= nv) return PR_ERR_INVALID;
     PR_PREP();
     (void)st;
-    const ViewLayout &l = L[view];
-    *ntiles = l.ntiles;
-    uint32_t total = 0;
-    if (hipMemcpyAsync(&total, at<uint32_t>(ws, l.toff) + l.ntiles, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+    (void)T;
+    const ViewDev &d = L.vd[view];
+    *ntiles = d.ntiles;
+    uint32_t ends[2] = {0, 0};
+    if (hipMemcpyAsync(&ends[0], at<uint32_t>(ws, L.toff) + d.tile_base, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&ends[1], at<uint32_t>(ws, L.toff) + d.tile_base + d.ntiles, 4, hipMemcpyDeviceToHost, s) !=
+            hipSuccess)
         return PR_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return PR_ERR_HIP;
+    uint32_t total = ends[1] - ends[0];
     *npairs = total;
-    if (offsets &&
-        hipMemcpyAsync(offsets, at<void>(ws, l.toff), ((size_t)l.ntiles + 1) * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
-        return PR_ERR_HIP;
+    if (offsets) {
+        if (hipMemcpyAsync(offsets, at<uint32_t>(ws, L.toff) + d.tile_base, ((size_t)d.ntiles + 1) * 4,
+                           hipMemcpyDeviceToHost, s) != hipSuccess)
+            return PR_ERR_HIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return PR_ERR_HIP;
+        for (int i = 0; i <= d.ntiles; ++i) offsets[i] -= (int32_t)ends[0];
+    }
     if (lists) {
-        if (cap < (int64_t)total || (int64_t)total > l.cap) return PR_ERR_INVALID;
-        if (total && hipMemcpyAsync(lists, at<void>(ws, l.lists), (size_t)total * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+        if (cap < (int64_t)total || (int64_t)ends[1] > L.cap) return PR_ERR_INVALID;
+        if (total && hipMemcpyAsync(lists, at<int32_t>(ws, L.lists) + ends[0], (size_t)total * 4,
+                                    hipMemcpyDeviceToHost, s) != hipSuccess)
             return PR_ERR_HIP;
     }
     return hipStreamSynchronize(s) == hipSuccess ? PR_OK : PR_ERR_HIP;

@@ -84,7 +84,9 @@ PRG void radial_map(const Geom &g, double e, double x0, double x1, double &o0, d
     double d0 = x0 - g.fov[0], d1 = x1 - g.fov[1];
     double rho = sqrt(d0 * d0 + d1 * d1);
     if (rho == 0.0 || e == 1.0) { o0 = x0; o1 = x1; return; }
-    double s = pow(rho / g.rad, e - 1.0);
+    double q = rho / g.rad;
+    // (rho/R)^(e-1); the square-law density (e = 2 or 1/2) avoids pow
+    double s = e == 2.0 ? q : (e == 0.5 ? sqrt(1.0 / q) : pow(q, e - 1.0));
     o0 = g.fov[0] + d0 * s;
     o1 = g.fov[1] + d1 * s;
 }
@@ -371,16 +373,15 @@ PRG void tile_display(const Geom &g, int tile, int tx, int ty, double box[4], do
     tw[1] = clamp01(umax + kSlackTime);
 }
 
-// Conservative test of one (triangle, tile) pair.  kWindow triangles: the
-// window is cut to the tile's own time window, the six projected end
-// vertices of that window bound the triangle's image over it, and a
-// separating-axis test (box axes and the edge normals of both end
-// triangles) against the tile's display box rejects the pair.  kClipped
-// triangles use their whole-frame display box.
-PRG bool tile_test(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double win[2],
-                   const double tri_box[4], int tile, int tx, int ty) {
-    double tb[4], tw[2];
-    tile_display(g, tile, tx, ty, tb, tw);
+// Conservative test of one (triangle, tile) pair given the tile's display
+// box tb and time window tw (tile_display).  kWindow triangles: the window
+// is cut to the tile's own time window, the six projected end vertices of
+// that window bound the triangle's image over it, and a separating-axis
+// test (box axes and the edge normals of both end triangles) against the
+// tile's display box rejects the pair.  kClipped triangles use their
+// whole-frame display box.
+PRG bool tile_test_with(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double win[2],
+                        const double tri_box[4], const double tb[4], const double tw[2]) {
     if (kind == kClipped)
         return !(tri_box[1] < tb[0] || tri_box[0] > tb[1] || tri_box[3] < tb[2] || tri_box[2] > tb[3]);
     double w0 = dmax(win[0], tw[0]), w1 = dmin(win[1], tw[1]);
@@ -391,8 +392,9 @@ PRG bool tile_test(const Geom &g, const double Ps[3][3], const double Pe[3][3], 
             double w = e ? w1 : w0;
             double P[3];
             for (int r = 0; r < 3; ++r) P[r] = (1.0 - w) * Ps[k][r] + w * Pe[k][r];
-            q[3 * e + k][0] = g.fx * P[0] / P[2] + g.cx;
-            q[3 * e + k][1] = g.fy * P[1] / P[2] + g.cy;
+            double iz = 1.0 / P[2];
+            q[3 * e + k][0] = g.fx * P[0] * iz + g.cx;
+            q[3 * e + k][1] = g.fy * P[1] * iz + g.cy;
         }
     double big = 1.0;
     for (int i = 0; i < 6; ++i) big = dmax(big, dmax(fabs(q[i][0]), fabs(q[i][1])));
@@ -423,6 +425,13 @@ PRG bool tile_test(const Geom &g, const double Ps[3][3], const double Pe[3][3], 
         if (pmax < bmin - m || pmin > bmax + m) return false;
     }
     return true;
+}
+
+PRG bool tile_test(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double win[2],
+                   const double tri_box[4], int tile, int tx, int ty) {
+    double tb[4], tw[2];
+    tile_display(g, tile, tx, ty, tb, tw);
+    return tile_test_with(g, Ps, Pe, kind, win, tri_box, tb, tw);
 }
 
 }  // namespace prg

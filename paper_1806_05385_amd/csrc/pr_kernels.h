@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "pr.h"
+#include "pr_geom.h"
 
 namespace prk {
 
@@ -31,11 +32,56 @@ struct TriBound {
     double w[4];       // kWindow: time window w[0..1]; kClipped: display box
 };
 
-// Per-view constants the later passes read (written by the bound kernel).
-struct ViewBlock {
-    float light0[3];   // R0 * light direction (camera space at t0)
-    float light1[3];   // R1 * light direction
-    float pad[2];
+// Display-space box of a tile's pixel centres and its frame-time window.
+struct TileInfo {
+    double box[4];
+    double tw[2];
+};
+
+// Per-pixel constants of a view (FP32 setup in the ray cast and shading).
+struct PixelConst {
+    float invW2, invH2;    // 2/W, 2/H
+    float fov0, fov1, invR, alpha;
+    float roll0, roll1;
+    float cx, cy, invfx, invfy;
+    float znear;
+    int W, H;
+    int mode;              // 0: alpha == 1, 1: alpha == 2, 2: general power
+};
+
+// One view as the kernels see it (lives in the workspace's view table).
+struct ViewDev {
+    pr_view view;
+    pr_mesh mesh;
+    PixelConst pc;
+    int32_t tile, tiles_x, tiles_y, ntiles;
+    int32_t tile_base;     // global index of the view's first tile
+    int32_t tri_block0;    // first 256-triangle block (bound and bin grids)
+    int32_t pix_block0;    // first 256-pixel block (shade and backward grids)
+    int32_t rec_w;         // float4 per record
+    int32_t rolling;
+    int32_t pad;
+    int64_t rec_off;       // float4 offset of the view's first record
+    int64_t tri_off;       // TriBound index of the view's first triangle
+    float light0[3];       // R0 * light direction (written by pr_shade)
+    float light1[3];       // R1 * light direction
+    prg::Geom g;           // FP64 camera geometry (written by k_write_views)
+};
+
+struct ViewTable {
+    int32_t nv, total_tiles, total_tri_blocks, total_pix_blocks;
+    int32_t tri_block0[PR_MAX_VIEWS + 1];
+    int32_t tile_base[PR_MAX_VIEWS + 1];
+    int32_t pix_block0[PR_MAX_VIEWS + 1];
+    int32_t pad;
+    ViewDev v[PR_MAX_VIEWS];
+};
+
+// Views written per k_write_views launch (kernel-argument size).
+constexpr int kViewsPerWrite = 2;
+struct ViewPack {
+    int32_t first, count, nv, total_tiles, total_tri_blocks, total_pix_blocks;
+    ViewDev v[kViewsPerWrite];
 };
 
 // Status block at the start of the workspace.
@@ -46,8 +92,20 @@ struct DevStatus {
     unsigned long long pairs_total;
     unsigned long long tests;
     unsigned long long hits;
-    uint32_t num_pairs[PR_MAX_VIEWS];   // per-view emission cursor
-    int32_t view_overflow[PR_MAX_VIEWS];
+    uint32_t num_pairs;    // emission cursor of the frame's (triangle, tile) pairs
+    uint32_t pad;
+};
+
+// Output / input pointers of the per-pixel passes, indexed by view.
+struct RayOut {
+    int32_t *id[PR_MAX_VIEWS];
+    float *depth[PR_MAX_VIEWS];
+};
+struct ShadeIO {
+    const int32_t *id[PR_MAX_VIEWS];
+    uint8_t *rgba8[PR_MAX_VIEWS];
+    float *rgb32[PR_MAX_VIEWS];
+    const float *albedo[PR_MAX_VIEWS];   // per view (the albedo of its mesh)
 };
 
 }  // namespace prk

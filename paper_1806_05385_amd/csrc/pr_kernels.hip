@@ -1,8 +1,14 @@
 // pr_kernels.hip -- gfx950 kernels of the perceptual rasterization hot path.
 //
+// Every pass covers all views of a call in one launch: views are laid end to
+// end in a global triangle / tile / pixel index space and a block finds its
+// view in the workspace's view table.
+//
 //   k_bound    one lane per triangle, FP64: camera-space vertices, near plane,
 //              rolling time window, foveated tile rectangle, FP32
 //              intersection record (Sec. 3.2 "Bounding", Sec. 4)
+//   k_tiles    one lane per tile: display box of its pixel centres and its
+//              frame-time window
 //   k_bin      one block per 256 triangles: every (triangle, tile) candidate
 //              of the block's rectangles tested conservatively, survivors
 //              compacted with a wave ballot + mbcnt prefix and one atomic
@@ -69,6 +75,52 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
+// view table
+// ---------------------------------------------------------------------------
+// Index of the last view whose base <= key (bases ascending, nv entries).
+__device__ __forceinline__ int find_view(const int32_t *base, int nv, int key) {
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= key) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_write_views(ViewPack p, ViewTable *__restrict__ T) {
+    int i = threadIdx.x;
+    if (i < p.count) {
+        const ViewDev &v = p.v[i];
+        T->v[p.first + i] = v;
+        prg::make_geom(v.view, T->v[p.first + i].g);
+        T->tri_block0[p.first + i] = v.tri_block0;
+        T->tile_base[p.first + i] = v.tile_base;
+        T->pix_block0[p.first + i] = v.pix_block0;
+    }
+    if (i == 0 && p.first + p.count == p.nv) {
+        T->nv = p.nv;
+        T->total_tiles = p.total_tiles;
+        T->total_tri_blocks = p.total_tri_blocks;
+        T->total_pix_blocks = p.total_pix_blocks;
+        T->tri_block0[p.nv] = p.total_tri_blocks;
+        T->tile_base[p.nv] = p.total_tiles;
+        T->pix_block0[p.nv] = p.total_pix_blocks;
+    }
+}
+
+// Camera-space light direction at each view's start and end.
+__global__ void k_view_light(ViewTable *__restrict__ T, pr_light light) {
+    int v = threadIdx.x;
+    if (v >= T->nv) return;
+    const prg::Geom &g = T->v[v].g;
+    double l[3] = {light.dir_world[0], light.dir_world[1], light.dir_world[2]};
+    for (int r = 0; r < 3; ++r) {
+        T->v[v].light0[r] = (float)(g.R0[3 * r] * l[0] + g.R0[3 * r + 1] * l[1] + g.R0[3 * r + 2] * l[2]);
+        T->v[v].light1[r] = (float)(g.R1[3 * r] * l[0] + g.R1[3 * r + 1] * l[1] + g.R1[3 * r + 2] * l[2]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // bound
 // ---------------------------------------------------------------------------
 __device__ inline void dcross(const double a[3], const double b[3], double o[3]) {
@@ -78,27 +130,16 @@ __device__ inline void dcross(const double a[3], const double b[3], double o[3])
 }
 __device__ inline double ddot(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
-// Camera-space light direction at the frame's start and end (one thread).
-__global__ void k_view_light(pr_view view, pr_light light, ViewBlock *__restrict__ vb) {
-    prg::Geom g;
-    prg::make_geom(view, g);
-    double l[3] = {light.dir_world[0], light.dir_world[1], light.dir_world[2]};
-    for (int r = 0; r < 3; ++r) {
-        vb->light0[r] = (float)(g.R0[3 * r] * l[0] + g.R0[3 * r + 1] * l[1] + g.R0[3 * r + 2] * l[2]);
-        vb->light1[r] = (float)(g.R1[3 * r] * l[0] + g.R1[3 * r + 1] * l[1] + g.R1[3 * r + 2] * l[2]);
-    }
-}
-
-template <bool ROLL>
-__global__ __launch_bounds__(256) void k_bound(pr_view view, pr_mesh mesh, int tile, float4 *__restrict__ rec,
+__global__ __launch_bounds__(256) void k_bound(const ViewTable *__restrict__ T, float4 *__restrict__ rec,
                                                TriBound *__restrict__ tb, DevStatus *__restrict__ st) {
-    prg::Geom g;
-    prg::make_geom(view, g);
-    int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= mesh.nt) return;
+    const int v = find_view(T->tri_block0, T->nv, blockIdx.x);
+    const ViewDev &vd = T->v[v];
+    int f = (blockIdx.x - vd.tri_block0) * 256 + threadIdx.x;
+    if (f >= vd.mesh.nt) return;
+    const prg::Geom &g = vd.g;
     double Ps[3][3], Pe[3][3];
     int32_t idx[3];
-    bool ok = prg::load_tri(mesh.v0, mesh.v1, mesh.tri, mesh.nv, f, g, Ps, Pe, idx);
+    bool ok = prg::load_tri(vd.mesh.v0, vd.mesh.v1, vd.mesh.tri, vd.mesh.nv, f, g, Ps, Pe, idx);
     TriBound b;
     b.rect[0] = 1; b.rect[1] = 1; b.rect[2] = 0; b.rect[3] = 0;
     b.kind = prg::kCulled;
@@ -113,7 +154,7 @@ __global__ __launch_bounds__(256) void k_bound(pr_view view, pr_mesh mesh, int t
             double box[4];
             prg::display_box(g, Ps, Pe, win[0], win[1], kind, box);
             int rect[4];
-            if (prg::tile_rect(g, box, tile, rect)) {
+            if (prg::tile_rect(g, box, vd.tile, rect)) {
                 for (int k = 0; k < 4; ++k) b.rect[k] = rect[k];
                 b.kind = kind;
                 if (kind == prg::kWindow) { b.w[0] = win[0]; b.w[1] = win[1]; }
@@ -121,7 +162,7 @@ __global__ __launch_bounds__(256) void k_bound(pr_view view, pr_mesh mesh, int t
             }
         }
     }
-    tb[f] = b;
+    tb[vd.tri_off + f] = b;
 
     // Intersection record.  Edge k joins vertices a = k+1, b = k+2.  Its
     // plane normal is computed from the lower-indexed mesh vertex as
@@ -175,15 +216,18 @@ __global__ __launch_bounds__(256) void k_bound(pr_view view, pr_mesh mesh, int t
         d0 = d1 = d2 = d3 = 0.0;
         for (int r = 0; r < 3; ++r) N0[r] = N1[r] = N2[r] = 0.0;
     }
-    float out[44];
-    if (ROLL) {
-        int n = 0;
-        for (int k = 0; k < 3; ++k) {
-            for (int r = 0; r < 3; ++r) out[n++] = (float)A[k][r];
-            for (int r = 0; r < 3; ++r) out[n++] = (float)B[k][r];
-            for (int r = 0; r < 3; ++r) out[n++] = (float)C[k][r];
-        }
+    if (vd.rolling) {
+        float out[44];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                out[9 * k + r] = (float)A[k][r];
+                out[9 * k + 3 + r] = (float)B[k][r];
+                out[9 * k + 6 + r] = (float)C[k][r];
+            }
         out[27] = (float)d0; out[28] = (float)d1; out[29] = (float)d2; out[30] = (float)d3;
+#pragma unroll
         for (int r = 0; r < 3; ++r) {
             out[31 + r] = (float)N0[r];
             out[34 + r] = (float)N1[r];
@@ -191,50 +235,80 @@ __global__ __launch_bounds__(256) void k_bound(pr_view view, pr_mesh mesh, int t
         }
         out[40] = __int_as_float(f);
         out[41] = out[42] = out[43] = 0.0f;
-        float4 *dst = rec + (int64_t)f * kRecRoll;
+        float4 *dst = rec + vd.rec_off + (int64_t)f * kRecRoll;
+#pragma unroll
         for (int q = 0; q < kRecRoll; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
     } else {
-        int n = 0;
+        float out[16];
+#pragma unroll
         for (int k = 0; k < 3; ++k)
-            for (int r = 0; r < 3; ++r) out[n++] = (float)A[k][r];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) out[3 * k + r] = (float)A[k][r];
         out[9] = (float)d0;
+#pragma unroll
         for (int r = 0; r < 3; ++r) out[10 + r] = (float)N0[r];
         out[13] = __int_as_float(f);
         out[14] = out[15] = 0.0f;
-        float4 *dst = rec + (int64_t)f * kRecStatic;
+        float4 *dst = rec + vd.rec_off + (int64_t)f * kRecStatic;
+#pragma unroll
         for (int q = 0; q < kRecStatic; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
     }
+}
+
+// ---------------------------------------------------------------------------
+// per-tile display boxes
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, TileInfo *__restrict__ ti) {
+    int gt = blockIdx.x * 256 + threadIdx.x;
+    if (gt >= T->total_tiles) return;
+    int v = find_view(T->tile_base, T->nv, gt);
+    const ViewDev &vd = T->v[v];
+    int lt = gt - vd.tile_base;
+    const prg::Geom &g = vd.g;
+    TileInfo t;
+    prg::tile_display(g, vd.tile, lt % vd.tiles_x, lt / vd.tiles_x, t.box, t.tw);
+    ti[gt] = t;
 }
 
 // ---------------------------------------------------------------------------
 // bin
 // ---------------------------------------------------------------------------
 struct Pair {
-    int32_t tile, slot, tri;
+    int32_t tile, slot, tri;   // global tile, slot in its list, triangle index in the view's mesh
 };
 
-__global__ __launch_bounds__(256) void k_bin(pr_view view, pr_mesh mesh, int tile, int tiles_x,
-                                             const TriBound *__restrict__ tb, uint32_t *__restrict__ tcount,
-                                             Pair *__restrict__ pairs, int64_t cap, uint32_t *__restrict__ cursor) {
+// Candidates are tested in chunks of kBinChunk; their pass bits are kept in
+// LDS, the block reserves space for all survivors of a chunk with one global
+// atomic, and each survivor takes its place from a ballot + mbcnt prefix
+// inside its wave plus the wave's offset in the block.
+constexpr int kBinChunk = 256 * 16;
+
+__global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, const TriBound *__restrict__ tb,
+                                             const TileInfo *__restrict__ ti, uint32_t *__restrict__ tcount,
+                                             Pair *__restrict__ pairs, int64_t cap, DevStatus *__restrict__ st) {
     __shared__ double s_P[256][18];
     __shared__ double s_w[256][4];
     __shared__ int s_rect[256][4];
     __shared__ int s_kind[256];
     __shared__ int s_pref[257];
     __shared__ int s_tmp[72];
-    prg::Geom g;
-    prg::make_geom(view, g);
-    int f0 = blockIdx.x * 256;
-    int j = threadIdx.x;
-    int f = f0 + j;
+    __shared__ unsigned long long s_pass[kBinChunk / 64];
+    __shared__ int s_wpref[kBinChunk / 64];
+    __shared__ uint32_t s_base;
+    const int v = find_view(T->tri_block0, T->nv, blockIdx.x);
+    const ViewDev &vd = T->v[v];
+    const prg::Geom &g = vd.g;
+    const int f0 = (blockIdx.x - vd.tri_block0) * 256;
+    const int j = threadIdx.x;
+    const int f = f0 + j;
     int cnt = 0;
-    if (f < mesh.nt) {
-        TriBound b = tb[f];
+    if (f < vd.mesh.nt) {
+        TriBound b = tb[vd.tri_off + f];
         if (b.kind != prg::kCulled && b.rect[0] <= b.rect[2] && b.rect[1] <= b.rect[3]) {
             cnt = (b.rect[2] - b.rect[0] + 1) * (b.rect[3] - b.rect[1] + 1);
             double Ps[3][3], Pe[3][3];
             int32_t idx[3];
-            prg::load_tri(mesh.v0, mesh.v1, mesh.tri, mesh.nv, f, g, Ps, Pe, idx);
+            prg::load_tri(vd.mesh.v0, vd.mesh.v1, vd.mesh.tri, vd.mesh.nv, f, g, Ps, Pe, idx);
             for (int k = 0; k < 3; ++k)
                 for (int r = 0; r < 3; ++r) {
                     s_P[j][3 * k + r] = Ps[k][r];
@@ -249,38 +323,78 @@ __global__ __launch_bounds__(256) void k_bin(pr_view view, pr_mesh mesh, int til
     s_pref[j] = ex;
     if (j == 255) s_pref[256] = total;
     __syncthreads();
-    for (int c = j; c < total; c += 256) {
-        // triangle of candidate c: largest q with s_pref[q] <= c
-        int lo = 0, hi = 255;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (s_pref[mid] <= c) lo = mid; else hi = mid - 1;
-        }
-        int q = lo;
-        int local = c - s_pref[q];
-        int rw = s_rect[q][2] - s_rect[q][0] + 1;
-        int tx = s_rect[q][0] + local % rw, ty = s_rect[q][1] + local / rw;
-        double Ps[3][3], Pe[3][3];
-        for (int k = 0; k < 3; ++k)
-            for (int r = 0; r < 3; ++r) {
-                Ps[k][r] = s_P[q][3 * k + r];
-                Pe[k][r] = s_P[q][9 + 3 * k + r];
+    const int wid = j >> 6, lane = __lane_id();
+    for (int c0 = 0; c0 < total; c0 += kBinChunk) {
+        const int cn = min(kBinChunk, total - c0);
+        // pass 1: test every candidate of the chunk, keep the bits
+        int mine = 0;
+        const int cn_up = (cn + 255) & ~255;   // same trip count for every thread
+        for (int i = j; i < cn_up; i += 256) {
+            bool pass = false;
+            if (i < cn) {
+                const int c = c0 + i;
+                int lo = 0, hi = 255;
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (s_pref[mid] <= c) lo = mid; else hi = mid - 1;
+                }
+                const int q = lo;
+                const int local = c - s_pref[q];
+                const int rw = s_rect[q][2] - s_rect[q][0] + 1;
+                const int tx = s_rect[q][0] + local % rw, ty = s_rect[q][1] + local / rw;
+                const int gt = vd.tile_base + ty * vd.tiles_x + tx;
+                double Ps[3][3], Pe[3][3];
+                for (int k = 0; k < 3; ++k)
+                    for (int r = 0; r < 3; ++r) {
+                        Ps[k][r] = s_P[q][3 * k + r];
+                        Pe[k][r] = s_P[q][9 + 3 * k + r];
+                    }
+                double w[4] = {s_w[q][0], s_w[q][1], s_w[q][2], s_w[q][3]};
+                const TileInfo t = ti[gt];
+                pass = prg::tile_test_with(g, Ps, Pe, s_kind[q], w, w, t.box, t.tw);
             }
-        double w[4] = {s_w[q][0], s_w[q][1], s_w[q][2], s_w[q][3]};
-        bool pass = prg::tile_test(g, Ps, Pe, s_kind[q], w, w, tile, tx, ty);
-        unsigned long long m = __ballot(pass);
-        if (m) {
-            unsigned leader = __ffsll((unsigned long long)m) - 1;
-            unsigned base = 0;
-            if (__lane_id() == leader) base = atomicAdd(cursor, (unsigned)__popcll(m));
-            base = __shfl(base, leader, 64);
-            if (pass) {
-                unsigned i = base + lanes_below(m);
-                int t = ty * tiles_x + tx;
-                unsigned slot = atomicAdd(&tcount[t], 1u);
-                if ((int64_t)i < cap) pairs[i] = Pair{t, (int32_t)slot, f0 + q};
+            unsigned long long m = __ballot(pass);
+            if (lane == 0) s_pass[i >> 6] = m;
+            mine += pass;
+        }
+        // block total of survivors -> one reservation
+        int ctotal;
+        block_excl_scan(mine, s_tmp, ctotal);
+        if (j == 0) s_base = ctotal ? atomicAdd(&st->num_pairs, (unsigned)ctotal) : 0u;
+        __syncthreads();
+        // pass 2: survivors take their slots in candidate order (prefix over the bit words)
+        // word w covers candidates [64 w, 64 w + 64); per-word prefix by one wave
+        if (wid == 0) {
+            int nw = (cn + 63) / 64;
+            int carry = 0;
+            for (int w0 = 0; w0 < nw; w0 += 64) {
+                int cw = w0 + lane < nw ? __popcll(s_pass[w0 + lane]) : 0;
+                int inc = wave_incl_scan(cw);
+                if (w0 + lane < nw) s_wpref[w0 + lane] = carry + inc - cw;
+                carry += __shfl(inc, 63, 64);
             }
         }
+        __syncthreads();
+        for (int i = j; i < cn; i += 256) {
+            unsigned long long m = s_pass[i >> 6];
+            if (!((m >> (i & 63)) & 1ull)) continue;
+            const int c = c0 + i;
+            int lo = 0, hi = 255;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (s_pref[mid] <= c) lo = mid; else hi = mid - 1;
+            }
+            const int q = lo;
+            const int local = c - s_pref[q];
+            const int rw = s_rect[q][2] - s_rect[q][0] + 1;
+            const int tx = s_rect[q][0] + local % rw, ty = s_rect[q][1] + local / rw;
+            const int gt = vd.tile_base + ty * vd.tiles_x + tx;
+            unsigned below = __popcll(m & ((1ull << (i & 63)) - 1ull));
+            unsigned idx = s_base + (unsigned)s_wpref[i >> 6] + below;
+            unsigned slot = atomicAdd(&tcount[gt], 1u);
+            if ((int64_t)idx < cap) pairs[idx] = Pair{gt, (int32_t)slot, f0 + q};
+        }
+        __syncthreads();
     }
 }
 
@@ -339,16 +453,13 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
 // scatter pairs into tile lists; flags overflow
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_scatter(const Pair *__restrict__ pairs, const uint32_t *__restrict__ toff,
-                                                 int32_t *__restrict__ lists, int64_t cap, int view,
+                                                 int32_t *__restrict__ lists, int64_t cap,
                                                  DevStatus *__restrict__ st) {
-    uint32_t np = st->num_pairs[view];
+    uint32_t np = st->num_pairs;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        atomicAdd(&st->pairs_total, (unsigned long long)np);
-        atomicMax(&st->pairs_required, (unsigned long long)np);
-        if ((int64_t)np > cap) {
-            st->view_overflow[view] = 1;
-            st->overflow = 1;
-        }
+        st->pairs_total = np;
+        st->pairs_required = np;
+        if ((int64_t)np > cap) st->overflow = 1;
     }
     if ((int64_t)np > cap) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)np; i += (int64_t)gridDim.x * blockDim.x) {
@@ -360,16 +471,6 @@ __global__ __launch_bounds__(256) void k_scatter(const Pair *__restrict__ pairs,
 // ---------------------------------------------------------------------------
 // ray cast
 // ---------------------------------------------------------------------------
-struct PixelConst {
-    float invW2, invH2;    // 2/W, 2/H
-    float fov0, fov1, invR, alpha;
-    float roll0, roll1;
-    float cx, cy, invfx, invfy;
-    float znear;
-    int W, H;
-    int mode;              // 0: alpha == 1, 1: alpha == 2, 2: general power
-};
-
 // Per-pixel setup: foveated sample -> display point (unfoveate) -> time ->
 // ray direction (rx, ry, 1).
 __device__ __forceinline__ void pixel_setup(const PixelConst &pc, int px, int py, float &t, float &rx, float &ry) {
@@ -396,23 +497,25 @@ __device__ __forceinline__ float edge_roll(float ax, float ay, float az, float b
     return fmaf(ry, ey, fmaf(rx, ex, ez));
 }
 
-template <bool ROLL, int TILE>
+template <int TILE>
 struct RayCfg {
     static constexpr int NT = TILE * TILE >= 256 ? 256 : 64;
     static constexpr int PPL = TILE * TILE / NT;
-    static constexpr int RECW = ROLL ? kRecRoll : kRecStatic;
     static constexpr int CHUNK = 64;
 };
 
+// One tile of one view: stage the tile's list through LDS, test every pixel
+// against every staged triangle, keep the nearest packed (depth, id).
 template <bool ROLL, int TILE, bool COUNT>
-__global__ __launch_bounds__((RayCfg<ROLL, TILE>::NT)) void k_raycast(
-    PixelConst pc, int tiles_x, const float4 *__restrict__ rec, const uint32_t *__restrict__ toff,
-    const int32_t *__restrict__ lists, int32_t *__restrict__ out_id, float *__restrict__ out_depth, int view,
-    DevStatus *__restrict__ st) {
-    using C = RayCfg<ROLL, TILE>;
-    __shared__ float4 s_rec[C::CHUNK * C::RECW];
-    const int tile = blockIdx.x;
-    const int tx = tile % tiles_x, ty = tile / tiles_x;
+__device__ __forceinline__ void raycast_tile(const ViewDev &vd, int lt, const float4 *__restrict__ rec,
+                                             int beg, int end, const int32_t *__restrict__ lists,
+                                             float4 *s_rec, int32_t *__restrict__ out_id,
+                                             float *__restrict__ out_depth, DevStatus *__restrict__ st) {
+    using C = RayCfg<TILE>;
+    constexpr int RECW = ROLL ? kRecRoll : kRecStatic;
+    const PixelConst &pc = vd.pc;
+    const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
+    const float4 *vrec = rec + vd.rec_off;
     float t[C::PPL], rx[C::PPL], ry[C::PPL];
     unsigned long long best[C::PPL];
     int nvalid = 0;
@@ -424,23 +527,17 @@ __global__ __launch_bounds__((RayCfg<ROLL, TILE>::NT)) void k_raycast(
         best[k] = ~0ull;
         nvalid += (px < pc.W && py < pc.H);
     }
-    const bool ovf = st->view_overflow[view] != 0;
-    int beg = 0, end = 0;
-    if (!ovf) {
-        beg = (int)toff[tile];
-        end = (int)toff[tile + 1];
-    }
     unsigned hits = 0;
     for (int base = beg; base < end; base += C::CHUNK) {
         int n = min(C::CHUNK, end - base);
-        for (int i = threadIdx.x; i < n * C::RECW; i += C::NT) {
-            int r = i / C::RECW, c = i - r * C::RECW;
+        for (int i = threadIdx.x; i < n * RECW; i += C::NT) {
+            int r = i / RECW, c = i - r * RECW;
             int f = lists[base + r];
-            s_rec[i] = rec[(int64_t)f * C::RECW + c];
+            s_rec[i] = vrec[(int64_t)f * RECW + c];
         }
         __syncthreads();
         for (int jj = 0; jj < n; ++jj) {
-            const float4 *R = s_rec + jj * C::RECW;
+            const float4 *R = s_rec + jj * RECW;
             if (ROLL) {
                 float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4], r5 = R[5], r6 = R[6], r7 = R[7];
                 bool pass[C::PPL];
@@ -521,74 +618,102 @@ __global__ __launch_bounds__((RayCfg<ROLL, TILE>::NT)) void k_raycast(
     }
 }
 
+template <int TILE, bool COUNT>
+__global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable *__restrict__ T,
+                                                               const float4 *__restrict__ rec,
+                                                               const uint32_t *__restrict__ toff,
+                                                               const int32_t *__restrict__ lists, RayOut out,
+                                                               DevStatus *__restrict__ st) {
+    __shared__ float4 s_rec[RayCfg<TILE>::CHUNK * kRecRoll];
+    const int gt = blockIdx.x;
+    const int v = find_view(T->tile_base, T->nv, gt);
+    const ViewDev &vd = T->v[v];
+    int beg = 0, end = 0;
+    if (!st->overflow) {
+        beg = (int)toff[gt];
+        end = (int)toff[gt + 1];
+    }
+    if (vd.rolling)
+        raycast_tile<true, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, s_rec, out.id[v], out.depth[v], st);
+    else
+        raycast_tile<false, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, s_rec, out.id[v], out.depth[v], st);
+}
+
 // ---------------------------------------------------------------------------
 // shade
 // ---------------------------------------------------------------------------
-template <bool ROLL>
-__global__ __launch_bounds__(256) void k_shade(PixelConst pc, const float4 *__restrict__ rec,
-                                               const int32_t *__restrict__ ids, const int32_t *__restrict__ tri,
-                                               const float *__restrict__ albedo, const ViewBlock *__restrict__ vb,
-                                               float ambient, int nt, uint8_t *__restrict__ rgba8,
-                                               float *__restrict__ rgb32) {
-    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// Edge-plane normals c_k(t), face normal N(t) of triangle id at time t.
+__device__ __forceinline__ void record_at(const ViewDev &vd, const float4 *__restrict__ rec, int id, float t,
+                                          float ck[3][3], float N[3]) {
+    if (vd.rolling) {
+        const float4 *R = rec + vd.rec_off + (int64_t)id * kRecRoll;
+        float v[40];
+        for (int q = 0; q < 10; ++q) {
+            float4 x = R[q];
+            v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+        }
+        for (int k = 0; k < 3; ++k)
+            for (int r = 0; r < 3; ++r)
+                ck[k][r] = fmaf(t, fmaf(t, v[9 * k + 6 + r], v[9 * k + 3 + r]), v[9 * k + r]);
+        for (int r = 0; r < 3; ++r) N[r] = fmaf(t, fmaf(t, v[37 + r], v[34 + r]), v[31 + r]);
+    } else {
+        const float4 *R = rec + vd.rec_off + (int64_t)id * kRecStatic;
+        float4 a = R[0], b = R[1], d = R[2], e4 = R[3];
+        float v[13] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, d.x, d.y, d.z, d.w, e4.x};
+        for (int k = 0; k < 3; ++k)
+            for (int r = 0; r < 3; ++r) ck[k][r] = v[3 * k + r];
+        for (int r = 0; r < 3; ++r) N[r] = v[10 + r];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_shade(const ViewTable *__restrict__ T, const float4 *__restrict__ rec,
+                                               ShadeIO io, float ambient) {
+    const int v = find_view(T->pix_block0, T->nv, blockIdx.x);
+    const ViewDev &vd = T->v[v];
+    const PixelConst &pc = vd.pc;
+    int64_t p = (int64_t)(blockIdx.x - vd.pix_block0) * 256 + threadIdx.x;
     if (p >= (int64_t)pc.W * pc.H) return;
-    int id = ids[p];
-    if (id >= nt) id = -1;   // ids outside the mesh shade as misses
+    int id = io.id[v][p];
+    if (id >= vd.mesh.nt) id = -1;   // ids outside the mesh shade as misses
     float c[3] = {0.0f, 0.0f, 0.0f};
     if (id >= 0) {
         int px = (int)(p % pc.W), py = (int)(p / pc.W);
         float t, rx, ry;
         pixel_setup(pc, px, py, t, rx, ry);
         float ck[3][3], N[3];
-        if (ROLL) {
-            const float4 *R = rec + (int64_t)id * kRecRoll;
-            float v[40];
-            for (int q = 0; q < 10; ++q) {
-                float4 x = R[q];
-                v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
-            }
-            for (int k = 0; k < 3; ++k)
-                for (int r = 0; r < 3; ++r)
-                    ck[k][r] = fmaf(t, fmaf(t, v[9 * k + 6 + r], v[9 * k + 3 + r]), v[9 * k + r]);
-            for (int r = 0; r < 3; ++r) N[r] = fmaf(t, fmaf(t, v[37 + r], v[34 + r]), v[31 + r]);
-        } else {
-            const float4 *R = rec + (int64_t)id * kRecStatic;
-            float4 a = R[0], b = R[1], d = R[2], e4 = R[3];
-            float v[13] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, d.x, d.y, d.z, d.w, e4.x};
-            for (int k = 0; k < 3; ++k)
-                for (int r = 0; r < 3; ++r) ck[k][r] = v[3 * k + r];
-            for (int r = 0; r < 3; ++r) N[r] = v[10 + r];
-        }
+        record_at(vd, rec, id, t, ck, N);
         float e[3];
         for (int k = 0; k < 3; ++k) e[k] = fmaf(ry, ck[k][1], fmaf(rx, ck[k][0], ck[k][2]));
         float S = e[0] + e[1] + e[2];
         float inn = rsqrtf(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
         float sg = (N[0] * rx + N[1] * ry + N[2]) > 0.0f ? -inn : inn;
         float L[3];
-        for (int r = 0; r < 3; ++r) L[r] = fmaf(t, vb->light1[r] - vb->light0[r], vb->light0[r]);
+        for (int r = 0; r < 3; ++r) L[r] = fmaf(t, vd.light1[r] - vd.light0[r], vd.light0[r]);
         float inl = rsqrtf(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
         float ndl = sg * inl * (N[0] * L[0] + N[1] * L[1] + N[2] * L[2]);
         float s = ambient + (1.0f - ambient) * fmaxf(ndl, 0.0f);
         float invS = 1.0f / S;
+        const float *alb = io.albedo[v];
         for (int k = 0; k < 3; ++k) {
-            int v = tri[3 * (int64_t)id + k];
+            int vi = vd.mesh.tri[3 * (int64_t)id + k];
             float mu = e[k] * invS;
-            for (int ch = 0; ch < 3; ++ch) c[ch] = fmaf(mu, albedo[3 * (int64_t)v + ch], c[ch]);
+            for (int ch = 0; ch < 3; ++ch) c[ch] = fmaf(mu, alb[3 * (int64_t)vi + ch], c[ch]);
         }
         for (int ch = 0; ch < 3; ++ch) c[ch] *= s;
     }
-    if (rgb32) {
-        rgb32[3 * p] = c[0];
-        rgb32[3 * p + 1] = c[1];
-        rgb32[3 * p + 2] = c[2];
+    if (io.rgb32[v]) {
+        float *o = io.rgb32[v];
+        o[3 * p] = c[0];
+        o[3 * p + 1] = c[1];
+        o[3 * p + 2] = c[2];
     }
-    if (rgba8) {
+    if (io.rgba8[v]) {
         uchar4 o;
         o.x = (uint8_t)floorf(fminf(fmaxf(c[0], 0.0f), 1.0f) * 255.0f + 0.5f);
         o.y = (uint8_t)floorf(fminf(fmaxf(c[1], 0.0f), 1.0f) * 255.0f + 0.5f);
         o.z = (uint8_t)floorf(fminf(fmaxf(c[2], 0.0f), 1.0f) * 255.0f + 0.5f);
         o.w = id >= 0 ? 255 : 0;
-        reinterpret_cast<uchar4 *>(rgba8)[p] = o;
+        reinterpret_cast<uchar4 *>(io.rgba8[v])[p] = o;
     }
 }
 
