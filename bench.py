@@ -92,6 +92,33 @@ def main():
     if os.path.exists(tpath):
         traffic = json.load(open(tpath)).get('bytes_per_launch')
 
+    # backward / forward on the differentiation workload (100,820 triangles,
+    # 512x512, rolling + foveated, moving camera): forward = bound + bin +
+    # raycast + shade (fp32 rgb), backward = pr_backward
+    gsc = scenegen.make_grad()
+    gr = Renderer(gsc.meshes, gsc.views, tile=args.tile, light=gsc.light_dir, ambient=gsc.ambient)
+    gr.frame(check=True)
+    dl = [torch.ones_like(gr.outputs[0]['rgb32'])]
+    for _ in range(3):
+        gr.frame(check=False)
+        gr.backward(dl)
+    nrep = max(10, args.steps)
+    f0, f1, b1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    fwd_ms, bwd_ms = [], []
+    for _ in range(nrep):
+        f0.record(stream)
+        gr.bound()
+        gr.bin()
+        gr.raycast()
+        gr.shade(rgba8=False, rgb32=True)
+        f1.record(stream)
+        gr.backward(dl)
+        b1.record(stream)
+        torch.cuda.synchronize()
+        fwd_ms.append(f0.elapsed_time(f1))
+        bwd_ms.append(f1.elapsed_time(b1))
+    fwd_med, bwd_med = float(np.median(fwd_ms)), float(np.median(bwd_ms))
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -131,6 +158,9 @@ def main():
         'tests_per_s': round(tests / (ray_ms_avg * 1e-3), 1),
         'ste': round(hits / max(tests, 1), 4),
         'pairs_per_frame': int(st.pairs_total),
+        'bwd_fwd': round(bwd_med / fwd_med, 3),
+        'grad_workload': {'triangles': int(gsc.meshes[0].nt), 'size': 512, 'fwd_ms': round(fwd_med, 4),
+                          'bwd_ms': round(bwd_med, 4)},
         'wall_s': round(wall, 3),
         'roofline': {'bound': 'alu', 'achieved': round(achieved, 3), 'peak': PEAK_FP32_TFLOPS,
                      'unit': 'TFLOP/s', 'frac': round(achieved / PEAK_FP32_TFLOPS, 4), 'traffic': traffic,

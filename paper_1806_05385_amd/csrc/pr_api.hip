@@ -23,9 +23,9 @@ size_t up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 struct Layout {
     int nv;
     ViewDev vd[PR_MAX_VIEWS];
-    int total_tiles, total_tri_blocks, total_pix_blocks, nparts;
-    int64_t cap, total_rec4, total_tris;
-    size_t table, tinfo, rec, tb, tcount, toff, part, pairs, lists, bytes;
+    int total_tiles, total_tri_blocks, total_pix_blocks, total_vtx_blocks, nparts;
+    int64_t cap, total_rec4, total_tris, total_gacc;
+    size_t table, tinfo, rec, tb, tcount, toff, part, pairs, lists, gacc, pacc, bytes;
 };
 
 bool finite_all(const float *p, int n) {
@@ -86,7 +86,7 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     int rc = check_args(meshes, nm, views, nv, tu);
     if (rc) return rc;
     L.nv = nv;
-    int64_t tiles = 0, tri_blocks = 0, pix_blocks = 0, rec4 = 0, tris = 0;
+    int64_t tiles = 0, tri_blocks = 0, pix_blocks = 0, vtx_blocks = 0, rec4 = 0, tris = 0, gacc = 0;
     for (int v = 0; v < nv; ++v) {
         const pr_view &V = views[v];
         const pr_mesh &M = meshes[V.mesh];
@@ -106,13 +106,21 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
         d.rec_w = d.rolling ? kRecRoll : kRecStatic;
         d.rec_off = rec4;
         d.tri_off = tris;
+        d.vtx_block0 = (int32_t)vtx_blocks;
+        d.gacc_off = gacc;
+        vtx_blocks += (M.nv + 255) / 256;
+        gacc += 6 * (int64_t)M.nv;
         tiles += d.ntiles;
         tri_blocks += (M.nt + 255) / 256;
         pix_blocks += ((int64_t)V.width * V.height + 255) / 256;
         rec4 += (int64_t)M.nt * d.rec_w;
         tris += M.nt;
     }
-    if (tiles + 1 > INT32_MAX / 2 || tri_blocks > INT32_MAX / 2 || pix_blocks > INT32_MAX / 2) return PR_ERR_INVALID;
+    if (tiles + 1 > INT32_MAX / 2 || tri_blocks > INT32_MAX / 2 || pix_blocks > INT32_MAX / 2 ||
+        vtx_blocks > INT32_MAX / 2)
+        return PR_ERR_INVALID;
+    L.total_vtx_blocks = (int)vtx_blocks;
+    L.total_gacc = gacc;
     L.total_tiles = (int)tiles;
     L.total_tri_blocks = (int)tri_blocks;
     L.total_pix_blocks = (int)pix_blocks;
@@ -130,6 +138,8 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     L.part = off; off = up(off + (size_t)L.nparts * 4);
     L.pairs = off; off = up(off + (size_t)L.cap * sizeof(Pair));
     L.lists = off; off = up(off + (size_t)L.cap * 4);
+    L.gacc = off; off = up(off + (size_t)gacc * 4);
+    L.pacc = off; off = up(off + (size_t)PR_MAX_VIEWS * kPoseAcc * 8);
     L.bytes = off;
     return PR_OK;
 }
@@ -202,6 +212,7 @@ int pr_bound(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const 
         p.total_tiles = L.total_tiles;
         p.total_tri_blocks = L.total_tri_blocks;
         p.total_pix_blocks = L.total_pix_blocks;
+        p.total_vtx_blocks = L.total_vtx_blocks;
         for (int i = 0; i < p.count; ++i) p.v[i] = L.vd[first + i];
         hipLaunchKernelGGL(k_write_views, dim3(1), dim3(64), 0, s, p, T);
     }
@@ -286,9 +297,46 @@ int pr_backward(const pr_mesh *meshes, int nm, const pr_view *views, int nv, con
                 size_t ws_bytes, const int32_t *const *tri_id, const pr_light *light, const float *const *albedo,
                 const float *const *dl_drgb, float *const *dv0, float *const *dv1, float *dpose0, float *dpose1,
                 void *stream) {
-    (void)meshes; (void)nm; (void)views; (void)nv; (void)tuning; (void)ws; (void)ws_bytes; (void)tri_id;
-    (void)light; (void)albedo; (void)dl_drgb; (void)dv0; (void)dv1; (void)dpose0; (void)dpose1; (void)stream;
-    return PR_ERR_UNSUPPORTED;
+    if (!tri_id || !light || !albedo || !dl_drgb || !dv0 || !dv1 || !dpose0 || !dpose1) return PR_ERR_INVALID;
+    if (!isfinite(light->ambient) || !isfinite(light->dir_world[0]) || !isfinite(light->dir_world[1]) ||
+        !isfinite(light->dir_world[2]))
+        return PR_ERR_INVALID;
+    if (!views || !meshes || nv < 1 || nv > PR_MAX_VIEWS || nm < 1 || nm > PR_MAX_VIEWS) return PR_ERR_INVALID;
+    for (int v = 0; v < nv; ++v) {
+        if (!tri_id[v] || !dl_drgb[v]) return PR_ERR_INVALID;
+        int m = views[v].mesh;
+        if (m < 0 || m >= nm) return PR_ERR_INVALID;
+        if (meshes[m].nv > 0 && (!dv0[m] || !dv1[m] || (meshes[m].nt > 0 && !albedo[m]))) return PR_ERR_INVALID;
+    }
+    PR_PREP();
+    BwdIO io;
+    BwdOut out;
+    memset(&io, 0, sizeof(io));
+    memset(&out, 0, sizeof(out));
+    for (int v = 0; v < nv; ++v) {
+        io.id[v] = tri_id[v];
+        io.dl[v] = dl_drgb[v];
+        io.albedo[v] = albedo[views[v].mesh];
+    }
+    bool used[PR_MAX_VIEWS] = {false};
+    for (int v = 0; v < nv; ++v) used[views[v].mesh] = true;
+    for (int m = 0; m < nm; ++m) {
+        out.dv0[m] = dv0[m];
+        out.dv1[m] = dv1[m];
+        if (used[m] && meshes[m].nv > 0) {
+            fill_u32(dv0[m], 0u, 3 * (int64_t)meshes[m].nv, s);
+            fill_u32(dv1[m], 0u, 3 * (int64_t)meshes[m].nv, s);
+        }
+    }
+    fill_u32(at<void>(ws, L.gacc), 0u, L.total_gacc, s);
+    fill_u32(at<void>(ws, L.pacc), 0u, (int64_t)PR_MAX_VIEWS * kPoseAcc * 2, s);
+    hipLaunchKernelGGL(k_view_light, dim3(1), dim3(64), 0, s, T, *light);
+    hipLaunchKernelGGL(k_bwd_pixel, dim3(L.total_pix_blocks), dim3(256), 0, s, T, io, light->ambient,
+                       at<float>(ws, L.gacc), at<double>(ws, L.pacc));
+    if (L.total_vtx_blocks > 0)
+        hipLaunchKernelGGL(k_bwd_vertex, dim3(L.total_vtx_blocks), dim3(256), 0, s, T, at<float>(ws, L.gacc), out);
+    hipLaunchKernelGGL(k_bwd_pose, dim3(1), dim3(64), 0, s, T, at<double>(ws, L.pacc), *light, dpose0, dpose1);
+    return launched();
 }
 
 int pr_status_read(const void *ws, size_t ws_bytes, pr_status *out, void *stream) {

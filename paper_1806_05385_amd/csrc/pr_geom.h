@@ -55,6 +55,51 @@ PRG void rodrigues(const float *wf, double R[9]) {
         }
 }
 
+// dR/dw_i of Rodrigues' formula, dR[9 i + 3 r + c] (Gallego & Yezzi,
+// "A compact formula for the derivative of a 3-D rotation in exponential
+// coordinates", 2015):  dR/dw_i = (w_i [w]x + [w x ((I - R) e_i)]x) R / |w|^2,
+// and [e_i]x + ([e_i]x [w]x + [w]x [e_i]x) / 2 for |w| < 1e-6.
+PRG void rodrigues_jac(const float *wf, double dR[27]) {
+    double w[3] = {wf[0], wf[1], wf[2]};
+    double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    double R[9];
+    rodrigues(wf, R);
+    auto skew = [](const double v[3], double S[9]) {
+        S[0] = 0; S[1] = -v[2]; S[2] = v[1];
+        S[3] = v[2]; S[4] = 0; S[5] = -v[0];
+        S[6] = -v[1]; S[7] = v[0]; S[8] = 0;
+    };
+    double W[9];
+    skew(w, W);
+    for (int i = 0; i < 3; ++i) {
+        double e[3] = {0, 0, 0};
+        e[i] = 1.0;
+        double Ei[9];
+        skew(e, Ei);
+        double *o = dR + 9 * i;
+        if (th2 < 1e-12) {
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) {
+                    double s = 0;
+                    for (int k = 0; k < 3; ++k) s += Ei[3 * r + k] * W[3 * k + c] + W[3 * r + k] * Ei[3 * k + c];
+                    o[3 * r + c] = Ei[3 * r + c] + 0.5 * s;
+                }
+        } else {
+            double u[3] = {e[0] - R[i], e[1] - R[3 + i], e[2] - R[6 + i]};   // (I - R) e_i
+            double x[3] = {w[1] * u[2] - w[2] * u[1], w[2] * u[0] - w[0] * u[2], w[0] * u[1] - w[1] * u[0]};
+            double X[9], M[9];
+            skew(x, X);
+            for (int k = 0; k < 9; ++k) M[k] = (w[i] * W[k] + X[k]) / th2;
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) {
+                    double s = 0;
+                    for (int k = 0; k < 3; ++k) s += M[3 * r + k] * R[3 * k + c];
+                    o[3 * r + c] = s;
+                }
+        }
+    }
+}
+
 // Distance from the fovea to the farthest image corner.
 PRG double fovea_radius(double f0, double f1) {
     double ex = fabs(f0) + 1.0, ey = fabs(f1) + 1.0;

@@ -63,24 +63,35 @@ struct ViewDev {
     int32_t pad;
     int64_t rec_off;       // float4 offset of the view's first record
     int64_t tri_off;       // TriBound index of the view's first triangle
-    float light0[3];       // R0 * light direction (written by pr_shade)
+    int32_t vtx_block0;    // first 256-vertex block (backward vertex pass)
+    int32_t pad2;
+    int64_t gacc_off;      // float offset of the view's backward accumulators [2][nv][3]
+    float light0[3];       // R0 * light direction (written by pr_shade / pr_backward)
     float light1[3];       // R1 * light direction
+    float R0f[9], T0f[3], R1f[9], T1f[3];   // FP32 copies of the poses (backward)
     prg::Geom g;           // FP64 camera geometry (written by k_write_views)
 };
+
+// Per-view backward partial sums (FP64): [0..2] sum (1-t) dL/dLw,
+// [3..5] sum t dL/dLw (light direction before normalisation), [6..8] dL/dT0,
+// [9..17] dL/dR0 (vertex part), [18..20] dL/dT1, [21..29] dL/dR1, 2 pad.
+constexpr int kPoseAcc = 32;
 
 struct ViewTable {
     int32_t nv, total_tiles, total_tri_blocks, total_pix_blocks;
     int32_t tri_block0[PR_MAX_VIEWS + 1];
     int32_t tile_base[PR_MAX_VIEWS + 1];
     int32_t pix_block0[PR_MAX_VIEWS + 1];
-    int32_t pad;
+    int32_t vtx_block0[PR_MAX_VIEWS + 1];
+    int32_t total_vtx_blocks;
+    int32_t pad[2];
     ViewDev v[PR_MAX_VIEWS];
 };
 
 // Views written per k_write_views launch (kernel-argument size).
 constexpr int kViewsPerWrite = 2;
 struct ViewPack {
-    int32_t first, count, nv, total_tiles, total_tri_blocks, total_pix_blocks;
+    int32_t first, count, nv, total_tiles, total_tri_blocks, total_pix_blocks, total_vtx_blocks, pad;
     ViewDev v[kViewsPerWrite];
 };
 
@@ -106,6 +117,16 @@ struct ShadeIO {
     uint8_t *rgba8[PR_MAX_VIEWS];
     float *rgb32[PR_MAX_VIEWS];
     const float *albedo[PR_MAX_VIEWS];   // per view (the albedo of its mesh)
+};
+
+struct BwdIO {
+    const int32_t *id[PR_MAX_VIEWS];
+    const float *dl[PR_MAX_VIEWS];       // dL/drgb [H][W][3]
+    const float *albedo[PR_MAX_VIEWS];   // per view (the albedo of its mesh)
+};
+struct BwdOut {
+    float *dv0[PR_MAX_VIEWS];            // per mesh
+    float *dv1[PR_MAX_VIEWS];
 };
 
 }  // namespace prk

@@ -91,8 +91,12 @@ __global__ void k_write_views(ViewPack p, ViewTable *__restrict__ T) {
     int i = threadIdx.x;
     if (i < p.count) {
         const ViewDev &v = p.v[i];
-        T->v[p.first + i] = v;
-        prg::make_geom(v.view, T->v[p.first + i].g);
+        ViewDev &d = T->v[p.first + i];
+        d = v;
+        prg::make_geom(v.view, d.g);
+        for (int q = 0; q < 9; ++q) { d.R0f[q] = (float)d.g.R0[q]; d.R1f[q] = (float)d.g.R1[q]; }
+        for (int q = 0; q < 3; ++q) { d.T0f[q] = (float)d.g.T0[q]; d.T1f[q] = (float)d.g.T1[q]; }
+        T->vtx_block0[p.first + i] = v.vtx_block0;
         T->tri_block0[p.first + i] = v.tri_block0;
         T->tile_base[p.first + i] = v.tile_base;
         T->pix_block0[p.first + i] = v.pix_block0;
@@ -102,6 +106,8 @@ __global__ void k_write_views(ViewPack p, ViewTable *__restrict__ T) {
         T->total_tiles = p.total_tiles;
         T->total_tri_blocks = p.total_tri_blocks;
         T->total_pix_blocks = p.total_pix_blocks;
+        T->total_vtx_blocks = p.total_vtx_blocks;
+        T->vtx_block0[p.nv] = p.total_vtx_blocks;
         T->tri_block0[p.nv] = p.total_tri_blocks;
         T->tile_base[p.nv] = p.total_tiles;
         T->pix_block0[p.nv] = p.total_pix_blocks;
@@ -714,6 +720,227 @@ __global__ __launch_bounds__(256) void k_shade(const ViewTable *__restrict__ T, 
         o.z = (uint8_t)floorf(fminf(fmaxf(c[2], 0.0f), 1.0f) * 255.0f + 0.5f);
         o.w = id >= 0 ? 255 : 0;
         reinterpret_cast<uchar4 *>(io.rgba8[v])[p] = o;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward: gradient of a loss of the shaded image with visibility fixed
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cross3f(const float a[3], const float b[3], float o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ __forceinline__ float dot3f(const float a[3], const float b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+__device__ __forceinline__ float wave_sum(float x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ __forceinline__ void cross3d(const double a[3], const double b[3], double o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// FP64 pixel setup (the backward is per pixel, not per test, so it can
+// afford it): foveated sample -> display point -> time -> ray.
+__device__ __forceinline__ void pixel_setup_d(const prg::Geom &g, int px, int py, double &t, double r[3]) {
+    double y0 = (2.0 * px + 1.0) / g.W - 1.0, y1 = 1.0 - (2.0 * py + 1.0) / g.H;
+    double x0, x1;
+    prg::radial_map(g, g.alpha, y0, y1, x0, x1);
+    double u = 0.5 * (g.roll[0] * (x0 + 1.0) + g.roll[1] * (x1 + 1.0));
+    t = prg::clamp01(u);
+    r[0] = (x0 - g.cx) / g.fx;
+    r[1] = (x1 - g.cy) / g.fy;
+    r[2] = 1.0;
+}
+
+// Per pixel: the shading chain c = (sum_k mu_k a_k) (k_a + (1-k_a) max(0,
+// n.l)) taken back through the barycentrics mu_k = e_k / S (e_1 = r.(P2 x
+// P0), e_2 = r.(P0 x P1), mu_0 = 1 - mu_1 - mu_2), the face normal n, the
+// rolling light l(t) and the camera-space interpolation P_k(t) =
+// (1-t) Ps_k + t Pe_k.  Writes dL/dPs, dL/dPe per vertex (FP32 atomics) and
+// the view's pose and light partial sums (FP64).  The geometry is FP64: near
+// grazing incidence (ray almost in the triangle's plane) the barycentric
+// terms scale like 1/S^2 and FP32 rounding of the ray alone would move
+// them by 2^-24 / cos(incidence).
+__global__ __launch_bounds__(256) void k_bwd_pixel(const ViewTable *__restrict__ T, BwdIO io, float ka,
+                                                   float *__restrict__ gacc, double *__restrict__ pacc) {
+    const int v = find_view(T->pix_block0, T->nv, blockIdx.x);
+    const ViewDev &vd = T->v[v];
+    const prg::Geom &g = vd.g;
+    const PixelConst &pc = vd.pc;
+    int64_t p = (int64_t)(blockIdx.x - vd.pix_block0) * 256 + threadIdx.x;
+    double part[30];
+    for (int q = 0; q < 30; ++q) part[q] = 0.0;
+    int id = p < (int64_t)pc.W * pc.H ? io.id[v][p] : -1;
+    if (id >= vd.mesh.nt) id = -1;
+    if (id >= 0) {
+        int px = (int)(p % pc.W), py = (int)(p / pc.W);
+        double t, r[3];
+        pixel_setup_d(g, px, py, t, r);
+        // base vertex P0 and edges E1 = P1 - P0, E2 = P2 - P0 at time t, the
+        // edges from exact world-space differences
+        int vi[3];
+        for (int k = 0; k < 3; ++k) vi[k] = vd.mesh.tri[3 * (int64_t)id + k];
+        double a0[3], b0[3], ds[2][3], de[2][3];
+        for (int q = 0; q < 3; ++q) {
+            a0[q] = vd.mesh.v0[3 * (int64_t)vi[0] + q];
+            b0[q] = vd.mesh.v1[3 * (int64_t)vi[0] + q];
+        }
+        for (int k = 1; k < 3; ++k)
+            for (int q = 0; q < 3; ++q) {
+                ds[k - 1][q] = (double)vd.mesh.v0[3 * (int64_t)vi[k] + q] - a0[q];
+                de[k - 1][q] = (double)vd.mesh.v1[3 * (int64_t)vi[k] + q] - b0[q];
+            }
+        double P0[3], E1[3], E2[3];
+        for (int q = 0; q < 3; ++q) {
+            const double *R0 = g.R0 + 3 * q, *R1 = g.R1 + 3 * q;
+            double ps = R0[0] * a0[0] + R0[1] * a0[1] + R0[2] * a0[2] + g.T0[q];
+            double pe = R1[0] * b0[0] + R1[1] * b0[1] + R1[2] * b0[2] + g.T1[q];
+            P0[q] = (1.0 - t) * ps + t * pe;
+            double s1 = R0[0] * ds[0][0] + R0[1] * ds[0][1] + R0[2] * ds[0][2];
+            double e1 = R1[0] * de[0][0] + R1[1] * de[0][1] + R1[2] * de[0][2];
+            double s2 = R0[0] * ds[1][0] + R0[1] * ds[1][1] + R0[2] * ds[1][2];
+            double e2 = R1[0] * de[1][0] + R1[1] * de[1][1] + R1[2] * de[1][2];
+            E1[q] = (1.0 - t) * s1 + t * e1;
+            E2[q] = (1.0 - t) * s2 + t * e2;
+        }
+        // forward: N = E1 x E2, S = r.N, e1 = r.(E2 x P0), e2 = r.(P0 x E1)
+        double N[3], x1[3], x2[3];
+        cross3d(E1, E2, N);
+        cross3d(E2, P0, x1);
+        cross3d(P0, E1, x2);
+        auto dot = [](const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+        const double S = dot(r, N);
+        const double mu1 = dot(r, x1) / S, mu2 = dot(r, x2) / S;
+        const double nn = sqrt(dot(N, N));
+        double m[3] = {N[0] / nn, N[1] / nn, N[2] / nn};
+        const double sg = dot(m, r) > 0.0 ? -1.0 : 1.0;
+        double n[3] = {sg * m[0], sg * m[1], sg * m[2]};
+        double Lw[3];
+        for (int q = 0; q < 3; ++q) Lw[q] = (1.0 - t) * vd.light0[q] + t * vd.light1[q];
+        const double ln = sqrt(dot(Lw, Lw));
+        double l[3] = {Lw[0] / ln, Lw[1] / ln, Lw[2] / ln};
+        const double ndl = dot(n, l);
+        const double s = ka + (1.0 - ka) * (ndl > 0.0 ? ndl : 0.0);
+        const float *alb = io.albedo[v];
+        double al0[3], d1a[3], d2a[3], a[3];
+        for (int ch = 0; ch < 3; ++ch) {
+            al0[ch] = alb[3 * (int64_t)vi[0] + ch];
+            d1a[ch] = alb[3 * (int64_t)vi[1] + ch] - al0[ch];
+            d2a[ch] = alb[3 * (int64_t)vi[2] + ch] - al0[ch];
+            a[ch] = al0[ch] + mu1 * d1a[ch] + mu2 * d2a[ch];   // a = sum_k mu_k a_k
+        }
+        // backward
+        const float *gcp = io.dl[v] + 3 * p;
+        double gc[3] = {gcp[0], gcp[1], gcp[2]};
+        const double gs = dot(gc, a);
+        double ga[3] = {gc[0] * s, gc[1] * s, gc[2] * s};
+        const double gmu1 = dot(ga, d1a), gmu2 = dot(ga, d2a);
+        const double gndl = ndl > 0.0 ? gs * (1.0 - ka) : 0.0;
+        double gm[3], gl[3];
+        for (int q = 0; q < 3; ++q) { gm[q] = sg * gndl * l[q]; gl[q] = gndl * n[q]; }
+        const double mg = dot(m, gm), lg = dot(l, gl);
+        const double ge1 = gmu1 / S, ge2 = gmu2 / S;
+        const double gS = -(gmu1 * mu1 + gmu2 * mu2) / S;
+        double gN[3];
+        for (int q = 0; q < 3; ++q) {
+            gN[q] = (gm[q] - m[q] * mg) / nn + gS * r[q];
+            const double gLw = (gl[q] - l[q] * lg) / ln;
+            part[q] = (1.0 - t) * gLw;
+            part[3 + q] = t * gLw;
+        }
+        double P0xr[3], rxP0[3], rxE2[3], E1xr[3], E2xgN[3], gNxE1[3];
+        cross3d(P0, r, P0xr);
+        cross3d(r, P0, rxP0);
+        cross3d(r, E2, rxE2);
+        cross3d(E1, r, E1xr);
+        cross3d(E2, gN, E2xgN);
+        cross3d(gN, E1, gNxE1);
+        double gP[3][3], gd[3];   // gd = sum_k gP_k (the translation part)
+        for (int q = 0; q < 3; ++q) {
+            const double gE1 = ge2 * rxP0[q] + E2xgN[q];
+            const double gE2 = ge1 * P0xr[q] + gNxE1[q];
+            gd[q] = ge1 * rxE2[q] + ge2 * E1xr[q];
+            gP[1][q] = gE1;
+            gP[2][q] = gE2;
+            gP[0][q] = gd[q] - gE1 - gE2;
+        }
+        float *gs_ = gacc + vd.gacc_off;
+        float *ge_ = gs_ + 3 * (int64_t)vd.mesh.nv;
+        for (int k = 0; k < 3; ++k)
+            for (int q = 0; q < 3; ++q) {
+                atomicAdd(&gs_[3 * (int64_t)vi[k] + q], (float)((1.0 - t) * gP[k][q]));
+                atomicAdd(&ge_[3 * (int64_t)vi[k] + q], (float)(t * gP[k][q]));
+            }
+        // Pose partials of this pixel: dL/dT = sum_k w gP_k = w gd and
+        // dL/dR = sum_k w gP_k v_k^T = w (gd v_0^T + gE1 (v_1 - v_0)^T +
+        // gE2 (v_2 - v_0)^T), w = 1-t (start) or t (end).
+        for (int e2 = 0; e2 < 2; ++e2) {
+            const double w = e2 ? t : 1.0 - t;
+            const double *v0p = e2 ? b0 : a0;
+            const double(*dd)[3] = e2 ? de : ds;
+            for (int rr = 0; rr < 3; ++rr) {
+                part[6 + 12 * e2 + rr] = w * gd[rr];
+                for (int c = 0; c < 3; ++c)
+                    part[6 + 12 * e2 + 3 + 3 * rr + c] =
+                        w * (gd[rr] * v0p[c] + gP[1][rr] * dd[0][c] + gP[2][rr] * dd[1][c]);
+            }
+        }
+    }
+    // pose and light partials: FP64 wave sums, one FP64 atomic per wave and value
+    for (int q = 0; q < 30; ++q) {
+        double x = part[q];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (__lane_id() == 0 && x != 0.0) atomicAdd(&pacc[kPoseAcc * v + q], x);
+    }
+}
+
+// Per vertex of each view: world-space gradients dv = R^T dP (accumulated
+// over the views sharing a mesh).
+__global__ __launch_bounds__(256) void k_bwd_vertex(const ViewTable *__restrict__ T, const float *__restrict__ gacc,
+                                                    BwdOut out) {
+    const int v = find_view(T->vtx_block0, T->nv, blockIdx.x);
+    const ViewDev &vd = T->v[v];
+    const int i = (blockIdx.x - vd.vtx_block0) * 256 + threadIdx.x;
+    if (i >= vd.mesh.nv) return;
+    const float *gs = gacc + vd.gacc_off + 3 * (int64_t)i;
+    const float *ge = gs + 3 * (int64_t)vd.mesh.nv;
+    float *o0 = out.dv0[vd.view.mesh] + 3 * (int64_t)i;
+    float *o1 = out.dv1[vd.view.mesh] + 3 * (int64_t)i;
+    for (int c = 0; c < 3; ++c) {
+        float d0 = vd.R0f[c] * gs[0] + vd.R0f[3 + c] * gs[1] + vd.R0f[6 + c] * gs[2];
+        float d1 = vd.R1f[c] * ge[0] + vd.R1f[3 + c] * ge[1] + vd.R1f[6 + c] * ge[2];
+        atomicAdd(&o0[c], d0);
+        atomicAdd(&o1[c], d1);
+    }
+}
+
+// Per view: dL/dR = vertex part + light part (sum (1-t) dL/dLw) l^T, then the
+// rotation-vector gradient through Rodrigues' Jacobian.
+__global__ void k_bwd_pose(const ViewTable *__restrict__ T, const double *__restrict__ pacc, pr_light light,
+                           float *__restrict__ dpose0, float *__restrict__ dpose1) {
+    const int v = threadIdx.x;
+    if (v >= T->nv) return;
+    const ViewDev &vd = T->v[v];
+    const double *a = pacc + kPoseAcc * v;
+    const double lw[3] = {light.dir_world[0], light.dir_world[1], light.dir_world[2]};
+    for (int e = 0; e < 2; ++e) {
+        double gR[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) gR[3 * r + c] = a[6 + 12 * e + 3 + 3 * r + c] + a[3 * e + r] * lw[c];
+        double J[27];
+        prg::rodrigues_jac(e ? vd.view.pose1 : vd.view.pose0, J);
+        float *o = (e ? dpose1 : dpose0) + 6 * v;
+        for (int i = 0; i < 3; ++i) {
+            double s = 0.0;
+            for (int q = 0; q < 9; ++q) s += gR[q] * J[9 * i + q];
+            o[i] = (float)s;
+            o[3 + i] = (float)a[6 + 12 * e + i];
+        }
     }
 }
 

@@ -2,6 +2,7 @@
 every computation runs in the library's kernels (include/pr.h)."""
 from __future__ import annotations
 
+import copy
 import ctypes
 from dataclasses import dataclass
 
@@ -52,7 +53,7 @@ class Renderer:
         self.L = B.lib()
         self.device = torch.device(device)
         self.meshes = [m if isinstance(m, DeviceMesh) else DeviceMesh.from_numpy(m, device) for m in meshes]
-        self.views = list(views)
+        self.views = [copy.copy(v) for v in views]
         self.tile = tile
         self.flags = flags
         if not bin_capacity:
@@ -105,6 +106,48 @@ class Renderer:
         B.check('pr_shade', self.L.pr_shade(*self._args(), idp, ctypes.byref(self.light), alb, o8, o32,
                                             ctypes.c_void_p(_stream_handle())))
 
+    def backward(self, dl_drgb, ids=None):
+        """pr_backward: dL/drgb per view (float32 [H,W,3] cuda) -> (dv0, dv1)
+        per mesh ([V,3] cuda) and (dpose0, dpose1) [n_views, 6] cuda, with
+        visibility fixed to ``ids`` (default: this frame's ids)."""
+        nv = len(self.views)
+        if ids is None:
+            ids = [o['id'] for o in self.outputs]
+        dl = [d.contiguous() for d in dl_drgb]
+        for d, v in zip(dl, self.views):
+            assert d.is_cuda and d.dtype == torch.float32 and tuple(d.shape) == (v.height, v.width, 3)
+        dv0 = [torch.empty_like(m.v0) for m in self.meshes]
+        dv1 = [torch.empty_like(m.v1) for m in self.meshes]
+        dp0 = torch.empty((nv, 6), dtype=torch.float32, device=self.device)
+        dp1 = torch.empty((nv, 6), dtype=torch.float32, device=self.device)
+        B.check('pr_backward', self.L.pr_backward(
+            *self._args(), B.ptr_array([i.data_ptr() for i in ids]), ctypes.byref(self.light),
+            B.ptr_array([m.albedo.data_ptr() for m in self.meshes]), B.ptr_array([d.data_ptr() for d in dl]),
+            B.ptr_array([x.data_ptr() for x in dv0]), B.ptr_array([x.data_ptr() for x in dv1]),
+            ctypes.c_void_p(dp0.data_ptr()), ctypes.c_void_p(dp1.data_ptr()), ctypes.c_void_p(_stream_handle())))
+        return dv0, dv1, dp0, dp1
+
+    def set_geometry(self, mesh: int, v0=None, v1=None):
+        """Point mesh ``mesh`` at new vertex tensors (float32 [V,3] cuda)."""
+        m = self.meshes[mesh]
+        if v0 is not None:
+            m.v0 = v0.detach().contiguous()
+        if v1 is not None:
+            m.v1 = v1.detach().contiguous()
+        self.c_meshes[mesh] = m.pr()
+
+    def set_poses(self, view: int, pose0=None, pose1=None):
+        """New world->view poses (6 floats: rotation vector, translation)."""
+        pv = self.c_views[view]
+        if pose0 is not None:
+            self.views[view].pose0 = [float(x) for x in pose0]
+            for k in range(6):
+                pv.pose0[k] = float(pose0[k])
+        if pose1 is not None:
+            self.views[view].pose1 = [float(x) for x in pose1]
+            for k in range(6):
+                pv.pose1[k] = float(pose1[k])
+
     def status(self) -> B.PrStatus:
         st = B.PrStatus()
         B.check('pr_status_read', self.L.pr_status_read(ctypes.c_void_p(self.ws_ptr), self.ws_bytes,
@@ -150,3 +193,34 @@ def render_scene(scene, tile: int = 16, shade: bool = True, flags: int = 0, devi
                  device=device)
     out = r.frame(shade=shade)
     return r, out
+
+
+class PerceptualRender(torch.autograd.Function):
+    """Differentiable rolling + foveated Lambert render of one mesh seen by
+    the renderer's views (all of one size).  Visibility (the triangle id of
+    every pixel) is held fixed in the backward pass.
+
+    forward(renderer, v0, v1, pose0, pose1) -> rgb [n_views, H, W, 3]
+      v0, v1: float32 [V, 3] cuda (world positions at the frame's start/end)
+      pose0, pose1: float32 [n_views, 6] (rotation vector, translation)
+    Gradients flow to v0, v1, pose0 and pose1 (same devices as the inputs)."""
+
+    @staticmethod
+    def forward(ctx, renderer, v0, v1, pose0, pose1):
+        renderer.set_geometry(0, v0, v1)
+        p0 = pose0.detach().cpu().tolist()
+        p1 = pose1.detach().cpu().tolist()
+        for i in range(len(renderer.views)):
+            renderer.set_poses(i, p0[i], p1[i])
+        out = renderer.frame(shade=True)
+        ctx.renderer = renderer
+        ctx.ids = [o['id'].clone() for o in out]
+        ctx.pose_devices = (pose0.device, pose1.device)
+        return torch.stack([o['rgb32'] for o in out]).clone()
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        r = ctx.renderer
+        dl = [grad_rgb[i].contiguous().float() for i in range(grad_rgb.shape[0])]
+        dv0, dv1, dp0, dp1 = r.backward(dl, ids=ctx.ids)
+        return None, dv0[0], dv1[0], dp0.to(ctx.pose_devices[0]), dp1.to(ctx.pose_devices[1])

@@ -1,0 +1,125 @@
+"""GPU backward (pr_backward, PerceptualRender) against the FP64 oracle's
+analytic frozen-visibility gradient of L = sum (c - c*)^2, itself pinned by
+central differences in test_oracle_pins.py.  Both sides use the oracle's
+visibility (its id buffer is handed to the GPU) and the same upstream
+gradient dL/dc = 2 (c - c*) with c the oracle's colours: near grazing
+incidence the barycentric terms scale like 1/S^2, so the few silhouette
+pixels whose FP32 forward colour differs from the FP64 one by ~1e-4 would
+otherwise move the pose sums by more than the backward's own error (the
+forward colours are checked separately, to 1 LSB in RGBA8).
+
+Tolerance: |g - g_ref| <= 1e-3 max(|g_ref|, 1e-3 max|g_ref|) per component,
+except for listed near-edge vertices: a vertex that receives a contribution
+from a pixel whose ray passes within 1e-4 rad of an edge plane of its
+triangle (normalised edge magnitude < 1e-4).  There the barycentric of the
+opposite vertex is tiny and rounding the ray to FP32 (2^-24) alone changes
+it by 2^-24 / ehat relative, so those vertices are checked at 5e-2."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-3
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail('no GPU visible')
+    return torch
+
+
+def _close(g, ref, floor_frac=1e-3):
+    """|g - ref| <= 1e-3 max(|ref|, 1e-3 max|ref|) componentwise."""
+    g = np.asarray(g, np.float64)
+    ref = np.asarray(ref, np.float64)
+    tol = REL * np.maximum(np.abs(ref), floor_frac * np.abs(ref).max())
+    bad = np.abs(g - ref) > tol
+    return bad, np.abs(g - ref) / np.maximum(np.abs(ref), 1e-30)
+
+
+def _case(size, f):
+    torch = _torch()
+    from paper_1806_05385_amd.render import Renderer
+    sc = scenegen.make_grad(seed=5, size=size, f=f)
+    mesh, view, target = sc.meshes[0], sc.views[0], sc.extra['target']
+    light = oracle.light_block(sc)
+    orc_t = oracle.Oracle(target, view)
+    tgt = orc_t.shade(orc_t.render()['id'], light)
+    orc = oracle.Oracle(mesh, view)
+    oid = orc.render()['id']
+    L, g0, g1, gp0, gp1 = orc.loss_grad(oid, light, tgt)
+    r = Renderer(sc.meshes, sc.views, tile=16, light=sc.light_dir, ambient=sc.ambient)
+    r.frame()
+    ids = torch.as_tensor(oid.reshape(view.height, view.width)).cuda()
+    r.shade(ids=[ids])
+    rgb = r.outputs[0]['rgb32']
+    tg = torch.as_tensor(tgt.reshape(view.height, view.width, 3), dtype=torch.float32).cuda()
+    c_ref = orc.shade(oid, light)
+    dl = torch.as_tensor(2.0 * (c_ref - tgt).reshape(view.height, view.width, 3), dtype=torch.float32).cuda()
+    dv0, dv1, dp0, dp1 = r.backward([dl], ids=[ids])
+    o = orc.render()
+    edge_px = (o['id'] >= 0) & (o['ehat'] < 1e-4)
+    near = np.zeros(mesh.nv, bool)
+    near[np.unique(mesh.tri[o['id'][edge_px]].ravel())] = True
+    return dict(L=L, g0=g0, g1=g1, gp0=gp0, gp1=gp1, dv0=dv0[0].cpu().numpy(), dv1=dv1[0].cpu().numpy(),
+                dp0=dp0[0].cpu().numpy(), dp1=dp1[0].cpu().numpy(), gpu_L=float(((rgb - tg) ** 2).sum()),
+                r=r, sc=sc, oid=oid, tgt=tgt, near=near)
+
+
+@pytest.mark.parametrize('size,f', [(96, 16), (512, 71)])
+def test_gradients_match_fp64_reference(size, f):
+    """(96, f=16): small; (512, f=71): the differentiation workload at full
+    size (100,820 triangles, 512x512, rolling + foveated, moving camera)."""
+    c = _case(size, f)
+    assert abs(c['gpu_L'] - c['L']) <= 1e-4 * c['L']
+    for name, g, ref in [('dv0', c['dv0'], c['g0']), ('dv1', c['dv1'], c['g1']),
+                         ('dpose0', c['dp0'], c['gp0']), ('dpose1', c['dp1'], c['gp1'])]:
+        bad, rel = _close(g, ref)
+        nz = np.abs(ref) > 1e-3 * np.abs(ref).max()
+        listed = 0
+        if name.startswith('dv'):
+            near = np.repeat(c['near'][:, None], 3, axis=1)
+            listed = int((bad & near).sum())
+            loose = np.abs(g - ref) <= 5e-2 * np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+            assert (loose | ~near).all(), (name, np.argwhere(near & ~loose)[:5])
+            bad = bad & ~near
+        print(f'\n{name}: {bad.sum()} of {bad.size} outside tolerance, {listed} listed near-edge; '
+              f'median rel err of significant components {np.median(rel[nz]):.2e}', flush=True)
+        assert np.abs(ref).max() > 0
+        assert not bad.any(), (name, np.argwhere(bad)[:5], g[bad][:5], ref[bad][:5])
+
+
+def test_autograd_function_matches_library_backward():
+    torch = _torch()
+    from paper_1806_05385_amd.render import PerceptualRender, Renderer
+    sc = scenegen.make_grad(seed=5, size=96, f=16)
+    r = Renderer(sc.meshes, sc.views, tile=16, light=sc.light_dir, ambient=sc.ambient)
+    m = r.meshes[0]
+    v0 = m.v0.clone().requires_grad_(True)
+    v1 = m.v1.clone().requires_grad_(True)
+    p0 = torch.tensor(np.array([sc.views[0].pose0]), dtype=torch.float32, requires_grad=True)
+    p1 = torch.tensor(np.array([sc.views[0].pose1]), dtype=torch.float32, requires_grad=True)
+    rgb = PerceptualRender.apply(r, v0, v1, p0, p1)
+    target = torch.rand(rgb.shape, generator=torch.Generator(device='cuda').manual_seed(0), device='cuda')
+    loss = ((rgb - target) ** 2).sum()
+    loss.backward()
+    dv0, dv1, dp0, dp1 = r.backward([2.0 * (rgb[0].detach() - target[0])], ids=[r.outputs[0]['id']])
+    # two runs differ only in the order of FP32 atomic additions
+    for g, ref in [(v0.grad, dv0[0]), (v1.grad, dv1[0]), (p0.grad, dp0.cpu()), (p1.grad, dp1.cpu())]:
+        assert torch.allclose(g, ref, rtol=1e-4, atol=1e-5 * float(ref.abs().max()))
+    assert p0.grad.abs().max() > 0 and v0.grad.abs().max() > 0
+
+
+def test_translation_identity_on_device():
+    """sum_v dL/dv0_v = R0^T dL/dT0 holds for the device gradients too."""
+    c = _case(96, 16)
+    from scipy.spatial.transform import Rotation
+    v = c['sc'].views[0]
+    R0 = Rotation.from_rotvec(np.asarray(v.pose0[:3], np.float64)).as_matrix()
+    lhs = c['dv0'].astype(np.float64).sum(0)
+    rhs = R0.T @ c['dp0'][3:].astype(np.float64)
+    assert np.abs(lhs - rhs).max() <= 1e-4 * np.abs(rhs).max()
