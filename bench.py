@@ -119,6 +119,56 @@ def main():
         bwd_ms.append(f1.elapsed_time(b1))
     fwd_med, bwd_med = float(np.median(fwd_ms)), float(np.median(bwd_ms))
 
+    # batched form: 64 views (log-uniform 128..2048 px, 1k..500k triangles)
+    # in one autotuned hipGraph frame vs 64 sequential plain frames
+    from paper_1806_05385_amd.render import Batch
+    bsc = scenegen.make_batch()
+    torch.cuda.synchronize()
+    bt = Batch(bsc.meshes, bsc.views, tile=0, light=bsc.light_dir, ambient=bsc.ambient, rgba8=True)
+    binfo = bt.info()
+    for _ in range(2):
+        bt.launch()
+    nb = max(5, args.steps // 5)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(nb):
+        bt.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1) / nb
+    assert not bt.status().overflow
+    seq = []
+    for v in bsc.views:
+        vv = scenegen.View(**{**v.__dict__, 'mesh': 0})
+        rr = Renderer([bt.meshes[v.mesh]], [vv], tile=binfo['tile'], light=bsc.light_dir, ambient=bsc.ambient)
+        rr.frame(check=True)
+        seq.append(rr)
+
+    def seq_round():
+        for rr in seq:
+            rr.bound()
+            rr.bin()
+            rr.raycast()
+            rr.shade(rgba8=True, rgb32=False)
+    seq_round()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(nb):
+        seq_round()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1) / nb
+    n_views = len(bsc.views)
+    batch_out = {'views': n_views, 'pixels': int(sum(v.width * v.height for v in bsc.views)),
+                 'triangles': int(sum(bsc.meshes[v.mesh].nt for v in bsc.views)), 'tile': binfo['tile'],
+                 'trial_ms': binfo['trial_ms'], 'batched_ms': round(batch_ms, 4), 'sequential_ms': round(seq_ms, 4),
+                 'batched_views_per_s': round(n_views / (batch_ms * 1e-3), 1),
+                 'sequential_views_per_s': round(n_views / (seq_ms * 1e-3), 1),
+                 'speedup': round(seq_ms / batch_ms, 3)}
+    bt.close()
+    del seq
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -159,6 +209,7 @@ def main():
         'ste': round(hits / max(tests, 1), 4),
         'pairs_per_frame': int(st.pairs_total),
         'bwd_fwd': round(bwd_med / fwd_med, 3),
+        'batch': batch_out,
         'grad_workload': {'triangles': int(gsc.meshes[0].nt), 'size': 512, 'fwd_ms': round(fwd_med, 4),
                           'bwd_ms': round(bwd_med, 4)},
         'wall_s': round(wall, 3),

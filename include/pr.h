@@ -125,7 +125,9 @@ typedef struct pr_light {
 /* tile: square tile side in pixels, one of 8, 16, 32.
  * bin_capacity: (triangle, tile) pairs each view's tile lists can hold.
  * flags: PR_FLAG_COUNT makes pr_raycast count ray-triangle tests and hits
- * (sample test efficiency) into the status block. */
+ * (sample test efficiency) into the status block; PR_FLAG_PERSISTENT makes
+ * it order the tiles longest list first and run one resident grid that
+ * pulls tiles from a device-wide queue (the batched form). */
 typedef struct pr_tuning {
     int32_t tile;
     int32_t bin_capacity;
@@ -134,6 +136,7 @@ typedef struct pr_tuning {
 } pr_tuning;
 
 #define PR_FLAG_COUNT 1
+#define PR_FLAG_PERSISTENT 2
 
 /* Device-side conditions of the last frame (all views). */
 typedef struct pr_status {
@@ -194,6 +197,39 @@ int pr_backward(const pr_mesh *meshes, int nm, const pr_view *views, int nv, con
                 void *ws, size_t ws_bytes, const int32_t *const *tri_id, const pr_light *light,
                 const float *const *albedo, const float *const *dl_drgb, float *const *dv0,
                 float *const *dv1, float *dpose0, float *dpose1, void *stream);
+
+/* BATCHED FORM.  A batch renders many views (eyes, frames, scenes) of
+ * uneven size and triangle count as one frame: every pass is one launch over
+ * all views, the ray cast is one resident grid pulling (view, tile) items
+ * longest-first from a device queue, and the whole frame (bound, bin,
+ * raycast, shade) is captured once into a hipGraph that pr_batch_launch
+ * replays.
+ *
+ * pr_batch_create: meshes / views / light / albedo / outputs as for the
+ * per-call functions (device pointers; outputs tri_id and depth required,
+ * rgba8 and rgb32 may be NULL or hold NULL entries); they are bound into the
+ * graph, so their contents may change between launches but not their
+ * addresses, sizes or the views' parameters.  tuning->tile = 0 picks the
+ * tile size (8, 16, 32) by timed trial frames; tuning->bin_capacity = 0
+ * sizes the tile lists from a counting frame.  If the environment variable
+ * PR_TUNE_CACHE names a file, choices are read from and appended to it,
+ * keyed by device, view count and size classes.  The batch owns its
+ * workspace (allocated here), a private capture stream and the graph until
+ * pr_batch_destroy.  Synchronises the device while tuning.  Returns PR_OK
+ * and *out, or a negative code (nothing allocated). */
+typedef struct pr_batch pr_batch;
+int pr_batch_create(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
+                    const pr_light *light, const float *const *albedo, int32_t *const *tri_id, float *const *depth,
+                    uint8_t *const *rgba8, float *const *rgb32, pr_batch **out);
+/* Enqueues one frame of the batch on `stream`. */
+int pr_batch_launch(pr_batch *batch, void *stream);
+/* The tuning chosen, workspace bytes and the trial frame times (ms) for
+ * tiles 8, 16, 32 (0 where not tried).  Any pointer may be NULL. */
+int pr_batch_info(const pr_batch *batch, pr_tuning *chosen, size_t *ws_bytes, double *trial_ms);
+/* pr_status_read on the batch's workspace (synchronises `stream`). */
+int pr_batch_status(const pr_batch *batch, pr_status *out, void *stream);
+/* Frees everything the batch owns.  NULL is allowed. */
+int pr_batch_destroy(pr_batch *batch);
 
 /* Waits for `stream`, copies the workspace's status block into *out.
  * Returns PR_OK, PR_ERR_INVALID or PR_ERR_HIP. */

@@ -16,6 +16,7 @@ PR_ERR_WORKSPACE = -3
 PR_ERR_HIP = -4
 PR_MAX_VIEWS = 64
 PR_FLAG_COUNT = 1
+PR_FLAG_PERSISTENT = 2
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
 c_int32_p = ctypes.POINTER(ctypes.c_int32)
@@ -71,6 +72,13 @@ SIGNATURES = {
     'pr_debug_tile_lists': (ctypes.c_int, _FRAME[:5] + [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, c_int32_p,
                                                          c_int32_p, ctypes.c_int64, c_int32_p,
                                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    'pr_batch_create': (ctypes.c_int, [_MP, ctypes.c_int, _VP, ctypes.c_int, _TP, ctypes.POINTER(PrLight), _PP, _PP,
+                                       _PP, _PP, _PP, ctypes.POINTER(ctypes.c_void_p)]),
+    'pr_batch_launch': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    'pr_batch_info': (ctypes.c_int, [ctypes.c_void_p, _TP, ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.POINTER(ctypes.c_double)]),
+    'pr_batch_status': (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PrStatus), ctypes.c_void_p]),
+    'pr_batch_destroy': (ctypes.c_int, [ctypes.c_void_p]),
     'pr_host_time_interval': (ctypes.c_int, [_MP, ctypes.c_int32, _VP, ctypes.POINTER(ctypes.c_double)]),
     'pr_host_tile_rect': (ctypes.c_int, [_MP, ctypes.c_int32, _VP, ctypes.c_int32, c_int32_p]),
     'pr_host_tile_test': (ctypes.c_int, [_MP, ctypes.c_int32, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),

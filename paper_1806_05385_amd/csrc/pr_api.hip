@@ -7,6 +7,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
+#include <vector>
 
 #include "pr.h"
 #include "pr_kernels.hip"
@@ -25,7 +29,7 @@ struct Layout {
     ViewDev vd[PR_MAX_VIEWS];
     int total_tiles, total_tri_blocks, total_pix_blocks, total_vtx_blocks, nparts;
     int64_t cap, total_rec4, total_tris, total_gacc;
-    size_t table, tinfo, rec, tb, tcount, toff, part, pairs, lists, gacc, pacc, bytes;
+    size_t table, tinfo, rec, tb, tcount, toff, part, pairs, lists, gacc, pacc, sched, order, bytes;
 };
 
 bool finite_all(const float *p, int n) {
@@ -140,6 +144,8 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     L.lists = off; off = up(off + (size_t)L.cap * 4);
     L.gacc = off; off = up(off + (size_t)gacc * 4);
     L.pacc = off; off = up(off + (size_t)PR_MAX_VIEWS * kPoseAcc * 8);
+    L.sched = off; off = up(off + sizeof(Sched));
+    L.order = off; off = up(off + (size_t)tiles * 4);
     L.bytes = off;
     return PR_OK;
 }
@@ -173,16 +179,46 @@ void fill_u32(void *p, uint32_t v, int64_t n, hipStream_t s) {
     DevStatus *st = at<DevStatus>(ws, 0);                                 \
     ViewTable *T = at<ViewTable>(ws, L.table);
 
+// Blocks of a kernel the whole device keeps resident (persistent grids).
+template <typename K>
+int resident_blocks(K kernel, int threads) {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 1024;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return per_cu * prop.multiProcessorCount;
+}
+
+template <int TILE, bool COUNT>
+void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, DevStatus *st, ViewTable *T,
+                      hipStream_t s) {
+    using C = RayCfg<TILE>;
+    if (!(flags & PR_FLAG_PERSISTENT)) {
+        hipLaunchKernelGGL((k_raycast<TILE, COUNT>), dim3(L.total_tiles), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
+                           at<uint32_t>(ws, L.toff), at<int32_t>(ws, L.lists), out, st);
+        return;
+    }
+    Sched *S = at<Sched>(ws, L.sched);
+    const int nb = (L.total_tiles + 255) / 256;
+    fill_u32(S, 0u, (int64_t)(sizeof(Sched) / 4), s);
+    hipLaunchKernelGGL(k_sched_count, dim3(nb), dim3(256), 0, s, at<uint32_t>(ws, L.toff), L.total_tiles, S);
+    hipLaunchKernelGGL(k_sched_base, dim3(1), dim3(64), 0, s, S);
+    hipLaunchKernelGGL(k_sched_scatter, dim3(nb), dim3(256), 0, s, at<uint32_t>(ws, L.toff), L.total_tiles, S,
+                       at<int32_t>(ws, L.order));
+    static int resident = 0;
+    if (!resident) resident = resident_blocks(k_raycast_queue<TILE, COUNT>, C::NT);
+    const int grid = std::max(1, std::min(L.total_tiles, resident));
+    hipLaunchKernelGGL((k_raycast_queue<TILE, COUNT>), dim3(grid), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
+                       at<uint32_t>(ws, L.toff), at<int32_t>(ws, L.lists), out, st, at<int32_t>(ws, L.order),
+                       L.total_tiles, S);
+}
+
 template <int TILE>
 void launch_raycast(int flags, const Layout &L, void *ws, const RayOut &out, DevStatus *st, ViewTable *T,
                     hipStream_t s) {
-    using C = RayCfg<TILE>;
-    if (flags & PR_FLAG_COUNT)
-        hipLaunchKernelGGL((k_raycast<TILE, true>), dim3(L.total_tiles), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
-                           at<uint32_t>(ws, L.toff), at<int32_t>(ws, L.lists), out, st);
-    else
-        hipLaunchKernelGGL((k_raycast<TILE, false>), dim3(L.total_tiles), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
-                           at<uint32_t>(ws, L.toff), at<int32_t>(ws, L.lists), out, st);
+    if (flags & PR_FLAG_COUNT) launch_raycast_t<TILE, true>(flags, L, ws, out, st, T, s);
+    else launch_raycast_t<TILE, false>(flags, L, ws, out, st, T, s);
 }
 
 }  // namespace
@@ -445,6 +481,270 @@ int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32
     if (kind == prg::kWindow) { w[0] = win[0]; w[1] = win[1]; w[2] = w[3] = 0.0; }
     else for (int k = 0; k < 4; ++k) w[k] = box[k];
     return prg::tile_test(g, Ps, Pe, kind, w, w, tile, tx, ty) ? 1 : 0;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched form: hipGraph of one frame over all views, autotuned
+// ---------------------------------------------------------------------------
+struct pr_batch {
+    std::vector<pr_mesh> meshes;
+    std::vector<pr_view> views;
+    pr_tuning tuning;
+    pr_light light;
+    std::vector<const float *> albedo;
+    std::vector<int32_t *> ids;
+    std::vector<float *> depth;
+    std::vector<uint8_t *> rgba8;
+    std::vector<float *> rgb32;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double trial_ms[3] = {0, 0, 0};
+};
+
+namespace {
+
+int batch_frame(pr_batch *b, hipStream_t s) {
+    const int nm = (int)b->meshes.size(), nv = (int)b->views.size();
+    const pr_mesh *M = b->meshes.data();
+    const pr_view *V = b->views.data();
+    int rc = pr_bound(M, nm, V, nv, &b->tuning, b->ws, b->ws_bytes, s);
+    if (!rc) rc = pr_bin(M, nm, V, nv, &b->tuning, b->ws, b->ws_bytes, s);
+    if (!rc) rc = pr_raycast(M, nm, V, nv, &b->tuning, b->ws, b->ws_bytes, b->ids.data(), b->depth.data(), s);
+    bool shade = false;
+    for (int v = 0; v < nv; ++v) shade = shade || b->rgba8[v] || b->rgb32[v];
+    if (!rc && shade)
+        rc = pr_shade(M, nm, V, nv, &b->tuning, b->ws, b->ws_bytes, (const int32_t *const *)b->ids.data(), &b->light,
+                      b->albedo.data(), b->rgba8.data(), b->rgb32.data(), s);
+    return rc;
+}
+
+int batch_alloc(pr_batch *b) {
+    if (b->ws) {
+        hipFree(b->ws);
+        b->ws = nullptr;
+    }
+    size_t bytes = 0;
+    int rc = pr_workspace_size(b->meshes.data(), (int)b->meshes.size(), b->views.data(), (int)b->views.size(),
+                               &b->tuning, &bytes);
+    if (rc) return rc;
+    if (hipMalloc(&b->ws, bytes) != hipSuccess) {
+        b->ws = nullptr;
+        return PR_ERR_HIP;
+    }
+    b->ws_bytes = bytes;
+    return PR_OK;
+}
+
+// Runs frames until the tile lists fit; returns the capacity-checked status.
+int batch_fit(pr_batch *b) {
+    for (int attempt = 0; attempt < 6; ++attempt) {
+        int rc = batch_alloc(b);
+        if (rc) return rc;
+        rc = batch_frame(b, b->cs);
+        if (rc) return rc;
+        pr_status st;
+        rc = pr_status_read(b->ws, b->ws_bytes, &st, b->cs);
+        if (rc) return rc;
+        if (!st.overflow) return PR_OK;
+        int64_t need = st.pairs_required + st.pairs_required / 4 + 1024;
+        if (need > INT32_MAX) return PR_ERR_UNSUPPORTED;
+        b->tuning.bin_capacity = (int32_t)need;
+    }
+    return PR_ERR_HIP;
+}
+
+double batch_time(pr_batch *b, int reps) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return 1e30;
+    double best = 1e30;
+    for (int r = 0; r < reps; ++r) {
+        hipEventRecord(e0, b->cs);
+        batch_frame(b, b->cs);
+        hipEventRecord(e1, b->cs);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        best = std::min(best, (double)ms);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return best;
+}
+
+std::string tune_key(const pr_batch *b) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    hipGetDevice(&dev);
+    hipGetDeviceProperties(&prop, dev);
+    double px = 0, tris = 0;
+    for (const pr_view &v : b->views) {
+        px += (double)v.width * v.height;
+        tris += b->meshes[v.mesh].nt;
+    }
+    char key[256];
+    snprintf(key, sizeof(key), "%s nv=%d px=2^%d tris=2^%d", prop.gcnArchName, (int)b->views.size(),
+             (int)lround(log2(std::max(px, 1.0))), (int)lround(log2(std::max(tris, 1.0))));
+    for (char *c = key; *c; ++c)
+        if (*c == '\t' || *c == '\n') *c = ' ';
+    return key;
+}
+
+bool cache_lookup(const std::string &key, int &tile) {
+    const char *path = getenv("PR_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool hit = false;
+    while (fgets(line, sizeof(line), f)) {
+        char *tab = strchr(line, '\t');
+        if (!tab) continue;
+        *tab = 0;
+        if (key == line) {
+            int t = atoi(tab + 1);
+            if (t == 8 || t == 16 || t == 32) {
+                tile = t;
+                hit = true;
+            }
+        }
+    }
+    fclose(f);
+    return hit;
+}
+
+void cache_store(const std::string &key, int tile) {
+    const char *path = getenv("PR_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s\t%d\n", key.c_str(), tile);
+    fclose(f);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pr_batch_create(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
+                    const pr_light *light, const float *const *albedo, int32_t *const *tri_id, float *const *depth,
+                    uint8_t *const *rgba8, float *const *rgb32, pr_batch **out) {
+    if (!out || !tuning || !light || !albedo || !tri_id || !depth) return PR_ERR_INVALID;
+    *out = nullptr;
+    pr_tuning probe = *tuning;
+    if (probe.tile == 0) probe.tile = 16;
+    if (probe.bin_capacity == 0) probe.bin_capacity = 1;
+    size_t bytes = 0;
+    int rc = pr_workspace_size(meshes, nm, views, nv, &probe, &bytes);
+    if (rc) return rc;
+    for (int v = 0; v < nv; ++v)
+        if (!tri_id[v] || !depth[v]) return PR_ERR_INVALID;
+    pr_batch *b = new pr_batch();
+    b->meshes.assign(meshes, meshes + nm);
+    b->views.assign(views, views + nv);
+    b->light = *light;
+    b->albedo.assign(albedo, albedo + nm);
+    b->ids.assign(tri_id, tri_id + nv);
+    b->depth.assign(depth, depth + nv);
+    b->rgba8.assign(nv, nullptr);
+    b->rgb32.assign(nv, nullptr);
+    for (int v = 0; v < nv; ++v) {
+        if (rgba8) b->rgba8[v] = rgba8[v];
+        if (rgb32) b->rgb32[v] = rgb32[v];
+    }
+    b->tuning = *tuning;
+    b->tuning.flags |= PR_FLAG_PERSISTENT;
+    if (b->tuning.bin_capacity == 0) {
+        int64_t tris = 0;
+        for (const pr_view &v : b->views) tris += meshes[v.mesh].nt;
+        b->tuning.bin_capacity = (int32_t)std::min<int64_t>(2 * tris + 65536, INT32_MAX / 2);
+    }
+    if (hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return PR_ERR_HIP;
+    }
+    rc = PR_OK;
+    if (tuning->tile == 0) {
+        std::string key = tune_key(b);
+        int cached = 0;
+        if (cache_lookup(key, cached)) {
+            b->tuning.tile = cached;
+        } else {
+            const int cand[3] = {8, 16, 32};
+            double best = 1e30;
+            int best_tile = 16;
+            int32_t cap = b->tuning.bin_capacity;
+            for (int i = 0; i < 3 && !rc; ++i) {
+                b->tuning.tile = cand[i];
+                b->tuning.bin_capacity = cap;
+                rc = batch_fit(b);
+                if (rc) break;
+                double ms = batch_time(b, 3);
+                b->trial_ms[i] = ms;
+                if (ms < best) {
+                    best = ms;
+                    best_tile = cand[i];
+                }
+            }
+            b->tuning.tile = best_tile;
+            b->tuning.bin_capacity = cap;
+            if (!rc) cache_store(key, best_tile);
+        }
+    }
+    if (!rc) rc = batch_fit(b);
+    if (!rc && hipStreamSynchronize(b->cs) != hipSuccess) rc = PR_ERR_HIP;
+    if (!rc) {
+        if (hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = PR_ERR_HIP;
+        if (!rc) {
+            int frc = batch_frame(b, b->cs);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(b->cs, &g);
+            b->graph = g;
+            if (frc) rc = frc;
+            else if (e != hipSuccess || !g) rc = PR_ERR_HIP;
+        }
+        if (!rc && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) rc = PR_ERR_HIP;
+    }
+    if (rc) {
+        pr_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return PR_OK;
+}
+
+int pr_batch_launch(pr_batch *b, void *stream) {
+    if (!b || !b->exec) return PR_ERR_INVALID;
+    return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? PR_OK : PR_ERR_HIP;
+}
+
+int pr_batch_info(const pr_batch *b, pr_tuning *chosen, size_t *ws_bytes, double *trial_ms) {
+    if (!b) return PR_ERR_INVALID;
+    if (chosen) *chosen = b->tuning;
+    if (ws_bytes) *ws_bytes = b->ws_bytes;
+    if (trial_ms)
+        for (int i = 0; i < 3; ++i) trial_ms[i] = b->trial_ms[i];
+    return PR_OK;
+}
+
+int pr_batch_status(const pr_batch *b, pr_status *out, void *stream) {
+    if (!b || !b->ws) return PR_ERR_INVALID;
+    return pr_status_read(b->ws, b->ws_bytes, out, stream);
+}
+
+int pr_batch_destroy(pr_batch *b) {
+    if (!b) return PR_OK;
+    if (b->cs) hipStreamSynchronize(b->cs);
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->ws) hipFree(b->ws);
+    if (b->cs) hipStreamDestroy(b->cs);
+    delete b;
+    return PR_OK;
 }
 
 }  // extern "C"

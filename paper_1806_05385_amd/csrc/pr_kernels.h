@@ -107,6 +107,15 @@ struct DevStatus {
     uint32_t pad;
 };
 
+// Tile queue of the persistent ray cast: power-of-two list-length buckets.
+constexpr int kBuckets = 33;
+struct Sched {
+    uint32_t queue;
+    uint32_t pad[3];
+    uint32_t count[kBuckets];
+    uint32_t cursor[kBuckets];
+};
+
 // Output / input pointers of the per-pixel passes, indexed by view.
 struct RayOut {
     int32_t *id[PR_MAX_VIEWS];

@@ -646,6 +646,82 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
 }
 
 // ---------------------------------------------------------------------------
+// persistent ray cast over a longest-list-first tile queue
+// ---------------------------------------------------------------------------
+// Tiles are ordered by list length, longest first, in power-of-two buckets
+// (a counting sort: per-block histograms in LDS, one global atomic per
+// block and bucket), then a grid sized to the device's resident blocks pulls
+// tiles from a global atomic counter until the queue is empty.
+__device__ __forceinline__ int len_bucket(uint32_t len) { return len == 0u ? 0 : 32 - __clz(len); }
+
+__global__ __launch_bounds__(256) void k_sched_count(const uint32_t *__restrict__ toff, int n, Sched *__restrict__ S) {
+    __shared__ uint32_t h[kBuckets];
+    if (threadIdx.x < kBuckets) h[threadIdx.x] = 0u;
+    __syncthreads();
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) atomicAdd(&h[len_bucket(toff[i + 1] - toff[i])], 1u);
+    __syncthreads();
+    if (threadIdx.x < kBuckets && h[threadIdx.x]) atomicAdd(&S->count[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_sched_base(Sched *__restrict__ S) {
+    if (threadIdx.x != 0) return;
+    uint32_t sum = 0;
+    for (int b = kBuckets - 1; b >= 0; --b) {   // longest lists first
+        S->cursor[b] = sum;
+        sum += S->count[b];
+    }
+    S->queue = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_sched_scatter(const uint32_t *__restrict__ toff, int n, Sched *__restrict__ S,
+                                                       int32_t *__restrict__ order) {
+    __shared__ uint32_t h[kBuckets], base[kBuckets];
+    if (threadIdx.x < kBuckets) h[threadIdx.x] = 0u;
+    __syncthreads();
+    int i = blockIdx.x * 256 + threadIdx.x;
+    int b = 0;
+    uint32_t rank = 0;
+    if (i < n) {
+        b = len_bucket(toff[i + 1] - toff[i]);
+        rank = atomicAdd(&h[b], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kBuckets && h[threadIdx.x]) base[threadIdx.x] = atomicAdd(&S->cursor[threadIdx.x], h[threadIdx.x]);
+    __syncthreads();
+    if (i < n) order[base[b] + rank] = i;
+}
+
+template <int TILE, bool COUNT>
+__global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast_queue(
+    const ViewTable *__restrict__ T, const float4 *__restrict__ rec, const uint32_t *__restrict__ toff,
+    const int32_t *__restrict__ lists, RayOut out, DevStatus *__restrict__ st, const int32_t *__restrict__ order,
+    int ntiles, Sched *__restrict__ S) {
+    __shared__ float4 s_rec[RayCfg<TILE>::CHUNK * kRecRoll];
+    __shared__ int s_item;
+    const bool ovf = st->overflow != 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&S->queue, 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= ntiles) break;   // the same for every thread of the block
+        const int gt = order[item];
+        const int v = find_view(T->tile_base, T->nv, gt);
+        const ViewDev &vd = T->v[v];
+        int beg = 0, end = 0;
+        if (!ovf) {
+            beg = (int)toff[gt];
+            end = (int)toff[gt + 1];
+        }
+        if (vd.rolling)
+            raycast_tile<true, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, s_rec, out.id[v], out.depth[v], st);
+        else
+            raycast_tile<false, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, s_rec, out.id[v], out.depth[v], st);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // shade
 // ---------------------------------------------------------------------------
 // Edge-plane normals c_k(t), face normal N(t) of triangle id at time t.

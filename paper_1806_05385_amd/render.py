@@ -187,6 +187,74 @@ class Renderer:
         return off, lst[:npairs.value]
 
 
+class Batch:
+    """Batched form (pr_batch_*): all views rendered as one frame, captured
+    once into a hipGraph; ``launch()`` replays it on the current stream.
+    tile = 0 / bin_capacity = 0 let the library's autotuner choose."""
+
+    def __init__(self, meshes, views, tile: int = 0, bin_capacity: int = 0, light=None, ambient: float = 0.1,
+                 rgba8: bool = True, rgb32: bool = False, device='cuda'):
+        self.L = B.lib()
+        self.device = torch.device(device)
+        self.meshes = [m if isinstance(m, DeviceMesh) else DeviceMesh.from_numpy(m, device) for m in meshes]
+        self.views = [copy.copy(v) for v in views]
+        self.outputs = []
+        for v in self.views:
+            h, w = v.height, v.width
+            o = dict(id=torch.empty((h, w), dtype=torch.int32, device=self.device),
+                     depth=torch.empty((h, w), dtype=torch.float32, device=self.device))
+            if rgba8:
+                o['rgba8'] = torch.empty((h, w, 4), dtype=torch.uint8, device=self.device)
+            if rgb32:
+                o['rgb32'] = torch.empty((h, w, 3), dtype=torch.float32, device=self.device)
+            self.outputs.append(o)
+        nm = len(self.meshes)
+        self.c_meshes = (B.PrMesh * nm)(*[m.pr() for m in self.meshes])
+        self.c_views = (B.PrView * len(self.views))(*[B.make_view(v) for v in self.views])
+        self.light = B.make_light(light if light is not None else (0.0, 0.0, -1.0), ambient)
+        tu = B.PrTuning(tile, bin_capacity, 0, 0)
+        self.ptr = ctypes.c_void_p(0)
+
+        def arr(key):
+            if key not in self.outputs[0]:
+                return None
+            return B.ptr_array([o[key].data_ptr() for o in self.outputs])
+        torch.cuda.synchronize()
+        B.check('pr_batch_create', self.L.pr_batch_create(
+            self.c_meshes, nm, self.c_views, len(self.views), ctypes.byref(tu), ctypes.byref(self.light),
+            B.ptr_array([m.albedo.data_ptr() for m in self.meshes]), arr('id'), arr('depth'), arr('rgba8'),
+            arr('rgb32'), ctypes.byref(self.ptr)))
+
+    def launch(self):
+        B.check('pr_batch_launch', self.L.pr_batch_launch(self.ptr, ctypes.c_void_p(_stream_handle())))
+        return self.outputs
+
+    def info(self):
+        tu = B.PrTuning()
+        size = ctypes.c_size_t(0)
+        ms = (ctypes.c_double * 3)()
+        B.check('pr_batch_info', self.L.pr_batch_info(self.ptr, ctypes.byref(tu), ctypes.byref(size), ms))
+        return dict(tile=tu.tile, bin_capacity=tu.bin_capacity, flags=tu.flags, ws_bytes=size.value,
+                    trial_ms={8: ms[0], 16: ms[1], 32: ms[2]})
+
+    def status(self) -> B.PrStatus:
+        st = B.PrStatus()
+        B.check('pr_batch_status', self.L.pr_batch_status(self.ptr, ctypes.byref(st),
+                                                          ctypes.c_void_p(_stream_handle())))
+        return st
+
+    def close(self):
+        if self.ptr:
+            self.L.pr_batch_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def render_scene(scene, tile: int = 16, shade: bool = True, flags: int = 0, device='cuda'):
     """Render a scenegen.Scene; returns (renderer, outputs)."""
     r = Renderer(scene.meshes, scene.views, tile=tile, light=scene.light_dir, ambient=scene.ambient, flags=flags,

@@ -29,6 +29,7 @@ Tables 1 and 2; the scenes themselves are not available, so these stand in):
 """
 from __future__ import annotations
 
+import functools
 import math
 from dataclasses import dataclass, field
 
@@ -128,9 +129,11 @@ def head_pose(t_s: float, yaw_rate_deg: float, vel: tuple, eye_offset: float):
     return np.concatenate([omega, t_wv]).astype(np.float32)
 
 
+@functools.lru_cache(maxsize=64)
 def _geodesic_unit(f: int):
     """Icosahedron with every face split f x f, vertices pushed to the unit
-    sphere.  Returns (verts [10f^2+2, 3] float64, tris [20 f^2, 3] int32)."""
+    sphere.  Returns (verts [10f^2+2, 3] float64, tris [20 f^2, 3] int32);
+    cached per f (callers must not modify the arrays)."""
     p = (1.0 + math.sqrt(5.0)) / 2.0
     ico_v = np.array([[-1, p, 0], [1, p, 0], [-1, -p, 0], [1, -p, 0],
                       [0, -1, p], [0, 1, p], [0, -1, -p], [0, 1, -p],
@@ -140,37 +143,47 @@ def _geodesic_unit(f: int):
              (1, 5, 9), (5, 11, 4), (11, 10, 2), (10, 7, 6), (7, 1, 8),
              (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9),
              (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
-    key_to_idx: dict = {}
-    verts = []
-
-    def vid(weights):
-        # weights: dict ico_vertex -> integer weight (sum f); canonical key
-        key = tuple(sorted((k, w) for k, w in weights.items() if w))
-        idx = key_to_idx.get(key)
-        if idx is None:
-            pos = sum(ico_v[k] * w for k, w in key) / f
-            idx = len(verts)
-            key_to_idx[key] = idx
-            verts.append(pos / np.linalg.norm(pos))
-        return idx
-
-    tris = []
-    for (a, b, c) in ico_f:
-        grid = {}
-        for i in range(f + 1):
-            for j in range(f + 1 - i):
-                w = {a: f - i - j}
-                w[b] = w.get(b, 0) + i
-                w[c] = w.get(c, 0) + j
-                grid[(i, j)] = vid(w)
-        for i in range(f):
-            for j in range(f - i):
-                tris.append((grid[(i, j)], grid[(i + 1, j)], grid[(i, j + 1)]))
-                if i + j + 1 < f:
-                    tris.append((grid[(i + 1, j)], grid[(i + 1, j + 1)], grid[(i, j + 1)]))
-    v = np.array(verts)
-    t = np.array(tris, np.int32)
+    # every grid point of every face as integer weights on <= 3 icosahedron
+    # vertices; points shared by faces have equal canonical keys
+    ii, jj = np.meshgrid(np.arange(f + 1), np.arange(f + 1), indexing='ij')
+    sel = (ii + jj) <= f
+    gi, gj = ii[sel], jj[sel]                   # i outer, j inner
+    npf = gi.size
+    grid_id = -np.ones((f + 1, f + 1), np.int64)
+    grid_id[gi, gj] = np.arange(npf)
+    fa = np.array(ico_f)
+    idx = np.stack([np.repeat(fa[:, 0], npf), np.repeat(fa[:, 1], npf), np.repeat(fa[:, 2], npf)], axis=1)
+    wts = np.stack([np.tile(f - gi - gj, 20), np.tile(gi, 20), np.tile(gj, 20)], axis=1)
+    idx = np.where(wts > 0, idx, 15)
+    order = np.argsort(idx, axis=1, kind='stable')
+    idx_s = np.take_along_axis(idx, order, 1)
+    w_s = np.take_along_axis(wts, order, 1)
+    keys = ((idx_s[:, 0] * 256 + w_s[:, 0]) << 24) | ((idx_s[:, 1] * 256 + w_s[:, 1]) << 12) | (idx_s[:, 2] * 256 + w_s[:, 2])
+    _, first, inverse = np.unique(keys, return_index=True, return_inverse=True)
+    rank = np.empty(first.size, np.int64)
+    rank[np.argsort(first, kind='stable')] = np.arange(first.size)
+    vid = rank[inverse]                         # vertex id of every (face, point), first-appearance order
+    pos = np.zeros((first.size, 3))
+    wsum = (wts[:, :, None] * ico_v[np.minimum(idx, 11)]).sum(1) / f
+    pos[vid] = wsum
+    verts = pos / np.linalg.norm(pos, axis=1, keepdims=True)
+    tri_i, tri_j = np.meshgrid(np.arange(f), np.arange(f), indexing='ij')
+    ts = (tri_i + tri_j) < f
+    ti, tj = tri_i[ts], tri_j[ts]
+    t1 = np.stack([grid_id[ti, tj], grid_id[ti + 1, tj], grid_id[ti, tj + 1]], axis=1)
+    has2 = (ti + tj + 1) < f
+    t2 = np.stack([grid_id[ti + 1, tj], grid_id[np.minimum(ti + 1, f), np.minimum(tj + 1, f)],
+                   grid_id[ti, tj + 1]], axis=1)
+    both = np.stack([t1, t2], axis=1).reshape(-1, 3)
+    keep = np.stack([np.ones_like(has2), has2], axis=1).reshape(-1)
+    local = both[keep]
+    tris = (local[None, :, :] + (np.arange(20) * npf)[:, None, None]).reshape(-1, 3)
+    tris = vid[tris]
+    v = np.ascontiguousarray(verts)
+    t = np.ascontiguousarray(tris, np.int32)
     assert v.shape[0] == 10 * f * f + 2 and t.shape[0] == 20 * f * f
+    v.flags.writeable = False
+    t.flags.writeable = False
     return v, t
 
 
@@ -188,7 +201,44 @@ def displaced_sphere(rng, f, radius, centre):
     d, tri = _geodesic_unit(f)
     r = radius + _displacement(rng, d)
     v = d * r[:, None] + np.asarray(centre, np.float64)
-    return v, tri
+    return v, tri.copy()
+
+
+@functools.lru_cache(maxsize=8)
+def _box_template(tess: int):
+    """Unit-half-size box [-1,1]^3, every face split tess x tess, faces not
+    sharing vertices: (verts [6 (tess+1)^2, 3], tris [12 tess^2, 3])."""
+    verts, tris = [], []
+    for axis in range(3):
+        for sgn in (-1.0, 1.0):
+            u_ax, v_ax = [a for a in range(3) if a != axis]
+            base = len(verts)
+            for i in range(tess + 1):
+                for j in range(tess + 1):
+                    p = np.zeros(3)
+                    p[axis] = sgn
+                    p[u_ax] = -1 + 2 * i / tess
+                    p[v_ax] = -1 + 2 * j / tess
+                    verts.append(p)
+            for i in range(tess):
+                for j in range(tess):
+                    a = base + i * (tess + 1) + j
+                    b = a + tess + 1
+                    tris.append((a, b, a + 1))
+                    tris.append((b, b + 1, a + 1))
+    return np.array(verts), np.array(tris, np.int32)
+
+
+def random_boxes(rng, n, tess=1, lo=(-4, -2.5, 1.5), hi=(4, 2.5, 12), size=(0.05, 0.5)):
+    """n boxes at once: per-axis size log-U(size), uniform rotation, centre
+    U(lo, hi).  Returns (verts, tris)."""
+    tv, tt = _box_template(tess)
+    half = np.exp(rng.uniform(math.log(size[0]), math.log(size[1]), size=(n, 3))) / 2.0
+    rot = _random_rotation_matrices(rng, n)
+    centre = rng.uniform(lo, hi, size=(n, 3))
+    v = np.einsum('nij,nkj->nki', rot, tv[None] * half[:, None, :]) + centre[:, None, :]
+    t = tt[None] + (np.arange(n) * tv.shape[0])[:, None, None]
+    return v.reshape(-1, 3), t.reshape(-1, 3).astype(np.int32)
 
 
 def _box(rng, size, rot, centre, tess=3):
@@ -326,21 +376,19 @@ def make_large(seed: int = 3, size: int = 2160, n_obj: int = 1000, f: int = 10) 
     return Scene('large', [mesh], views)
 
 
-def make_batch(seed: int = 4, n_views: int = 64, max_side: int = 2048, max_tris: int = 500_000) -> Scene:
+def make_batch(seed: int = 4, n_views: int = 64, max_side: int = 2048, max_tris: int = 500_000,
+               min_side: int = 128, min_tris: int = 1000) -> Scene:
     meshes, views = [], []
     for k in range(n_views):
         rng = np.random.default_rng(4000 + k)
-        side = int(round(math.exp(rng.uniform(math.log(128), math.log(max_side)))))
-        n_t = int(round(math.exp(rng.uniform(math.log(1e3), math.log(max_tris)))))
+        side = int(round(math.exp(rng.uniform(math.log(min_side), math.log(max_side)))))
+        n_t = int(round(math.exp(rng.uniform(math.log(min_tris), math.log(max_tris)))))
         n_sphere = int(0.75 * n_t)
         f = max(1, int(round(math.sqrt(n_sphere / 20.0))))
         parts = [displaced_sphere(rng, f, 1.0, (0.0, 0.0, 3.0))]
         n_box = max(0, (n_t - 20 * f * f) // 12)
-        for _ in range(n_box):
-            size = np.exp(rng.uniform(math.log(0.05), math.log(0.5), size=3))
-            rot = _random_rotation_matrices(rng, 1)[0]
-            centre = rng.uniform((-4, -2.5, 1.5), (4, 2.5, 12))
-            parts.append(_box(rng, size, rot, centre, tess=1))
+        if n_box:
+            parts.append(random_boxes(rng, n_box, tess=1))
         v, tri = _concat(parts)
         v = v.astype(np.float32)
         meshes.append(Mesh(v0=v, v1=v.copy(), tri=tri, albedo=_albedo(rng, v.shape[0])))
