@@ -29,8 +29,13 @@ def main():
     ap.add_argument('--steps', type=int, default=50)
     ap.add_argument('--warmup', type=int, default=5)
     ap.add_argument('--tile', type=int, default=16)
+    ap.add_argument('--persistent', action='store_true', help='longest-first persistent ray cast')
     ap.add_argument('--cpu-pixels', type=int, default=49152)
     ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--only', choices=['all', 'hmd'], default='all',
+                    help='hmd: only the headline frame (no backward, batch or CPU legs; for profiling)')
+    ap.add_argument('--copy-bytes', type=int, default=0,
+                    help='only run a plain device copy of this many bytes 10 times (counter calibration)')
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({'error': 'this build runs on one GPU; --gpus above 1 is not supported'}))
@@ -44,17 +49,25 @@ def main():
     from paper_1806_05385_amd.render import Renderer
 
     torch.cuda.set_device(0)
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device='cuda')
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({'copy_bytes': args.copy_bytes, 'launches': 10}))
+        return
     sc = scenegen.make_hmd()
     mesh = sc.meshes[0]
     r = Renderer(sc.meshes, sc.views, tile=args.tile, light=sc.light_dir, ambient=sc.ambient)
     r.frame(check=True)            # sizes the tile-list capacity
     # one counting frame (not timed): ray-triangle tests and hits
-    r.flags = B.PR_FLAG_COUNT
+    r.flags = B.PR_FLAG_COUNT | (B.PR_FLAG_PERSISTENT if args.persistent else 0)
     r._prepare()
     r.frame(check=True)
     st = r.status()
     tests, hits = int(st.tests), int(st.hits)
-    r.flags = 0
+    r.flags = B.PR_FLAG_PERSISTENT if args.persistent else 0
     r._prepare()
     r.frame(check=True)
 
@@ -92,82 +105,87 @@ def main():
     if os.path.exists(tpath):
         traffic = json.load(open(tpath)).get('bytes_per_launch')
 
+    if args.only == 'hmd':
+        args.no_cpu_baseline = True
     # backward / forward on the differentiation workload (100,820 triangles,
     # 512x512, rolling + foveated, moving camera): forward = bound + bin +
     # raycast + shade (fp32 rgb), backward = pr_backward
-    gsc = scenegen.make_grad()
-    gr = Renderer(gsc.meshes, gsc.views, tile=args.tile, light=gsc.light_dir, ambient=gsc.ambient)
-    gr.frame(check=True)
-    dl = [torch.ones_like(gr.outputs[0]['rgb32'])]
-    for _ in range(3):
-        gr.frame(check=False)
-        gr.backward(dl)
-    nrep = max(10, args.steps)
-    f0, f1, b1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    fwd_ms, bwd_ms = [], []
-    for _ in range(nrep):
-        f0.record(stream)
-        gr.bound()
-        gr.bin()
-        gr.raycast()
-        gr.shade(rgba8=False, rgb32=True)
-        f1.record(stream)
-        gr.backward(dl)
-        b1.record(stream)
+    fwd_med = bwd_med = float('nan')
+    batch_out = None
+    if args.only == 'all':
+        gsc = scenegen.make_grad()
+        gr = Renderer(gsc.meshes, gsc.views, tile=args.tile, light=gsc.light_dir, ambient=gsc.ambient)
+        gr.frame(check=True)
+        dl = [torch.ones_like(gr.outputs[0]['rgb32'])]
+        for _ in range(3):
+            gr.frame(check=False)
+            gr.backward(dl)
+        nrep = max(10, args.steps)
+        f0, f1, b1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        fwd_ms, bwd_ms = [], []
+        for _ in range(nrep):
+            f0.record(stream)
+            gr.bound()
+            gr.bin()
+            gr.raycast()
+            gr.shade(rgba8=False, rgb32=True)
+            f1.record(stream)
+            gr.backward(dl)
+            b1.record(stream)
+            torch.cuda.synchronize()
+            fwd_ms.append(f0.elapsed_time(f1))
+            bwd_ms.append(f1.elapsed_time(b1))
+        fwd_med, bwd_med = float(np.median(fwd_ms)), float(np.median(bwd_ms))
+
+        # batched form: 64 views (log-uniform 128..2048 px, 1k..500k triangles)
+        # in one autotuned hipGraph frame vs 64 sequential plain frames
+        from paper_1806_05385_amd.render import Batch
+        bsc = scenegen.make_batch()
         torch.cuda.synchronize()
-        fwd_ms.append(f0.elapsed_time(f1))
-        bwd_ms.append(f1.elapsed_time(b1))
-    fwd_med, bwd_med = float(np.median(fwd_ms)), float(np.median(bwd_ms))
+        bt = Batch(bsc.meshes, bsc.views, tile=0, light=bsc.light_dir, ambient=bsc.ambient, rgba8=True)
+        binfo = bt.info()
+        for _ in range(2):
+            bt.launch()
+        nb = max(5, args.steps // 5)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(nb):
+            bt.launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        batch_ms = e0.elapsed_time(e1) / nb
+        assert not bt.status().overflow
+        seq = []
+        for v in bsc.views:
+            vv = scenegen.View(**{**v.__dict__, 'mesh': 0})
+            rr = Renderer([bt.meshes[v.mesh]], [vv], tile=binfo['tile'], light=bsc.light_dir, ambient=bsc.ambient)
+            rr.frame(check=True)
+            seq.append(rr)
 
-    # batched form: 64 views (log-uniform 128..2048 px, 1k..500k triangles)
-    # in one autotuned hipGraph frame vs 64 sequential plain frames
-    from paper_1806_05385_amd.render import Batch
-    bsc = scenegen.make_batch()
-    torch.cuda.synchronize()
-    bt = Batch(bsc.meshes, bsc.views, tile=0, light=bsc.light_dir, ambient=bsc.ambient, rgba8=True)
-    binfo = bt.info()
-    for _ in range(2):
-        bt.launch()
-    nb = max(5, args.steps // 5)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(nb):
-        bt.launch()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    batch_ms = e0.elapsed_time(e1) / nb
-    assert not bt.status().overflow
-    seq = []
-    for v in bsc.views:
-        vv = scenegen.View(**{**v.__dict__, 'mesh': 0})
-        rr = Renderer([bt.meshes[v.mesh]], [vv], tile=binfo['tile'], light=bsc.light_dir, ambient=bsc.ambient)
-        rr.frame(check=True)
-        seq.append(rr)
-
-    def seq_round():
-        for rr in seq:
-            rr.bound()
-            rr.bin()
-            rr.raycast()
-            rr.shade(rgba8=True, rgb32=False)
-    seq_round()
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(nb):
+        def seq_round():
+            for rr in seq:
+                rr.bound()
+                rr.bin()
+                rr.raycast()
+                rr.shade(rgba8=True, rgb32=False)
         seq_round()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    seq_ms = e0.elapsed_time(e1) / nb
-    n_views = len(bsc.views)
-    batch_out = {'views': n_views, 'pixels': int(sum(v.width * v.height for v in bsc.views)),
-                 'triangles': int(sum(bsc.meshes[v.mesh].nt for v in bsc.views)), 'tile': binfo['tile'],
-                 'trial_ms': binfo['trial_ms'], 'batched_ms': round(batch_ms, 4), 'sequential_ms': round(seq_ms, 4),
-                 'batched_views_per_s': round(n_views / (batch_ms * 1e-3), 1),
-                 'sequential_views_per_s': round(n_views / (seq_ms * 1e-3), 1),
-                 'speedup': round(seq_ms / batch_ms, 3)}
-    bt.close()
-    del seq
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(nb):
+            seq_round()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        seq_ms = e0.elapsed_time(e1) / nb
+        n_views = len(bsc.views)
+        batch_out = {'views': n_views, 'pixels': int(sum(v.width * v.height for v in bsc.views)),
+                     'triangles': int(sum(bsc.meshes[v.mesh].nt for v in bsc.views)), 'tile': binfo['tile'],
+                     'trial_ms': binfo['trial_ms'], 'batched_ms': round(batch_ms, 4), 'sequential_ms': round(seq_ms, 4),
+                     'batched_views_per_s': round(n_views / (batch_ms * 1e-3), 1),
+                     'sequential_views_per_s': round(n_views / (seq_ms * 1e-3), 1),
+                     'speedup': round(seq_ms / batch_ms, 3)}
+        bt.close()
+        del seq
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -208,10 +226,10 @@ def main():
         'tests_per_s': round(tests / (ray_ms_avg * 1e-3), 1),
         'ste': round(hits / max(tests, 1), 4),
         'pairs_per_frame': int(st.pairs_total),
-        'bwd_fwd': round(bwd_med / fwd_med, 3),
+        'bwd_fwd': round(bwd_med / fwd_med, 3) if args.only == 'all' else None,
         'batch': batch_out,
-        'grad_workload': {'triangles': int(gsc.meshes[0].nt), 'size': 512, 'fwd_ms': round(fwd_med, 4),
-                          'bwd_ms': round(bwd_med, 4)},
+        'grad_workload': {'triangles': 100820, 'size': 512, 'fwd_ms': round(fwd_med, 4),
+                          'bwd_ms': round(bwd_med, 4)} if args.only == 'all' else None,
         'wall_s': round(wall, 3),
         'roofline': {'bound': 'alu', 'achieved': round(achieved, 3), 'peak': PEAK_FP32_TFLOPS,
                      'unit': 'TFLOP/s', 'frac': round(achieved / PEAK_FP32_TFLOPS, 4), 'traffic': traffic,

@@ -211,7 +211,7 @@ void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, D
     const int grid = std::max(1, std::min(L.total_tiles, resident));
     hipLaunchKernelGGL((k_raycast_queue<TILE, COUNT>), dim3(grid), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
                        at<uint32_t>(ws, L.toff), at<int32_t>(ws, L.lists), out, st, at<int32_t>(ws, L.order),
-                       L.total_tiles, S);
+                       L.total_tiles);
 }
 
 template <int TILE>

@@ -381,24 +381,29 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
             }
         }
         __syncthreads();
-        for (int i = j; i < cn; i += 256) {
-            unsigned long long m = s_pass[i >> 6];
-            if (!((m >> (i & 63)) & 1ull)) continue;
-            const int c = c0 + i;
-            int lo = 0, hi = 255;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (s_pref[mid] <= c) lo = mid; else hi = mid - 1;
+        for (int i = j; i < cn_up; i += 256) {
+            const bool surv = i < cn && ((s_pass[i >> 6] >> (i & 63)) & 1ull);
+            int gt = 0, q = 0;
+            unsigned idx = 0;
+            if (surv) {
+                const int c = c0 + i;
+                int lo = 0, hi = 255;
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (s_pref[mid] <= c) lo = mid; else hi = mid - 1;
+                }
+                q = lo;
+                const int local = c - s_pref[q];
+                const int rw = s_rect[q][2] - s_rect[q][0] + 1;
+                const int tx = s_rect[q][0] + local % rw, ty = s_rect[q][1] + local / rw;
+                gt = vd.tile_base + ty * vd.tiles_x + tx;
+                const unsigned long long m = s_pass[i >> 6];
+                idx = s_base + (unsigned)s_wpref[i >> 6] + (unsigned)__popcll(m & ((1ull << (i & 63)) - 1ull));
             }
-            const int q = lo;
-            const int local = c - s_pref[q];
-            const int rw = s_rect[q][2] - s_rect[q][0] + 1;
-            const int tx = s_rect[q][0] + local % rw, ty = s_rect[q][1] + local / rw;
-            const int gt = vd.tile_base + ty * vd.tiles_x + tx;
-            unsigned below = __popcll(m & ((1ull << (i & 63)) - 1ull));
-            unsigned idx = s_base + (unsigned)s_wpref[i >> 6] + below;
-            unsigned slot = atomicAdd(&tcount[gt], 1u);
-            if ((int64_t)idx < cap) pairs[idx] = Pair{gt, (int32_t)slot, f0 + q};
+            if (surv) {
+                const unsigned slot = atomicAdd(&tcount[gt], 1u);
+                if ((int64_t)idx < cap) pairs[idx] = Pair{gt, (int32_t)slot, f0 + q};
+            }
         }
         __syncthreads();
     }
@@ -503,11 +508,16 @@ __device__ __forceinline__ float edge_roll(float ax, float ay, float az, float b
     return fmaf(ry, ey, fmaf(rx, ex, ez));
 }
 
+// Threads per tile block and pixels per lane: one wave for tiles up to
+// 16x16 (8x8: 1 px/lane, 16x16: 4 px/lane), four waves of 4 px/lane for
+// 32x32.  Several pixels per lane reuse each triangle record read from LDS.
+// The LDS chunk is sized so that a one-wave block holds 5.6 KB: 28 blocks
+// (7 waves per SIMD) fit a CU's 160 KB.
 template <int TILE>
 struct RayCfg {
-    static constexpr int NT = TILE * TILE >= 256 ? 256 : 64;
+    static constexpr int NT = TILE * TILE >= 1024 ? 256 : 64;
     static constexpr int PPL = TILE * TILE / NT;
-    static constexpr int CHUNK = 64;
+    static constexpr int CHUNK = NT == 64 ? 32 : 64;
 };
 
 // One tile of one view: stage the tile's list through LDS, test every pixel
@@ -650,8 +660,8 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
 // ---------------------------------------------------------------------------
 // Tiles are ordered by list length, longest first, in power-of-two buckets
 // (a counting sort: per-block histograms in LDS, one global atomic per
-// block and bucket), then a grid sized to the device's resident blocks pulls
-// tiles from a global atomic counter until the queue is empty.
+// block and bucket); a grid sized to the device's resident blocks then walks
+// the order with a static stride, so the longest lists start first.
 __device__ __forceinline__ int len_bucket(uint32_t len) { return len == 0u ? 0 : 32 - __clz(len); }
 
 __global__ __launch_bounds__(256) void k_sched_count(const uint32_t *__restrict__ toff, int n, Sched *__restrict__ S) {
@@ -696,16 +706,12 @@ template <int TILE, bool COUNT>
 __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast_queue(
     const ViewTable *__restrict__ T, const float4 *__restrict__ rec, const uint32_t *__restrict__ toff,
     const int32_t *__restrict__ lists, RayOut out, DevStatus *__restrict__ st, const int32_t *__restrict__ order,
-    int ntiles, Sched *__restrict__ S) {
+    int ntiles) {
     __shared__ float4 s_rec[RayCfg<TILE>::CHUNK * kRecRoll];
-    __shared__ int s_item;
     const bool ovf = st->overflow != 0;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(&S->queue, 1u);
-        __syncthreads();
-        const int item = s_item;
-        __syncthreads();
-        if (item >= ntiles) break;   // the same for every thread of the block
+    // block b takes items b, b + grid, b + 2 grid, ... of the longest-first
+    // order: the first round holds the longest lists, no queue atomics
+    for (int item = blockIdx.x; item < ntiles; item += gridDim.x) {
         const int gt = order[item];
         const int v = find_view(T->tile_base, T->nv, gt);
         const ViewDev &vd = T->v[v];
@@ -718,6 +724,7 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast_queue(
             raycast_tile<true, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, s_rec, out.id[v], out.depth[v], st);
         else
             raycast_tile<false, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, s_rec, out.id[v], out.depth[v], st);
+        __syncthreads();
     }
 }
 
