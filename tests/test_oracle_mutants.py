@@ -41,6 +41,10 @@ MUTANTS = {
     'grad_rotation_jacobian': ('for (int k = 0; k < 9; ++k) out[k] = Ei[k] + 0.5 * (A[k] + B[k]);',
                                'for (int k = 0; k < 9; ++k) out[k] = Ei[k];'),
     'grad_translation': ('gT0[rr] += gs_[rr];', 'gT0[rr] -= gs_[rr];'),
+    'ehat_not_normalised': ('double v = cn > 0 ? fabs(e[k]) / (rn * cn) : 0.0;',
+                            'double v = cn > 0 ? fabs(e[k]) / cn : 0.0;'),
+    'cosinc_not_normalised': ('cosinc[q] = nn > 0 ? fabs(dot3(N, r)) / nn : 0.0;',
+                              'cosinc[q] = nn > 0 ? fabs(dot3(N, r)) / norm3(N) : 0.0;'),
 }
 
 

@@ -419,3 +419,29 @@ def test_exact_depth_tie_goes_to_lower_index():
     assert hit.sum() > 50
     assert (o['id'][hit] == 1).all() and (o['id2'][hit] == 2).all()
     assert (o['z'][hit] == o['z2'][hit]).all()
+
+
+def test_edge_metric_and_incidence_cosine_closed_forms():
+    """ehat is the sine of the angle between the pixel ray and the nearest
+    edge plane through the eye; cosinc is |cos| of the ray / normal angle.
+    A triangle with one edge in the plane y = 0 (through the eye) and its
+    face in the plane z = 3: near that edge ehat = |r_y| / |r| and
+    cosinc = 1 / |r| everywhere."""
+    v = np.array([[-3, 0, 3], [3, 0, 3], [0, 3, 3]], np.float32)   # edge (0,1) lies in y = 0
+    mesh = scenegen.Mesh(v, v.copy(), np.array([[0, 1, 2]], np.int32), np.ones_like(v))
+    view = scenegen.View(32, 32, np.zeros(6, np.float32), np.zeros(6, np.float32), alpha=1.0, roll_dir=(0, 0))
+    orc = oracle.Oracle(mesh, view)
+    o = orc.render()
+    rows = [15, 14]                      # the two rows just above y = 0
+    checked = 0
+    for j in rows:
+        for i in range(12, 20):
+            p = j * 32 + i
+            _, x, t, r = oracle.pixel_setup(view, p)
+            hit, z, eh, cs = orc.eval_many(np.array([p]), np.array([0]), with_cos=True)
+            assert hit[0] and o['id'][p] == 0
+            assert abs(eh[0] - abs(r[1]) / np.linalg.norm(r)) < 1e-12
+            assert abs(cs[0] - 1.0 / np.linalg.norm(r)) < 1e-12
+            assert abs(o['ehat'][p] - eh[0]) < 1e-15
+            checked += 1
+    assert checked == 16
