@@ -23,6 +23,37 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X vector FP32 (packed FMA)
 PEAK_FP32_UNPACKED_TFLOPS = 78.6
 
 
+def kernel_source_sha() -> str:
+    """Hash of the kernel sources; a stored counter figure is valid only for
+    the sources it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ('pr_kernels.hip', 'pr_kernels.h', 'pr_geom.h'):
+        with open(os.path.join(ROOT, 'paper_1806_05385_amd', 'csrc', f), 'rb') as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per ray-cast launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None when the summary is
+    missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, 'profiles', 'k_raycast_hmd_traffic.txt')
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ':' in line and not line.startswith(' '):
+            k, v = line.split(':', 1)
+            kv[k.strip()] = v.strip()
+    if kv.get('kernel_source_sha') != kernel_source_sha():
+        return None
+    try:
+        return int(kv['bytes_per_launch'])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -34,9 +65,13 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--only', choices=['all', 'hmd'], default='all',
                     help='hmd: only the headline frame (no backward, batch or CPU legs; for profiling)')
+    ap.add_argument('--source-sha', action='store_true', help='print the kernel source hash and exit')
     ap.add_argument('--copy-bytes', type=int, default=0,
                     help='only run a plain device copy of this many bytes 10 times (counter calibration)')
     args = ap.parse_args()
+    if args.source_sha:
+        print(kernel_source_sha())
+        return
     if args.gpus != 1:
         print(json.dumps({'error': 'this build runs on one GPU; --gpus above 1 is not supported'}))
         sys.exit(2)
@@ -100,10 +135,7 @@ def main():
     rolling = any(v.roll_dir[0] or v.roll_dir[1] for v in sc.views)
     flop_test = FLOP_PER_TEST_MOVING if rolling else FLOP_PER_TEST_STATIC
     achieved = tests * flop_test / (ray_ms_avg * 1e-3) / 1e12
-    traffic = None
-    tpath = os.path.join(ROOT, 'profiles', 'raycast_hmd_traffic.json')
-    if os.path.exists(tpath):
-        traffic = json.load(open(tpath)).get('bytes_per_launch')
+    traffic = measured_traffic()
 
     if args.only == 'hmd':
         args.no_cpu_baseline = True
@@ -111,7 +143,7 @@ def main():
     # 512x512, rolling + foveated, moving camera): forward = bound + bin +
     # raycast + shade (fp32 rgb), backward = pr_backward
     fwd_med = bwd_med = float('nan')
-    batch_out = None
+    batch_out = large_out = None
     if args.only == 'all':
         gsc = scenegen.make_grad()
         gr = Renderer(gsc.meshes, gsc.views, tile=args.tile, light=gsc.light_dir, ambient=gsc.ambient)
@@ -187,6 +219,27 @@ def main():
         bt.close()
         del seq
 
+        # large workload (1,000 moving spheres = 2M triangles, 2 x 2160x2160)
+        lsc = scenegen.make_large()
+        lr = Renderer(lsc.meshes, lsc.views, tile=args.tile, light=lsc.light_dir, ambient=lsc.ambient)
+        lr.frame(check=True)
+        for _ in range(2):
+            lr.frame(check=False)
+        nl = max(5, args.steps // 5)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(nl):
+            lr.bound()
+            lr.bin()
+            lr.raycast()
+            lr.shade(rgba8=True, rgb32=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        assert not lr.status().overflow
+        large_out = {'triangles': int(lsc.meshes[0].nt), 'views': len(lsc.views), 'width': lsc.views[0].width,
+                     'height': lsc.views[0].height, 'frame_ms': round(e0.elapsed_time(e1) / nl, 4)}
+        del lr
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -228,6 +281,7 @@ def main():
         'pairs_per_frame': int(st.pairs_total),
         'bwd_fwd': round(bwd_med / fwd_med, 3) if args.only == 'all' else None,
         'batch': batch_out,
+        'large': large_out,
         'grad_workload': {'triangles': 100820, 'size': 512, 'fwd_ms': round(fwd_med, 4),
                           'bwd_ms': round(bwd_med, 4)} if args.only == 'all' else None,
         'wall_s': round(wall, 3),

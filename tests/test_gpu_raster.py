@@ -81,6 +81,23 @@ def test_hmd_full_size_sampled():
         assert_parity(rep)
 
 
+def test_large_full_size_sampled():
+    """The large workload at full size (1,000 moving geodesic spheres = 2M
+    triangles, 2 x 2160x2160, foveated + rolling); the oracle checks 1,000
+    sampled pixels per eye."""
+    sc = scenegen.make_large()
+    assert sc.meshes[0].nt == 2_000_000
+    r, out = _render(sc, 16)
+    for v, view in enumerate(sc.views):
+        pix = scenegen.sample_pixels(300 + v, view, 1000)
+        orc = oracle.Oracle(sc.meshes[0], view)
+        o = orc.render(pix)
+        rep = compare(orc, o, out[v]['id'].ravel()[pix], out[v]['depth'].ravel()[pix], pix, view.znear)
+        print(f"\nlarge eye {v}: {rep['hits']}/{len(pix)} hits, {rep['mismatch']} exempt", flush=True)
+        assert rep['hits'] > 0.05 * len(pix)
+        assert_parity(rep)
+
+
 def test_bound_invariant_on_device_lists():
     """Every oracle hit (occluded or not) lies in a tile whose device-built
     list holds the triangle (the bound never drops a covered fragment)."""
