@@ -92,7 +92,7 @@ extern "C" {
 
 /* A triangle mesh.  v0 / v1: float32 [nv][3] world positions at the frame's
  * start / end (v1 may equal v0); tri: int32 [nt][3] vertex indices in
- * [0, nv).  nt may be 0. */
+ * [0, nv).  0 <= nt < 2^28. */
 typedef struct pr_mesh {
     const float *v0;
     const float *v1;
@@ -166,8 +166,11 @@ int pr_bound(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const 
 
 /* Tile binning: every (triangle, tile) pair of the triangle's rectangle is
  * tested conservatively against the tile's display region over the tile's
- * own time window; surviving pairs are compacted (wave ballot + prefix) and
- * gathered into per-tile triangle lists.  Needs pr_bound first. */
+ * own time window, and for tiles of 16 and 32 pixels against each quadrant
+ * of the tile; surviving pairs are compacted (wave ballot + prefix) and
+ * gathered into per-tile triangle lists that carry the quadrant mask of
+ * each triangle (the ray cast skips the quadrants a triangle cannot
+ * cover).  Needs pr_bound first. */
 int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
            void *ws, size_t ws_bytes, void *stream);
 
@@ -240,7 +243,11 @@ const char *pr_status_string(int code);
 
 /* Copies one view's tile lists to host memory for inspection:
  * offsets: int32 [tiles+1] (host), lists: int32 [cap] (host; may be NULL to
- * query).  *ntiles receives the tile count, *npairs the list length.
+ * query).  Each list entry holds the triangle index in bits 0..27 and, in
+ * bits 28..31, the mask of the tile's quadrants (bit qx + 2 qy: the
+ * tile/2 x tile/2 pixels at column offset qx tile/2, row offset qy tile/2)
+ * the triangle may cover; 8x8 tiles are not split (mask 0xF).
+ * *ntiles receives the tile count, *npairs the list length.
  * Synchronises `stream`.  Used by tests of the bound's conservativeness. */
 int pr_debug_tile_lists(const pr_mesh *meshes, int nm, const pr_view *views, int nv,
                         const pr_tuning *tuning, const void *ws, size_t ws_bytes, int view,
@@ -255,8 +262,9 @@ int pr_debug_tile_lists(const pr_mesh *meshes, int nm, const pr_view *views, int
  *   plane cuts the triangle; the window is the whole frame).
  * pr_host_tile_rect: the triangle's inclusive tile rectangle
  *   rect = {x0, y0, x1, y1}; returns 0 if culled, 1 otherwise.
- * pr_host_tile_test: 1 if the pair (triangle f, tile (tx, ty)) survives
- *   binning, 0 if it is rejected (or the triangle is culled). */
+ * pr_host_tile_test: the quadrant mask binning gives the pair (triangle f,
+ *   tile (tx, ty)) (as in pr_debug_tile_lists); 0 if the pair is rejected
+ *   (or the triangle is culled). */
 int pr_host_time_interval(const pr_mesh *mesh, int32_t f, const pr_view *view, double *t);
 int pr_host_tile_rect(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t tile, int32_t *rect);
 int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t tile, int32_t tx,

@@ -45,6 +45,7 @@ int check_args(const pr_mesh *meshes, int nm, const pr_view *views, int nv, cons
         if (M.nv < 0 || M.nt < 0) return PR_ERR_INVALID;
         if (M.nt > 0 && (!M.v0 || !M.v1 || !M.tri || M.nv < 1)) return PR_ERR_INVALID;
         if ((int64_t)M.nt * 3 > INT32_MAX || (int64_t)M.nv * 3 > INT32_MAX) return PR_ERR_INVALID;
+        if ((uint32_t)M.nt > kListTriMask) return PR_ERR_INVALID;   // list entries hold 28-bit indices
     }
     for (int v = 0; v < nv; ++v) {
         const pr_view &V = views[v];
@@ -196,7 +197,7 @@ void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, D
     using C = RayCfg<TILE>;
     if (!(flags & PR_FLAG_PERSISTENT)) {
         hipLaunchKernelGGL((k_raycast<TILE, COUNT>), dim3(L.total_tiles), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
-                           at<uint32_t>(ws, L.toff), at<int32_t>(ws, L.lists), out, st);
+                           at<uint32_t>(ws, L.toff), at<uint32_t>(ws, L.lists), out, st);
         return;
     }
     Sched *S = at<Sched>(ws, L.sched);
@@ -210,7 +211,7 @@ void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, D
     if (!resident) resident = resident_blocks(k_raycast_queue<TILE, COUNT>, C::NT);
     const int grid = std::max(1, std::min(L.total_tiles, resident));
     hipLaunchKernelGGL((k_raycast_queue<TILE, COUNT>), dim3(grid), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
-                       at<uint32_t>(ws, L.toff), at<int32_t>(ws, L.lists), out, st, at<int32_t>(ws, L.order),
+                       at<uint32_t>(ws, L.toff), at<uint32_t>(ws, L.lists), out, st, at<int32_t>(ws, L.order),
                        L.total_tiles);
 }
 
@@ -263,7 +264,7 @@ int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     PR_PREP();
     fill_u32(at<void>(ws, L.tcount), 0u, (int64_t)L.total_tiles + 1, s);
     fill_u32(&st->num_pairs, 0u, 1, s);
-    hipLaunchKernelGGL(k_tiles, dim3((L.total_tiles + 255) / 256), dim3(256), 0, s, T, at<TileInfo>(ws, L.tinfo));
+    hipLaunchKernelGGL(k_tiles, dim3((L.total_tiles * 4 + 255) / 256), dim3(256), 0, s, T, at<TileInfo>(ws, L.tinfo));
     if (L.total_tri_blocks > 0)
         hipLaunchKernelGGL(k_bin, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<TriBound>(ws, L.tb),
                            at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<Pair>(ws, L.pairs), L.cap, st);
@@ -480,7 +481,7 @@ int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32
     double w[4];
     if (kind == prg::kWindow) { w[0] = win[0]; w[1] = win[1]; w[2] = w[3] = 0.0; }
     else for (int k = 0; k < 4; ++k) w[k] = box[k];
-    return prg::tile_test(g, Ps, Pe, kind, w, w, tile, tx, ty) ? 1 : 0;
+    return prg::tile_mask(g, Ps, Pe, kind, w, w, tile, tx, ty);
 }
 
 }  // extern "C"

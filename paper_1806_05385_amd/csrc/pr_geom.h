@@ -393,12 +393,12 @@ PRG bool tile_rect(const Geom &g, const double box[4], int tile, int rect[4]) {
     return true;
 }
 
-// Display box of a tile's pixel centres and its frame-time window.
-PRG void tile_display(const Geom &g, int tile, int tx, int ty, double box[4], double tw[2]) {
-    int i0 = tx * tile, j0 = ty * tile;
-    int i1 = i0 + tile - 1, j1 = j0 + tile - 1;
+// Display-space box of the pixel centres of columns [i0, i1] x rows [j0, j1]
+// (clipped to the image; false if that leaves no pixel).
+PRG bool region_display(const Geom &g, int i0, int i1, int j0, int j1, double box[4]) {
     if (i1 > g.W - 1) i1 = g.W - 1;
     if (j1 > g.H - 1) j1 = g.H - 1;
+    if (i0 > i1 || j0 > j1) return false;
     double a0 = 2.0 * (i0 + 0.5) / g.W - 1.0, a1 = 2.0 * (i1 + 0.5) / g.W - 1.0;
     double b0 = 1.0 - 2.0 * (j1 + 0.5) / g.H, b1 = 1.0 - 2.0 * (j0 + 0.5) / g.H;
     radial_bbox(g, g.alpha, a0, a1, b0, b1, box);
@@ -406,6 +406,11 @@ PRG void tile_display(const Geom &g, int tile, int tx, int ty, double box[4], do
         double m = kSlackNdc * (1.0 + fabs(box[k]));
         box[k] += (k & 1) ? m : -m;
     }
+    return true;
+}
+
+// Frame-time window of the display points in a box.
+PRG void tile_time(const Geom &g, const double box[4], double tw[2]) {
     if (!g.rolling) { tw[0] = tw[1] = 0.0; return; }
     double umin = 1e300, umax = -1e300;
     for (int c = 0; c < 4; ++c) {
@@ -418,19 +423,31 @@ PRG void tile_display(const Geom &g, int tile, int tx, int ty, double box[4], do
     tw[1] = clamp01(umax + kSlackTime);
 }
 
-// Conservative test of one (triangle, tile) pair given the tile's display
-// box tb and time window tw (tile_display).  kWindow triangles: the window
-// is cut to the tile's own time window, the six projected end vertices of
-// that window bound the triangle's image over it, and a separating-axis
-// test (box axes and the edge normals of both end triangles) against the
-// tile's display box rejects the pair.  kClipped triangles use their
-// whole-frame display box.
-PRG bool tile_test_with(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double win[2],
-                        const double tri_box[4], const double tb[4], const double tw[2]) {
-    if (kind == kClipped)
-        return !(tri_box[1] < tb[0] || tri_box[0] > tb[1] || tri_box[3] < tb[2] || tri_box[2] > tb[3]);
-    double w0 = dmax(win[0], tw[0]), w1 = dmin(win[1], tw[1]);
-    if (w0 > w1) return false;
+// Display box of a tile's pixel centres and its frame-time window.
+PRG void tile_display(const Geom &g, int tile, int tx, int ty, double box[4], double tw[2]) {
+    region_display(g, tx * tile, tx * tile + tile - 1, ty * tile, ty * tile + tile - 1, box);
+    tile_time(g, box, tw);
+}
+
+// Quadrant k = qx + 2 qy of a tile: the (tile/2)^2 pixels at column offset
+// qx * tile/2 and row offset qy * tile/2.  Display box of its pixel centres;
+// false if the quadrant lies outside the image.
+PRG bool quad_display(const Geom &g, int tile, int tx, int ty, int k, double box[4]) {
+    const int h = tile / 2;
+    const int i0 = tx * tile + (k & 1) * h, j0 = ty * tile + (k >> 1) * h;
+    return region_display(g, i0, i0 + h - 1, j0, j0 + h - 1, box);
+}
+
+// The triangle over a time window [w0, w1] as the separating-axis test
+// sees it: for each of eight axes (x, y and the three edge normals of each
+// end triangle) the interval its six projected end vertices cover, widened
+// by a rounding margin.
+struct Hull {
+    double n[8][2];
+    double lo[8], hi[8];
+};
+
+PRG void hull_project(const Geom &g, const double Ps[3][3], const double Pe[3][3], double w0, double w1, Hull &h) {
     double q[6][2];
     for (int k = 0; k < 3; ++k)
         for (int e = 0; e < 2; ++e) {
@@ -443,7 +460,6 @@ PRG bool tile_test_with(const Geom &g, const double Ps[3][3], const double Pe[3]
         }
     double big = 1.0;
     for (int i = 0; i < 6; ++i) big = dmax(big, dmax(fabs(q[i][0]), fabs(q[i][1])));
-    // axes: x, y, and the three edge normals of each end triangle
     for (int a = 0; a < 8; ++a) {
         double n0, n1;
         if (a == 0) { n0 = 1; n1 = 0; }
@@ -460,23 +476,85 @@ PRG bool tile_test_with(const Geom &g, const double Ps[3][3], const double Pe[3]
             pmin = dmin(pmin, s);
             pmax = dmax(pmax, s);
         }
-        double bmin = 1e300, bmax = -1e300;
-        for (int c = 0; c < 4; ++c) {
-            double s = n0 * tb[c & 1] + n1 * tb[2 + (c >> 1)];
-            bmin = dmin(bmin, s);
-            bmax = dmax(bmax, s);
-        }
         double m = 1e-12 * (fabs(n0) + fabs(n1)) * big;
-        if (pmax < bmin - m || pmin > bmax + m) return false;
+        h.n[a][0] = n0;
+        h.n[a][1] = n1;
+        h.lo[a] = pmin - m;
+        h.hi[a] = pmax + m;
+    }
+}
+
+// True unless one of the hull's axes separates it from the box.
+PRG bool hull_meets_box(const Hull &h, const double b[4]) {
+    for (int a = 0; a < 8; ++a) {
+        const double n0 = h.n[a][0], n1 = h.n[a][1];
+        const double bmin = n0 * (n0 >= 0.0 ? b[0] : b[1]) + n1 * (n1 >= 0.0 ? b[2] : b[3]);
+        const double bmax = n0 * (n0 >= 0.0 ? b[1] : b[0]) + n1 * (n1 >= 0.0 ? b[3] : b[2]);
+        if (h.hi[a] < bmin || h.lo[a] > bmax) return false;
     }
     return true;
 }
 
-PRG bool tile_test(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double win[2],
-                   const double tri_box[4], int tile, int tx, int ty) {
-    double tb[4], tw[2];
-    tile_display(g, tile, tx, ty, tb, tw);
-    return tile_test_with(g, Ps, Pe, kind, win, tri_box, tb, tw);
+PRG bool box_meets_box(const double a[4], const double b[4]) {
+    return !(a[1] < b[0] || a[0] > b[1] || a[3] < b[2] || a[2] > b[3]);
+}
+
+// Conservative test of one (triangle, tile) pair given the tile's display
+// box tb and time window tw (tile_display).  Returns the 4-bit mask of the
+// tile's quadrants the triangle may cover; 0 rejects the pair.  kWindow
+// triangles: the window is cut to the tile's own time window, the six
+// projected end vertices of that window bound the triangle's image over it
+// (Hull), a separating-axis test against the tile's display box keeps the
+// pair, and each quadrant box qb[k] whose bit k is set in qvalid is kept
+// if it meets the hull's x and y extents.  kClipped triangles compare
+// their whole-frame display box.  qb == nullptr: the tile is not split
+// (mask 0xF when it is kept).
+PRG int tile_mask_with(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double win[2],
+                       const double tri_box[4], const double tb[4], const double tw[2], const double (*qb)[4],
+                       int qvalid) {
+    double ext[4];
+    if (kind == kClipped) {
+        if (!box_meets_box(tri_box, tb)) return 0;
+        for (int k = 0; k < 4; ++k) ext[k] = tri_box[k];
+    } else {
+        double w0 = dmax(win[0], tw[0]), w1 = dmin(win[1], tw[1]);
+        if (w0 > w1) return 0;
+        Hull h;
+        hull_project(g, Ps, Pe, w0, w1, h);
+        if (!hull_meets_box(h, tb)) return 0;
+        ext[0] = h.lo[0]; ext[1] = h.hi[0]; ext[2] = h.lo[1]; ext[3] = h.hi[1];
+    }
+    if (!qb) return 0xF;
+    int mask = 0;
+    for (int k = 0; k < 4; ++k)
+        if (((qvalid >> k) & 1) && box_meets_box(ext, qb[k])) mask |= 1 << k;
+    return mask;
+}
+
+// Tiles of 16 pixels and more are split into quadrants.
+PRG bool split_quads(int tile) { return tile >= 16; }
+
+// The same from the tile's coordinates (host tests), with the tile box and
+// window built as the device builds them: a split tile's box is the union
+// of its quadrants' boxes.
+PRG int tile_mask(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double win[2],
+                  const double tri_box[4], int tile, int tx, int ty) {
+    double tb[4], tw[2], qb[4][4];
+    if (!split_quads(tile)) {
+        tile_display(g, tile, tx, ty, tb, tw);
+        return tile_mask_with(g, Ps, Pe, kind, win, tri_box, tb, tw, nullptr, 0);
+    }
+    int qvalid = 0;
+    tb[0] = tb[2] = 1e300;
+    tb[1] = tb[3] = -1e300;
+    for (int k = 0; k < 4; ++k)
+        if (quad_display(g, tile, tx, ty, k, qb[k])) {
+            qvalid |= 1 << k;
+            tb[0] = dmin(tb[0], qb[k][0]); tb[1] = dmax(tb[1], qb[k][1]);
+            tb[2] = dmin(tb[2], qb[k][2]); tb[3] = dmax(tb[3], qb[k][3]);
+        }
+    tile_time(g, tb, tw);
+    return tile_mask_with(g, Ps, Pe, kind, win, tri_box, tb, tw, qb, qvalid);
 }
 
 }  // namespace prg

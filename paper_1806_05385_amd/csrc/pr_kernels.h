@@ -32,11 +32,20 @@ struct TriBound {
     double w[4];       // kWindow: time window w[0..1]; kClipped: display box
 };
 
-// Display-space box of a tile's pixel centres and its frame-time window.
+// Display-space box of a tile's pixel centres and its frame-time window;
+// for tiles split into quadrants, the box of each quadrant (qvalid bit k:
+// quadrant k holds pixels of the image).
 struct TileInfo {
     double box[4];
     double tw[2];
+    int32_t qvalid;
+    int32_t pad;
+    double qb[4][4];
 };
+
+// Tile-list entry: triangle index in bits 0..27, quadrant mask in 28..31.
+constexpr int kListTriBits = 28;
+constexpr uint32_t kListTriMask = (1u << kListTriBits) - 1u;
 
 // Per-pixel constants of a view (FP32 setup in the ray cast and shading).
 struct PixelConst {

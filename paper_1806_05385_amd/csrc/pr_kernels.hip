@@ -7,17 +7,17 @@
 //   k_bound    one lane per triangle, FP64: camera-space vertices, near plane,
 //              rolling time window, foveated tile rectangle, FP32
 //              intersection record (Sec. 3.2 "Bounding", Sec. 4)
-//   k_tiles    one lane per tile: display box of its pixel centres and its
-//              frame-time window
+//   k_tiles    four lanes per tile: display box of its pixel centres (and of
+//              each quadrant's) and its frame-time window
 //   k_bin      one block per 256 triangles: every (triangle, tile) candidate
 //              of the block's rectangles tested conservatively, survivors
 //              compacted with a wave ballot + mbcnt prefix and one atomic
 //              per wave
 //   k_scan_*   exclusive scan of per-tile counts (three phases)
 //   k_scatter  pairs -> per-tile triangle lists
-//   k_raycast  one block per tile: the tile's list staged through LDS in
-//              chunks, every pixel's ray (foveated position, rolling time)
-//              tested against every staged triangle, nearest packed
+//   k_raycast  one four-wave block per tile: every pixel's ray (foveated
+//              position, rolling time) tested against the triangles of the
+//              tile's list, read as wave-uniform scalar loads; nearest packed
 //              (depth bits << 32 | id) kept in registers (Sec. 3.2
 //              "Intersection")
 //   k_shade    rolling Lambert shading of resolved ids (Sec. 3.2 "Shading")
@@ -264,30 +264,68 @@ __global__ __launch_bounds__(256) void k_bound(const ViewTable *__restrict__ T, 
 // ---------------------------------------------------------------------------
 // per-tile display boxes
 // ---------------------------------------------------------------------------
+// Four lanes per tile, lane q computing quadrant q's box; a split tile's box
+// is the union of its quadrants' boxes (every pixel centre of the tile lies
+// in its quadrant's box), an unsplit tile's box is computed by lane 0.
 __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, TileInfo *__restrict__ ti) {
-    int gt = blockIdx.x * 256 + threadIdx.x;
-    if (gt >= T->total_tiles) return;
-    int v = find_view(T->tile_base, T->nv, gt);
+    const int gid = blockIdx.x * 256 + threadIdx.x;
+    const int gt = gid >> 2, q = gid & 3;
+    const bool valid = gt < T->total_tiles;
+    const int v = find_view(T->tile_base, T->nv, valid ? gt : 0);
     const ViewDev &vd = T->v[v];
-    int lt = gt - vd.tile_base;
     const prg::Geom &g = vd.g;
-    TileInfo t;
-    prg::tile_display(g, vd.tile, lt % vd.tiles_x, lt / vd.tiles_x, t.box, t.tw);
-    ti[gt] = t;
+    const int lt = (valid ? gt : 0) - vd.tile_base;
+    const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
+    const bool split = prg::split_quads(vd.tile);
+    double qb[4] = {1e300, -1e300, 1e300, -1e300};
+    bool qok = false;
+    if (valid && split) qok = prg::quad_display(g, vd.tile, tx, ty, q, qb);
+    double box[4] = {qb[0], qb[1], qb[2], qb[3]};
+    if (!qok) { box[0] = box[2] = 1e300; box[1] = box[3] = -1e300; }
+#pragma unroll
+    for (int o = 1; o < 4; o <<= 1) {   // union over the tile's four lanes
+        box[0] = prg::dmin(box[0], __shfl_xor(box[0], o, 64));
+        box[1] = prg::dmax(box[1], __shfl_xor(box[1], o, 64));
+        box[2] = prg::dmin(box[2], __shfl_xor(box[2], o, 64));
+        box[3] = prg::dmax(box[3], __shfl_xor(box[3], o, 64));
+    }
+    const unsigned long long okb = __ballot(qok);
+    if (!valid) return;
+    TileInfo &t = ti[gt];
+    if (split) {
+        for (int r = 0; r < 4; ++r) t.qb[q][r] = qok ? qb[r] : 0.0;
+    }
+    if (q != 0) return;
+    double tw[2];
+    if (split) {
+        prg::tile_time(g, box, tw);
+        t.qvalid = (int32_t)((okb >> (__lane_id() & ~3)) & 0xFull);
+    } else {
+        prg::tile_display(g, vd.tile, tx, ty, box, tw);
+        t.qvalid = 0;
+        for (int k = 0; k < 4; ++k)
+            for (int r = 0; r < 4; ++r) t.qb[k][r] = 0.0;
+    }
+    for (int r = 0; r < 4; ++r) t.box[r] = box[r];
+    t.tw[0] = tw[0];
+    t.tw[1] = tw[1];
+    t.pad = 0;
 }
 
 // ---------------------------------------------------------------------------
 // bin
 // ---------------------------------------------------------------------------
 struct Pair {
-    int32_t tile, slot, tri;   // global tile, slot in its list, triangle index in the view's mesh
+    int32_t tile, slot, tri;   // global tile, slot in its list, list entry (triangle index | quadrant mask)
 };
 
-// Candidates are tested in chunks of kBinChunk; their pass bits are kept in
-// LDS, the block reserves space for all survivors of a chunk with one global
-// atomic, and each survivor takes its place from a ballot + mbcnt prefix
-// inside its wave plus the wave's offset in the block.
-constexpr int kBinChunk = 256 * 16;
+// Candidates are tested in chunks of kBinChunk; their pass bits and the
+// four bit planes of their quadrant masks are kept in LDS (53 KB per block:
+// three blocks fit a CU), the block reserves space for all survivors of a
+// chunk with one global atomic, and each survivor takes its place from the
+// prefix of the pass bits.  A survivor's list entry carries its quadrant
+// mask above the triangle index.
+constexpr int kBinChunk = 256 * 8;
 
 __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, const TriBound *__restrict__ tb,
                                              const TileInfo *__restrict__ ti, uint32_t *__restrict__ tcount,
@@ -299,6 +337,7 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
     __shared__ int s_pref[257];
     __shared__ int s_tmp[72];
     __shared__ unsigned long long s_pass[kBinChunk / 64];
+    __shared__ unsigned long long s_quad[4][kBinChunk / 64];
     __shared__ int s_wpref[kBinChunk / 64];
     __shared__ uint32_t s_base;
     const int v = find_view(T->tri_block0, T->nv, blockIdx.x);
@@ -336,7 +375,7 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
         int mine = 0;
         const int cn_up = (cn + 255) & ~255;   // same trip count for every thread
         for (int i = j; i < cn_up; i += 256) {
-            bool pass = false;
+            int mask = 0;
             if (i < cn) {
                 const int c = c0 + i;
                 int lo = 0, hi = 255;
@@ -356,11 +395,27 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
                         Pe[k][r] = s_P[q][9 + 3 * k + r];
                     }
                 double w[4] = {s_w[q][0], s_w[q][1], s_w[q][2], s_w[q][3]};
-                const TileInfo t = ti[gt];
-                pass = prg::tile_test_with(g, Ps, Pe, s_kind[q], w, w, t.box, t.tw);
+                const TileInfo &t = ti[gt];
+                double tb[4] = {t.box[0], t.box[1], t.box[2], t.box[3]}, tw[2] = {t.tw[0], t.tw[1]};
+                if (prg::split_quads(vd.tile)) {
+                    double qb[4][4];
+                    for (int k = 0; k < 4; ++k)
+                        for (int r = 0; r < 4; ++r) qb[k][r] = t.qb[k][r];
+                    mask = prg::tile_mask_with(g, Ps, Pe, s_kind[q], w, w, tb, tw, qb, t.qvalid);
+                } else {
+                    mask = prg::tile_mask_with(g, Ps, Pe, s_kind[q], w, w, tb, tw, nullptr, 0);
+                }
             }
+            const bool pass = mask != 0;
             unsigned long long m = __ballot(pass);
-            if (lane == 0) s_pass[i >> 6] = m;
+            unsigned long long qm[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) qm[k] = __ballot((mask >> k) & 1);
+            if (lane == 0) {
+                s_pass[i >> 6] = m;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) s_quad[k][i >> 6] = qm[k];
+            }
             mine += pass;
         }
         // block total of survivors -> one reservation
@@ -401,8 +456,12 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
                 idx = s_base + (unsigned)s_wpref[i >> 6] + (unsigned)__popcll(m & ((1ull << (i & 63)) - 1ull));
             }
             if (surv) {
+                uint32_t mask = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) mask |= (uint32_t)((s_quad[k][i >> 6] >> (i & 63)) & 1ull) << k;
                 const unsigned slot = atomicAdd(&tcount[gt], 1u);
-                if ((int64_t)idx < cap) pairs[idx] = Pair{gt, (int32_t)slot, f0 + q};
+                if ((int64_t)idx < cap)
+                    pairs[idx] = Pair{gt, (int32_t)slot, (int32_t)((uint32_t)(f0 + q) | (mask << kListTriBits))};
             }
         }
         __syncthreads();
@@ -500,148 +559,269 @@ __device__ __forceinline__ void pixel_setup(const PixelConst &pc, int px, int py
     ry = (x1 - pc.cy) * pc.invfy;
 }
 
-__device__ __forceinline__ float edge_roll(float ax, float ay, float az, float bx, float by, float bz, float cx,
-                                           float cy, float cz, float t, float rx, float ry) {
-    float ex = fmaf(t, fmaf(t, cx, bx), ax);
-    float ey = fmaf(t, fmaf(t, cy, by), ay);
-    float ez = fmaf(t, fmaf(t, cz, bz), az);
-    return fmaf(ry, ey, fmaf(rx, ex, ez));
-}
-
-// Threads per tile block and pixels per lane: one wave for tiles up to
-// 16x16 (8x8: 1 px/lane, 16x16: 4 px/lane), four waves of 4 px/lane for
-// 32x32.  Several pixels per lane reuse each triangle record read from LDS.
-// The LDS chunk is sized so that a one-wave block holds 5.6 KB: 28 blocks
-// (7 waves per SIMD) fit a CU's 160 KB.
+// A tile block has four waves.  8x8 and 16x16 tiles: every wave covers the
+// whole tile (8x8: one pixel per lane; 16x16: four pixels per lane, pixel
+// slot k of every lane in quadrant k, so a triangle whose quadrant mask
+// lacks bit k skips slot k for the whole wave) and takes every fourth
+// triangle of the list; the four partial results are merged through LDS.
+// Splitting the list keeps the longest lists off the critical path.
+// 32x32 tiles: wave w covers quadrant w (16x16, four pixels per lane) and
+// takes the whole list, skipping triangles whose mask lacks quadrant w.
+// Triangle records are wave-uniform: they are read through the scalar data
+// path into SGPRs and used as the scalar operand of the vector FMAs.
 template <int TILE>
 struct RayCfg {
-    static constexpr int NT = TILE * TILE >= 1024 ? 256 : 64;
-    static constexpr int PPL = TILE * TILE / NT;
-    static constexpr int CHUNK = NT == 64 ? 32 : 64;
+    static constexpr int NT = 256;
+    static constexpr int PPL = TILE == 8 ? 1 : 4;
+    static constexpr bool SPLIT = TILE != 32;   // list split over the waves
 };
 
-// One tile of one view: stage the tile's list through LDS, test every pixel
-// against every staged triangle, keep the nearest packed (depth, id).
+// LDS of a tile block: 16x16 tiles share the per-pixel ray terms (8 floats
+// per pixel), then hold the waves' partial (depth, id) keys.
+constexpr int kRayLds = 8192;
+
+// Pixel of slot k of lane `lane` in wave `wv` of a tile.
+template <int TILE>
+__device__ __forceinline__ void slot_pixel(int tx, int ty, int wv, int lane, int k, int &px, int &py) {
+    if (TILE == 8) {
+        px = tx * 8 + (lane & 7);
+        py = ty * 8 + (lane >> 3);
+    } else {
+        const int ox = TILE == 32 ? (wv & 1) * 16 : 0, oy = TILE == 32 ? (wv >> 1) * 16 : 0;
+        px = tx * TILE + ox + (k & 1) * 8 + (lane & 7);
+        py = ty * TILE + oy + (k >> 1) * 8 + (lane >> 3);
+    }
+}
+
+// Ray terms of one pixel: w = (rx, ry, t rx, t ry, t, t^2 rx, t^2 ry, t^2).
+__device__ __forceinline__ void ray_terms(const PixelConst &pc, int px, int py, float w[8]) {
+    float t, rx, ry;
+    pixel_setup(pc, px, py, t, rx, ry);
+    const float t2 = t * t;
+    w[0] = rx; w[1] = ry;
+    w[2] = t * rx; w[3] = t * ry; w[4] = t;
+    w[5] = t2 * rx; w[6] = t2 * ry; w[7] = t2;
+}
+
+// One tile of one view: test the pixels against the tile's list, keep the
+// nearest packed (depth, id).  Rolling: e_k = r . c_k(t) = A_kz + w . (A_kx,
+// A_ky, B_kx, B_ky, B_kz, C_kx, C_ky, C_kz): 8 FMA per edge.  Every
+// operation on a shared edge's coefficients is odd in them, so the two
+// triangles of that edge evaluate exactly negated edge functions
+// (watertight).  Ends with a block barrier (the LDS is reused by the next
+// tile of a persistent block).
 template <bool ROLL, int TILE, bool COUNT>
 __device__ __forceinline__ void raycast_tile(const ViewDev &vd, int lt, const float4 *__restrict__ rec,
-                                             int beg, int end, const int32_t *__restrict__ lists,
-                                             float4 *s_rec, int32_t *__restrict__ out_id,
-                                             float *__restrict__ out_depth, DevStatus *__restrict__ st) {
+                                             int beg, int end, const uint32_t *__restrict__ lists,
+                                             int32_t *__restrict__ out_id, float *__restrict__ out_depth,
+                                             DevStatus *__restrict__ st, float4 *s_lds) {
     using C = RayCfg<TILE>;
     constexpr int RECW = ROLL ? kRecRoll : kRecStatic;
     const PixelConst &pc = vd.pc;
     const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
-    const float4 *vrec = rec + vd.rec_off;
-    float t[C::PPL], rx[C::PPL], ry[C::PPL];
+    const int lane = __lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const float *vrec = reinterpret_cast<const float *>(rec + vd.rec_off);
+    float w[C::PPL][8];
     unsigned long long best[C::PPL];
-    int nvalid = 0;
-#pragma unroll
-    for (int k = 0; k < C::PPL; ++k) {
-        int q = threadIdx.x + k * C::NT;
-        int px = tx * TILE + q % TILE, py = ty * TILE + q / TILE;
-        pixel_setup(pc, px, py, t[k], rx[k], ry[k]);
-        best[k] = ~0ull;
-        nvalid += (px < pc.W && py < pc.H);
-    }
-    unsigned hits = 0;
-    for (int base = beg; base < end; base += C::CHUNK) {
-        int n = min(C::CHUNK, end - base);
-        for (int i = threadIdx.x; i < n * RECW; i += C::NT) {
-            int r = i / RECW, c = i - r * RECW;
-            int f = lists[base + r];
-            s_rec[i] = vrec[(int64_t)f * RECW + c];
+    int nvk[C::PPL];
+    if (TILE == 16) {
+        // wave wv computes slot wv's ray terms; every wave reads all four
+        {
+            int px, py;
+            slot_pixel<TILE>(tx, ty, 0, lane, wv, px, py);
+            float ww[8];
+            ray_terms(pc, px, py, ww);
+            s_lds[(wv * 2 + 0) * 64 + lane] = make_float4(ww[0], ww[1], ww[2], ww[3]);
+            s_lds[(wv * 2 + 1) * 64 + lane] = make_float4(ww[4], ww[5], ww[6], ww[7]);
         }
         __syncthreads();
-        for (int jj = 0; jj < n; ++jj) {
-            const float4 *R = s_rec + jj * RECW;
-            if (ROLL) {
-                float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4], r5 = R[5], r6 = R[6], r7 = R[7];
-                bool pass[C::PPL];
-                bool any = false;
+#pragma unroll
+        for (int k = 0; k < C::PPL; ++k) {
+            const float4 a = s_lds[(k * 2 + 0) * 64 + lane], b = s_lds[(k * 2 + 1) * 64 + lane];
+            w[k][0] = a.x; w[k][1] = a.y; w[k][2] = a.z; w[k][3] = a.w;
+            w[k][4] = b.x; w[k][5] = b.y; w[k][6] = b.z; w[k][7] = b.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < C::PPL; ++k) {
+            int px, py;
+            slot_pixel<TILE>(tx, ty, wv, lane, k, px, py);
+            ray_terms(pc, px, py, w[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < C::PPL; ++k) {
+        int px, py;
+        slot_pixel<TILE>(tx, ty, wv, lane, k, px, py);
+        best[k] = ~0ull;
+        nvk[k] = (px < pc.W && py < pc.H);
+    }
+    unsigned hits = 0;
+    unsigned long long tests = 0;
+    if (COUNT) {
+#pragma unroll
+        for (int k = 0; k < C::PPL; ++k)
+            for (int o = 32; o > 0; o >>= 1) nvk[k] += __shfl_xor(nvk[k], o, 64);
+    }
+    float znear = pc.znear;
+    asm volatile("" : "+v"(znear));   // held in a VGPR through the loop
+    // Each iteration issues the current record's scalar loads together with
+    // the next list entry's, and waits for them once: the record values are
+    // pinned in SGPRs (so the quadrant branches do not reload them) and the
+    // next entry's address is ready when the iteration ends.
+    constexpr int STEP = C::SPLIT ? 4 : 1;
+    const int first = beg + (C::SPLIT ? wv : 0);
+    uint32_t next = first < end ? lists[first] : 0u;
+    for (int j = first; j < end; j += STEP) {
+        const uint32_t ent = __builtin_amdgcn_readfirstlane(next);
+        if (j + STEP < end) next = lists[j + STEP];
+        const uint32_t qm = TILE == 8 ? 0xFu : ent >> kListTriBits;
+        if (TILE == 32 && !((qm >> wv) & 1u)) continue;
+        const float *Rp = vrec + (size_t)(ent & kListTriMask) * (RECW * 4);
+        constexpr int NREC = ROLL ? 41 : 14;
+        float R[NREC];
+#pragma unroll
+        for (int i = 0; i < NREC; ++i) R[i] = Rp[i];
+#pragma unroll
+        for (int i = 0; i < NREC; ++i) asm volatile("" : "+s"(R[i]));
+        if (ROLL) {
+            bool pass[C::PPL];
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < C::PPL; ++k) {
+                pass[k] = false;
+                if (TILE == 16 && !((qm >> k) & 1u)) continue;
+                if (COUNT) tests += (unsigned)nvk[k];
+                float e[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const float *c = R + 9 * q;   // A_x A_y A_z B_x B_y B_z C_x C_y C_z
+                    float a = fmaf(w[k][0], c[0], c[2]);
+                    a = fmaf(w[k][1], c[1], a);
+                    a = fmaf(w[k][2], c[3], a);
+                    a = fmaf(w[k][3], c[4], a);
+                    a = fmaf(w[k][4], c[5], a);
+                    a = fmaf(w[k][5], c[6], a);
+                    a = fmaf(w[k][6], c[7], a);
+                    e[q] = fmaf(w[k][7], c[8], a);
+                }
+                const float lo = fminf(fminf(e[0], e[1]), e[2]), hi = fmaxf(fmaxf(e[0], e[1]), e[2]);
+                pass[k] = lo >= 0.0f || hi <= 0.0f;
+                any = any || pass[k];
+            }
+            if (any) {
+                // d0..d3 = R[27..30], N0 = R[31..33], N1 = R[34..36], N2 = R[37..39], id = R[40]
+                const float *N = R + 31;
 #pragma unroll
                 for (int k = 0; k < C::PPL; ++k) {
-                    float e0 = edge_roll(r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, t[k], rx[k], ry[k]);
-                    float e1 = edge_roll(r2.y, r2.z, r2.w, r3.x, r3.y, r3.z, r3.w, r4.x, r4.y, t[k], rx[k], ry[k]);
-                    float e2 = edge_roll(r4.z, r4.w, r5.x, r5.y, r5.z, r5.w, r6.x, r6.y, r6.z, t[k], rx[k], ry[k]);
-                    float lo = fminf(fminf(e0, e1), e2), hi = fmaxf(fmaxf(e0, e1), e2);
-                    pass[k] = lo >= 0.0f || hi <= 0.0f;
-                    any = any || pass[k];
-                }
-                if (any) {
-                    float4 r8 = R[8], r9 = R[9], r10 = R[10];
-#pragma unroll
-                    for (int k = 0; k < C::PPL; ++k) {
-                        if (!pass[k]) continue;
-                        float tk = t[k];
-                        // N(t): N0 = (r7.w, r8.x, r8.y), N1 = (r8.z, r8.w, r9.x), N2 = (r9.y, r9.z, r9.w)
-                        float nx = fmaf(tk, fmaf(tk, r9.y, r8.z), r7.w);
-                        float ny = fmaf(tk, fmaf(tk, r9.z, r8.w), r8.x);
-                        float nz = fmaf(tk, fmaf(tk, r9.w, r9.x), r8.y);
-                        float S = fmaf(ry[k], ny, fmaf(rx[k], nx, nz));
-                        float D = fmaf(tk, fmaf(tk, fmaf(tk, r7.z, r7.y), r7.x), r6.w);
-                        float z = D * __builtin_amdgcn_rcpf(S);
-                        if (z >= pc.znear && z <= 3.0e38f) {
-                            unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | __float_as_uint(r10.x);
-                            best[k] = key < best[k] ? key : best[k];
-                            if (COUNT) ++hits;
-                        }
+                    if (!pass[k]) continue;
+                    float S = fmaf(w[k][0], N[0], N[2]);
+                    S = fmaf(w[k][1], N[1], S);
+                    S = fmaf(w[k][2], N[3], S);
+                    S = fmaf(w[k][3], N[4], S);
+                    S = fmaf(w[k][4], N[5], S);
+                    S = fmaf(w[k][5], N[6], S);
+                    S = fmaf(w[k][6], N[7], S);
+                    S = fmaf(w[k][7], N[8], S);
+                    const float tk = w[k][4];
+                    const float D = fmaf(tk, fmaf(tk, fmaf(tk, R[30], R[29]), R[28]), R[27]);
+                    const float z = D * __builtin_amdgcn_rcpf(S);
+                    if (z >= znear && z <= 3.0e38f) {
+                        const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | __float_as_uint(R[40]);
+                        best[k] = key < best[k] ? key : best[k];
+                        if (COUNT) ++hits;
                     }
                 }
-            } else {
-                float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3];
+            }
+        } else {
 #pragma unroll
-                for (int k = 0; k < C::PPL; ++k) {
-                    float e0 = fmaf(ry[k], r0.y, fmaf(rx[k], r0.x, r0.z));
-                    float e1 = fmaf(ry[k], r1.x, fmaf(rx[k], r0.w, r1.y));
-                    float e2 = fmaf(ry[k], r1.w, fmaf(rx[k], r1.z, r2.x));
-                    float lo = fminf(fminf(e0, e1), e2), hi = fmaxf(fmaxf(e0, e1), e2);
-                    if (lo >= 0.0f || hi <= 0.0f) {
-                        // N0 = (r2.z, r2.w, r3.x), d0 = r2.y, id = r3.y
-                        float S = fmaf(ry[k], r2.w, fmaf(rx[k], r2.z, r3.x));
-                        float z = r2.y * __builtin_amdgcn_rcpf(S);
-                        if (z >= pc.znear && z <= 3.0e38f) {
-                            unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | __float_as_uint(r3.y);
-                            best[k] = key < best[k] ? key : best[k];
-                            if (COUNT) ++hits;
-                        }
+            for (int k = 0; k < C::PPL; ++k) {
+                if (TILE == 16 && !((qm >> k) & 1u)) continue;
+                if (COUNT) tests += (unsigned)nvk[k];
+                // A0 = R[0..2], A1 = R[3..5], A2 = R[6..8], d0 = R[9], N0 = R[10..12], id = R[13]
+                const float e0 = fmaf(w[k][1], R[1], fmaf(w[k][0], R[0], R[2]));
+                const float e1 = fmaf(w[k][1], R[4], fmaf(w[k][0], R[3], R[5]));
+                const float e2 = fmaf(w[k][1], R[7], fmaf(w[k][0], R[6], R[8]));
+                const float lo = fminf(fminf(e0, e1), e2), hi = fmaxf(fmaxf(e0, e1), e2);
+                if (lo >= 0.0f || hi <= 0.0f) {
+                    const float S = fmaf(w[k][1], R[11], fmaf(w[k][0], R[10], R[12]));
+                    const float z = R[9] * __builtin_amdgcn_rcpf(S);
+                    if (z >= znear && z <= 3.0e38f) {
+                        const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | __float_as_uint(R[13]);
+                        best[k] = key < best[k] ? key : best[k];
+                        if (COUNT) ++hits;
                     }
                 }
             }
         }
-        __syncthreads();
     }
+    if (C::SPLIT) {
+        // merge the four waves' keys: wave wv finishes slot wv (8x8: wave 0
+        // finishes the tile)
+        unsigned long long *s_key = reinterpret_cast<unsigned long long *>(s_lds);
+        __syncthreads();   // every wave has read its ray terms
 #pragma unroll
-    for (int k = 0; k < C::PPL; ++k) {
-        int q = threadIdx.x + k * C::NT;
-        int px = tx * TILE + q % TILE, py = ty * TILE + q / TILE;
-        if (px < pc.W && py < pc.H) {
-            int64_t p = (int64_t)py * pc.W + px;
-            bool miss = best[k] == ~0ull;
-            out_id[p] = miss ? -1 : (int32_t)(uint32_t)(best[k] & 0xffffffffu);
-            out_depth[p] = miss ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(best[k] >> 32));
+        for (int k = 0; k < C::PPL; ++k) s_key[(wv * C::PPL + k) * 64 + lane] = best[k];
+        __syncthreads();
+        const int slot = TILE == 16 ? wv : 0;
+        if (TILE == 16 || wv == 0) {
+            unsigned long long m = s_key[slot * 64 + lane];
+#pragma unroll
+            for (int o = 1; o < 4; ++o) {
+                const unsigned long long b = s_key[(o * C::PPL + slot) * 64 + lane];
+                m = b < m ? b : m;
+            }
+            int px, py;
+            slot_pixel<TILE>(tx, ty, 0, lane, slot, px, py);
+            if (px < pc.W && py < pc.H) {
+                const int64_t p = (int64_t)py * pc.W + px;
+                const bool miss = m == ~0ull;
+                out_id[p] = miss ? -1 : (int32_t)(uint32_t)(m & 0xffffffffu);
+                out_depth[p] = miss ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(m >> 32));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < C::PPL; ++k) {
+            int px, py;
+            slot_pixel<TILE>(tx, ty, wv, lane, k, px, py);
+            if (px < pc.W && py < pc.H) {
+                const int64_t p = (int64_t)py * pc.W + px;
+                const bool miss = best[k] == ~0ull;
+                out_id[p] = miss ? -1 : (int32_t)(uint32_t)(best[k] & 0xffffffffu);
+                out_depth[p] = miss ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(best[k] >> 32));
+            }
         }
     }
     if (COUNT) {
-        // tests = list length x valid pixels of the tile; hits summed per wave
+        // tests: valid pixels of the slots a triangle was evaluated on
         unsigned long long h = hits;
         for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
-        int nv = nvalid;
-        for (int o = 32; o > 0; o >>= 1) nv += __shfl_xor(nv, o, 64);
-        if (__lane_id() == 0) {
+        if (lane == 0) {
             atomicAdd(&st->hits, h);
-            atomicAdd(&st->tests, (unsigned long long)nv * (unsigned long long)(end - beg));
+            atomicAdd(&st->tests, tests);
         }
     }
+    __syncthreads();
+}
+
+// Block b -> tile: consecutive blocks go to the eight XCDs in turn, so XCD
+// x is given the x-th contiguous eighth of the tiles (neighbouring tiles
+// share triangle records in that XCD's L2).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
 template <int TILE, bool COUNT>
 __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable *__restrict__ T,
                                                                const float4 *__restrict__ rec,
                                                                const uint32_t *__restrict__ toff,
-                                                               const int32_t *__restrict__ lists, RayOut out,
+                                                               const uint32_t *__restrict__ lists, RayOut out,
                                                                DevStatus *__restrict__ st) {
-    __shared__ float4 s_rec[RayCfg<TILE>::CHUNK * kRecRoll];
-    const int gt = blockIdx.x;
+    __shared__ float4 s_lds[kRayLds / 16];
+    const int gt = xcd_tile(blockIdx.x, gridDim.x);
     const int v = find_view(T->tile_base, T->nv, gt);
     const ViewDev &vd = T->v[v];
     int beg = 0, end = 0;
@@ -650,9 +830,9 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
         end = (int)toff[gt + 1];
     }
     if (vd.rolling)
-        raycast_tile<true, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, s_rec, out.id[v], out.depth[v], st);
+        raycast_tile<true, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, out.id[v], out.depth[v], st, s_lds);
     else
-        raycast_tile<false, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, s_rec, out.id[v], out.depth[v], st);
+        raycast_tile<false, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, out.id[v], out.depth[v], st, s_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -705,9 +885,9 @@ __global__ __launch_bounds__(256) void k_sched_scatter(const uint32_t *__restric
 template <int TILE, bool COUNT>
 __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast_queue(
     const ViewTable *__restrict__ T, const float4 *__restrict__ rec, const uint32_t *__restrict__ toff,
-    const int32_t *__restrict__ lists, RayOut out, DevStatus *__restrict__ st, const int32_t *__restrict__ order,
+    const uint32_t *__restrict__ lists, RayOut out, DevStatus *__restrict__ st, const int32_t *__restrict__ order,
     int ntiles) {
-    __shared__ float4 s_rec[RayCfg<TILE>::CHUNK * kRecRoll];
+    __shared__ float4 s_lds[kRayLds / 16];
     const bool ovf = st->overflow != 0;
     // block b takes items b, b + grid, b + 2 grid, ... of the longest-first
     // order: the first round holds the longest lists, no queue atomics
@@ -721,10 +901,11 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast_queue(
             end = (int)toff[gt + 1];
         }
         if (vd.rolling)
-            raycast_tile<true, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, s_rec, out.id[v], out.depth[v], st);
+            raycast_tile<true, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, out.id[v], out.depth[v], st,
+                                            s_lds);
         else
-            raycast_tile<false, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, s_rec, out.id[v], out.depth[v], st);
-        __syncthreads();
+            raycast_tile<false, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, out.id[v], out.depth[v], st,
+                                             s_lds);
     }
 }
 

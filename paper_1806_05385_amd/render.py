@@ -171,7 +171,8 @@ class Renderer:
         return self.outputs
 
     def tile_lists(self, view: int):
-        """(offsets [tiles+1], lists [pairs]) of one view, copied to the host."""
+        """(offsets [tiles+1], triangle [pairs], quadrant mask [pairs]) of one
+        view's tile lists, copied to the host."""
         import numpy as np
         ntiles = ctypes.c_int32(0)
         npairs = ctypes.c_int64(0)
@@ -184,7 +185,8 @@ class Renderer:
         B.check('pr_debug_tile_lists', self.L.pr_debug_tile_lists(
             *a[:5], *a[5:], view, off.ctypes.data_as(B.c_int32_p), lst.ctypes.data_as(B.c_int32_p),
             lst.shape[0], ctypes.byref(ntiles), ctypes.byref(npairs), ctypes.c_void_p(_stream_handle())))
-        return off, lst[:npairs.value]
+        ent = lst[:npairs.value].view(np.uint32)
+        return off, (ent & 0x0FFFFFFF).astype(np.int32), (ent >> 28).astype(np.int32)
 
 
 class Batch:

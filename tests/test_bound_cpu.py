@@ -47,7 +47,13 @@ def _check_hits(scene, tile, max_pix=None, seed=0):
         t = oracle.pixel_setup(view, p)[2]
         ok = kind in (1, 2) and r is not None and r[0] <= tx <= r[2] and r[1] <= ty <= r[3]
         ok = ok and (kind == 2 or w[0] <= t <= w[1])
-        ok = ok and L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), tile, tx, ty) == 1
+        mask = L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), tile, tx, ty)
+        if tile >= 16:   # the pixel's quadrant of its tile must be in the pair's mask
+            h = tile // 2
+            quad = int(i % tile >= h) + 2 * int(j % tile >= h)
+            ok = ok and mask > 0 and (mask >> quad) & 1 == 1
+        else:
+            ok = ok and mask == 0xF
         if not ok:
             missed.append((p, f, kind, tuple(w), r, t))
     return len(hp), missed, cache
@@ -122,10 +128,24 @@ def test_bound_is_tight_enough_to_reject_pairs():
         for ty in range(rect[1], rect[3] + 1):
             for tx in range(rect[0], rect[2] + 1):
                 cand += 1
-                kept += L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), 8, tx, ty)
+                kept += L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), 8, tx, ty) != 0
     tiles = 16 * 16
     assert cand < 0.1 * tiles * mesh.nt
     assert kept <= cand
+    # quadrant masks of 16-pixel tiles: kept quadrants never exceed kept
+    # tiles x 4, and most kept pairs skip at least one quadrant
+    quads = pairs = 0
+    for f in range(mesh.nt):
+        if L.pr_host_tile_rect(ctypes.byref(hm), f, ctypes.byref(pv), 16, rect) != 1:
+            continue
+        for ty in range(rect[1], rect[3] + 1):
+            for tx in range(rect[0], rect[2] + 1):
+                m = L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), 16, tx, ty)
+                assert 0 <= m <= 0xF
+                if m:
+                    pairs += 1
+                    quads += bin(m).count('1')
+    assert pairs > 0 and quads < 0.6 * 4 * pairs
 
 
 def _brute_window(mesh, view, f, n=20001):

@@ -100,22 +100,30 @@ def test_large_full_size_sampled():
 
 def test_bound_invariant_on_device_lists():
     """Every oracle hit (occluded or not) lies in a tile whose device-built
-    list holds the triangle (the bound never drops a covered fragment)."""
+    list holds the triangle, with the pixel's quadrant in the entry's mask
+    (the bound never drops a covered fragment)."""
     sc = scenegen.make_moving_soup(seed=32, n_tris=800, width=160, height=144, alpha=2.0, roll=(1.0, 0.0),
                                    yaw_deg_s=3000.0, obj_speed=30.0, side=(0.03, 0.5))
-    for tile in (8, 16):
+    for tile in (8, 16, 32):
         r, out = _render(sc, tile)
-        off, lst = r.tile_lists(0)
+        off, lst, qm = r.tile_lists(0)
         v = sc.views[0]
         hp, ht, he = oracle.Oracle(sc.meshes[0], v).all_hits()
         tiles_x = (v.width + tile - 1) // tile
         tid = (hp // v.width // tile) * tiles_x + (hp % v.width) // tile
-        members = set()
+        h = tile // 2
+        quad = ((hp % v.width) % tile >= h).astype(int) + 2 * ((hp // v.width) % tile >= h).astype(int)
+        members = {}
         for t in np.unique(tid):
-            for f in lst[off[t]:off[t + 1]]:
-                members.add((int(t), int(f)))
-        missing = [(int(p), int(f)) for p, f, t in zip(hp, ht, tid) if (int(t), int(f)) not in members]
-        assert len(hp) > 2000 and not missing, missing[:5]
+            for f, m in zip(lst[off[t]:off[t + 1]], qm[off[t]:off[t + 1]]):
+                members[(int(t), int(f))] = int(m)
+        missing = [(int(p), int(f)) for p, f, t, q in zip(hp, ht, tid, quad)
+                   if (members.get((int(t), int(f)), 0) >> (int(q) if tile >= 16 else 0)) & 1 == 0]
+        assert len(hp) > 2000 and not missing, (tile, missing[:5])
+        if tile == 8:
+            assert (qm == 0xF).all()
+        else:
+            assert (qm > 0).all() and (qm <= 0xF).all()
         # lists hold distinct triangles
         for t in range(len(off) - 1):
             seg = lst[off[t]:off[t + 1]]
