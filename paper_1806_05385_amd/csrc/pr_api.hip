@@ -196,7 +196,8 @@ void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, D
                       hipStream_t s) {
     using C = RayCfg<TILE>;
     if (!(flags & PR_FLAG_PERSISTENT)) {
-        hipLaunchKernelGGL((k_raycast<TILE, COUNT>), dim3(L.total_tiles), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
+        hipLaunchKernelGGL((k_raycast<TILE, COUNT>), dim3(ray_items<TILE>(L.total_tiles)), dim3(C::NT), 0, s, T,
+                           at<float4>(ws, L.rec),
                            at<uint32_t>(ws, L.toff), at<uint32_t>(ws, L.lists), out, st);
         return;
     }
@@ -209,10 +210,11 @@ void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, D
                        at<int32_t>(ws, L.order));
     static int resident = 0;
     if (!resident) resident = resident_blocks(k_raycast_queue<TILE, COUNT>, C::NT);
-    const int grid = std::max(1, std::min(L.total_tiles, resident));
+    const int nitems = ray_items<TILE>(L.total_tiles);
+    const int grid = std::max(1, std::min(nitems, resident));
     hipLaunchKernelGGL((k_raycast_queue<TILE, COUNT>), dim3(grid), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
                        at<uint32_t>(ws, L.toff), at<uint32_t>(ws, L.lists), out, st, at<int32_t>(ws, L.order),
-                       L.total_tiles);
+                       nitems);
 }
 
 template <int TILE>
@@ -386,8 +388,13 @@ int pr_status_read(const void *ws, size_t ws_bytes, pr_status *out, void *stream
     out->nonfinite = d.nonfinite;
     out->pairs_required = (int64_t)d.pairs_required;
     out->pairs_total = (int64_t)d.pairs_total;
-    out->tests = (int64_t)d.tests;
-    out->hits = (int64_t)d.hits;
+    unsigned long long tests = d.tests, hits = d.hits;
+    for (int i = 0; i < kCountSlots; ++i) {
+        tests += d.cnt[i][0];
+        hits += d.cnt[i][1];
+    }
+    out->tests = (int64_t)tests;
+    out->hits = (int64_t)hits;
     return PR_OK;
 }
 

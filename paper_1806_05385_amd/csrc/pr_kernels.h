@@ -9,20 +9,27 @@
 
 namespace prk {
 
-// Intersection record of one triangle, written by the bound kernel.
-// Rolling views (float4 x 11): for edge k (opposite vertex k) the camera-
-// space edge-plane normal c_k(t) = P_a(t) x P_b(t) = A_k + t B_k + t^2 C_k,
-// laid out A0 B0 C0 A1 B1 C1 A2 B2 C2 (27 floats); the triple product
-// D(t) = P_0(t) . (P_1(t) x P_2(t)) = d0 + t d1 + t^2 d2 + t^3 d3; the face
-// normal N(t) = (P_1 - P_0) x (P_2 - P_0) = N0 + t N1 + t^2 N2; the
-// triangle index (int bits); 3 pad.  The ray r = (rx, ry, 1) at time t
-// passes edge k on the side sign(e_k), e_k = r . c_k(t); the hit depth is
-// z = D(t) / (r . N(t)).  N is stored separately although it equals
-// sum_k c_k: near grazing incidence r . N is much smaller than the edge
-// terms and their sum would lose it to cancellation in FP32.
-// Non-rolling views (float4 x 4, t = 0): A0 A1 A2 d0 N0 id pad pad.
+// Intersection record of one triangle, written by the bound kernel.  For
+// edge o (opposite vertex o) the camera-space edge-plane normal
+// c_o(t) = P_a(t) x P_b(t) = A_o + t B_o + t^2 C_o; the ray r = (rx, ry, 1)
+// at time t passes edge o on the side sign(e_o), e_o = r . c_o(t).  The face
+// normal N(t) = (P_1 - P_0) x (P_2 - P_0) = N0 + t N1 + t^2 N2 gives the hit
+// depth z = D(t) / (r . N(t)), D(t) = P_0(t) . (P_1(t) x P_2(t)) = d0 + t d1
+// + t^2 d2 + t^3 d3.  N is stored although it equals sum_o c_o: near grazing
+// incidence r . N is much smaller than the edge terms and their sum would
+// lose it to cancellation in FP32.  Every quantity is linear in the ray
+// terms (rx, ry, t rx, t ry, t, t^2 rx, t^2 ry, t^2) plus a constant; the
+// record stores, for outputs o = e_0, e_1, e_2, S = r . N, the coefficient
+// matrix M[k][o] (k: ray term) at 4k + o, then the constants (A_oz, N0z),
+// d0..d3 and the triangle index.  Rolling views: 11 float4 (M 32, constants
+// 4 at 32, d 4 at 36, id at 40, 3 pad).  Non-rolling views (t = 0): 6 float4
+// (M for terms rx, ry and two zero terms: 16, constants 4 at 16, d0 at 20,
+// id at 21, 2 pad).
 constexpr int kRecRoll = 11;
-constexpr int kRecStatic = 4;
+constexpr int kRecStatic = 6;
+
+// Spread slots of the PR_FLAG_COUNT counters (tests, hits).
+constexpr int kCountSlots = 64;
 
 // Per-triangle bound (64 bytes).
 struct TriBound {
@@ -114,6 +121,7 @@ struct DevStatus {
     unsigned long long hits;
     uint32_t num_pairs;    // emission cursor of the frame's (triangle, tile) pairs
     uint32_t pad;
+    unsigned long long cnt[kCountSlots][2];   // ray-cast tests, hits, spread over slots
 };
 
 // Tile queue of the persistent ray cast: power-of-two list-length buckets.

@@ -222,39 +222,45 @@ __global__ __launch_bounds__(256) void k_bound(const ViewTable *__restrict__ T, 
         d0 = d1 = d2 = d3 = 0.0;
         for (int r = 0; r < 3; ++r) N0[r] = N1[r] = N2[r] = 0.0;
     }
+    // Record (layout in RecLayout): M[k][o] = coefficient of ray term k in
+    // output o (e_0, e_1, e_2: the edge functions r . c_o(t); S = r . N(t)),
+    // the terms being (rx, ry, t rx, t ry, t, t^2 rx, t^2 ry, t^2) and the
+    // constant (term 1) stored apart.
+    double M[8][4], K4[4];
+    for (int o = 0; o < 4; ++o) {
+        const double *a0 = o < 3 ? A[o] : N0, *b0 = o < 3 ? B[o] : N1, *c0 = o < 3 ? C[o] : N2;
+        M[0][o] = a0[0]; M[1][o] = a0[1];
+        M[2][o] = b0[0]; M[3][o] = b0[1]; M[4][o] = b0[2];
+        M[5][o] = c0[0]; M[6][o] = c0[1]; M[7][o] = c0[2];
+        K4[o] = a0[2];
+    }
     if (vd.rolling) {
         float out[44];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 8; ++k)
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                out[9 * k + r] = (float)A[k][r];
-                out[9 * k + 3 + r] = (float)B[k][r];
-                out[9 * k + 6 + r] = (float)C[k][r];
-            }
-        out[27] = (float)d0; out[28] = (float)d1; out[29] = (float)d2; out[30] = (float)d3;
+            for (int o = 0; o < 4; ++o) out[4 * k + o] = (float)M[k][o];
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            out[31 + r] = (float)N0[r];
-            out[34 + r] = (float)N1[r];
-            out[37 + r] = (float)N2[r];
-        }
+        for (int o = 0; o < 4; ++o) out[32 + o] = (float)K4[o];
+        out[36] = (float)d0; out[37] = (float)d1; out[38] = (float)d2; out[39] = (float)d3;
         out[40] = __int_as_float(f);
         out[41] = out[42] = out[43] = 0.0f;
         float4 *dst = rec + vd.rec_off + (int64_t)f * kRecRoll;
 #pragma unroll
         for (int q = 0; q < kRecRoll; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
     } else {
-        float out[16];
+        float out[24];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int r = 0; r < 3; ++r) out[3 * k + r] = (float)A[k][r];
-        out[9] = (float)d0;
-#pragma unroll
-        for (int r = 0; r < 3; ++r) out[10 + r] = (float)N0[r];
-        out[13] = __int_as_float(f);
-        out[14] = out[15] = 0.0f;
+        for (int o = 0; o < 4; ++o) {
+            out[o] = (float)M[0][o];
+            out[4 + o] = (float)M[1][o];
+            out[8 + o] = 0.0f;
+            out[12 + o] = 0.0f;
+            out[16 + o] = (float)K4[o];
+        }
+        out[20] = (float)d0;
+        out[21] = __int_as_float(f);
+        out[22] = out[23] = 0.0f;
         float4 *dst = rec + vd.rec_off + (int64_t)f * kRecStatic;
 #pragma unroll
         for (int q = 0; q < kRecStatic; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
@@ -559,40 +565,6 @@ __device__ __forceinline__ void pixel_setup(const PixelConst &pc, int px, int py
     ry = (x1 - pc.cy) * pc.invfy;
 }
 
-// A tile block has four waves.  8x8 and 16x16 tiles: every wave covers the
-// whole tile (8x8: one pixel per lane; 16x16: four pixels per lane, pixel
-// slot k of every lane in quadrant k, so a triangle whose quadrant mask
-// lacks bit k skips slot k for the whole wave) and takes every fourth
-// triangle of the list; the four partial results are merged through LDS.
-// Splitting the list keeps the longest lists off the critical path.
-// 32x32 tiles: wave w covers quadrant w (16x16, four pixels per lane) and
-// takes the whole list, skipping triangles whose mask lacks quadrant w.
-// Triangle records are wave-uniform: they are read through the scalar data
-// path into SGPRs and used as the scalar operand of the vector FMAs.
-template <int TILE>
-struct RayCfg {
-    static constexpr int NT = 256;
-    static constexpr int PPL = TILE == 8 ? 1 : 4;
-    static constexpr bool SPLIT = TILE != 32;   // list split over the waves
-};
-
-// LDS of a tile block: 16x16 tiles share the per-pixel ray terms (8 floats
-// per pixel), then hold the waves' partial (depth, id) keys.
-constexpr int kRayLds = 8192;
-
-// Pixel of slot k of lane `lane` in wave `wv` of a tile.
-template <int TILE>
-__device__ __forceinline__ void slot_pixel(int tx, int ty, int wv, int lane, int k, int &px, int &py) {
-    if (TILE == 8) {
-        px = tx * 8 + (lane & 7);
-        py = ty * 8 + (lane >> 3);
-    } else {
-        const int ox = TILE == 32 ? (wv & 1) * 16 : 0, oy = TILE == 32 ? (wv >> 1) * 16 : 0;
-        px = tx * TILE + ox + (k & 1) * 8 + (lane & 7);
-        py = ty * TILE + oy + (k >> 1) * 8 + (lane >> 3);
-    }
-}
-
 // Ray terms of one pixel: w = (rx, ry, t rx, t ry, t, t^2 rx, t^2 ry, t^2).
 __device__ __forceinline__ void ray_terms(const PixelConst &pc, int px, int py, float w[8]) {
     float t, rx, ry;
@@ -603,213 +575,256 @@ __device__ __forceinline__ void ray_terms(const PixelConst &pc, int px, int py, 
     w[5] = t2 * rx; w[6] = t2 * ry; w[7] = t2;
 }
 
-// One tile of one view: test the pixels against the tile's list, keep the
-// nearest packed (depth, id).  Rolling: e_k = r . c_k(t) = A_kz + w . (A_kx,
-// A_ky, B_kx, B_ky, B_kz, C_kx, C_ky, C_kz): 8 FMA per edge.  Every
-// operation on a shared edge's coefficients is odd in them, so the two
-// triangles of that edge evaluate exactly negated edge functions
-// (watertight).  Ends with a block barrier (the LDS is reused by the next
-// tile of a persistent block).
-template <bool ROLL, int TILE, bool COUNT>
-__device__ __forceinline__ void raycast_tile(const ViewDev &vd, int lt, const float4 *__restrict__ rec,
+// The ray cast works on 8x8 cells: one wave per cell, four waves (cells) per
+// block.  8x8 tiles: a block takes four consecutive tiles; 16x16 tiles: a
+// block takes one tile, wave w its quadrant w; 32x32 tiles: a block takes
+// one quadrant of a tile, wave w one 8x8 cell of it.  A wave walks its
+// tile's list, keeps the triangles whose quadrant mask covers its cell
+// (ballot + mbcnt into a per-wave LDS buffer) and tests them four at a time
+// against its 64 pixels with MFMA.
+//
+// The edge functions of a group of four triangles at 16 pixels are one
+// v_mfma_f32_16x16x4f32 product per four ray terms: rows (A operand) are
+// (triangle g, output o) with o = e_0, e_1, e_2 and the depth denominator
+// S = r . N(t); columns (B operand) are pixels; K runs over the ray terms
+// w = (rx, ry, t rx, t ry, t, t^2 rx, t^2 ry, t^2) (two products; one for
+// non-rolling views, whose terms are (rx, ry, 0, 0)), and the accumulator
+// starts at the constant terms.  Lane l then holds e_0, e_1, e_2, S of
+// triangle l / 16 at pixel l % 16 of the 16-pixel block.  Every operation
+// on a shared edge's coefficients is odd in them (products and sums of
+// exactly negated values round to exactly negated results), so the two
+// triangles of an edge evaluate exactly negated edge functions
+// (watertight).
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int TILE>
+struct RayCfg {
+    static constexpr int NT = 256;                    // four cells per block
+};
+
+// Work items (blocks) of a frame for a tile size.
+template <int TILE>
+__host__ __device__ inline int ray_items(int ntiles) {
+    return TILE == 8 ? (ntiles + 3) / 4 : (TILE == 16 ? ntiles : 4 * ntiles);
+}
+
+// Per-wave buffer of selected list entries: up to 3 carried + 64 new.
+constexpr int kSelCap = 68;
+
+// Record layout (floats).  Rolling: M[k][o] at 4k + o (k: the eight ray
+// terms, o: e_0, e_1, e_2, S), constants at 32..35, d0..d3 at 36..39, id at
+// 40.  Non-rolling: M[k][o] at 4k + o for k < 4 (terms rx, ry, 0, 0),
+// constants at 16..19, d0 at 20, id at 21.
+template <bool ROLL>
+struct RecLayout {
+    static constexpr int W = ROLL ? 4 * kRecRoll : 4 * kRecStatic;
+    static constexpr int C = ROLL ? 32 : 16;
+    static constexpr int D = ROLL ? 36 : 20;
+    static constexpr int ID = ROLL ? 40 : 21;
+};
+
+// One 8x8 cell of one view.  (cx0, cy0): its first pixel; q: the quadrant
+// bit its list entries must carry (-1: no filter).
+template <bool ROLL, bool COUNT>
+__device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0, int q, const float *__restrict__ vrec,
                                              int beg, int end, const uint32_t *__restrict__ lists,
                                              int32_t *__restrict__ out_id, float *__restrict__ out_depth,
-                                             DevStatus *__restrict__ st, float4 *s_lds) {
-    using C = RayCfg<TILE>;
-    constexpr int RECW = ROLL ? kRecRoll : kRecStatic;
+                                             unsigned long long *__restrict__ cnt, int32_t *s_sel) {
+    using RL = RecLayout<ROLL>;
     const PixelConst &pc = vd.pc;
-    const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
     const int lane = __lane_id();
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const float *vrec = reinterpret_cast<const float *>(rec + vd.rec_off);
-    float w[C::PPL][8];
-    unsigned long long best[C::PPL];
-    int nvk[C::PPL];
-    if (TILE == 16) {
-        // wave wv computes slot wv's ray terms; every wave reads all four
-        {
-            int px, py;
-            slot_pixel<TILE>(tx, ty, 0, lane, wv, px, py);
-            float ww[8];
-            ray_terms(pc, px, py, ww);
-            s_lds[(wv * 2 + 0) * 64 + lane] = make_float4(ww[0], ww[1], ww[2], ww[3]);
-            s_lds[(wv * 2 + 1) * 64 + lane] = make_float4(ww[4], ww[5], ww[6], ww[7]);
-        }
-        __syncthreads();
+    const int kq = lane >> 4, jl = lane & 15;
+    // B operands: ray terms of pixel 16 b + jl of the cell, term kq (+ 4)
+    float bt0[4], bt1[4], tb[4];
 #pragma unroll
-        for (int k = 0; k < C::PPL; ++k) {
-            const float4 a = s_lds[(k * 2 + 0) * 64 + lane], b = s_lds[(k * 2 + 1) * 64 + lane];
-            w[k][0] = a.x; w[k][1] = a.y; w[k][2] = a.z; w[k][3] = a.w;
-            w[k][4] = b.x; w[k][5] = b.y; w[k][6] = b.z; w[k][7] = b.w;
+    for (int b = 0; b < 4; ++b) {
+        const int j = 16 * b + jl;
+        float w[8];
+        ray_terms(pc, cx0 + (j & 7), cy0 + (j >> 3), w);
+        if (ROLL) {
+            bt0[b] = kq == 0 ? w[0] : kq == 1 ? w[1] : kq == 2 ? w[2] : w[3];
+            bt1[b] = kq == 0 ? w[4] : kq == 1 ? w[5] : kq == 2 ? w[6] : w[7];
+        } else {
+            bt0[b] = kq == 0 ? w[0] : kq == 1 ? w[1] : 0.0f;
+            bt1[b] = 0.0f;
         }
-    } else {
-#pragma unroll
-        for (int k = 0; k < C::PPL; ++k) {
-            int px, py;
-            slot_pixel<TILE>(tx, ty, wv, lane, k, px, py);
-            ray_terms(pc, px, py, w[k]);
-        }
+        tb[b] = w[4];
     }
-#pragma unroll
-    for (int k = 0; k < C::PPL; ++k) {
-        int px, py;
-        slot_pixel<TILE>(tx, ty, wv, lane, k, px, py);
-        best[k] = ~0ull;
-        nvk[k] = (px < pc.W && py < pc.H);
-    }
+    unsigned long long best[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+    const float znear = pc.znear;
     unsigned hits = 0;
     unsigned long long tests = 0;
+    int nvc = 0;   // valid pixels of the cell (PR_FLAG_COUNT)
     if (COUNT) {
-#pragma unroll
-        for (int k = 0; k < C::PPL; ++k)
-            for (int o = 32; o > 0; o >>= 1) nvk[k] += __shfl_xor(nvk[k], o, 64);
+        const int px = cx0 + (lane & 7), py = cy0 + (lane >> 3);
+        nvc = __popcll(__ballot(px < pc.W && py < pc.H));
     }
-    float znear = pc.znear;
-    asm volatile("" : "+v"(znear));   // held in a VGPR through the loop
-    // Each iteration issues the current record's scalar loads together with
-    // the next list entry's, and waits for them once: the record values are
-    // pinned in SGPRs (so the quadrant branches do not reload them) and the
-    // next entry's address is ready when the iteration ends.
-    constexpr int STEP = C::SPLIT ? 4 : 1;
-    const int first = beg + (C::SPLIT ? wv : 0);
-    uint32_t next = first < end ? lists[first] : 0u;
-    for (int j = first; j < end; j += STEP) {
-        const uint32_t ent = __builtin_amdgcn_readfirstlane(next);
-        if (j + STEP < end) next = lists[j + STEP];
-        const uint32_t qm = TILE == 8 ? 0xFu : ent >> kListTriBits;
-        if (TILE == 32 && !((qm >> wv) & 1u)) continue;
-        const float *Rp = vrec + (size_t)(ent & kListTriMask) * (RECW * 4);
-        constexpr int NREC = ROLL ? 41 : 14;
-        float R[NREC];
-#pragma unroll
-        for (int i = 0; i < NREC; ++i) R[i] = Rp[i];
-#pragma unroll
-        for (int i = 0; i < NREC; ++i) asm volatile("" : "+s"(R[i]));
-        if (ROLL) {
-            bool pass[C::PPL];
-            bool any = false;
-#pragma unroll
-            for (int k = 0; k < C::PPL; ++k) {
-                pass[k] = false;
-                if (TILE == 16 && !((qm >> k) & 1u)) continue;
-                if (COUNT) tests += (unsigned)nvk[k];
-                float e[3];
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    const float *c = R + 9 * q;   // A_x A_y A_z B_x B_y B_z C_x C_y C_z
-                    float a = fmaf(w[k][0], c[0], c[2]);
-                    a = fmaf(w[k][1], c[1], a);
-                    a = fmaf(w[k][2], c[3], a);
-                    a = fmaf(w[k][3], c[4], a);
-                    a = fmaf(w[k][4], c[5], a);
-                    a = fmaf(w[k][5], c[6], a);
-                    a = fmaf(w[k][6], c[7], a);
-                    e[q] = fmaf(w[k][7], c[8], a);
-                }
-                const float lo = fminf(fminf(e[0], e[1]), e[2]), hi = fmaxf(fmaxf(e[0], e[1]), e[2]);
-                pass[k] = lo >= 0.0f || hi <= 0.0f;
-                any = any || pass[k];
+    // A operand of lane l: triangle (l >> 2) & 3 of the group, output l & 3,
+    // term kq (+ 4)
+    const int ga = (lane >> 2) & 3, aoff = 4 * kq + (lane & 3);
+    int nbuf = 0;
+    uint32_t ent_next = beg + lane < end ? lists[beg + lane] : 0u;
+    for (int c = beg; c < end; c += 64) {
+        const uint32_t ent = ent_next;
+        const bool inl = c + lane < end;
+        if (c + 64 + lane < end) ent_next = lists[c + 64 + lane];
+        const bool sel = inl && (q < 0 || ((ent >> (kListTriBits + q)) & 1u));
+        const unsigned long long m = __ballot(sel);
+        const int pos = nbuf + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (sel) s_sel[pos] = (int32_t)(ent & kListTriMask);
+        nbuf += __popcll(m);
+        const bool last = c + 64 >= end;
+        const int ngr = last ? (nbuf + 3) >> 2 : nbuf >> 2;
+        // software pipeline: the next group's loads are issued before the
+        // current group's products
+        float a0n = 0.0f, a1n = 0.0f, dn0 = 0.0f, dn1 = 0.0f, dn2 = 0.0f, dn3 = 0.0f;
+        v4f cn = {0.0f, 0.0f, 0.0f, 0.0f};
+        uint32_t idn = 0;
+        bool vn = false;
+        auto load_group = [&](int g) {
+            const int ia = 4 * g + ga, ic = 4 * g + kq;
+            const int fa = ia < nbuf ? s_sel[ia] : -1;
+            const int fc = ic < nbuf ? s_sel[ic] : -1;
+            a0n = 0.0f; a1n = 0.0f;
+            if (fa >= 0) {
+                const float *R = vrec + (size_t)fa * RL::W;
+                a0n = R[aoff];
+                if (ROLL) a1n = R[16 + aoff];
             }
-            if (any) {
-                // d0..d3 = R[27..30], N0 = R[31..33], N1 = R[34..36], N2 = R[37..39], id = R[40]
-                const float *N = R + 31;
-#pragma unroll
-                for (int k = 0; k < C::PPL; ++k) {
-                    if (!pass[k]) continue;
-                    float S = fmaf(w[k][0], N[0], N[2]);
-                    S = fmaf(w[k][1], N[1], S);
-                    S = fmaf(w[k][2], N[3], S);
-                    S = fmaf(w[k][3], N[4], S);
-                    S = fmaf(w[k][4], N[5], S);
-                    S = fmaf(w[k][5], N[6], S);
-                    S = fmaf(w[k][6], N[7], S);
-                    S = fmaf(w[k][7], N[8], S);
-                    const float tk = w[k][4];
-                    const float D = fmaf(tk, fmaf(tk, fmaf(tk, R[30], R[29]), R[28]), R[27]);
-                    const float z = D * __builtin_amdgcn_rcpf(S);
-                    if (z >= znear && z <= 3.0e38f) {
-                        const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | __float_as_uint(R[40]);
-                        best[k] = key < best[k] ? key : best[k];
-                        if (COUNT) ++hits;
-                    }
+            vn = fc >= 0;
+            cn = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            dn0 = dn1 = dn2 = dn3 = 0.0f;
+            idn = 0u;
+            if (vn) {
+                const float *R = vrec + (size_t)fc * RL::W;
+                const float4 c4 = *reinterpret_cast<const float4 *>(R + RL::C);
+                cn = v4f{c4.x, c4.y, c4.z, c4.w};
+                if (ROLL) {
+                    const float4 d4 = *reinterpret_cast<const float4 *>(R + RL::D);
+                    dn0 = d4.x; dn1 = d4.y; dn2 = d4.z; dn3 = d4.w;
+                } else {
+                    dn0 = R[RL::D];
                 }
+                idn = __float_as_uint(R[RL::ID]);
             }
-        } else {
+        };
+        if (ngr > 0) load_group(0);
+        for (int g = 0; g < ngr; ++g) {
+            const float a0 = a0n, a1 = a1n, d0 = dn0, d1 = dn1, d2 = dn2, d3 = dn3;
+            const v4f c0 = cn;
+            const uint32_t id = idn;
+            const bool valid = vn;
+            if (g + 1 < ngr) load_group(g + 1);
+            if (COUNT) tests += (unsigned long long)min(4, nbuf - 4 * g) * (unsigned)nvc;
+            // all eight products first, so the matrix pipe runs ahead of the
+            // tests
+            v4f acc[4];
 #pragma unroll
-            for (int k = 0; k < C::PPL; ++k) {
-                if (TILE == 16 && !((qm >> k) & 1u)) continue;
-                if (COUNT) tests += (unsigned)nvk[k];
-                // A0 = R[0..2], A1 = R[3..5], A2 = R[6..8], d0 = R[9], N0 = R[10..12], id = R[13]
-                const float e0 = fmaf(w[k][1], R[1], fmaf(w[k][0], R[0], R[2]));
-                const float e1 = fmaf(w[k][1], R[4], fmaf(w[k][0], R[3], R[5]));
-                const float e2 = fmaf(w[k][1], R[7], fmaf(w[k][0], R[6], R[8]));
-                const float lo = fminf(fminf(e0, e1), e2), hi = fmaxf(fmaxf(e0, e1), e2);
-                if (lo >= 0.0f || hi <= 0.0f) {
-                    const float S = fmaf(w[k][1], R[11], fmaf(w[k][0], R[10], R[12]));
-                    const float z = R[9] * __builtin_amdgcn_rcpf(S);
-                    if (z >= znear && z <= 3.0e38f) {
-                        const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | __float_as_uint(R[13]);
-                        best[k] = key < best[k] ? key : best[k];
-                        if (COUNT) ++hits;
+            for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bt0[b], c0, 0, 0, 0);
+            if (ROLL) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bt1[b], acc[b], 0, 0, 0);
+            }
+            if (valid) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const float lo = fminf(fminf(acc[b][0], acc[b][1]), acc[b][2]);
+                    const float hi = fmaxf(fmaxf(acc[b][0], acc[b][1]), acc[b][2]);
+                    if (lo >= 0.0f || hi <= 0.0f) {
+                        const float t = tb[b];
+                        const float D = ROLL ? fmaf(t, fmaf(t, fmaf(t, d3, d2), d1), d0) : d0;
+                        const float z = D * __builtin_amdgcn_rcpf(acc[b][3]);
+                        if (z >= znear && z <= 3.0e38f) {
+                            const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | id;
+                            best[b] = key < best[b] ? key : best[b];
+                            if (COUNT) ++hits;
+                        }
                     }
                 }
             }
         }
+        // carry the entries of an incomplete group to the next chunk
+        const int used = ngr << 2;
+        if (!last) {
+            const int left = nbuf - used;
+            int32_t keep = 0;
+            if (lane < left) keep = s_sel[used + lane];
+            if (lane < left) s_sel[lane] = keep;
+            nbuf = left;
+        }
     }
-    if (C::SPLIT) {
-        // merge the four waves' keys: wave wv finishes slot wv (8x8: wave 0
-        // finishes the tile)
-        unsigned long long *s_key = reinterpret_cast<unsigned long long *>(s_lds);
-        __syncthreads();   // every wave has read its ray terms
+    // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the same pixel for different
+    // triangles of each group: take the minimum, then lane l writes pixel l
 #pragma unroll
-        for (int k = 0; k < C::PPL; ++k) s_key[(wv * C::PPL + k) * 64 + lane] = best[k];
-        __syncthreads();
-        const int slot = TILE == 16 ? wv : 0;
-        if (TILE == 16 || wv == 0) {
-            unsigned long long m = s_key[slot * 64 + lane];
-#pragma unroll
-            for (int o = 1; o < 4; ++o) {
-                const unsigned long long b = s_key[(o * C::PPL + slot) * 64 + lane];
-                m = b < m ? b : m;
-            }
-            int px, py;
-            slot_pixel<TILE>(tx, ty, 0, lane, slot, px, py);
-            if (px < pc.W && py < pc.H) {
-                const int64_t p = (int64_t)py * pc.W + px;
-                const bool miss = m == ~0ull;
-                out_id[p] = miss ? -1 : (int32_t)(uint32_t)(m & 0xffffffffu);
-                out_depth[p] = miss ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(m >> 32));
-            }
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < C::PPL; ++k) {
-            int px, py;
-            slot_pixel<TILE>(tx, ty, wv, lane, k, px, py);
-            if (px < pc.W && py < pc.H) {
-                const int64_t p = (int64_t)py * pc.W + px;
-                const bool miss = best[k] == ~0ull;
-                out_id[p] = miss ? -1 : (int32_t)(uint32_t)(best[k] & 0xffffffffu);
-                out_depth[p] = miss ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(best[k] >> 32));
-            }
-        }
+    for (int b = 0; b < 4; ++b) {
+        unsigned long long o = __shfl_xor(best[b], 16, 64);
+        best[b] = o < best[b] ? o : best[b];
+        o = __shfl_xor(best[b], 32, 64);
+        best[b] = o < best[b] ? o : best[b];
+    }
+    const unsigned long long mine = kq == 0 ? best[0] : kq == 1 ? best[1] : kq == 2 ? best[2] : best[3];
+    const int px = cx0 + (lane & 7), py = cy0 + (lane >> 3);
+    if (px < pc.W && py < pc.H) {
+        const int64_t p = (int64_t)py * pc.W + px;
+        const bool miss = mine == ~0ull;
+        out_id[p] = miss ? -1 : (int32_t)(uint32_t)(mine & 0xffffffffu);
+        out_depth[p] = miss ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(mine >> 32));
     }
     if (COUNT) {
-        // tests: valid pixels of the slots a triangle was evaluated on
         unsigned long long h = hits;
         for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
         if (lane == 0) {
-            atomicAdd(&st->hits, h);
-            atomicAdd(&st->tests, tests);
+            atomicAdd(&cnt[0], tests);
+            atomicAdd(&cnt[1], h);
         }
     }
-    __syncthreads();
 }
 
-// Block b -> tile: consecutive blocks go to the eight XCDs in turn, so XCD
-// x is given the x-th contiguous eighth of the tiles (neighbouring tiles
+// Block item -> wave's cell.  src maps an item-level tile index to a global
+// tile (identity, or the longest-first order of the persistent form).
+template <int TILE, bool COUNT>
+__device__ __forceinline__ void raycast_item(const ViewTable *__restrict__ T, const float4 *__restrict__ rec,
+                                             const uint32_t *__restrict__ toff, const uint32_t *__restrict__ lists,
+                                             const RayOut &out, DevStatus *__restrict__ st, int item,
+                                             const int32_t *__restrict__ order, int32_t *s_sel_block) {
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ntiles = T->total_tiles;
+    int k = TILE == 8 ? 4 * item + wv : (TILE == 16 ? item : item >> 2);
+    if (k >= ntiles) return;
+    const int gt = order ? order[k] : k;
+    const int v = find_view(T->tile_base, T->nv, gt);
+    const ViewDev &vd = T->v[v];
+    const int lt = gt - vd.tile_base;
+    const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
+    int cx0 = tx * TILE, cy0 = ty * TILE, q = -1;
+    if (TILE == 16) {
+        q = wv;
+        cx0 += (q & 1) * 8;
+        cy0 += (q >> 1) * 8;
+    } else if (TILE == 32) {
+        q = item & 3;
+        cx0 += (q & 1) * 16 + (wv & 1) * 8;
+        cy0 += (q >> 1) * 16 + (wv >> 1) * 8;
+    }
+    if (cx0 >= vd.pc.W || cy0 >= vd.pc.H) return;   // cell outside the image
+    int beg = 0, end = 0;
+    if (!st->overflow) {
+        beg = (int)toff[gt];
+        end = (int)toff[gt + 1];
+    }
+    const float *vrec = reinterpret_cast<const float *>(rec + vd.rec_off);
+    unsigned long long *cnt = &st->cnt[blockIdx.x & (kCountSlots - 1)][0];
+    int32_t *s_sel = s_sel_block + wv * kSelCap;
+    if (vd.rolling)
+        raycast_cell<true, COUNT>(vd, cx0, cy0, q, vrec, beg, end, lists, out.id[v], out.depth[v], cnt, s_sel);
+    else
+        raycast_cell<false, COUNT>(vd, cx0, cy0, q, vrec, beg, end, lists, out.id[v], out.depth[v], cnt, s_sel);
+}
+
+// Block b -> item: consecutive blocks go to the eight XCDs in turn, so XCD
+// x is given the x-th contiguous eighth of the items (neighbouring tiles
 // share triangle records in that XCD's L2).
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
+__device__ __forceinline__ int xcd_item(int b, int nb) {
     const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
     return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
@@ -820,19 +835,8 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
                                                                const uint32_t *__restrict__ toff,
                                                                const uint32_t *__restrict__ lists, RayOut out,
                                                                DevStatus *__restrict__ st) {
-    __shared__ float4 s_lds[kRayLds / 16];
-    const int gt = xcd_tile(blockIdx.x, gridDim.x);
-    const int v = find_view(T->tile_base, T->nv, gt);
-    const ViewDev &vd = T->v[v];
-    int beg = 0, end = 0;
-    if (!st->overflow) {
-        beg = (int)toff[gt];
-        end = (int)toff[gt + 1];
-    }
-    if (vd.rolling)
-        raycast_tile<true, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, out.id[v], out.depth[v], st, s_lds);
-    else
-        raycast_tile<false, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, out.id[v], out.depth[v], st, s_lds);
+    __shared__ int32_t s_sel[4 * kSelCap];
+    raycast_item<TILE, COUNT>(T, rec, toff, lists, out, st, xcd_item(blockIdx.x, gridDim.x), nullptr, s_sel);
 }
 
 // ---------------------------------------------------------------------------
@@ -886,27 +890,12 @@ template <int TILE, bool COUNT>
 __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast_queue(
     const ViewTable *__restrict__ T, const float4 *__restrict__ rec, const uint32_t *__restrict__ toff,
     const uint32_t *__restrict__ lists, RayOut out, DevStatus *__restrict__ st, const int32_t *__restrict__ order,
-    int ntiles) {
-    __shared__ float4 s_lds[kRayLds / 16];
-    const bool ovf = st->overflow != 0;
+    int nitems) {
+    __shared__ int32_t s_sel[4 * kSelCap];
     // block b takes items b, b + grid, b + 2 grid, ... of the longest-first
     // order: the first round holds the longest lists, no queue atomics
-    for (int item = blockIdx.x; item < ntiles; item += gridDim.x) {
-        const int gt = order[item];
-        const int v = find_view(T->tile_base, T->nv, gt);
-        const ViewDev &vd = T->v[v];
-        int beg = 0, end = 0;
-        if (!ovf) {
-            beg = (int)toff[gt];
-            end = (int)toff[gt + 1];
-        }
-        if (vd.rolling)
-            raycast_tile<true, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, out.id[v], out.depth[v], st,
-                                            s_lds);
-        else
-            raycast_tile<false, TILE, COUNT>(vd, gt - vd.tile_base, rec, beg, end, lists, out.id[v], out.depth[v], st,
-                                             s_lds);
-    }
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x)
+        raycast_item<TILE, COUNT>(T, rec, toff, lists, out, st, item, order, s_sel);
 }
 
 // ---------------------------------------------------------------------------
@@ -915,24 +904,23 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast_queue(
 // Edge-plane normals c_k(t), face normal N(t) of triangle id at time t.
 __device__ __forceinline__ void record_at(const ViewDev &vd, const float4 *__restrict__ rec, int id, float t,
                                           float ck[3][3], float N[3]) {
+    // c_o(t) = (M0 + t M2 + t^2 M5, M1 + t M3 + t^2 M6, K + t M4 + t^2 M7)
     if (vd.rolling) {
-        const float4 *R = rec + vd.rec_off + (int64_t)id * kRecRoll;
-        float v[40];
-        for (int q = 0; q < 10; ++q) {
-            float4 x = R[q];
-            v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+        const float *R = reinterpret_cast<const float *>(rec + vd.rec_off + (int64_t)id * kRecRoll);
+        for (int o = 0; o < 4; ++o) {
+            float *dst = o < 3 ? ck[o] : N;
+            dst[0] = fmaf(t, fmaf(t, R[20 + o], R[8 + o]), R[o]);
+            dst[1] = fmaf(t, fmaf(t, R[24 + o], R[12 + o]), R[4 + o]);
+            dst[2] = fmaf(t, fmaf(t, R[28 + o], R[16 + o]), R[32 + o]);
         }
-        for (int k = 0; k < 3; ++k)
-            for (int r = 0; r < 3; ++r)
-                ck[k][r] = fmaf(t, fmaf(t, v[9 * k + 6 + r], v[9 * k + 3 + r]), v[9 * k + r]);
-        for (int r = 0; r < 3; ++r) N[r] = fmaf(t, fmaf(t, v[37 + r], v[34 + r]), v[31 + r]);
     } else {
-        const float4 *R = rec + vd.rec_off + (int64_t)id * kRecStatic;
-        float4 a = R[0], b = R[1], d = R[2], e4 = R[3];
-        float v[13] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, d.x, d.y, d.z, d.w, e4.x};
-        for (int k = 0; k < 3; ++k)
-            for (int r = 0; r < 3; ++r) ck[k][r] = v[3 * k + r];
-        for (int r = 0; r < 3; ++r) N[r] = v[10 + r];
+        const float *R = reinterpret_cast<const float *>(rec + vd.rec_off + (int64_t)id * kRecStatic);
+        for (int o = 0; o < 4; ++o) {
+            float *dst = o < 3 ? ck[o] : N;
+            dst[0] = R[o];
+            dst[1] = R[4 + o];
+            dst[2] = R[16 + o];
+        }
     }
 }
 
