@@ -60,7 +60,8 @@ def main():
     ap.add_argument('--steps', type=int, default=50)
     ap.add_argument('--warmup', type=int, default=5)
     ap.add_argument('--tile', type=int, default=16)
-    ap.add_argument('--persistent', action='store_true', help='longest-first persistent ray cast')
+    ap.add_argument('--no-persistent', dest='persistent', action='store_false',
+                    help='one block per tile item instead of the longest-first persistent ray cast')
     ap.add_argument('--cpu-pixels', type=int, default=49152)
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--only', choices=['all', 'hmd'], default='all',

@@ -92,7 +92,7 @@ extern "C" {
 
 /* A triangle mesh.  v0 / v1: float32 [nv][3] world positions at the frame's
  * start / end (v1 may equal v0); tri: int32 [nt][3] vertex indices in
- * [0, nv).  0 <= nt < 2^28. */
+ * [0, nv).  0 <= nt <= 24,403,223 (records of a view stay under 4 GiB). */
 typedef struct pr_mesh {
     const float *v0;
     const float *v1;

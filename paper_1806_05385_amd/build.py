@@ -14,6 +14,8 @@ FLAGS = [
     '-O3', '-std=c++17', '-fPIC', '-shared', '--offload-arch=gfx950',
     # keep packed-FP32 VALU instructions out of the generated code
     '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops',
+    # matrix products read and write VGPRs directly (no AGPR copies)
+    '-mllvm', '-amdgpu-mfma-vgpr-form',
     '-Wno-unused-command-line-argument',
 ]
 

@@ -46,6 +46,8 @@ int check_args(const pr_mesh *meshes, int nm, const pr_view *views, int nv, cons
         if (M.nt > 0 && (!M.v0 || !M.v1 || !M.tri || M.nv < 1)) return PR_ERR_INVALID;
         if ((int64_t)M.nt * 3 > INT32_MAX || (int64_t)M.nv * 3 > INT32_MAX) return PR_ERR_INVALID;
         if ((uint32_t)M.nt > kListTriMask) return PR_ERR_INVALID;   // list entries hold 28-bit indices
+        // a view's records are addressed with 32-bit byte offsets
+        if ((uint64_t)M.nt * kRecRoll * 16 >= (1ull << 32)) return PR_ERR_INVALID;
     }
     for (int v = 0; v < nv; ++v) {
         const pr_view &V = views[v];
@@ -203,9 +205,7 @@ void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, D
     }
     Sched *S = at<Sched>(ws, L.sched);
     const int nb = (L.total_tiles + 255) / 256;
-    fill_u32(S, 0u, (int64_t)(sizeof(Sched) / 4), s);
-    hipLaunchKernelGGL(k_sched_count, dim3(nb), dim3(256), 0, s, at<uint32_t>(ws, L.toff), L.total_tiles, S);
-    hipLaunchKernelGGL(k_sched_base, dim3(1), dim3(64), 0, s, S);
+    fill_u32(S->cursor, 0u, kBuckets, s);
     hipLaunchKernelGGL(k_sched_scatter, dim3(nb), dim3(256), 0, s, at<uint32_t>(ws, L.toff), L.total_tiles, S,
                        at<int32_t>(ws, L.order));
     static int resident = 0;
@@ -241,7 +241,6 @@ int pr_workspace_size(const pr_mesh *meshes, int nm, const pr_view *views, int n
 int pr_bound(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning, void *ws,
              size_t ws_bytes, void *stream) {
     PR_PREP();
-    fill_u32(st, 0u, (int64_t)(sizeof(DevStatus) / 4), s);
     for (int first = 0; first < nv; first += kViewsPerWrite) {
         ViewPack p;
         memset(&p, 0, sizeof(p));
@@ -253,7 +252,7 @@ int pr_bound(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const 
         p.total_pix_blocks = L.total_pix_blocks;
         p.total_vtx_blocks = L.total_vtx_blocks;
         for (int i = 0; i < p.count; ++i) p.v[i] = L.vd[first + i];
-        hipLaunchKernelGGL(k_write_views, dim3(1), dim3(64), 0, s, p, T);
+        hipLaunchKernelGGL(k_write_views, dim3(1), dim3(64), 0, s, p, T, st);
     }
     if (L.total_tri_blocks > 0)
         hipLaunchKernelGGL(k_bound, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec),
@@ -264,18 +263,16 @@ int pr_bound(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const 
 int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning, void *ws,
            size_t ws_bytes, void *stream) {
     PR_PREP();
-    fill_u32(at<void>(ws, L.tcount), 0u, (int64_t)L.total_tiles + 1, s);
-    fill_u32(&st->num_pairs, 0u, 1, s);
-    hipLaunchKernelGGL(k_tiles, dim3((L.total_tiles * 4 + 255) / 256), dim3(256), 0, s, T, at<TileInfo>(ws, L.tinfo));
+    hipLaunchKernelGGL(k_tiles, dim3(((L.total_tiles + 1) * 4 + 255) / 256), dim3(256), 0, s, T,
+                       at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<Sched>(ws, L.sched), st);
     if (L.total_tri_blocks > 0)
         hipLaunchKernelGGL(k_bin, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<TriBound>(ws, L.tb),
                            at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<Pair>(ws, L.pairs), L.cap, st);
     int n = L.total_tiles + 1;
     hipLaunchKernelGGL(k_scan_reduce, dim3(L.nparts), dim3(256), 0, s, at<uint32_t>(ws, L.tcount), n,
                        at<uint32_t>(ws, L.part));
-    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(1024), 0, s, at<uint32_t>(ws, L.part), L.nparts);
-    hipLaunchKernelGGL(k_scan_apply, dim3(L.nparts), dim3(256), 0, s, at<uint32_t>(ws, L.tcount), n,
-                       at<uint32_t>(ws, L.part), at<uint32_t>(ws, L.toff));
+    hipLaunchKernelGGL(k_scan_apply, dim3(L.nparts), dim3(256), 0, s, at<uint32_t>(ws, L.tcount), n, L.total_tiles,
+                       at<uint32_t>(ws, L.part), at<uint32_t>(ws, L.toff), at<Sched>(ws, L.sched));
     int sb = (int)std::min<int64_t>(std::max<int64_t>((L.cap + 255) / 256, 1), 2048);
     hipLaunchKernelGGL(k_scatter, dim3(sb), dim3(256), 0, s, at<Pair>(ws, L.pairs), at<uint32_t>(ws, L.toff),
                        at<int32_t>(ws, L.lists), L.cap, st);
@@ -326,9 +323,7 @@ int pr_shade(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const 
         any = any || io.rgba8[v] || io.rgb32[v];
     }
     if (!any) return PR_OK;
-    hipLaunchKernelGGL(k_view_light, dim3(1), dim3(64), 0, s, T, *light);
-    hipLaunchKernelGGL(k_shade, dim3(L.total_pix_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec), io,
-                       light->ambient);
+    hipLaunchKernelGGL(k_shade, dim3(L.total_pix_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec), io, *light);
     return launched();
 }
 

@@ -87,8 +87,12 @@ __device__ __forceinline__ int find_view(const int32_t *base, int nv, int key) {
     return lo;
 }
 
-__global__ void k_write_views(ViewPack p, ViewTable *__restrict__ T) {
+__global__ void k_write_views(ViewPack p, ViewTable *__restrict__ T, DevStatus *__restrict__ st) {
     int i = threadIdx.x;
+    if (p.first == 0) {   // the frame's first launch resets the status block
+        uint32_t *w = reinterpret_cast<uint32_t *>(st);
+        for (int k = i; k < (int)(sizeof(DevStatus) / 4); k += blockDim.x) w[k] = 0u;
+    }
     if (i < p.count) {
         const ViewDev &v = p.v[i];
         ViewDev &d = T->v[p.first + i];
@@ -273,10 +277,16 @@ __global__ __launch_bounds__(256) void k_bound(const ViewTable *__restrict__ T, 
 // Four lanes per tile, lane q computing quadrant q's box; a split tile's box
 // is the union of its quadrants' boxes (every pixel centre of the tile lies
 // in its quadrant's box), an unsplit tile's box is computed by lane 0.
-__global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, TileInfo *__restrict__ ti) {
+__global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, TileInfo *__restrict__ ti,
+                                               uint32_t *__restrict__ tcount, Sched *__restrict__ S,
+                                               DevStatus *__restrict__ st) {
     const int gid = blockIdx.x * 256 + threadIdx.x;
     const int gt = gid >> 2, q = gid & 3;
     const bool valid = gt < T->total_tiles;
+    // clear the counters the binning pass accumulates into
+    if (q == 0 && gt <= T->total_tiles) tcount[gt] = 0u;
+    if (gid < kBuckets) S->count[gid] = 0u;
+    if (gid == 0) st->num_pairs = 0u;
     const int v = find_view(T->tile_base, T->nv, valid ? gt : 0);
     const ViewDev &vd = T->v[v];
     const prg::Geom &g = vd.g;
@@ -325,13 +335,21 @@ struct Pair {
     int32_t tile, slot, tri;   // global tile, slot in its list, list entry (triangle index | quadrant mask)
 };
 
-// Candidates are tested in chunks of kBinChunk; their pass bits and the
-// four bit planes of their quadrant masks are kept in LDS (53 KB per block:
-// three blocks fit a CU), the block reserves space for all survivors of a
-// chunk with one global atomic, and each survivor takes its place from the
-// prefix of the pass bits.  A survivor's list entry carries its quadrant
-// mask above the triangle index.
-constexpr int kBinChunk = 256 * 8;
+// Each round gives every thread kBinPer consecutive candidates (mostly of
+// one or two triangles, found with one binary search over the block's
+// candidate prefix).  A thread keeps its candidates' quadrant masks in a
+// register (4 bits each), the block reserves space for all survivors of the
+// round with one global atomic, and each survivor takes its slot in its
+// tile's list with an atomic on the tile's count.  A survivor's list entry
+// carries its quadrant mask above the triangle index.
+constexpr int kBinPer = 8;
+
+// (triangle q, local candidate index) -> global tile of the candidate.
+__device__ __forceinline__ int bin_tile(const ViewDev &vd, const int (*s_rect)[4], int q, int local) {
+    const int rw = s_rect[q][2] - s_rect[q][0] + 1;
+    const int tx = s_rect[q][0] + local % rw, ty = s_rect[q][1] + local / rw;
+    return vd.tile_base + ty * vd.tiles_x + tx;
+}
 
 __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, const TriBound *__restrict__ tb,
                                              const TileInfo *__restrict__ ti, uint32_t *__restrict__ tcount,
@@ -342,9 +360,6 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
     __shared__ int s_kind[256];
     __shared__ int s_pref[257];
     __shared__ int s_tmp[72];
-    __shared__ unsigned long long s_pass[kBinChunk / 64];
-    __shared__ unsigned long long s_quad[4][kBinChunk / 64];
-    __shared__ int s_wpref[kBinChunk / 64];
     __shared__ uint32_t s_base;
     const int v = find_view(T->tri_block0, T->nv, blockIdx.x);
     const ViewDev &vd = T->v[v];
@@ -370,107 +385,74 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
         }
     }
     int total;
-    int ex = block_excl_scan(cnt, s_tmp, total);
+    const int ex = block_excl_scan(cnt, s_tmp, total);
     s_pref[j] = ex;
     if (j == 255) s_pref[256] = total;
     __syncthreads();
-    const int wid = j >> 6, lane = __lane_id();
-    for (int c0 = 0; c0 < total; c0 += kBinChunk) {
-        const int cn = min(kBinChunk, total - c0);
-        // pass 1: test every candidate of the chunk, keep the bits
-        int mine = 0;
-        const int cn_up = (cn + 255) & ~255;   // same trip count for every thread
-        for (int i = j; i < cn_up; i += 256) {
-            int mask = 0;
-            if (i < cn) {
-                const int c = c0 + i;
-                int lo = 0, hi = 255;
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (s_pref[mid] <= c) lo = mid; else hi = mid - 1;
-                }
-                const int q = lo;
-                const int local = c - s_pref[q];
-                const int rw = s_rect[q][2] - s_rect[q][0] + 1;
-                const int tx = s_rect[q][0] + local % rw, ty = s_rect[q][1] + local / rw;
-                const int gt = vd.tile_base + ty * vd.tiles_x + tx;
+    const bool split = prg::split_quads(vd.tile);
+    for (int c0 = 0; c0 < total; c0 += 256 * kBinPer) {
+        const int my0 = c0 + j * kBinPer;
+        const int myn = max(0, min(kBinPer, total - my0));
+        int q0 = 0, l0 = 0;
+        uint32_t masks = 0;
+        if (myn > 0) {
+            int lo = 0, hi = 255;   // last triangle whose candidates start at or before my0
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_pref[mid] <= my0) lo = mid; else hi = mid - 1;
+            }
+            q0 = lo;
+            l0 = my0 - s_pref[q0];
+            int q = q0, local = l0;
+            for (int k = 0; k < myn; ++k) {
+                while (local >= s_pref[q + 1] - s_pref[q]) { ++q; local = 0; }
+                const int gt = bin_tile(vd, s_rect, q, local);
                 double Ps[3][3], Pe[3][3];
-                for (int k = 0; k < 3; ++k)
+                for (int a = 0; a < 3; ++a)
                     for (int r = 0; r < 3; ++r) {
-                        Ps[k][r] = s_P[q][3 * k + r];
-                        Pe[k][r] = s_P[q][9 + 3 * k + r];
+                        Ps[a][r] = s_P[q][3 * a + r];
+                        Pe[a][r] = s_P[q][9 + 3 * a + r];
                     }
-                double w[4] = {s_w[q][0], s_w[q][1], s_w[q][2], s_w[q][3]};
+                const double w[4] = {s_w[q][0], s_w[q][1], s_w[q][2], s_w[q][3]};
                 const TileInfo &t = ti[gt];
-                double tb[4] = {t.box[0], t.box[1], t.box[2], t.box[3]}, tw[2] = {t.tw[0], t.tw[1]};
-                if (prg::split_quads(vd.tile)) {
+                const double tbx[4] = {t.box[0], t.box[1], t.box[2], t.box[3]}, tw[2] = {t.tw[0], t.tw[1]};
+                int mask;
+                if (split) {
                     double qb[4][4];
-                    for (int k = 0; k < 4; ++k)
-                        for (int r = 0; r < 4; ++r) qb[k][r] = t.qb[k][r];
-                    mask = prg::tile_mask_with(g, Ps, Pe, s_kind[q], w, w, tb, tw, qb, t.qvalid);
+                    for (int a = 0; a < 4; ++a)
+                        for (int r = 0; r < 4; ++r) qb[a][r] = t.qb[a][r];
+                    mask = prg::tile_mask_with(g, Ps, Pe, s_kind[q], w, w, tbx, tw, qb, t.qvalid);
                 } else {
-                    mask = prg::tile_mask_with(g, Ps, Pe, s_kind[q], w, w, tb, tw, nullptr, 0);
+                    mask = prg::tile_mask_with(g, Ps, Pe, s_kind[q], w, w, tbx, tw, nullptr, 0);
                 }
-            }
-            const bool pass = mask != 0;
-            unsigned long long m = __ballot(pass);
-            unsigned long long qm[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) qm[k] = __ballot((mask >> k) & 1);
-            if (lane == 0) {
-                s_pass[i >> 6] = m;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) s_quad[k][i >> 6] = qm[k];
-            }
-            mine += pass;
-        }
-        // block total of survivors -> one reservation
-        int ctotal;
-        block_excl_scan(mine, s_tmp, ctotal);
-        if (j == 0) s_base = ctotal ? atomicAdd(&st->num_pairs, (unsigned)ctotal) : 0u;
-        __syncthreads();
-        // pass 2: survivors take their slots in candidate order (prefix over the bit words)
-        // word w covers candidates [64 w, 64 w + 64); per-word prefix by one wave
-        if (wid == 0) {
-            int nw = (cn + 63) / 64;
-            int carry = 0;
-            for (int w0 = 0; w0 < nw; w0 += 64) {
-                int cw = w0 + lane < nw ? __popcll(s_pass[w0 + lane]) : 0;
-                int inc = wave_incl_scan(cw);
-                if (w0 + lane < nw) s_wpref[w0 + lane] = carry + inc - cw;
-                carry += __shfl(inc, 63, 64);
+                masks |= (uint32_t)mask << (4 * k);
+                ++local;
             }
         }
+        int ns = 0;
+#pragma unroll
+        for (int k = 0; k < kBinPer; ++k) ns += ((masks >> (4 * k)) & 0xFu) != 0u;
+        int rtotal;
+        const int rex = block_excl_scan(ns, s_tmp, rtotal);
+        if (j == 0) s_base = rtotal ? atomicAdd(&st->num_pairs, (unsigned)rtotal) : 0u;
         __syncthreads();
-        for (int i = j; i < cn_up; i += 256) {
-            const bool surv = i < cn && ((s_pass[i >> 6] >> (i & 63)) & 1ull);
-            int gt = 0, q = 0;
-            unsigned idx = 0;
-            if (surv) {
-                const int c = c0 + i;
-                int lo = 0, hi = 255;
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (s_pref[mid] <= c) lo = mid; else hi = mid - 1;
+        if (ns) {
+            uint32_t idx = s_base + (uint32_t)rex;
+            int q = q0, local = l0;
+            for (int k = 0; k < myn; ++k) {
+                while (local >= s_pref[q + 1] - s_pref[q]) { ++q; local = 0; }
+                const uint32_t m = (masks >> (4 * k)) & 0xFu;
+                if (m) {
+                    const int gt = bin_tile(vd, s_rect, q, local);
+                    const unsigned slot = atomicAdd(&tcount[gt], 1u);
+                    if ((int64_t)idx < cap)
+                        pairs[idx] = Pair{gt, (int32_t)slot, (int32_t)((uint32_t)(f0 + q) | (m << kListTriBits))};
+                    ++idx;
                 }
-                q = lo;
-                const int local = c - s_pref[q];
-                const int rw = s_rect[q][2] - s_rect[q][0] + 1;
-                const int tx = s_rect[q][0] + local % rw, ty = s_rect[q][1] + local / rw;
-                gt = vd.tile_base + ty * vd.tiles_x + tx;
-                const unsigned long long m = s_pass[i >> 6];
-                idx = s_base + (unsigned)s_wpref[i >> 6] + (unsigned)__popcll(m & ((1ull << (i & 63)) - 1ull));
-            }
-            if (surv) {
-                uint32_t mask = 0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) mask |= (uint32_t)((s_quad[k][i >> 6] >> (i & 63)) & 1ull) << k;
-                const unsigned slot = atomicAdd(&tcount[gt], 1u);
-                if ((int64_t)idx < cap)
-                    pairs[idx] = Pair{gt, (int32_t)slot, (int32_t)((uint32_t)(f0 + q) | (mask << kListTriBits))};
+                ++local;
             }
         }
-        __syncthreads();
+        __syncthreads();   // s_base is rewritten next round
     }
 }
 
@@ -492,37 +474,40 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict_
     if (threadIdx.x == 0) part[blockIdx.x] = (uint32_t)total;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_part(uint32_t *__restrict__ part, int nb) {
-    __shared__ int s_tmp[72];
-    int carry = 0;
-    for (int base = 0; base < nb; base += 1024) {
-        int i = base + threadIdx.x;
-        int v = i < nb ? (int)part[i] : 0;
-        int total;
-        int ex = block_excl_scan(v, s_tmp, total);
-        if (i < nb) part[i] = (uint32_t)(ex + carry);
-        carry += total;
-    }
-}
+// Exclusive scan of the per-tile counts: the block's offset is the sum of
+// the partial sums of the blocks before it (few: one per 2048 tiles).  The
+// block also adds its tiles' list-length buckets to the persistent ray
+// cast's histogram (S->count, cleared by k_tiles).
+__device__ __forceinline__ int len_bucket(uint32_t len) { return len == 0u ? 0 : 32 - __clz(len); }
 
-__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__ in, int n,
-                                                    const uint32_t *__restrict__ part, uint32_t *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__ in, int n, int ntiles,
+                                                    const uint32_t *__restrict__ part, uint32_t *__restrict__ out,
+                                                    Sched *__restrict__ S) {
     __shared__ int s_tmp[72];
-    int base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    __shared__ uint32_t h[kBuckets];
+    if (threadIdx.x < kBuckets) h[threadIdx.x] = 0u;
+    int pre = 0;
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += 256) pre += (int)part[i];
+    int total;
+    block_excl_scan(pre, s_tmp, total);
+    pre = total;
+    const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
     int v[kScanItems];
-    int s = 0;
+    int sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         v[k] = base + k < n ? (int)in[base + k] : 0;
-        s += v[k];
+        sum += v[k];
     }
-    int total;
-    int ex = block_excl_scan(s, s_tmp, total) + (int)part[blockIdx.x];
+    int ex = block_excl_scan(sum, s_tmp, total) + pre;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n) out[base + k] = (uint32_t)ex;
+        if (base + k < ntiles) atomicAdd(&h[len_bucket((uint32_t)v[k])], 1u);
         ex += v[k];
     }
+    __syncthreads();
+    if (threadIdx.x < kBuckets && h[threadIdx.x]) atomicAdd(&S->count[threadIdx.x], h[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -634,21 +619,28 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
     const PixelConst &pc = vd.pc;
     const int lane = __lane_id();
     const int kq = lane >> 4, jl = lane & 15;
-    // B operands: ray terms of pixel 16 b + jl of the cell, term kq (+ 4)
+    // B operands: ray terms kq and kq + 4 of pixel 16 b + jl of the cell.
+    // Lane l sets up pixel l; the others fetch its (t, rx, ry).
     float bt0[4], bt1[4], tb[4];
+    {
+        float t, rx, ry;
+        pixel_setup(pc, cx0 + (lane & 7), cy0 + (lane >> 3), t, rx, ry);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int j = 16 * b + jl;
-        float w[8];
-        ray_terms(pc, cx0 + (j & 7), cy0 + (j >> 3), w);
-        if (ROLL) {
-            bt0[b] = kq == 0 ? w[0] : kq == 1 ? w[1] : kq == 2 ? w[2] : w[3];
-            bt1[b] = kq == 0 ? w[4] : kq == 1 ? w[5] : kq == 2 ? w[6] : w[7];
-        } else {
-            bt0[b] = kq == 0 ? w[0] : kq == 1 ? w[1] : 0.0f;
-            bt1[b] = 0.0f;
+        for (int b = 0; b < 4; ++b) {
+            const int src = 16 * b + jl;
+            const float tj = __shfl(t, src, 64), rxj = __shfl(rx, src, 64), ryj = __shfl(ry, src, 64);
+            if (ROLL) {
+                // terms (rx, ry, t rx, t ry) and (t, t^2 rx, t^2 ry, t^2)
+                const float u = kq == 0 ? rxj : kq == 1 ? ryj : kq == 2 ? tj * rxj : tj * ryj;
+                const float t2 = tj * tj;
+                bt0[b] = u;
+                bt1[b] = kq == 0 ? tj : kq == 1 ? t2 * rxj : kq == 2 ? t2 * ryj : t2;
+            } else {
+                bt0[b] = kq == 0 ? rxj : kq == 1 ? ryj : 0.0f;
+                bt1[b] = 0.0f;
+            }
+            tb[b] = tj;
         }
-        tb[b] = w[4];
     }
     unsigned long long best[4] = {~0ull, ~0ull, ~0ull, ~0ull};
     const float znear = pc.znear;
@@ -677,72 +669,72 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
         const int ngr = last ? (nbuf + 3) >> 2 : nbuf >> 2;
         // software pipeline: the next group's loads are issued before the
         // current group's products
-        float a0n = 0.0f, a1n = 0.0f, dn0 = 0.0f, dn1 = 0.0f, dn2 = 0.0f, dn3 = 0.0f;
-        v4f cn = {0.0f, 0.0f, 0.0f, 0.0f};
-        uint32_t idn = 0;
-        bool vn = false;
-        auto load_group = [&](int g) {
-            const int ia = 4 * g + ga, ic = 4 * g + kq;
-            const int fa = ia < nbuf ? s_sel[ia] : -1;
-            const int fc = ic < nbuf ? s_sel[ic] : -1;
-            a0n = 0.0f; a1n = 0.0f;
-            if (fa >= 0) {
-                const float *R = vrec + (size_t)fa * RL::W;
-                a0n = R[aoff];
-                if (ROLL) a1n = R[16 + aoff];
-            }
-            vn = fc >= 0;
-            cn = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-            dn0 = dn1 = dn2 = dn3 = 0.0f;
-            idn = 0u;
-            if (vn) {
-                const float *R = vrec + (size_t)fc * RL::W;
-                const float4 c4 = *reinterpret_cast<const float4 *>(R + RL::C);
-                cn = v4f{c4.x, c4.y, c4.z, c4.w};
-                if (ROLL) {
-                    const float4 d4 = *reinterpret_cast<const float4 *>(R + RL::D);
-                    dn0 = d4.x; dn1 = d4.y; dn2 = d4.z; dn3 = d4.w;
-                } else {
-                    dn0 = R[RL::D];
-                }
-                idn = __float_as_uint(R[RL::ID]);
-            }
+        // Two register sets alternate (software pipeline without copies):
+        // the next group's loads are issued before the current group's
+        // products.  Lanes past the selection load the first selected
+        // triangle's record (always in bounds); their rows are ignored
+        // through `valid`.  Record offsets are 32-bit byte offsets from the
+        // view's record base (a view's records are smaller than 4 GiB).
+        struct Group {
+            float a0, a1, d0, d1, d2, d3;
+            v4f c;
+            uint32_t id;
+            bool valid;
         };
-        if (ngr > 0) load_group(0);
-        for (int g = 0; g < ngr; ++g) {
-            const float a0 = a0n, a1 = a1n, d0 = dn0, d1 = dn1, d2 = dn2, d3 = dn3;
-            const v4f c0 = cn;
-            const uint32_t id = idn;
-            const bool valid = vn;
-            if (g + 1 < ngr) load_group(g + 1);
+        const char *vbase = reinterpret_cast<const char *>(vrec);
+        auto load_group = [&](Group &G, int g) {
+            const int ia = 4 * g + ga, ic = 4 * g + kq;
+            const uint32_t oa = (uint32_t)s_sel[ia < nbuf ? ia : 0] * (uint32_t)(RL::W * 4);
+            const uint32_t oc = (uint32_t)s_sel[ic < nbuf ? ic : 0] * (uint32_t)(RL::W * 4);
+            G.a0 = *reinterpret_cast<const float *>(vbase + oa + 4 * aoff);
+            G.a1 = ROLL ? *reinterpret_cast<const float *>(vbase + oa + 4 * (16 + aoff)) : 0.0f;
+            G.valid = ic < nbuf;
+            const float4 c4 = *reinterpret_cast<const float4 *>(vbase + oc + 4 * RL::C);
+            G.c = v4f{c4.x, c4.y, c4.z, c4.w};
+            if (ROLL) {
+                const float4 d4 = *reinterpret_cast<const float4 *>(vbase + oc + 4 * RL::D);
+                G.d0 = d4.x; G.d1 = d4.y; G.d2 = d4.z; G.d3 = d4.w;
+            } else {
+                G.d0 = *reinterpret_cast<const float *>(vbase + oc + 4 * RL::D);
+                G.d1 = G.d2 = G.d3 = 0.0f;
+            }
+            G.id = *reinterpret_cast<const uint32_t *>(vbase + oc + 4 * RL::ID);
+        };
+        auto run_group = [&](const Group &G, int g) {
             if (COUNT) tests += (unsigned long long)min(4, nbuf - 4 * g) * (unsigned)nvc;
-            // all eight products first, so the matrix pipe runs ahead of the
-            // tests
+            // all products first, so the matrix pipe runs ahead of the tests
             v4f acc[4];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bt0[b], c0, 0, 0, 0);
+            for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(G.a0, bt0[b], G.c, 0, 0, 0);
             if (ROLL) {
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bt1[b], acc[b], 0, 0, 0);
+                for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(G.a1, bt1[b], acc[b], 0, 0, 0);
             }
-            if (valid) {
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const float lo = fminf(fminf(acc[b][0], acc[b][1]), acc[b][2]);
-                    const float hi = fmaxf(fmaxf(acc[b][0], acc[b][1]), acc[b][2]);
-                    if (lo >= 0.0f || hi <= 0.0f) {
-                        const float t = tb[b];
-                        const float D = ROLL ? fmaf(t, fmaf(t, fmaf(t, d3, d2), d1), d0) : d0;
-                        const float z = D * __builtin_amdgcn_rcpf(acc[b][3]);
-                        if (z >= znear && z <= 3.0e38f) {
-                            const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | id;
-                            best[b] = key < best[b] ? key : best[b];
-                            if (COUNT) ++hits;
-                        }
-                    }
+            for (int b = 0; b < 4; ++b) {
+                const float lo = fminf(fminf(acc[b][0], acc[b][1]), acc[b][2]);
+                const float hi = fmaxf(fmaxf(acc[b][0], acc[b][1]), acc[b][2]);
+                if (G.valid & ((lo >= 0.0f) | (hi <= 0.0f))) {   // skipped when no lane passes
+                    const float t = tb[b];
+                    const float D = ROLL ? fmaf(t, fmaf(t, fmaf(t, G.d3, G.d2), G.d1), G.d0) : G.d0;
+                    const float z = D * __builtin_amdgcn_rcpf(acc[b][3]);
+                    const bool hit = (z >= znear) & (z <= 3.0e38f);
+                    const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | G.id;
+                    best[b] = hit & (key < best[b]) ? key : best[b];
+                    if (COUNT) hits += hit;
                 }
             }
+        };
+        Group GA, GB;
+        if (ngr > 0) load_group(GA, 0);
+        int g = 0;
+        for (; g + 1 < ngr; g += 2) {
+            load_group(GB, g + 1);
+            run_group(GA, g);
+            load_group(GA, g + 2);   // unconditional: keeps the wait for GB partial
+            run_group(GB, g + 1);
         }
+        if (g < ngr) run_group(GA, g);
         // carry the entries of an incomplete group to the next chunk
         const int used = ngr << 2;
         if (!last) {
@@ -846,31 +838,19 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
 // (a counting sort: per-block histograms in LDS, one global atomic per
 // block and bucket); a grid sized to the device's resident blocks then walks
 // the order with a static stride, so the longest lists start first.
-__device__ __forceinline__ int len_bucket(uint32_t len) { return len == 0u ? 0 : 32 - __clz(len); }
-
-__global__ __launch_bounds__(256) void k_sched_count(const uint32_t *__restrict__ toff, int n, Sched *__restrict__ S) {
-    __shared__ uint32_t h[kBuckets];
-    if (threadIdx.x < kBuckets) h[threadIdx.x] = 0u;
-    __syncthreads();
-    int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n) atomicAdd(&h[len_bucket(toff[i + 1] - toff[i])], 1u);
-    __syncthreads();
-    if (threadIdx.x < kBuckets && h[threadIdx.x]) atomicAdd(&S->count[threadIdx.x], h[threadIdx.x]);
-}
-
-__global__ void k_sched_base(Sched *__restrict__ S) {
-    if (threadIdx.x != 0) return;
-    uint32_t sum = 0;
-    for (int b = kBuckets - 1; b >= 0; --b) {   // longest lists first
-        S->cursor[b] = sum;
-        sum += S->count[b];
-    }
-    S->queue = 0u;
-}
-
+// Tile order of the persistent ray cast: longest lists first, by
+// power-of-two length bucket (counting sort on the histogram k_scan_apply
+// built; S->cursor cleared before the launch).
 __global__ __launch_bounds__(256) void k_sched_scatter(const uint32_t *__restrict__ toff, int n, Sched *__restrict__ S,
                                                        int32_t *__restrict__ order) {
-    __shared__ uint32_t h[kBuckets], base[kBuckets];
+    __shared__ uint32_t h[kBuckets], base[kBuckets], first[kBuckets];
+    if (threadIdx.x == 0) {
+        uint32_t sum = 0;
+        for (int b = kBuckets - 1; b >= 0; --b) {   // longest lists first
+            first[b] = sum;
+            sum += S->count[b];
+        }
+    }
     if (threadIdx.x < kBuckets) h[threadIdx.x] = 0u;
     __syncthreads();
     int i = blockIdx.x * 256 + threadIdx.x;
@@ -881,7 +861,8 @@ __global__ __launch_bounds__(256) void k_sched_scatter(const uint32_t *__restric
         rank = atomicAdd(&h[b], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < kBuckets && h[threadIdx.x]) base[threadIdx.x] = atomicAdd(&S->cursor[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < kBuckets && h[threadIdx.x])
+        base[threadIdx.x] = first[threadIdx.x] + atomicAdd(&S->cursor[threadIdx.x], h[threadIdx.x]);
     __syncthreads();
     if (i < n) order[base[b] + rank] = i;
 }
@@ -925,7 +906,8 @@ __device__ __forceinline__ void record_at(const ViewDev &vd, const float4 *__res
 }
 
 __global__ __launch_bounds__(256) void k_shade(const ViewTable *__restrict__ T, const float4 *__restrict__ rec,
-                                               ShadeIO io, float ambient) {
+                                               ShadeIO io, pr_light light) {
+    const float ambient = light.ambient;
     const int v = find_view(T->pix_block0, T->nv, blockIdx.x);
     const ViewDev &vd = T->v[v];
     const PixelConst &pc = vd.pc;
@@ -945,8 +927,15 @@ __global__ __launch_bounds__(256) void k_shade(const ViewTable *__restrict__ T, 
         float S = e[0] + e[1] + e[2];
         float inn = rsqrtf(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
         float sg = (N[0] * rx + N[1] * ry + N[2]) > 0.0f ? -inn : inn;
+        // light direction in camera space at the pixel's time
         float L[3];
-        for (int r = 0; r < 3; ++r) L[r] = fmaf(t, vd.light1[r] - vd.light0[r], vd.light0[r]);
+        for (int r = 0; r < 3; ++r) {
+            const float l0 = vd.R0f[3 * r] * light.dir_world[0] + vd.R0f[3 * r + 1] * light.dir_world[1] +
+                             vd.R0f[3 * r + 2] * light.dir_world[2];
+            const float l1 = vd.R1f[3 * r] * light.dir_world[0] + vd.R1f[3 * r + 1] * light.dir_world[1] +
+                             vd.R1f[3 * r + 2] * light.dir_world[2];
+            L[r] = fmaf(t, l1 - l0, l0);
+        }
         float inl = rsqrtf(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
         float ndl = sg * inl * (N[0] * L[0] + N[1] * L[1] + N[2] * L[2]);
         float s = ambient + (1.0f - ambient) * fmaxf(ndl, 0.0f);
