@@ -288,7 +288,7 @@ def main():
         'wall_s': round(wall, 3),
         'roofline': {'bound': 'alu', 'achieved': round(achieved, 3), 'peak': PEAK_FP32_TFLOPS,
                      'unit': 'TFLOP/s', 'frac': round(achieved / PEAK_FP32_TFLOPS, 4), 'traffic': traffic,
-                     'kernel': 'k_raycast', 'flop_per_test': flop_test,
+                     'kernel': 'k_raycast_queue' if args.persistent else 'k_raycast', 'flop_per_test': flop_test,
                      'frac_of_unpacked_peak': round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4)},
         'cpu_baseline': cpu,
     }

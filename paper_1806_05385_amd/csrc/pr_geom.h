@@ -438,63 +438,6 @@ PRG bool quad_display(const Geom &g, int tile, int tx, int ty, int k, double box
     return region_display(g, i0, i0 + h - 1, j0, j0 + h - 1, box);
 }
 
-// The triangle over a time window [w0, w1] as the separating-axis test
-// sees it: for each of eight axes (x, y and the three edge normals of each
-// end triangle) the interval its six projected end vertices cover, widened
-// by a rounding margin.
-struct Hull {
-    double n[8][2];
-    double lo[8], hi[8];
-};
-
-PRG void hull_project(const Geom &g, const double Ps[3][3], const double Pe[3][3], double w0, double w1, Hull &h) {
-    double q[6][2];
-    for (int k = 0; k < 3; ++k)
-        for (int e = 0; e < 2; ++e) {
-            double w = e ? w1 : w0;
-            double P[3];
-            for (int r = 0; r < 3; ++r) P[r] = (1.0 - w) * Ps[k][r] + w * Pe[k][r];
-            double iz = 1.0 / P[2];
-            q[3 * e + k][0] = g.fx * P[0] * iz + g.cx;
-            q[3 * e + k][1] = g.fy * P[1] * iz + g.cy;
-        }
-    double big = 1.0;
-    for (int i = 0; i < 6; ++i) big = dmax(big, dmax(fabs(q[i][0]), fabs(q[i][1])));
-    for (int a = 0; a < 8; ++a) {
-        double n0, n1;
-        if (a == 0) { n0 = 1; n1 = 0; }
-        else if (a == 1) { n0 = 0; n1 = 1; }
-        else {
-            int e = (a - 2) / 3, k = (a - 2) % 3;
-            const double *p = q[3 * e + k], *r = q[3 * e + (k + 1) % 3];
-            n0 = -(r[1] - p[1]);
-            n1 = r[0] - p[0];
-        }
-        double pmin = 1e300, pmax = -1e300;
-        for (int i = 0; i < 6; ++i) {
-            double s = n0 * q[i][0] + n1 * q[i][1];
-            pmin = dmin(pmin, s);
-            pmax = dmax(pmax, s);
-        }
-        double m = 1e-12 * (fabs(n0) + fabs(n1)) * big;
-        h.n[a][0] = n0;
-        h.n[a][1] = n1;
-        h.lo[a] = pmin - m;
-        h.hi[a] = pmax + m;
-    }
-}
-
-// True unless one of the hull's axes separates it from the box.
-PRG bool hull_meets_box(const Hull &h, const double b[4]) {
-    for (int a = 0; a < 8; ++a) {
-        const double n0 = h.n[a][0], n1 = h.n[a][1];
-        const double bmin = n0 * (n0 >= 0.0 ? b[0] : b[1]) + n1 * (n1 >= 0.0 ? b[2] : b[3]);
-        const double bmax = n0 * (n0 >= 0.0 ? b[1] : b[0]) + n1 * (n1 >= 0.0 ? b[3] : b[2]);
-        if (h.hi[a] < bmin || h.lo[a] > bmax) return false;
-    }
-    return true;
-}
-
 PRG bool box_meets_box(const double a[4], const double b[4]) {
     return !(a[1] < b[0] || a[0] > b[1] || a[3] < b[2] || a[2] > b[3]);
 }
@@ -502,13 +445,14 @@ PRG bool box_meets_box(const double a[4], const double b[4]) {
 // Conservative test of one (triangle, tile) pair given the tile's display
 // box tb and time window tw (tile_display).  Returns the 4-bit mask of the
 // tile's quadrants the triangle may cover; 0 rejects the pair.  kWindow
-// triangles: the window is cut to the tile's own time window, the six
-// projected end vertices of that window bound the triangle's image over it
-// (Hull), a separating-axis test against the tile's display box keeps the
-// pair, and each quadrant box qb[k] whose bit k is set in qvalid is kept
-// if it meets the hull's x and y extents.  kClipped triangles compare
-// their whole-frame display box.  qb == nullptr: the tile is not split
-// (mask 0xF when it is kept).
+// triangles: the window is cut to the tile's own time window; the six
+// projected end vertices of that window bound the triangle's image over
+// it, and a separating-axis test (their x and y extents, then the edge
+// normals of both end triangles) against the tile's display box keeps the
+// pair; each quadrant box qb[k] whose bit k is set in qvalid is kept if it
+// meets the vertices' x and y extents.  kClipped triangles compare their
+// whole-frame display box.  qb == nullptr: the tile is not split (mask 0xF
+// when it is kept).
 PRG int tile_mask_with(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double win[2],
                        const double tri_box[4], const double tb[4], const double tw[2], const double (*qb)[4],
                        int qvalid) {
@@ -519,16 +463,67 @@ PRG int tile_mask_with(const Geom &g, const double Ps[3][3], const double Pe[3][
     } else {
         double w0 = dmax(win[0], tw[0]), w1 = dmin(win[1], tw[1]);
         if (w0 > w1) return 0;
-        Hull h;
-        hull_project(g, Ps, Pe, w0, w1, h);
-        if (!hull_meets_box(h, tb)) return 0;
-        ext[0] = h.lo[0]; ext[1] = h.hi[0]; ext[2] = h.lo[1]; ext[3] = h.hi[1];
+        // the six projected end vertices of [w0, w1]
+        double q[6][2];
+        for (int k = 0; k < 3; ++k)
+            for (int e = 0; e < 2; ++e) {
+                const double w = e ? w1 : w0;
+                double P[3];
+                for (int r = 0; r < 3; ++r) P[r] = (1.0 - w) * Ps[k][r] + w * Pe[k][r];
+                const double iz = 1.0 / P[2];
+                q[3 * e + k][0] = g.fx * P[0] * iz + g.cx;
+                q[3 * e + k][1] = g.fy * P[1] * iz + g.cy;
+            }
+        double big = 1.0;
+        for (int i = 0; i < 6; ++i) big = dmax(big, dmax(fabs(q[i][0]), fabs(q[i][1])));
+        // separating axes, tested one at a time: x, y (the hull's extents,
+        // kept for the quadrant tests), then the edge normals of both end
+        // triangles
+        ext[0] = ext[2] = 1e300;
+        ext[1] = ext[3] = -1e300;
+        for (int i = 0; i < 6; ++i) {
+            ext[0] = dmin(ext[0], q[i][0]); ext[1] = dmax(ext[1], q[i][0]);
+            ext[2] = dmin(ext[2], q[i][1]); ext[3] = dmax(ext[3], q[i][1]);
+        }
+        const double mxy = 1e-12 * big;
+        ext[0] -= mxy; ext[1] += mxy; ext[2] -= mxy; ext[3] += mxy;
+        if (!box_meets_box(ext, tb)) return 0;
+        for (int a = 0; a < 6; ++a) {
+            const int e = a / 3, k = a % 3;
+            const double *p = q[3 * e + k], *r = q[3 * e + (k + 1) % 3];
+            const double n0 = -(r[1] - p[1]), n1 = r[0] - p[0];
+            double pmin = 1e300, pmax = -1e300;
+            for (int i = 0; i < 6; ++i) {
+                const double sp = n0 * q[i][0] + n1 * q[i][1];
+                pmin = dmin(pmin, sp);
+                pmax = dmax(pmax, sp);
+            }
+            const double m = 1e-12 * (fabs(n0) + fabs(n1)) * big;
+            const double bmin = n0 * (n0 >= 0.0 ? tb[0] : tb[1]) + n1 * (n1 >= 0.0 ? tb[2] : tb[3]);
+            const double bmax = n0 * (n0 >= 0.0 ? tb[1] : tb[0]) + n1 * (n1 >= 0.0 ? tb[3] : tb[2]);
+            if (pmax + m < bmin || pmin - m > bmax) return 0;
+        }
     }
     if (!qb) return 0xF;
     int mask = 0;
     for (int k = 0; k < 4; ++k)
         if (((qvalid >> k) & 1) && box_meets_box(ext, qb[k])) mask |= 1 << k;
     return mask;
+}
+
+// FP32 rounding of a bound towards -inf / +inf (the stored tile boxes).
+PRG float f32_down(double x) {
+    float f = (float)x;
+    return (double)f > x ? nextafterf(f, -INFINITY) : f;
+}
+PRG float f32_up(double x) {
+    float f = (float)x;
+    return (double)f < x ? nextafterf(f, INFINITY) : f;
+}
+// A box [lo0, hi0, lo1, hi1] rounded outwards to FP32 and widened back.
+PRG void box_outward(double b[4]) {
+    b[0] = f32_down(b[0]); b[1] = f32_up(b[1]);
+    b[2] = f32_down(b[2]); b[3] = f32_up(b[3]);
 }
 
 // Tiles of 16 pixels and more are split into quadrants.
@@ -542,19 +537,25 @@ PRG int tile_mask(const Geom &g, const double Ps[3][3], const double Pe[3][3], i
     double tb[4], tw[2], qb[4][4];
     if (!split_quads(tile)) {
         tile_display(g, tile, tx, ty, tb, tw);
-        return tile_mask_with(g, Ps, Pe, kind, win, tri_box, tb, tw, nullptr, 0);
+    } else {
+        tb[0] = tb[2] = 1e300;
+        tb[1] = tb[3] = -1e300;
     }
     int qvalid = 0;
-    tb[0] = tb[2] = 1e300;
-    tb[1] = tb[3] = -1e300;
-    for (int k = 0; k < 4; ++k)
-        if (quad_display(g, tile, tx, ty, k, qb[k])) {
-            qvalid |= 1 << k;
-            tb[0] = dmin(tb[0], qb[k][0]); tb[1] = dmax(tb[1], qb[k][1]);
-            tb[2] = dmin(tb[2], qb[k][2]); tb[3] = dmax(tb[3], qb[k][3]);
-        }
-    tile_time(g, tb, tw);
-    return tile_mask_with(g, Ps, Pe, kind, win, tri_box, tb, tw, qb, qvalid);
+    if (split_quads(tile)) {
+        for (int k = 0; k < 4; ++k)
+            if (quad_display(g, tile, tx, ty, k, qb[k])) {
+                qvalid |= 1 << k;
+                tb[0] = dmin(tb[0], qb[k][0]); tb[1] = dmax(tb[1], qb[k][1]);
+                tb[2] = dmin(tb[2], qb[k][2]); tb[3] = dmax(tb[3], qb[k][3]);
+                box_outward(qb[k]);
+            }
+        tile_time(g, tb, tw);
+    }
+    box_outward(tb);
+    tw[0] = f32_down(tw[0]);
+    tw[1] = f32_up(tw[1]);
+    return tile_mask_with(g, Ps, Pe, kind, win, tri_box, tb, tw, split_quads(tile) ? qb : nullptr, qvalid);
 }
 
 }  // namespace prg

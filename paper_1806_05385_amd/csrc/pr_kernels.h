@@ -41,13 +41,15 @@ struct TriBound {
 
 // Display-space box of a tile's pixel centres and its frame-time window;
 // for tiles split into quadrants, the box of each quadrant (qvalid bit k:
-// quadrant k holds pixels of the image).
+// quadrant k holds pixels of the image).  Computed in FP64 and rounded
+// outwards to FP32 (lower ends down, upper ends up), so each stored box
+// contains the exact one.  96 bytes.
 struct TileInfo {
-    double box[4];
-    double tw[2];
+    float box[4];
+    float tw[2];
     int32_t qvalid;
     int32_t pad;
-    double qb[4][4];
+    float qb[4][4];
 };
 
 // Tile-list entry: triangle index in bits 0..27, quadrant mask in 28..31.

@@ -11,8 +11,8 @@
 //              each quadrant's) and its frame-time window
 //   k_bin      one block per 256 triangles: every (triangle, tile) candidate
 //              of the block's rectangles tested conservatively, survivors
-//              compacted with a wave ballot + mbcnt prefix and one atomic
-//              per wave
+//              compacted with one reservation per round and a slot in their
+//              tile's list
 //   k_scan_*   exclusive scan of per-tile counts (three phases)
 //   k_scatter  pairs -> per-tile triangle lists
 //   k_raycast  one four-wave block per tile: every pixel's ray (foveated
@@ -309,7 +309,10 @@ __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, 
     if (!valid) return;
     TileInfo &t = ti[gt];
     if (split) {
-        for (int r = 0; r < 4; ++r) t.qb[q][r] = qok ? qb[r] : 0.0;
+        t.qb[q][0] = qok ? prg::f32_down(qb[0]) : 0.0f;
+        t.qb[q][1] = qok ? prg::f32_up(qb[1]) : 0.0f;
+        t.qb[q][2] = qok ? prg::f32_down(qb[2]) : 0.0f;
+        t.qb[q][3] = qok ? prg::f32_up(qb[3]) : 0.0f;
     }
     if (q != 0) return;
     double tw[2];
@@ -320,11 +323,14 @@ __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, 
         prg::tile_display(g, vd.tile, tx, ty, box, tw);
         t.qvalid = 0;
         for (int k = 0; k < 4; ++k)
-            for (int r = 0; r < 4; ++r) t.qb[k][r] = 0.0;
+            for (int r = 0; r < 4; ++r) t.qb[k][r] = 0.0f;
     }
-    for (int r = 0; r < 4; ++r) t.box[r] = box[r];
-    t.tw[0] = tw[0];
-    t.tw[1] = tw[1];
+    t.box[0] = prg::f32_down(box[0]);
+    t.box[1] = prg::f32_up(box[1]);
+    t.box[2] = prg::f32_down(box[2]);
+    t.box[3] = prg::f32_up(box[3]);
+    t.tw[0] = prg::f32_down(tw[0]);
+    t.tw[1] = prg::f32_up(tw[1]);
     t.pad = 0;
 }
 
@@ -351,108 +357,133 @@ __device__ __forceinline__ int bin_tile(const ViewDev &vd, const int (*s_rect)[4
     return vd.tile_base + ty * vd.tiles_x + tx;
 }
 
+// One block per kBinTris triangles.  Each round gives every thread `per`
+// consecutive candidates, per = ceil(candidates / 256) up to kBinPer, so all
+// threads of the block share the work.
+constexpr int kBinTris = 256;
+
 __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, const TriBound *__restrict__ tb,
                                              const TileInfo *__restrict__ ti, uint32_t *__restrict__ tcount,
                                              Pair *__restrict__ pairs, int64_t cap, DevStatus *__restrict__ st) {
-    __shared__ double s_P[256][18];
-    __shared__ double s_w[256][4];
-    __shared__ int s_rect[256][4];
-    __shared__ int s_kind[256];
-    __shared__ int s_pref[257];
+    __shared__ double s_P[kBinTris][18];
+    __shared__ double s_w[kBinTris][4];
+    __shared__ int s_rect[kBinTris][4];
+    __shared__ int s_kind[kBinTris];
+    __shared__ int s_pref[kBinTris + 1];
     __shared__ int s_tmp[72];
     __shared__ uint32_t s_base;
-    const int v = find_view(T->tri_block0, T->nv, blockIdx.x);
-    const ViewDev &vd = T->v[v];
-    const prg::Geom &g = vd.g;
-    const int f0 = (blockIdx.x - vd.tri_block0) * 256;
     const int j = threadIdx.x;
-    const int f = f0 + j;
-    int cnt = 0;
-    if (f < vd.mesh.nt) {
-        TriBound b = tb[vd.tri_off + f];
-        if (b.kind != prg::kCulled && b.rect[0] <= b.rect[2] && b.rect[1] <= b.rect[3]) {
-            cnt = (b.rect[2] - b.rect[0] + 1) * (b.rect[3] - b.rect[1] + 1);
-            double Ps[3][3], Pe[3][3];
-            int32_t idx[3];
-            prg::load_tri(vd.mesh.v0, vd.mesh.v1, vd.mesh.tri, vd.mesh.nv, f, g, Ps, Pe, idx);
-            for (int k = 0; k < 3; ++k)
-                for (int r = 0; r < 3; ++r) {
-                    s_P[j][3 * k + r] = Ps[k][r];
-                    s_P[j][9 + 3 * k + r] = Pe[k][r];
+    {
+        const int v = find_view(T->tri_block0, T->nv, blockIdx.x);
+        const ViewDev &vd = T->v[v];
+        const prg::Geom &g = vd.g;
+        const int f0 = (blockIdx.x - vd.tri_block0) * kBinTris;
+        {
+            const int f = f0 + j;
+            int cnt = 0;
+            if (f < vd.mesh.nt) {
+                TriBound b = tb[vd.tri_off + f];
+                if (b.kind != prg::kCulled && b.rect[0] <= b.rect[2] && b.rect[1] <= b.rect[3]) {
+                    cnt = (b.rect[2] - b.rect[0] + 1) * (b.rect[3] - b.rect[1] + 1);
+                    double Ps[3][3], Pe[3][3];
+                    int32_t idx[3];
+                    prg::load_tri(vd.mesh.v0, vd.mesh.v1, vd.mesh.tri, vd.mesh.nv, f, g, Ps, Pe, idx);
+                    for (int k = 0; k < 3; ++k)
+                        for (int r = 0; r < 3; ++r) {
+                            s_P[j][3 * k + r] = Ps[k][r];
+                            s_P[j][9 + 3 * k + r] = Pe[k][r];
+                        }
+                    for (int k = 0; k < 4; ++k) { s_rect[j][k] = b.rect[k]; s_w[j][k] = b.w[k]; }
+                    s_kind[j] = b.kind;
                 }
-            for (int k = 0; k < 4; ++k) { s_rect[j][k] = b.rect[k]; s_w[j][k] = b.w[k]; }
-            s_kind[j] = b.kind;
-        }
-    }
-    int total;
-    const int ex = block_excl_scan(cnt, s_tmp, total);
-    s_pref[j] = ex;
-    if (j == 255) s_pref[256] = total;
-    __syncthreads();
-    const bool split = prg::split_quads(vd.tile);
-    for (int c0 = 0; c0 < total; c0 += 256 * kBinPer) {
-        const int my0 = c0 + j * kBinPer;
-        const int myn = max(0, min(kBinPer, total - my0));
-        int q0 = 0, l0 = 0;
-        uint32_t masks = 0;
-        if (myn > 0) {
-            int lo = 0, hi = 255;   // last triangle whose candidates start at or before my0
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_pref[mid] <= my0) lo = mid; else hi = mid - 1;
             }
-            q0 = lo;
-            l0 = my0 - s_pref[q0];
-            int q = q0, local = l0;
-            for (int k = 0; k < myn; ++k) {
-                while (local >= s_pref[q + 1] - s_pref[q]) { ++q; local = 0; }
-                const int gt = bin_tile(vd, s_rect, q, local);
-                double Ps[3][3], Pe[3][3];
-                for (int a = 0; a < 3; ++a)
-                    for (int r = 0; r < 3; ++r) {
-                        Ps[a][r] = s_P[q][3 * a + r];
-                        Pe[a][r] = s_P[q][9 + 3 * a + r];
-                    }
-                const double w[4] = {s_w[q][0], s_w[q][1], s_w[q][2], s_w[q][3]};
-                const TileInfo &t = ti[gt];
-                const double tbx[4] = {t.box[0], t.box[1], t.box[2], t.box[3]}, tw[2] = {t.tw[0], t.tw[1]};
-                int mask;
-                if (split) {
-                    double qb[4][4];
-                    for (int a = 0; a < 4; ++a)
-                        for (int r = 0; r < 4; ++r) qb[a][r] = t.qb[a][r];
-                    mask = prg::tile_mask_with(g, Ps, Pe, s_kind[q], w, w, tbx, tw, qb, t.qvalid);
-                } else {
-                    mask = prg::tile_mask_with(g, Ps, Pe, s_kind[q], w, w, tbx, tw, nullptr, 0);
-                }
-                masks |= (uint32_t)mask << (4 * k);
-                ++local;
-            }
+            int total;
+            const int ex = block_excl_scan(cnt, s_tmp, total);
+            s_pref[j] = ex;
+            if (j == kBinTris - 1) s_pref[kBinTris] = total;
         }
-        int ns = 0;
-#pragma unroll
-        for (int k = 0; k < kBinPer; ++k) ns += ((masks >> (4 * k)) & 0xFu) != 0u;
-        int rtotal;
-        const int rex = block_excl_scan(ns, s_tmp, rtotal);
-        if (j == 0) s_base = rtotal ? atomicAdd(&st->num_pairs, (unsigned)rtotal) : 0u;
         __syncthreads();
-        if (ns) {
-            uint32_t idx = s_base + (uint32_t)rex;
-            int q = q0, local = l0;
-            for (int k = 0; k < myn; ++k) {
-                while (local >= s_pref[q + 1] - s_pref[q]) { ++q; local = 0; }
-                const uint32_t m = (masks >> (4 * k)) & 0xFu;
-                if (m) {
-                    const int gt = bin_tile(vd, s_rect, q, local);
-                    const unsigned slot = atomicAdd(&tcount[gt], 1u);
-                    if ((int64_t)idx < cap)
-                        pairs[idx] = Pair{gt, (int32_t)slot, (int32_t)((uint32_t)(f0 + q) | (m << kListTriBits))};
-                    ++idx;
+        const int total = s_pref[kBinTris];
+        const int per = min(kBinPer, max(1, (total + 255) >> 8));
+        const bool split = prg::split_quads(vd.tile);
+        for (int c0 = 0; c0 < total; c0 += 256 * per) {
+            const int my0 = c0 + j * per;
+            const int myn = max(0, min(per, total - my0));
+            int q0 = 0, l0 = 0;
+            uint32_t masks = 0;
+            if (myn > 0) {
+                int lo = 0, hi = kBinTris - 1;   // last triangle whose candidates start at or before my0
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_pref[mid] <= my0) lo = mid; else hi = mid - 1;
                 }
-                ++local;
+                q0 = lo;
+                l0 = my0 - s_pref[q0];
+                // the next candidate's tile box is loaded while the current one
+                // is tested
+                int q = q0, local = l0;
+                while (local >= s_pref[q + 1] - s_pref[q]) { ++q; local = 0; }
+                int gt = bin_tile(vd, s_rect, q, local);
+                float4 nb0 = *reinterpret_cast<const float4 *>(&ti[gt].box[0]);
+                float4 nb1 = *reinterpret_cast<const float4 *>(&ti[gt].tw[0]);
+                for (int k = 0; k < myn; ++k) {
+                    const float4 b0 = nb0, b1 = nb1;
+                    const int cq = q, cgt = gt;
+                    if (k + 1 < myn) {
+                        ++local;
+                        while (local >= s_pref[q + 1] - s_pref[q]) { ++q; local = 0; }
+                        gt = bin_tile(vd, s_rect, q, local);
+                        nb0 = *reinterpret_cast<const float4 *>(&ti[gt].box[0]);
+                        nb1 = *reinterpret_cast<const float4 *>(&ti[gt].tw[0]);
+                    }
+                    double Ps[3][3], Pe[3][3];
+                    for (int a = 0; a < 3; ++a)
+                        for (int r = 0; r < 3; ++r) {
+                            Ps[a][r] = s_P[cq][3 * a + r];
+                            Pe[a][r] = s_P[cq][9 + 3 * a + r];
+                        }
+                    const double w[4] = {s_w[cq][0], s_w[cq][1], s_w[cq][2], s_w[cq][3]};
+                    const double tbx[4] = {b0.x, b0.y, b0.z, b0.w}, tw[2] = {b1.x, b1.y};
+                    int mask;
+                    if (split) {
+                        double qb[4][4];
+                        const float4 *qp = reinterpret_cast<const float4 *>(&ti[cgt].qb[0][0]);
+                        for (int a = 0; a < 4; ++a) {
+                            const float4 x = qp[a];
+                            qb[a][0] = x.x; qb[a][1] = x.y; qb[a][2] = x.z; qb[a][3] = x.w;
+                        }
+                        mask = prg::tile_mask_with(g, Ps, Pe, s_kind[cq], w, w, tbx, tw, qb, __float_as_int(b1.z));
+                    } else {
+                        mask = prg::tile_mask_with(g, Ps, Pe, s_kind[cq], w, w, tbx, tw, nullptr, 0);
+                    }
+                    masks |= (uint32_t)mask << (4 * k);
+                }
             }
+            int ns = 0;
+#pragma unroll
+            for (int k = 0; k < kBinPer; ++k) ns += ((masks >> (4 * k)) & 0xFu) != 0u;
+            int rtotal;
+            const int rex = block_excl_scan(ns, s_tmp, rtotal);
+            if (j == 0) s_base = rtotal ? atomicAdd(&st->num_pairs, (unsigned)rtotal) : 0u;
+            __syncthreads();
+            if (ns) {
+                uint32_t idx = s_base + (uint32_t)rex;
+                int q = q0, local = l0;
+                for (int k = 0; k < myn; ++k) {
+                    while (local >= s_pref[q + 1] - s_pref[q]) { ++q; local = 0; }
+                    const uint32_t m = (masks >> (4 * k)) & 0xFu;
+                    if (m) {
+                        const int gt = bin_tile(vd, s_rect, q, local);
+                        const unsigned slot = atomicAdd(&tcount[gt], 1u);
+                        if ((int64_t)idx < cap)
+                            pairs[idx] = Pair{gt, (int32_t)slot, (int32_t)((uint32_t)(f0 + q) | (m << kListTriBits))};
+                        ++idx;
+                    }
+                    ++local;
+                }
+            }
+            __syncthreads();   // s_base is rewritten next round
         }
-        __syncthreads();   // s_base is rewritten next round
     }
 }
 
