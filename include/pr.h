@@ -123,7 +123,9 @@ typedef struct pr_light {
 } pr_light;
 
 /* tile: square tile side in pixels, one of 8, 16, 32.
- * bin_capacity: (triangle, tile) pairs each view's tile lists can hold.
+ * bin_capacity: (triangle, tile) candidate pairs a frame can hold (all
+ *   views; each candidate of a triangle's tile rectangle takes one slot,
+ *   and the tile lists hold the candidates that survive the tile test).
  * flags: PR_FLAG_COUNT makes pr_raycast count ray-triangle tests and hits
  * (sample test efficiency) into the status block; PR_FLAG_PERSISTENT makes
  * it order the tiles longest list first and run one resident grid that
@@ -140,10 +142,10 @@ typedef struct pr_tuning {
 
 /* Device-side conditions of the last frame (all views). */
 typedef struct pr_status {
-    int32_t overflow;          /* 1 if the frame's pairs exceeded bin_capacity */
+    int32_t overflow;          /* 1 if the frame's candidates exceeded bin_capacity */
     int32_t nonfinite;         /* triangles with a bad index or non-finite vertex (culled) */
-    int64_t pairs_required;    /* pairs the frame needed (all views) */
-    int64_t pairs_total;       /* same, as counted */
+    int64_t pairs_required;    /* candidate slots the frame needed (all views) */
+    int64_t pairs_total;       /* (triangle, tile) pairs in the tile lists */
     int64_t tests;             /* ray-triangle tests (PR_FLAG_COUNT) */
     int64_t hits;              /* tests that passed (PR_FLAG_COUNT) */
 } pr_status;

@@ -29,7 +29,7 @@ struct Layout {
     ViewDev vd[PR_MAX_VIEWS];
     int total_tiles, total_tri_blocks, total_pix_blocks, total_vtx_blocks, nparts;
     int64_t cap, total_rec4, total_tris, total_gacc;
-    size_t table, tinfo, rec, tb, tcount, toff, part, pairs, lists, gacc, pacc, sched, order, bytes;
+    size_t table, tinfo, rec, tb, bcand, boff, bpart, tcount, toff, part, pairs, lists, gacc, pacc, sched, order, bytes;
 };
 
 bool finite_all(const float *p, int n) {
@@ -140,6 +140,9 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     L.tinfo = off; off = up(off + (size_t)tiles * sizeof(TileInfo));
     L.rec = off; off = up(off + (size_t)rec4 * sizeof(float4));
     L.tb = off; off = up(off + (size_t)tris * sizeof(TriBound));
+    L.bcand = off; off = up(off + ((size_t)tri_blocks + 1) * 4);
+    L.boff = off; off = up(off + ((size_t)tri_blocks + 1) * 4);
+    L.bpart = off; off = up(off + ((size_t)tri_blocks / 256 + 1) * 4);
     L.tcount = off; off = up(off + ((size_t)tiles + 1) * 4);
     L.toff = off; off = up(off + ((size_t)tiles + 1) * 4);
     L.part = off; off = up(off + (size_t)L.nparts * 4);
@@ -256,18 +259,22 @@ int pr_bound(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const 
     }
     if (L.total_tri_blocks > 0)
         hipLaunchKernelGGL(k_bound, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec),
-                           at<TriBound>(ws, L.tb), st);
+                           at<TriBound>(ws, L.tb), st, at<int32_t>(ws, L.bcand));
     return launched();
 }
 
 int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning, void *ws,
            size_t ws_bytes, void *stream) {
     PR_PREP();
-    hipLaunchKernelGGL(k_tiles, dim3(((L.total_tiles + 1) * 4 + 255) / 256), dim3(256), 0, s, T,
-                       at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<Sched>(ws, L.sched), st);
+    const int tile_blocks = ((L.total_tiles + 1) * 4 + 255) / 256;
+    const int chunk_blocks = (L.total_tri_blocks + 255) / 256;
+    hipLaunchKernelGGL(k_tiles, dim3(std::max(tile_blocks, chunk_blocks)), dim3(256), 0, s, T,
+                       at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<Sched>(ws, L.sched),
+                       at<int32_t>(ws, L.bcand), at<int32_t>(ws, L.boff), at<uint32_t>(ws, L.bpart), st);
     if (L.total_tri_blocks > 0)
         hipLaunchKernelGGL(k_bin, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<TriBound>(ws, L.tb),
-                           at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<Pair>(ws, L.pairs), L.cap, st);
+                           at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<int32_t>(ws, L.boff),
+                           at<uint32_t>(ws, L.bpart), at<Pair>(ws, L.pairs), L.cap);
     int n = L.total_tiles + 1;
     hipLaunchKernelGGL(k_scan_reduce, dim3(L.nparts), dim3(256), 0, s, at<uint32_t>(ws, L.tcount), n,
                        at<uint32_t>(ws, L.part));
@@ -275,7 +282,7 @@ int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
                        at<uint32_t>(ws, L.part), at<uint32_t>(ws, L.toff), at<Sched>(ws, L.sched));
     int sb = (int)std::min<int64_t>(std::max<int64_t>((L.cap + 255) / 256, 1), 2048);
     hipLaunchKernelGGL(k_scatter, dim3(sb), dim3(256), 0, s, at<Pair>(ws, L.pairs), at<uint32_t>(ws, L.toff),
-                       at<int32_t>(ws, L.lists), L.cap, st);
+                       at<int32_t>(ws, L.lists), L.cap, L.total_tiles, st);
     return launched();
 }
 

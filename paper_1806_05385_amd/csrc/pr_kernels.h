@@ -121,8 +121,7 @@ struct DevStatus {
     unsigned long long pairs_total;
     unsigned long long tests;
     unsigned long long hits;
-    uint32_t num_pairs;    // emission cursor of the frame's (triangle, tile) pairs
-    uint32_t pad;
+    uint32_t pad[2];
     unsigned long long cnt[kCountSlots][2];   // ray-cast tests, hits, spread over slots
 };
 

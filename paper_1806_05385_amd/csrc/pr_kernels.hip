@@ -140,12 +140,10 @@ __device__ inline void dcross(const double a[3], const double b[3], double o[3])
 }
 __device__ inline double ddot(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
-__global__ __launch_bounds__(256) void k_bound(const ViewTable *__restrict__ T, float4 *__restrict__ rec,
-                                               TriBound *__restrict__ tb, DevStatus *__restrict__ st) {
-    const int v = find_view(T->tri_block0, T->nv, blockIdx.x);
-    const ViewDev &vd = T->v[v];
-    int f = (blockIdx.x - vd.tri_block0) * 256 + threadIdx.x;
-    if (f >= vd.mesh.nt) return;
+// Per-triangle bound and record of one triangle (k_bound).  Returns the
+// number of (triangle, tile) candidates of its tile rectangle.
+__device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, float4 *__restrict__ rec,
+                                         TriBound *__restrict__ tb, DevStatus *__restrict__ st) {
     const prg::Geom &g = vd.g;
     double Ps[3][3], Pe[3][3];
     int32_t idx[3];
@@ -269,6 +267,22 @@ __global__ __launch_bounds__(256) void k_bound(const ViewTable *__restrict__ T, 
 #pragma unroll
         for (int q = 0; q < kRecStatic; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
     }
+    return b.kind == prg::kCulled ? 0 : (b.rect[2] - b.rect[0] + 1) * (b.rect[3] - b.rect[1] + 1);
+}
+
+// One lane per triangle; the block's candidate total (the binning block of
+// the same 256 triangles) goes to bcand[block].
+__global__ __launch_bounds__(256) void k_bound(const ViewTable *__restrict__ T, float4 *__restrict__ rec,
+                                               TriBound *__restrict__ tb, DevStatus *__restrict__ st,
+                                               int32_t *__restrict__ bcand) {
+    __shared__ int s_tmp[72];
+    const int v = find_view(T->tri_block0, T->nv, blockIdx.x);
+    const ViewDev &vd = T->v[v];
+    const int f = (blockIdx.x - vd.tri_block0) * 256 + threadIdx.x;
+    const int cnt = f < vd.mesh.nt ? bound_tri(vd, f, rec, tb, st) : 0;
+    int total;
+    block_excl_scan(cnt, s_tmp, total);
+    if (threadIdx.x == 0) bcand[blockIdx.x] = total;
 }
 
 // ---------------------------------------------------------------------------
@@ -276,17 +290,34 @@ __global__ __launch_bounds__(256) void k_bound(const ViewTable *__restrict__ T, 
 // ---------------------------------------------------------------------------
 // Four lanes per tile, lane q computing quadrant q's box; a split tile's box
 // is the union of its quadrants' boxes (every pixel centre of the tile lies
-// in its quadrant's box), an unsplit tile's box is computed by lane 0.
+// in its quadrant's box), an unsplit tile's box is computed by lane 0.  The
+// kernel also clears the binning counters and scans the binning blocks'
+// candidate totals in chunks of 256 (grid: at least one block per chunk).
 __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, TileInfo *__restrict__ ti,
-                                               uint32_t *__restrict__ tcount, Sched *__restrict__ S,
+                                               uint32_t *__restrict__ tcount, Sched *__restrict__ S, const int32_t *__restrict__ bcand,
+                                               int32_t *__restrict__ boff, uint32_t *__restrict__ part,
                                                DevStatus *__restrict__ st) {
+    __shared__ int s_tmp[72];
     const int gid = blockIdx.x * 256 + threadIdx.x;
     const int gt = gid >> 2, q = gid & 3;
     const bool valid = gt < T->total_tiles;
     // clear the counters the binning pass accumulates into
     if (q == 0 && gt <= T->total_tiles) tcount[gt] = 0u;
     if (gid < kBuckets) S->count[gid] = 0u;
-    if (gid == 0) st->num_pairs = 0u;
+    if (blockIdx.x < (T->total_tri_blocks + 255) / 256) {
+        // the binning blocks' candidate slots: local exclusive scan of 256
+        // block totals here; k_bin adds the totals of the chunks before
+        const int nb = T->total_tri_blocks;
+        const int b = blockIdx.x * 256 + threadIdx.x;
+        const int c = b < nb ? bcand[b] : 0;
+        int tot;
+        const int ex = block_excl_scan(c, s_tmp, tot);
+        if (b < nb) boff[b] = ex;
+        if (threadIdx.x == 0) {
+            part[blockIdx.x] = (uint32_t)tot;
+            atomicAdd(&st->pairs_required, (unsigned long long)tot);
+        }
+    }
     const int v = find_view(T->tile_base, T->nv, valid ? gt : 0);
     const ViewDev &vd = T->v[v];
     const prg::Geom &g = vd.g;
@@ -338,7 +369,9 @@ __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, 
 // bin
 // ---------------------------------------------------------------------------
 struct Pair {
-    int32_t tile, slot, tri;   // global tile, slot in its list, list entry (triangle index | quadrant mask)
+    int32_t tile;    // global tile, -1: rejected candidate
+    int32_t slot;    // slot in the tile's list
+    int32_t entry;   // list entry (triangle index | quadrant mask)
 };
 
 // Each round gives every thread kBinPer consecutive candidates (mostly of
@@ -364,14 +397,14 @@ constexpr int kBinTris = 256;
 
 __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, const TriBound *__restrict__ tb,
                                              const TileInfo *__restrict__ ti, uint32_t *__restrict__ tcount,
-                                             Pair *__restrict__ pairs, int64_t cap, DevStatus *__restrict__ st) {
+                                             const int32_t *__restrict__ boff, const uint32_t *__restrict__ bpart,
+                                             Pair *__restrict__ pairs, int64_t cap) {
     __shared__ double s_P[kBinTris][18];
     __shared__ double s_w[kBinTris][4];
     __shared__ int s_rect[kBinTris][4];
     __shared__ int s_kind[kBinTris];
     __shared__ int s_pref[kBinTris + 1];
     __shared__ int s_tmp[72];
-    __shared__ uint32_t s_base;
     const int j = threadIdx.x;
     {
         const int v = find_view(T->tri_block0, T->nv, blockIdx.x);
@@ -402,7 +435,13 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
             s_pref[j] = ex;
             if (j == kBinTris - 1) s_pref[kBinTris] = total;
         }
-        __syncthreads();
+        // the block's first candidate slot: its offset in its chunk of 256
+        // blocks plus the totals of the chunks before
+        int cpre = 0;
+        for (int i = j; i < (int)(blockIdx.x >> 8); i += 256) cpre += (int)bpart[i];
+        int ctot;
+        block_excl_scan(cpre, s_tmp, ctot);
+        const int64_t s_off = (int64_t)boff[blockIdx.x] + ctot;
         const int total = s_pref[kBinTris];
         const int per = min(kBinPer, max(1, (total + 255) >> 8));
         const bool split = prg::split_quads(vd.tile);
@@ -459,30 +498,22 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
                     masks |= (uint32_t)mask << (4 * k);
                 }
             }
-            int ns = 0;
-#pragma unroll
-            for (int k = 0; k < kBinPer; ++k) ns += ((masks >> (4 * k)) & 0xFu) != 0u;
-            int rtotal;
-            const int rex = block_excl_scan(ns, s_tmp, rtotal);
-            if (j == 0) s_base = rtotal ? atomicAdd(&st->num_pairs, (unsigned)rtotal) : 0u;
-            __syncthreads();
-            if (ns) {
-                uint32_t idx = s_base + (uint32_t)rex;
+            // every candidate owns a pair slot (boff: the block's first); a
+            // survivor takes its place in its tile's list with an atomic on
+            // the tile's count (the thread's atomics are issued back to back)
+            if (myn > 0) {
+                const int64_t base = s_off + my0;
                 int q = q0, local = l0;
                 for (int k = 0; k < myn; ++k) {
                     while (local >= s_pref[q + 1] - s_pref[q]) { ++q; local = 0; }
                     const uint32_t m = (masks >> (4 * k)) & 0xFu;
-                    if (m) {
-                        const int gt = bin_tile(vd, s_rect, q, local);
-                        const unsigned slot = atomicAdd(&tcount[gt], 1u);
-                        if ((int64_t)idx < cap)
-                            pairs[idx] = Pair{gt, (int32_t)slot, (int32_t)((uint32_t)(f0 + q) | (m << kListTriBits))};
-                        ++idx;
-                    }
+                    const int gt = bin_tile(vd, s_rect, q, local);
+                    const uint32_t slot = m ? atomicAdd(&tcount[gt], 1u) : 0u;
+                    if (base + k < cap)
+                        pairs[base + k] = Pair{m ? gt : -1, (int32_t)slot, (int32_t)((uint32_t)(f0 + q) | (m << kListTriBits))};
                     ++local;
                 }
             }
-            __syncthreads();   // s_base is rewritten next round
         }
     }
 }
@@ -542,21 +573,20 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// scatter pairs into tile lists; flags overflow
+// scatter pairs into tile lists (slot order within a list is arbitrary)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_scatter(const Pair *__restrict__ pairs, const uint32_t *__restrict__ toff,
-                                                 int32_t *__restrict__ lists, int64_t cap,
+                                                 int32_t *__restrict__ lists, int64_t cap, int ntiles,
                                                  DevStatus *__restrict__ st) {
-    uint32_t np = st->num_pairs;
+    const int64_t n = (int64_t)st->pairs_required;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->pairs_total = np;
-        st->pairs_required = np;
-        if ((int64_t)np > cap) st->overflow = 1;
+        st->pairs_total = toff[ntiles];
+        if (n > cap) st->overflow = 1;
     }
-    if ((int64_t)np > cap) return;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)np; i += (int64_t)gridDim.x * blockDim.x) {
-        Pair p = pairs[i];
-        lists[toff[p.tile] + p.slot] = p.tri;
+    if (n > cap) return;   // overflow: the ray cast writes misses
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const Pair p = pairs[i];
+        if (p.tile >= 0) lists[toff[p.tile] + p.slot] = p.entry;
     }
 }
 

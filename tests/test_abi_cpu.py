@@ -57,7 +57,7 @@ def test_workspace_size_and_argument_checks():
     big = ctypes.c_size_t(0)
     tu2 = B.PrTuning(16, 100000, 0, 0)
     assert L.pr_workspace_size(meshes, 1, views, 1, ctypes.byref(tu2), ctypes.byref(big)) == B.PR_OK
-    assert big.value >= size.value + (100000 - 1000) * 16 - 1024
+    assert big.value >= size.value + (100000 - 1000) * 16 - 1024   # 12-byte pair + 4-byte list entry
     bad = [
         dict(width=0), dict(height=20000), dict(mesh=3), dict(alpha=0.5), dict(znear=0.0), dict(fx=0.0),
         dict(fovea=(1.5, 0.0)), dict(alpha=float('nan')),
