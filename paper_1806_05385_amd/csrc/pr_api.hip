@@ -490,7 +490,7 @@ int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32
     double w[4];
     if (kind == prg::kWindow) { w[0] = win[0]; w[1] = win[1]; w[2] = w[3] = 0.0; }
     else for (int k = 0; k < 4; ++k) w[k] = box[k];
-    return prg::tile_mask(g, Ps, Pe, kind, w, w, tile, tx, ty);
+    return prg::tile_mask(g, Ps, Pe, kind, w, tile, tx, ty);
 }
 
 }  // extern "C"

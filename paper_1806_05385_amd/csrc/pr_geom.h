@@ -438,79 +438,6 @@ PRG bool quad_display(const Geom &g, int tile, int tx, int ty, int k, double box
     return region_display(g, i0, i0 + h - 1, j0, j0 + h - 1, box);
 }
 
-PRG bool box_meets_box(const double a[4], const double b[4]) {
-    return !(a[1] < b[0] || a[0] > b[1] || a[3] < b[2] || a[2] > b[3]);
-}
-
-// Conservative test of one (triangle, tile) pair given the tile's display
-// box tb and time window tw (tile_display).  Returns the 4-bit mask of the
-// tile's quadrants the triangle may cover; 0 rejects the pair.  kWindow
-// triangles: the window is cut to the tile's own time window; the six
-// projected end vertices of that window bound the triangle's image over
-// it, and a separating-axis test (their x and y extents, then the edge
-// normals of both end triangles) against the tile's display box keeps the
-// pair; each quadrant box qb[k] whose bit k is set in qvalid is kept if it
-// meets the vertices' x and y extents.  kClipped triangles compare their
-// whole-frame display box.  qb == nullptr: the tile is not split (mask 0xF
-// when it is kept).
-PRG int tile_mask_with(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double win[2],
-                       const double tri_box[4], const double tb[4], const double tw[2], const double (*qb)[4],
-                       int qvalid) {
-    double ext[4];
-    if (kind == kClipped) {
-        if (!box_meets_box(tri_box, tb)) return 0;
-        for (int k = 0; k < 4; ++k) ext[k] = tri_box[k];
-    } else {
-        double w0 = dmax(win[0], tw[0]), w1 = dmin(win[1], tw[1]);
-        if (w0 > w1) return 0;
-        // the six projected end vertices of [w0, w1]
-        double q[6][2];
-        for (int k = 0; k < 3; ++k)
-            for (int e = 0; e < 2; ++e) {
-                const double w = e ? w1 : w0;
-                double P[3];
-                for (int r = 0; r < 3; ++r) P[r] = (1.0 - w) * Ps[k][r] + w * Pe[k][r];
-                const double iz = 1.0 / P[2];
-                q[3 * e + k][0] = g.fx * P[0] * iz + g.cx;
-                q[3 * e + k][1] = g.fy * P[1] * iz + g.cy;
-            }
-        double big = 1.0;
-        for (int i = 0; i < 6; ++i) big = dmax(big, dmax(fabs(q[i][0]), fabs(q[i][1])));
-        // separating axes, tested one at a time: x, y (the hull's extents,
-        // kept for the quadrant tests), then the edge normals of both end
-        // triangles
-        ext[0] = ext[2] = 1e300;
-        ext[1] = ext[3] = -1e300;
-        for (int i = 0; i < 6; ++i) {
-            ext[0] = dmin(ext[0], q[i][0]); ext[1] = dmax(ext[1], q[i][0]);
-            ext[2] = dmin(ext[2], q[i][1]); ext[3] = dmax(ext[3], q[i][1]);
-        }
-        const double mxy = 1e-12 * big;
-        ext[0] -= mxy; ext[1] += mxy; ext[2] -= mxy; ext[3] += mxy;
-        if (!box_meets_box(ext, tb)) return 0;
-        for (int a = 0; a < 6; ++a) {
-            const int e = a / 3, k = a % 3;
-            const double *p = q[3 * e + k], *r = q[3 * e + (k + 1) % 3];
-            const double n0 = -(r[1] - p[1]), n1 = r[0] - p[0];
-            double pmin = 1e300, pmax = -1e300;
-            for (int i = 0; i < 6; ++i) {
-                const double sp = n0 * q[i][0] + n1 * q[i][1];
-                pmin = dmin(pmin, sp);
-                pmax = dmax(pmax, sp);
-            }
-            const double m = 1e-12 * (fabs(n0) + fabs(n1)) * big;
-            const double bmin = n0 * (n0 >= 0.0 ? tb[0] : tb[1]) + n1 * (n1 >= 0.0 ? tb[2] : tb[3]);
-            const double bmax = n0 * (n0 >= 0.0 ? tb[1] : tb[0]) + n1 * (n1 >= 0.0 ? tb[3] : tb[2]);
-            if (pmax + m < bmin || pmin - m > bmax) return 0;
-        }
-    }
-    if (!qb) return 0xF;
-    int mask = 0;
-    for (int k = 0; k < 4; ++k)
-        if (((qvalid >> k) & 1) && box_meets_box(ext, qb[k])) mask |= 1 << k;
-    return mask;
-}
-
 // FP32 rounding of a bound towards -inf / +inf (the stored tile boxes).
 PRG float f32_down(double x) {
     float f = (float)x;
@@ -520,42 +447,136 @@ PRG float f32_up(double x) {
     float f = (float)x;
     return (double)f < x ? nextafterf(f, INFINITY) : f;
 }
-// A box [lo0, hi0, lo1, hi1] rounded outwards to FP32 and widened back.
-PRG void box_outward(double b[4]) {
-    b[0] = f32_down(b[0]); b[1] = f32_up(b[1]);
-    b[2] = f32_down(b[2]); b[3] = f32_up(b[3]);
+// The triangle's image over its whole time window as the per-tile test
+// sees it, built once per triangle: the projected window-end vertices'
+// x and y extents and six edge axes of the two end triangles, each
+// interval computed in FP64 for the FP32-rounded axis and rounded outwards
+// to FP32 (any axis direction gives a valid separating-axis test).
+// kClipped triangles: their display box as extents, no edge axes.  128 B.
+struct SatRec {
+    float ext[4];      // x lo, x hi, y lo, y hi
+    float win[2];      // time window (kClipped: [0, 1])
+    int32_t kind;
+    int32_t pad;
+    float ax[6][4];    // axis n0, n1 and the interval lo, hi
+};
+
+PRG float f32_clamp(float x) { return x < -1e30f ? -1e30f : (x > 1e30f ? 1e30f : x); }
+
+PRG void sat_build(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double w[4],
+                   SatRec &R) {
+    R.kind = kind;
+    R.pad = 0;
+    if (kind != kWindow) {
+        R.ext[0] = f32_down(w[0]); R.ext[1] = f32_up(w[1]);
+        R.ext[2] = f32_down(w[2]); R.ext[3] = f32_up(w[3]);
+        R.win[0] = 0.0f; R.win[1] = 1.0f;
+        for (int a = 0; a < 6; ++a) { R.ax[a][0] = R.ax[a][1] = 0.0f; R.ax[a][2] = -1.0f; R.ax[a][3] = 1.0f; }
+        return;
+    }
+    const double w0 = w[0], w1 = w[1];
+    R.win[0] = f32_down(w0);
+    R.win[1] = f32_up(w1);
+    double q[6][2];
+    for (int k = 0; k < 3; ++k)
+        for (int e = 0; e < 2; ++e) {
+            const double t = e ? w1 : w0;
+            double P[3];
+            for (int r = 0; r < 3; ++r) P[r] = (1.0 - t) * Ps[k][r] + t * Pe[k][r];
+            const double iz = 1.0 / P[2];
+            q[3 * e + k][0] = g.fx * P[0] * iz + g.cx;
+            q[3 * e + k][1] = g.fy * P[1] * iz + g.cy;
+        }
+    double big = 1.0;
+    for (int i = 0; i < 6; ++i) big = dmax(big, dmax(fabs(q[i][0]), fabs(q[i][1])));
+    double ext[4] = {1e300, -1e300, 1e300, -1e300};
+    for (int i = 0; i < 6; ++i) {
+        ext[0] = dmin(ext[0], q[i][0]); ext[1] = dmax(ext[1], q[i][0]);
+        ext[2] = dmin(ext[2], q[i][1]); ext[3] = dmax(ext[3], q[i][1]);
+    }
+    const double mxy = 1e-12 * big;
+    R.ext[0] = f32_clamp(f32_down(ext[0] - mxy)); R.ext[1] = f32_clamp(f32_up(ext[1] + mxy));
+    R.ext[2] = f32_clamp(f32_down(ext[2] - mxy)); R.ext[3] = f32_clamp(f32_up(ext[3] + mxy));
+    for (int a = 0; a < 6; ++a) {
+        const int e = a / 3, k = a % 3;
+        const double *p = q[3 * e + k], *r = q[3 * e + (k + 1) % 3];
+        const float n0 = (float)(-(r[1] - p[1])), n1 = (float)(r[0] - p[0]);
+        double lo = 1e300, hi = -1e300;
+        for (int i = 0; i < 6; ++i) {
+            const double sp = (double)n0 * q[i][0] + (double)n1 * q[i][1];
+            lo = dmin(lo, sp);
+            hi = dmax(hi, sp);
+        }
+        const double m = 1e-12 * (fabs((double)n0) + fabs((double)n1)) * big;
+        R.ax[a][0] = n0;
+        R.ax[a][1] = n1;
+        R.ax[a][2] = f32_clamp(f32_down(lo - m));
+        R.ax[a][3] = f32_clamp(f32_up(hi + m));
+    }
+}
+
+PRG bool fbox_meets(const float a[4], const float b[4]) {
+    return !(a[1] < b[0] || a[0] > b[1] || a[3] < b[2] || a[2] > b[3]);
+}
+
+// Per-tile test in FP32 against a tile's display box tb and time window tw
+// (outward-rounded FP32).  Returns the 4-bit mask of the quadrants (boxes
+// qb[k] with bit k of qvalid) the triangle may cover; 0 rejects the pair;
+// qb == nullptr: no split (0xF when kept).  The box's projection on an axis
+// is rounded at most twice in FP32 (2^-23 relative); the test widens it by
+// 1e-6 of its magnitude.
+PRG int sat_mask(const SatRec &R, const float tb[4], const float tw[2], const float (*qb)[4], int qvalid) {
+    if (R.win[1] < tw[0] || R.win[0] > tw[1]) return 0;
+    if (!fbox_meets(R.ext, tb)) return 0;
+    const float B = fmaxf(1.0f, fmaxf(fmaxf(fabsf(tb[0]), fabsf(tb[1])), fmaxf(fabsf(tb[2]), fabsf(tb[3]))));
+    for (int a = 0; a < 6; ++a) {
+        const float n0 = R.ax[a][0], n1 = R.ax[a][1];
+        const float bmin = fmaf(n0, n0 >= 0.0f ? tb[0] : tb[1], n1 * (n1 >= 0.0f ? tb[2] : tb[3]));
+        const float bmax = fmaf(n0, n0 >= 0.0f ? tb[1] : tb[0], n1 * (n1 >= 0.0f ? tb[3] : tb[2]));
+        const float m = 1e-6f * (fabsf(n0) + fabsf(n1)) * B;
+        if (R.ax[a][3] < bmin - m || R.ax[a][2] > bmax + m) return 0;
+    }
+    if (!qb) return 0xF;
+    int mask = 0;
+    for (int k = 0; k < 4; ++k)
+        if (((qvalid >> k) & 1) && fbox_meets(R.ext, qb[k])) mask |= 1 << k;
+    return mask;
 }
 
 // Tiles of 16 pixels and more are split into quadrants.
 PRG bool split_quads(int tile) { return tile >= 16; }
 
-// The same from the tile's coordinates (host tests), with the tile box and
-// window built as the device builds them: a split tile's box is the union
-// of its quadrants' boxes.
-PRG int tile_mask(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double win[2],
-                  const double tri_box[4], int tile, int tx, int ty) {
+// The same from the tile's coordinates (host tests), with the tile boxes
+// and window built and rounded as the device builds them: a split tile's
+// box is the union of its quadrants' boxes.
+PRG int tile_mask(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double w[4],
+                  int tile, int tx, int ty) {
     double tb[4], tw[2], qb[4][4];
+    int qvalid = 0;
     if (!split_quads(tile)) {
         tile_display(g, tile, tx, ty, tb, tw);
     } else {
         tb[0] = tb[2] = 1e300;
         tb[1] = tb[3] = -1e300;
-    }
-    int qvalid = 0;
-    if (split_quads(tile)) {
         for (int k = 0; k < 4; ++k)
             if (quad_display(g, tile, tx, ty, k, qb[k])) {
                 qvalid |= 1 << k;
                 tb[0] = dmin(tb[0], qb[k][0]); tb[1] = dmax(tb[1], qb[k][1]);
                 tb[2] = dmin(tb[2], qb[k][2]); tb[3] = dmax(tb[3], qb[k][3]);
-                box_outward(qb[k]);
             }
         tile_time(g, tb, tw);
     }
-    box_outward(tb);
-    tw[0] = f32_down(tw[0]);
-    tw[1] = f32_up(tw[1]);
-    return tile_mask_with(g, Ps, Pe, kind, win, tri_box, tb, tw, split_quads(tile) ? qb : nullptr, qvalid);
+    float ftb[4] = {f32_down(tb[0]), f32_up(tb[1]), f32_down(tb[2]), f32_up(tb[3])};
+    float ftw[2] = {f32_down(tw[0]), f32_up(tw[1])};
+    float fqb[4][4];
+    for (int k = 0; k < 4; ++k) {
+        const bool ok = (qvalid >> k) & 1;
+        fqb[k][0] = ok ? f32_down(qb[k][0]) : 0.0f; fqb[k][1] = ok ? f32_up(qb[k][1]) : 0.0f;
+        fqb[k][2] = ok ? f32_down(qb[k][2]) : 0.0f; fqb[k][3] = ok ? f32_up(qb[k][3]) : 0.0f;
+    }
+    SatRec R;
+    sat_build(g, Ps, Pe, kind, w, R);
+    return sat_mask(R, ftb, ftw, split_quads(tile) ? fqb : nullptr, qvalid);
 }
 
 }  // namespace prg

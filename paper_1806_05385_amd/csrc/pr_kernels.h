@@ -32,6 +32,7 @@ constexpr int kRecStatic = 6;
 constexpr int kCountSlots = 64;
 
 // Per-triangle bound (64 bytes).
+// Per-triangle bound (64 bytes).
 struct TriBound {
     int32_t rect[4];   // inclusive tile rectangle x0, y0, x1, y1 (x0 > x1: culled)
     int32_t kind;      // prg::kCulled / kWindow / kClipped

@@ -384,25 +384,26 @@ struct Pair {
 constexpr int kBinPer = 8;
 
 // (triangle q, local candidate index) -> global tile of the candidate.
-__device__ __forceinline__ int bin_tile(const ViewDev &vd, const int (*s_rect)[4], int q, int local) {
+__device__ __forceinline__ int bin_tile(const ViewDev &vd, const int (*s_rect)[5], int q, int local) {
     const int rw = s_rect[q][2] - s_rect[q][0] + 1;
     const int tx = s_rect[q][0] + local % rw, ty = s_rect[q][1] + local / rw;
     return vd.tile_base + ty * vd.tiles_x + tx;
 }
 
-// One block per kBinTris triangles.  Each round gives every thread `per`
-// consecutive candidates, per = ceil(candidates / 256) up to kBinPer, so all
-// threads of the block share the work.
+// One block per kBinTris triangles.  Each triangle's test record is built
+// once (FP64, rounded outwards to FP32) into LDS; each round gives
+// every thread `per` consecutive candidates, per = ceil(candidates / 256) up
+// to kBinPer, tested in FP32 against the tile's FP32 boxes.
 constexpr int kBinTris = 256;
 
 __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, const TriBound *__restrict__ tb,
                                              const TileInfo *__restrict__ ti, uint32_t *__restrict__ tcount,
                                              const int32_t *__restrict__ boff, const uint32_t *__restrict__ bpart,
                                              Pair *__restrict__ pairs, int64_t cap) {
-    __shared__ double s_P[kBinTris][18];
-    __shared__ double s_w[kBinTris][4];
-    __shared__ int s_rect[kBinTris][4];
-    __shared__ int s_kind[kBinTris];
+    // odd row strides (33 and 5 words) keep lanes reading different
+    // triangles on different LDS banks
+    __shared__ uint32_t s_sat[kBinTris][33];
+    __shared__ int s_rect[kBinTris][5];
     __shared__ int s_pref[kBinTris + 1];
     __shared__ int s_tmp[72];
     const int j = threadIdx.x;
@@ -412,22 +413,23 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
         const prg::Geom &g = vd.g;
         const int f0 = (blockIdx.x - vd.tri_block0) * kBinTris;
         {
+            // one lane per triangle: its tile rectangle and its test record
+            // (FP64, once per triangle)
             const int f = f0 + j;
             int cnt = 0;
             if (f < vd.mesh.nt) {
-                TriBound b = tb[vd.tri_off + f];
+                const TriBound b = tb[vd.tri_off + f];
                 if (b.kind != prg::kCulled && b.rect[0] <= b.rect[2] && b.rect[1] <= b.rect[3]) {
                     cnt = (b.rect[2] - b.rect[0] + 1) * (b.rect[3] - b.rect[1] + 1);
                     double Ps[3][3], Pe[3][3];
                     int32_t idx[3];
                     prg::load_tri(vd.mesh.v0, vd.mesh.v1, vd.mesh.tri, vd.mesh.nv, f, g, Ps, Pe, idx);
-                    for (int k = 0; k < 3; ++k)
-                        for (int r = 0; r < 3; ++r) {
-                            s_P[j][3 * k + r] = Ps[k][r];
-                            s_P[j][9 + 3 * k + r] = Pe[k][r];
-                        }
-                    for (int k = 0; k < 4; ++k) { s_rect[j][k] = b.rect[k]; s_w[j][k] = b.w[k]; }
-                    s_kind[j] = b.kind;
+                    prg::SatRec R;
+                    prg::sat_build(g, Ps, Pe, b.kind, b.w, R);
+                    const uint32_t *rw = reinterpret_cast<const uint32_t *>(&R);
+#pragma unroll
+                    for (int i = 0; i < 32; ++i) s_sat[j][i] = rw[i];
+                    for (int k = 0; k < 4; ++k) s_rect[j][k] = b.rect[k];
                 }
             }
             int total;
@@ -458,42 +460,39 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
                 }
                 q0 = lo;
                 l0 = my0 - s_pref[q0];
-                // the next candidate's tile box is loaded while the current one
-                // is tested
+                // the next candidate's tile info is loaded while the current
+                // one is tested
                 int q = q0, local = l0;
                 while (local >= s_pref[q + 1] - s_pref[q]) { ++q; local = 0; }
                 int gt = bin_tile(vd, s_rect, q, local);
-                float4 nb0 = *reinterpret_cast<const float4 *>(&ti[gt].box[0]);
-                float4 nb1 = *reinterpret_cast<const float4 *>(&ti[gt].tw[0]);
+                float4 nt[6];
+#pragma unroll
+                for (int i = 0; i < 6; ++i) nt[i] = reinterpret_cast<const float4 *>(&ti[gt])[i];
                 for (int k = 0; k < myn; ++k) {
-                    const float4 b0 = nb0, b1 = nb1;
-                    const int cq = q, cgt = gt;
+                    float4 tt[6];
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) tt[i] = nt[i];
+                    const int cq = q;
                     if (k + 1 < myn) {
                         ++local;
                         while (local >= s_pref[q + 1] - s_pref[q]) { ++q; local = 0; }
                         gt = bin_tile(vd, s_rect, q, local);
-                        nb0 = *reinterpret_cast<const float4 *>(&ti[gt].box[0]);
-                        nb1 = *reinterpret_cast<const float4 *>(&ti[gt].tw[0]);
+#pragma unroll
+                        for (int i = 0; i < 6; ++i) nt[i] = reinterpret_cast<const float4 *>(&ti[gt])[i];
                     }
-                    double Ps[3][3], Pe[3][3];
-                    for (int a = 0; a < 3; ++a)
-                        for (int r = 0; r < 3; ++r) {
-                            Ps[a][r] = s_P[cq][3 * a + r];
-                            Pe[a][r] = s_P[cq][9 + 3 * a + r];
-                        }
-                    const double w[4] = {s_w[cq][0], s_w[cq][1], s_w[cq][2], s_w[cq][3]};
-                    const double tbx[4] = {b0.x, b0.y, b0.z, b0.w}, tw[2] = {b1.x, b1.y};
+                    // TileInfo words: box 0..3, tw 4..5, qvalid 6, pad 7, qb 8..23
+                    const float tbx[4] = {tt[0].x, tt[0].y, tt[0].z, tt[0].w}, tw[2] = {tt[1].x, tt[1].y};
+                    prg::SatRec R;
+                    uint32_t *rw = reinterpret_cast<uint32_t *>(&R);
+#pragma unroll
+                    for (int i = 0; i < 32; ++i) rw[i] = s_sat[cq][i];
                     int mask;
                     if (split) {
-                        double qb[4][4];
-                        const float4 *qp = reinterpret_cast<const float4 *>(&ti[cgt].qb[0][0]);
-                        for (int a = 0; a < 4; ++a) {
-                            const float4 x = qp[a];
-                            qb[a][0] = x.x; qb[a][1] = x.y; qb[a][2] = x.z; qb[a][3] = x.w;
-                        }
-                        mask = prg::tile_mask_with(g, Ps, Pe, s_kind[cq], w, w, tbx, tw, qb, __float_as_int(b1.z));
+                        const float qb[4][4] = {{tt[2].x, tt[2].y, tt[2].z, tt[2].w}, {tt[3].x, tt[3].y, tt[3].z, tt[3].w},
+                                                {tt[4].x, tt[4].y, tt[4].z, tt[4].w}, {tt[5].x, tt[5].y, tt[5].z, tt[5].w}};
+                        mask = prg::sat_mask(R, tbx, tw, qb, __float_as_int(tt[1].z));
                     } else {
-                        mask = prg::tile_mask_with(g, Ps, Pe, s_kind[cq], w, w, tbx, tw, nullptr, 0);
+                        mask = prg::sat_mask(R, tbx, tw, nullptr, 0);
                     }
                     masks |= (uint32_t)mask << (4 * k);
                 }
