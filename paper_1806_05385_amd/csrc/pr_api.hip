@@ -151,7 +151,7 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     L.gacc = off; off = up(off + (size_t)gacc * 4);
     L.pacc = off; off = up(off + (size_t)PR_MAX_VIEWS * kPoseAcc * 8);
     L.sched = off; off = up(off + sizeof(Sched));
-    L.order = off; off = up(off + (size_t)tiles * 4);
+    L.order = off; off = up(off + (size_t)tiles * 16);
     L.bytes = off;
     return PR_OK;
 }
@@ -209,15 +209,14 @@ void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, D
     Sched *S = at<Sched>(ws, L.sched);
     const int nb = (L.total_tiles + 255) / 256;
     fill_u32(S->cursor, 0u, kBuckets, s);
-    hipLaunchKernelGGL(k_sched_scatter, dim3(nb), dim3(256), 0, s, at<uint32_t>(ws, L.toff), L.total_tiles, S,
-                       at<int32_t>(ws, L.order));
+    hipLaunchKernelGGL(k_sched_scatter, dim3(nb), dim3(256), 0, s, T, at<uint32_t>(ws, L.toff), L.total_tiles, S,
+                       at<int4>(ws, L.order), st);
     static int resident = 0;
     if (!resident) resident = resident_blocks(k_raycast_queue<TILE, COUNT>, C::NT);
     const int nitems = ray_items<TILE>(L.total_tiles);
     const int grid = std::max(1, std::min(nitems, resident));
     hipLaunchKernelGGL((k_raycast_queue<TILE, COUNT>), dim3(grid), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
-                       at<uint32_t>(ws, L.toff), at<uint32_t>(ws, L.lists), out, st, at<int32_t>(ws, L.order),
-                       nitems);
+                       at<uint32_t>(ws, L.lists), out, st, at<int4>(ws, L.order), nitems);
 }
 
 template <int TILE>

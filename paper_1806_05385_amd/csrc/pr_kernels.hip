@@ -832,19 +832,29 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
     }
 }
 
-// Block item -> wave's cell.  src maps an item-level tile index to a global
-// tile (identity, or the longest-first order of the persistent form).
+// A tile as the ray cast takes it: global tile, view, list begin and end
+// (x < 0: none).
+__device__ __forceinline__ int4 tile_rec(const ViewTable *__restrict__ T, const uint32_t *__restrict__ toff,
+                                         int gt, bool ovf) {
+    const int v = find_view(T->tile_base, T->nv, gt);
+    return ovf ? make_int4(gt, v, 0, 0) : make_int4(gt, v, (int)toff[gt], (int)toff[gt + 1]);
+}
+
+// The wave's tile index of a block item: 8x8 tiles: four tiles per item;
+// 16x16: one; 32x32: one quadrant of a tile per item.
+template <int TILE>
+__device__ __forceinline__ int item_tile(int item, int wv) {
+    return TILE == 8 ? 4 * item + wv : (TILE == 16 ? item : item >> 2);
+}
+
+// Block item -> the wave's 8x8 cell of tile record tr.
 template <int TILE, bool COUNT>
 __device__ __forceinline__ void raycast_item(const ViewTable *__restrict__ T, const float4 *__restrict__ rec,
-                                             const uint32_t *__restrict__ toff, const uint32_t *__restrict__ lists,
-                                             const RayOut &out, DevStatus *__restrict__ st, int item,
-                                             const int32_t *__restrict__ order, int32_t *s_sel_block) {
+                                             const uint32_t *__restrict__ lists, const RayOut &out,
+                                             DevStatus *__restrict__ st, int item, int4 tr, int32_t *s_sel_block) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int ntiles = T->total_tiles;
-    int k = TILE == 8 ? 4 * item + wv : (TILE == 16 ? item : item >> 2);
-    if (k >= ntiles) return;
-    const int gt = order ? order[k] : k;
-    const int v = find_view(T->tile_base, T->nv, gt);
+    if (tr.x < 0) return;
+    const int gt = tr.x, v = tr.y;
     const ViewDev &vd = T->v[v];
     const int lt = gt - vd.tile_base;
     const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
@@ -859,18 +869,13 @@ __device__ __forceinline__ void raycast_item(const ViewTable *__restrict__ T, co
         cy0 += (q >> 1) * 16 + (wv >> 1) * 8;
     }
     if (cx0 >= vd.pc.W || cy0 >= vd.pc.H) return;   // cell outside the image
-    int beg = 0, end = 0;
-    if (!st->overflow) {
-        beg = (int)toff[gt];
-        end = (int)toff[gt + 1];
-    }
     const float *vrec = reinterpret_cast<const float *>(rec + vd.rec_off);
     unsigned long long *cnt = &st->cnt[blockIdx.x & (kCountSlots - 1)][0];
     int32_t *s_sel = s_sel_block + wv * kSelCap;
     if (vd.rolling)
-        raycast_cell<true, COUNT>(vd, cx0, cy0, q, vrec, beg, end, lists, out.id[v], out.depth[v], cnt, s_sel);
+        raycast_cell<true, COUNT>(vd, cx0, cy0, q, vrec, tr.z, tr.w, lists, out.id[v], out.depth[v], cnt, s_sel);
     else
-        raycast_cell<false, COUNT>(vd, cx0, cy0, q, vrec, beg, end, lists, out.id[v], out.depth[v], cnt, s_sel);
+        raycast_cell<false, COUNT>(vd, cx0, cy0, q, vrec, tr.z, tr.w, lists, out.id[v], out.depth[v], cnt, s_sel);
 }
 
 // Block b -> item: consecutive blocks go to the eight XCDs in turn, so XCD
@@ -888,7 +893,10 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
                                                                const uint32_t *__restrict__ lists, RayOut out,
                                                                DevStatus *__restrict__ st) {
     __shared__ int32_t s_sel[4 * kSelCap];
-    raycast_item<TILE, COUNT>(T, rec, toff, lists, out, st, xcd_item(blockIdx.x, gridDim.x), nullptr, s_sel);
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    const int k = item_tile<TILE>(item, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+    const int4 tr = k < T->total_tiles ? tile_rec(T, toff, k, st->overflow != 0) : make_int4(-1, 0, 0, 0);
+    raycast_item<TILE, COUNT>(T, rec, lists, out, st, item, tr, s_sel);
 }
 
 // ---------------------------------------------------------------------------
@@ -901,8 +909,9 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
 // Tile order of the persistent ray cast: longest lists first, by
 // power-of-two length bucket (counting sort on the histogram k_scan_apply
 // built; S->cursor cleared before the launch).
-__global__ __launch_bounds__(256) void k_sched_scatter(const uint32_t *__restrict__ toff, int n, Sched *__restrict__ S,
-                                                       int32_t *__restrict__ order) {
+__global__ __launch_bounds__(256) void k_sched_scatter(const ViewTable *__restrict__ T, const uint32_t *__restrict__ toff,
+                                                       int n, Sched *__restrict__ S, int4 *__restrict__ order,
+                                                       const DevStatus *__restrict__ st) {
     __shared__ uint32_t h[kBuckets], base[kBuckets], first[kBuckets];
     if (threadIdx.x == 0) {
         uint32_t sum = 0;
@@ -924,19 +933,30 @@ __global__ __launch_bounds__(256) void k_sched_scatter(const uint32_t *__restric
     if (threadIdx.x < kBuckets && h[threadIdx.x])
         base[threadIdx.x] = first[threadIdx.x] + atomicAdd(&S->cursor[threadIdx.x], h[threadIdx.x]);
     __syncthreads();
-    if (i < n) order[base[b] + rank] = i;
+    if (i < n) order[base[b] + rank] = tile_rec(T, toff, i, st->overflow != 0);
 }
 
 template <int TILE, bool COUNT>
 __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast_queue(
-    const ViewTable *__restrict__ T, const float4 *__restrict__ rec, const uint32_t *__restrict__ toff,
-    const uint32_t *__restrict__ lists, RayOut out, DevStatus *__restrict__ st, const int32_t *__restrict__ order,
-    int nitems) {
+    const ViewTable *__restrict__ T, const float4 *__restrict__ rec, const uint32_t *__restrict__ lists, RayOut out,
+    DevStatus *__restrict__ st, const int4 *__restrict__ order, int nitems) {
     __shared__ int32_t s_sel[4 * kSelCap];
     // block b takes items b, b + grid, b + 2 grid, ... of the longest-first
-    // order: the first round holds the longest lists, no queue atomics
-    for (int item = blockIdx.x; item < nitems; item += gridDim.x)
-        raycast_item<TILE, COUNT>(T, rec, toff, lists, out, st, item, order, s_sel);
+    // order (the first round holds the longest lists, no queue atomics); the
+    // next item's tile record is loaded while the current one is cast
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ntiles = T->total_tiles;
+    int item = blockIdx.x;
+    int k = item_tile<TILE>(item, wv);
+    int4 cur = item < nitems && k < ntiles ? order[k] : make_int4(-1, 0, 0, 0);
+    while (item < nitems) {
+        const int nxt = item + gridDim.x;
+        k = item_tile<TILE>(nxt, wv);
+        const int4 pre = nxt < nitems && k < ntiles ? order[k] : make_int4(-1, 0, 0, 0);
+        raycast_item<TILE, COUNT>(T, rec, lists, out, st, item, cur, s_sel);
+        item = nxt;
+        cur = pre;
+    }
 }
 
 // ---------------------------------------------------------------------------
