@@ -672,7 +672,7 @@ struct RecLayout {
 // bit its list entries must carry (-1: no filter).
 template <bool ROLL, bool COUNT>
 __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0, int q, const float *__restrict__ vrec,
-                                             int beg, int end, const uint32_t *__restrict__ lists,
+                                             int beg, int end, const uint32_t *__restrict__ lists, uint32_t ent0,
                                              int32_t *__restrict__ out_id, float *__restrict__ out_depth,
                                              unsigned long long *__restrict__ cnt, int32_t *s_sel) {
     using RL = RecLayout<ROLL>;
@@ -715,7 +715,7 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
     // term kq (+ 4)
     const int ga = (lane >> 2) & 3, aoff = 4 * kq + (lane & 3);
     int nbuf = 0;
-    uint32_t ent_next = beg + lane < end ? lists[beg + lane] : 0u;
+    uint32_t ent_next = ent0;   // lists[beg + lane], loaded by the caller
     for (int c = beg; c < end; c += 64) {
         const uint32_t ent = ent_next;
         const bool inl = c + lane < end;
@@ -847,11 +847,19 @@ __device__ __forceinline__ int item_tile(int item, int wv) {
     return TILE == 8 ? 4 * item + wv : (TILE == 16 ? item : item >> 2);
 }
 
-// Block item -> the wave's 8x8 cell of tile record tr.
+// The lane's entry of the first 64 of a tile record's list.
+__device__ __forceinline__ uint32_t first_entries(const uint32_t *__restrict__ lists, int4 tr) {
+    const int i = tr.z + (int)__lane_id();
+    return tr.x >= 0 && i < tr.w ? lists[i] : 0u;
+}
+
+// Block item -> the wave's 8x8 cell of tile record tr (ent0: the lane's
+// first list entry).
 template <int TILE, bool COUNT>
 __device__ __forceinline__ void raycast_item(const ViewTable *__restrict__ T, const float4 *__restrict__ rec,
                                              const uint32_t *__restrict__ lists, const RayOut &out,
-                                             DevStatus *__restrict__ st, int item, int4 tr, int32_t *s_sel_block) {
+                                             DevStatus *__restrict__ st, int item, int4 tr, uint32_t ent0,
+                                             int32_t *s_sel_block) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (tr.x < 0) return;
     const int gt = tr.x, v = tr.y;
@@ -873,9 +881,9 @@ __device__ __forceinline__ void raycast_item(const ViewTable *__restrict__ T, co
     unsigned long long *cnt = &st->cnt[blockIdx.x & (kCountSlots - 1)][0];
     int32_t *s_sel = s_sel_block + wv * kSelCap;
     if (vd.rolling)
-        raycast_cell<true, COUNT>(vd, cx0, cy0, q, vrec, tr.z, tr.w, lists, out.id[v], out.depth[v], cnt, s_sel);
+        raycast_cell<true, COUNT>(vd, cx0, cy0, q, vrec, tr.z, tr.w, lists, ent0, out.id[v], out.depth[v], cnt, s_sel);
     else
-        raycast_cell<false, COUNT>(vd, cx0, cy0, q, vrec, tr.z, tr.w, lists, out.id[v], out.depth[v], cnt, s_sel);
+        raycast_cell<false, COUNT>(vd, cx0, cy0, q, vrec, tr.z, tr.w, lists, ent0, out.id[v], out.depth[v], cnt, s_sel);
 }
 
 // Block b -> item: consecutive blocks go to the eight XCDs in turn, so XCD
@@ -896,7 +904,7 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
     const int item = xcd_item(blockIdx.x, gridDim.x);
     const int k = item_tile<TILE>(item, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
     const int4 tr = k < T->total_tiles ? tile_rec(T, toff, k, st->overflow != 0) : make_int4(-1, 0, 0, 0);
-    raycast_item<TILE, COUNT>(T, rec, lists, out, st, item, tr, s_sel);
+    raycast_item<TILE, COUNT>(T, rec, lists, out, st, item, tr, first_entries(lists, tr), s_sel);
 }
 
 // ---------------------------------------------------------------------------
@@ -942,20 +950,27 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast_queue(
     DevStatus *__restrict__ st, const int4 *__restrict__ order, int nitems) {
     __shared__ int32_t s_sel[4 * kSelCap];
     // block b takes items b, b + grid, b + 2 grid, ... of the longest-first
-    // order (the first round holds the longest lists, no queue atomics); the
-    // next item's tile record is loaded while the current one is cast
+    // order (the first round holds the longest lists, no queue atomics).
+    // While an item is cast, the tile record two items ahead and the first
+    // list entries of the next item are loaded.
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ntiles = T->total_tiles;
+    const int G = gridDim.x;
+    auto fetch = [&](int it) {
+        const int k = item_tile<TILE>(it, wv);
+        return it < nitems && k < ntiles ? order[k] : make_int4(-1, 0, 0, 0);
+    };
     int item = blockIdx.x;
-    int k = item_tile<TILE>(item, wv);
-    int4 cur = item < nitems && k < ntiles ? order[k] : make_int4(-1, 0, 0, 0);
+    int4 cur = fetch(item), nx1 = fetch(item + G);
+    uint32_t ecur = first_entries(lists, cur);
     while (item < nitems) {
-        const int nxt = item + gridDim.x;
-        k = item_tile<TILE>(nxt, wv);
-        const int4 pre = nxt < nitems && k < ntiles ? order[k] : make_int4(-1, 0, 0, 0);
-        raycast_item<TILE, COUNT>(T, rec, lists, out, st, item, cur, s_sel);
-        item = nxt;
-        cur = pre;
+        const int4 nx2 = fetch(item + 2 * G);
+        const uint32_t enx = first_entries(lists, nx1);
+        raycast_item<TILE, COUNT>(T, rec, lists, out, st, item, cur, ecur, s_sel);
+        item += G;
+        cur = nx1;
+        nx1 = nx2;
+        ecur = enx;
     }
 }
 
