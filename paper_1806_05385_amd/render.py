@@ -49,7 +49,7 @@ class Renderer:
     raised to what the device reported and the frame is run again."""
 
     def __init__(self, meshes, views, tile: int = 16, bin_capacity: int = 0, light=None, ambient: float = 0.1,
-                 flags: int = 0, device='cuda'):
+                 flags: int = B.PR_FLAG_PERSISTENT, device='cuda'):
         self.L = B.lib()
         self.device = torch.device(device)
         self.meshes = [m if isinstance(m, DeviceMesh) else DeviceMesh.from_numpy(m, device) for m in meshes]
@@ -257,7 +257,7 @@ class Batch:
             pass
 
 
-def render_scene(scene, tile: int = 16, shade: bool = True, flags: int = 0, device='cuda'):
+def render_scene(scene, tile: int = 16, shade: bool = True, flags: int = B.PR_FLAG_PERSISTENT, device='cuda'):
     """Render a scenegen.Scene; returns (renderer, outputs)."""
     r = Renderer(scene.meshes, scene.views, tile=tile, light=scene.light_dir, ambient=scene.ambient, flags=flags,
                  device=device)

@@ -26,8 +26,8 @@ def _render(scene, tile=16, **kw):
     return r, [{k: v.cpu().numpy() for k, v in o.items()} for o in out]
 
 
-def _full_parity(scene, tile=16, view=0):
-    r, out = _render(scene, tile)
+def _full_parity(scene, tile=16, view=0, **kw):
+    r, out = _render(scene, tile, **kw)
     v = scene.views[view]
     orc = oracle.Oracle(scene.meshes[v.mesh], v)
     o = orc.render()
@@ -41,9 +41,12 @@ def _full_parity(scene, tile=16, view=0):
 
 
 @pytest.mark.parametrize('tile', [8, 16, 32])
-def test_tiny_full_frame(tile):
-    """2,000-triangle soup, static camera, 256x256, foveated, rolling off."""
-    _full_parity(scenegen.make_tiny(), tile)
+@pytest.mark.parametrize('flags', [0, 2])
+def test_tiny_full_frame(tile, flags):
+    """2,000-triangle soup, static camera, 256x256, foveated, rolling off;
+    one block per tile item (flags 0) and the persistent longest-first
+    ray cast (flags 2)."""
+    _full_parity(scenegen.make_tiny(), tile, flags=flags)
 
 
 @pytest.mark.parametrize('alpha,roll,fovea,tile', [
@@ -54,6 +57,7 @@ def test_moving_soup_full_frame(alpha, roll, fovea, tile):
     image size (not a multiple of the tile)."""
     sc = scenegen.make_moving_soup(seed=31, n_tris=1500, width=203, height=171, alpha=alpha, roll=roll,
                                    yaw_deg_s=2000.0, obj_speed=20.0, fovea=fovea, side=(0.03, 0.5))
+    _full_parity(sc, tile, flags=0)
     _full_parity(sc, tile)
 
 
