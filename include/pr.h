@@ -127,9 +127,10 @@ typedef struct pr_light {
  *   views; each candidate of a triangle's tile rectangle takes one slot,
  *   and the tile lists hold the candidates that survive the tile test).
  * flags: PR_FLAG_COUNT makes pr_raycast count ray-triangle tests and hits
- * (sample test efficiency) into the status block; PR_FLAG_PERSISTENT makes
- * it order the tiles longest list first and run one resident grid that
- * pulls tiles from a device-wide queue (the batched form). */
+ * (sample test efficiency) into the status block: a test is one triangle at
+ * one pixel the ray cast evaluates; PR_FLAG_PERSISTENT makes it order the
+ * tiles longest list first and run one resident grid that walks that order
+ * with a fixed stride. */
 typedef struct pr_tuning {
     int32_t tile;
     int32_t bin_capacity;

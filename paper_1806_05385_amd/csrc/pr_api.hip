@@ -146,7 +146,7 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     L.tcount = off; off = up(off + ((size_t)tiles + 1) * 4);
     L.toff = off; off = up(off + ((size_t)tiles + 1) * 4);
     L.part = off; off = up(off + (size_t)L.nparts * 4);
-    L.pairs = off; off = up(off + (size_t)L.cap * sizeof(Pair));
+    L.pairs = off; off = up(off + (size_t)L.cap * 12);   // Pairs: tile, slot, entry arrays
     L.lists = off; off = up(off + (size_t)L.cap * 4);
     L.gacc = off; off = up(off + (size_t)gacc * 4);
     L.pacc = off; off = up(off + (size_t)PR_MAX_VIEWS * kPoseAcc * 8);
@@ -166,6 +166,12 @@ template <typename T>
 T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
 
 int launched() { return hipGetLastError() == hipSuccess ? PR_OK : PR_ERR_HIP; }
+
+// The candidate pair arrays (cap words each) in the workspace.
+Pairs pairs_at(const Layout &L, void *ws) {
+    int32_t *base = at<int32_t>(ws, L.pairs);
+    return Pairs{base, reinterpret_cast<uint32_t *>(base + L.cap), reinterpret_cast<uint32_t *>(base + 2 * (size_t)L.cap)};
+}
 
 void fill_u32(void *p, uint32_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
@@ -273,14 +279,14 @@ int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     if (L.total_tri_blocks > 0)
         hipLaunchKernelGGL(k_bin, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<TriBound>(ws, L.tb),
                            at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<int32_t>(ws, L.boff),
-                           at<uint32_t>(ws, L.bpart), at<Pair>(ws, L.pairs), L.cap);
+                           at<uint32_t>(ws, L.bpart), pairs_at(L, ws), L.cap);
     int n = L.total_tiles + 1;
     hipLaunchKernelGGL(k_scan_reduce, dim3(L.nparts), dim3(256), 0, s, at<uint32_t>(ws, L.tcount), n,
                        at<uint32_t>(ws, L.part));
     hipLaunchKernelGGL(k_scan_apply, dim3(L.nparts), dim3(256), 0, s, at<uint32_t>(ws, L.tcount), n, L.total_tiles,
                        at<uint32_t>(ws, L.part), at<uint32_t>(ws, L.toff), at<Sched>(ws, L.sched));
     int sb = (int)std::min<int64_t>(std::max<int64_t>((L.cap + 255) / 256, 1), 2048);
-    hipLaunchKernelGGL(k_scatter, dim3(sb), dim3(256), 0, s, at<Pair>(ws, L.pairs), at<uint32_t>(ws, L.toff),
+    hipLaunchKernelGGL(k_scatter, dim3(sb), dim3(256), 0, s, pairs_at(L, ws), at<uint32_t>(ws, L.toff),
                        at<int32_t>(ws, L.lists), L.cap, L.total_tiles, st);
     return launched();
 }
@@ -534,7 +540,7 @@ int batch_frame(pr_batch *b, hipStream_t s) {
 
 int batch_alloc(pr_batch *b) {
     if (b->ws) {
-        hipFree(b->ws);
+        (void)hipFree(b->ws);
         b->ws = nullptr;
     }
     size_t bytes = 0;
@@ -570,33 +576,35 @@ int batch_fit(pr_batch *b) {
 double batch_time(pr_batch *b, int reps) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return 1e30;
+    // a trial whose launches or timing fail counts as infinitely slow
     double best = 1e30;
     for (int r = 0; r < reps; ++r) {
-        hipEventRecord(e0, b->cs);
-        batch_frame(b, b->cs);
-        hipEventRecord(e1, b->cs);
-        hipEventSynchronize(e1);
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (hipEventRecord(e0, b->cs) != hipSuccess || batch_frame(b, b->cs) != PR_OK ||
+            hipEventRecord(e1, b->cs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            best = 1e30;
+            break;
+        }
         best = std::min(best, (double)ms);
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return best;
 }
 
 std::string tune_key(const pr_batch *b) {
     int dev = 0;
     hipDeviceProp_t prop;
-    hipGetDevice(&dev);
-    hipGetDeviceProperties(&prop, dev);
+    const char *arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
     double px = 0, tris = 0;
     for (const pr_view &v : b->views) {
         px += (double)v.width * v.height;
         tris += b->meshes[v.mesh].nt;
     }
     char key[256];
-    snprintf(key, sizeof(key), "%s nv=%d px=2^%d tris=2^%d", prop.gcnArchName, (int)b->views.size(),
+    snprintf(key, sizeof(key), "%s nv=%d px=2^%d tris=2^%d", arch, (int)b->views.size(),
              (int)lround(log2(std::max(px, 1.0))), (int)lround(log2(std::max(tris, 1.0))));
     for (char *c = key; *c; ++c)
         if (*c == '\t' || *c == '\n') *c = ' ';
@@ -747,11 +755,12 @@ int pr_batch_status(const pr_batch *b, pr_status *out, void *stream) {
 
 int pr_batch_destroy(pr_batch *b) {
     if (!b) return PR_OK;
-    if (b->cs) hipStreamSynchronize(b->cs);
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    if (b->ws) hipFree(b->ws);
-    if (b->cs) hipStreamDestroy(b->cs);
+    // teardown: errors of these calls leave nothing further to release
+    if (b->cs) (void)hipStreamSynchronize(b->cs);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ws) (void)hipFree(b->ws);
+    if (b->cs) (void)hipStreamDestroy(b->cs);
     delete b;
     return PR_OK;
 }

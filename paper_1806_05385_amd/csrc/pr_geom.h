@@ -214,9 +214,29 @@ PRG int quad_roots01(double a, double b, double c, double r[2]) {
     double q = -0.5 * (b + (b >= 0 ? sqrt(disc) : -sqrt(disc)));
     double t1 = q / a;
     double t2 = q != 0.0 ? c / q : t1;
-    if (t1 > 0.0 && t1 < 1.0) r[n++] = t1;
-    if (t2 > 0.0 && t2 < 1.0 && t2 != t1) r[n++] = t2;
-    return n;
+    const bool k1 = t1 > 0.0 && t1 < 1.0, k2 = t2 > 0.0 && t2 < 1.0 && t2 != t1;
+    if (k1) r[0] = t1;
+    if (k2) {
+        if (k1) r[1] = t2;
+        else r[0] = t2;
+    }
+    return (int)k1 + (int)k2;
+}
+
+// Compare-exchange and an 8-input sorting network (Batcher's odd-even
+// merge sort, 19 comparators): fixed indices keep the array in registers.
+PRG void cswap(double &a, double &b) {
+    const double lo = dmin(a, b), hi = dmax(a, b);
+    a = lo;
+    b = hi;
+}
+PRG void sort8(double v[8]) {
+    cswap(v[0], v[1]); cswap(v[2], v[3]); cswap(v[4], v[5]); cswap(v[6], v[7]);
+    cswap(v[0], v[2]); cswap(v[1], v[3]); cswap(v[4], v[6]); cswap(v[5], v[7]);
+    cswap(v[1], v[2]); cswap(v[5], v[6]);
+    cswap(v[0], v[4]); cswap(v[1], v[5]); cswap(v[2], v[6]); cswap(v[3], v[7]);
+    cswap(v[2], v[4]); cswap(v[3], v[5]);
+    cswap(v[1], v[2]); cswap(v[3], v[4]); cswap(v[5], v[6]);
 }
 
 enum { kCulled = 0, kWindow = 1, kClipped = 2 };
@@ -256,10 +276,10 @@ PRG int time_window(const Geom &g, const double Ps[3][3], const double Pe[3][3],
         return kWindow;
     }
     double hc[3][3];  // h_k = hc[k][0] + hc[k][1] t + hc[k][2] t^2
-    double bp[8];
-    int nb = 0;
-    bp[nb++] = 0.0;
-    bp[nb++] = 1.0;
+    // breakpoints: 0, 1 and each quadratic's roots in (0, 1), sorted; an
+    // unused slot holds 2 (past the frame), sorts last and is skipped
+    double bp[8] = {0.0, 1.0, 2.0, 2.0, 2.0, 2.0, 2.0, 2.0};
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
         double n0 = scan_numer(g, Ps[k]);
         double n1 = scan_numer(g, Pe[k]) - n0;
@@ -267,21 +287,18 @@ PRG int time_window(const Geom &g, const double Ps[3][3], const double Pe[3][3],
         hc[k][0] = n0;
         hc[k][1] = n1 - z0;
         hc[k][2] = -z1;
-        double r[2];
-        int nr = quad_roots01(hc[k][2], hc[k][1], hc[k][0], r);
-        for (int i = 0; i < nr; ++i) bp[nb++] = r[i];
+        double r[2] = {2.0, 2.0};
+        quad_roots01(hc[k][2], hc[k][1], hc[k][0], r);
+        bp[2 + 2 * k] = r[0];
+        bp[3 + 2 * k] = r[1];
     }
-    // sort breakpoints (at most 8)
-    for (int i = 1; i < nb; ++i) {
-        double v = bp[i];
-        int j = i - 1;
-        while (j >= 0 && bp[j] > v) { bp[j + 1] = bp[j]; --j; }
-        bp[j + 1] = v;
-    }
+    sort8(bp);
     double lo = 2.0, hi = -1.0;
-    for (int i = 0; i < nb; ++i) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
         // the breakpoint itself
         double t = bp[i];
+        if (t > 1.0) continue;
         double hmin = 1e300, hmax = -1e300;
         for (int k = 0; k < 3; ++k) {
             double h = hc[k][0] + t * (hc[k][1] + t * hc[k][2]);
@@ -294,7 +311,7 @@ PRG int time_window(const Geom &g, const double Ps[3][3], const double Pe[3][3],
         else rel = hmin <= 0.0 && hmax >= 0.0;
         if (rel) { lo = dmin(lo, t); hi = dmax(hi, t); }
         // the gap to the next breakpoint
-        if (i + 1 < nb && bp[i + 1] > t) {
+        if (i + 1 < 8 && bp[i + 1] <= 1.0 && bp[i + 1] > t) {
             double m = 0.5 * (t + bp[i + 1]);
             hmin = 1e300; hmax = -1e300;
             for (int k = 0; k < 3; ++k) {
@@ -334,13 +351,20 @@ PRG void display_box(const Geom &g, const double Ps[3][3], const double Pe[3][3]
         box[0] = dmin(box[0], x); box[1] = dmax(box[1], x);
         box[2] = dmin(box[2], y); box[3] = dmax(box[3], y);
     };
+    // fixed trip counts (guarded by n) keep pts in registers
     if (kind == kWindow) {
-        for (int i = 0; i < n; ++i) add(pts[i]);
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            if (i < n) add(pts[i]);
     } else {
-        for (int i = 0; i < n; ++i)
-            if (pts[i][2] >= g.znear) add(pts[i]);
-        for (int i = 0; i < n; ++i)
-            for (int j = i + 1; j < n; ++j) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            if (i < n && pts[i][2] >= g.znear) add(pts[i]);
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = i + 1; j < 6; ++j) {
+                if (j >= n) continue;
                 bool ii = pts[i][2] >= g.znear, jj = pts[j][2] >= g.znear;
                 if (ii == jj) continue;
                 double s = (g.znear - pts[i][2]) / (pts[j][2] - pts[i][2]);

@@ -368,10 +368,12 @@ __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, 
 // ---------------------------------------------------------------------------
 // bin
 // ---------------------------------------------------------------------------
-struct Pair {
-    int32_t tile;    // global tile, -1: rejected candidate
-    int32_t slot;    // slot in the tile's list
-    int32_t entry;   // list entry (triangle index | quadrant mask)
+// Candidate pairs, one slot per candidate, as three arrays of cap words
+// (separate word stores: no register copies into store tuples).
+struct Pairs {
+    int32_t *tile;     // global tile, -1: rejected candidate
+    uint32_t *slot;    // slot in the tile's list
+    uint32_t *entry;   // list entry (triangle index | quadrant mask)
 };
 
 // Each round gives every thread kBinPer consecutive candidates (mostly of
@@ -383,11 +385,41 @@ struct Pair {
 // carries its quadrant mask above the triangle index.
 constexpr int kBinPer = 8;
 
-// (triangle q, local candidate index) -> global tile of the candidate.
-__device__ __forceinline__ int bin_tile(const ViewDev &vd, const int (*s_rect)[5], int q, int local) {
+// A thread's walk over its consecutive candidates: triangle q of the block,
+// candidate `local` of its tile rectangle, the rectangle column lx and the
+// global tile gt.  Only the start divides; each step moves one tile right
+// or to the next row or triangle.
+struct BinCursor {
+    int q, local, lx, gt;
+};
+
+__device__ __forceinline__ int bin_count(const int *s_pref, int q) { return s_pref[q + 1] - s_pref[q]; }
+
+__device__ __forceinline__ BinCursor bin_start(const ViewDev &vd, const int (*s_rect)[5], const int *s_pref, int q,
+                                               int local) {
+    while (local >= bin_count(s_pref, q)) { ++q; local = 0; }
     const int rw = s_rect[q][2] - s_rect[q][0] + 1;
-    const int tx = s_rect[q][0] + local % rw, ty = s_rect[q][1] + local / rw;
-    return vd.tile_base + ty * vd.tiles_x + tx;
+    const int lx = local % rw, ly = local / rw;
+    return BinCursor{q, local, lx, vd.tile_base + (s_rect[q][1] + ly) * vd.tiles_x + s_rect[q][0] + lx};
+}
+
+// Next candidate (the caller knows one follows).
+__device__ __forceinline__ void bin_step(BinCursor &c, const ViewDev &vd, const int (*s_rect)[5], const int *s_pref) {
+    ++c.local;
+    if (c.local >= bin_count(s_pref, c.q)) {
+        do { ++c.q; } while (bin_count(s_pref, c.q) == 0);
+        c.local = 0;
+        c.lx = 0;
+        c.gt = vd.tile_base + s_rect[c.q][1] * vd.tiles_x + s_rect[c.q][0];
+        return;
+    }
+    const int rw = s_rect[c.q][2] - s_rect[c.q][0] + 1;
+    ++c.lx;
+    ++c.gt;
+    if (c.lx == rw) {
+        c.lx = 0;
+        c.gt += vd.tiles_x - rw;
+    }
 }
 
 // One block per kBinTris triangles.  Each triangle's test record is built
@@ -399,7 +431,7 @@ constexpr int kBinTris = 256;
 __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, const TriBound *__restrict__ tb,
                                              const TileInfo *__restrict__ ti, uint32_t *__restrict__ tcount,
                                              const int32_t *__restrict__ boff, const uint32_t *__restrict__ bpart,
-                                             Pair *__restrict__ pairs, int64_t cap) {
+                                             Pairs pairs, int64_t cap) {
     // odd row strides (33 and 5 words) keep lanes reading different
     // triangles on different LDS banks
     __shared__ uint32_t s_sat[kBinTris][33];
@@ -426,7 +458,9 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
                     prg::load_tri(vd.mesh.v0, vd.mesh.v1, vd.mesh.tri, vd.mesh.nv, f, g, Ps, Pe, idx);
                     prg::SatRec R;
                     prg::sat_build(g, Ps, Pe, b.kind, b.w, R);
-                    const uint32_t *rw = reinterpret_cast<const uint32_t *>(&R);
+                    uint32_t rw[32];   // the record's words (memcpy: no type punning)
+                    static_assert(sizeof(R) == sizeof(rw), "SatRec is 32 words");
+                    __builtin_memcpy(rw, &R, sizeof(rw));
 #pragma unroll
                     for (int i = 0; i < 32; ++i) s_sat[j][i] = rw[i];
                     for (int k = 0; k < 4; ++k) s_rect[j][k] = b.rect[k];
@@ -461,31 +495,33 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
                 q0 = lo;
                 l0 = my0 - s_pref[q0];
                 // the next candidate's tile info is loaded while the current
-                // one is tested
-                int q = q0, local = l0;
-                while (local >= s_pref[q + 1] - s_pref[q]) { ++q; local = 0; }
-                int gt = bin_tile(vd, s_rect, q, local);
+                // one is tested; the triangle's test record is read from LDS
+                // when the triangle changes
+                BinCursor cur = bin_start(vd, s_rect, s_pref, q0, l0);
                 float4 nt[6];
 #pragma unroll
-                for (int i = 0; i < 6; ++i) nt[i] = reinterpret_cast<const float4 *>(&ti[gt])[i];
+                for (int i = 0; i < 6; ++i) nt[i] = reinterpret_cast<const float4 *>(&ti[cur.gt])[i];
+                uint32_t rw[32];   // words of the current triangle's test record
+                int rq = -1;
                 for (int k = 0; k < myn; ++k) {
                     float4 tt[6];
 #pragma unroll
                     for (int i = 0; i < 6; ++i) tt[i] = nt[i];
-                    const int cq = q;
+                    const int cq = cur.q;
                     if (k + 1 < myn) {
-                        ++local;
-                        while (local >= s_pref[q + 1] - s_pref[q]) { ++q; local = 0; }
-                        gt = bin_tile(vd, s_rect, q, local);
+                        bin_step(cur, vd, s_rect, s_pref);
 #pragma unroll
-                        for (int i = 0; i < 6; ++i) nt[i] = reinterpret_cast<const float4 *>(&ti[gt])[i];
+                        for (int i = 0; i < 6; ++i) nt[i] = reinterpret_cast<const float4 *>(&ti[cur.gt])[i];
                     }
+                    if (cq != rq) {
+#pragma unroll
+                        for (int i = 0; i < 32; ++i) rw[i] = s_sat[cq][i];
+                        rq = cq;
+                    }
+                    prg::SatRec R;
+                    __builtin_memcpy(&R, rw, sizeof(R));
                     // TileInfo words: box 0..3, tw 4..5, qvalid 6, pad 7, qb 8..23
                     const float tbx[4] = {tt[0].x, tt[0].y, tt[0].z, tt[0].w}, tw[2] = {tt[1].x, tt[1].y};
-                    prg::SatRec R;
-                    uint32_t *rw = reinterpret_cast<uint32_t *>(&R);
-#pragma unroll
-                    for (int i = 0; i < 32; ++i) rw[i] = s_sat[cq][i];
                     int mask;
                     if (split) {
                         const float qb[4][4] = {{tt[2].x, tt[2].y, tt[2].z, tt[2].w}, {tt[3].x, tt[3].y, tt[3].z, tt[3].w},
@@ -499,19 +535,46 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
             }
             // every candidate owns a pair slot (boff: the block's first); a
             // survivor takes its place in its tile's list with an atomic on
-            // the tile's count (the thread's atomics are issued back to back)
+            // the tile's count.  All of the thread's atomics are issued
+            // before any result is used (unrolled, fixed register slots), so
+            // their latencies overlap.
             if (myn > 0) {
                 const int64_t base = s_off + my0;
-                int q = q0, local = l0;
-                for (int k = 0; k < myn; ++k) {
-                    while (local >= s_pref[q + 1] - s_pref[q]) { ++q; local = 0; }
-                    const uint32_t m = (masks >> (4 * k)) & 0xFu;
-                    const int gt = bin_tile(vd, s_rect, q, local);
-                    const uint32_t slot = m ? atomicAdd(&tcount[gt], 1u) : 0u;
-                    if (base + k < cap)
-                        pairs[base + k] = Pair{m ? gt : -1, (int32_t)slot, (int32_t)((uint32_t)(f0 + q) | (m << kListTriBits))};
-                    ++local;
+                BinCursor cur = bin_start(vd, s_rect, s_pref, q0, l0);
+                int ptile[kBinPer];
+                uint32_t pslot[kBinPer], pent[kBinPer];
+#pragma unroll
+                for (int k = 0; k < kBinPer; ++k) {
+                    ptile[k] = -1;
+                    pslot[k] = 0u;
+                    pent[k] = 0u;
+                    if (k < myn) {
+                        if (k > 0) bin_step(cur, vd, s_rect, s_pref);
+                        const uint32_t m = (masks >> (4 * k)) & 0xFu;
+                        if (m) {
+                            ptile[k] = cur.gt;
+                            pslot[k] = atomicAdd(&tcount[cur.gt], 1u);
+                        }
+                        pent[k] = (uint32_t)(f0 + cur.q) | (m << kListTriBits);
+                    }
                 }
+                // one wait for all returned slots, then the stores (a store
+                // interleaved with the waits would be waited for as well)
+                asm volatile("" ::"v"(pslot[0]), "v"(pslot[1]), "v"(pslot[2]), "v"(pslot[3]), "v"(pslot[4]),
+                             "v"(pslot[5]), "v"(pslot[6]), "v"(pslot[7]));
+                static_assert(kBinPer == 8, "one operand per slot");
+                // slots past the capacity are dropped (the overflow is
+                // reported); one set of addresses with immediate offsets
+                const int nw = (int)min<int64_t>((int64_t)myn, cap - base);
+                int32_t *pt = pairs.tile + base;
+                uint32_t *ps = pairs.slot + base, *pe = pairs.entry + base;
+#pragma unroll
+                for (int k = 0; k < kBinPer; ++k)
+                    if (k < nw) {
+                        pt[k] = ptile[k];
+                        ps[k] = pslot[k];
+                        pe[k] = pent[k];
+                    }
             }
         }
     }
@@ -574,7 +637,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
 // ---------------------------------------------------------------------------
 // scatter pairs into tile lists (slot order within a list is arbitrary)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_scatter(const Pair *__restrict__ pairs, const uint32_t *__restrict__ toff,
+__global__ __launch_bounds__(256) void k_scatter(Pairs pairs, const uint32_t *__restrict__ toff,
                                                  int32_t *__restrict__ lists, int64_t cap, int ntiles,
                                                  DevStatus *__restrict__ st) {
     const int64_t n = (int64_t)st->pairs_required;
@@ -584,8 +647,8 @@ __global__ __launch_bounds__(256) void k_scatter(const Pair *__restrict__ pairs,
     }
     if (n > cap) return;   // overflow: the ray cast writes misses
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const Pair p = pairs[i];
-        if (p.tile >= 0) lists[toff[p.tile] + p.slot] = p.entry;
+        const int32_t tile = pairs.tile[i];
+        if (tile >= 0) lists[toff[tile] + pairs.slot[i]] = (int32_t)pairs.entry[i];
     }
 }
 
@@ -702,7 +765,10 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
             tb[b] = tj;
         }
     }
-    unsigned long long best[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+    // packed (depth bits, id) keys; kFar (depth +inf) is above every finite
+    // positive depth's key, so a key below it is a finite hit
+    constexpr unsigned long long kFar = 0x7f80000000000000ull;
+    unsigned long long best[4] = {kFar, kFar, kFar, kFar};
     const float znear = pc.znear;
     unsigned hits = 0;
     unsigned long long tests = 0;
@@ -723,18 +789,17 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
         const bool sel = inl && (q < 0 || ((ent >> (kListTriBits + q)) & 1u));
         const unsigned long long m = __ballot(sel);
         const int pos = nbuf + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        if (sel) s_sel[pos] = (int32_t)(ent & kListTriMask);
+        // the record's float4 offset (below 2^28: a view's records are
+        // smaller than 4 GiB)
+        if (sel) s_sel[pos] = (int32_t)((ent & kListTriMask) * (uint32_t)(RL::W / 4));
         nbuf += __popcll(m);
         const bool last = c + 64 >= end;
         const int ngr = last ? (nbuf + 3) >> 2 : nbuf >> 2;
-        // software pipeline: the next group's loads are issued before the
-        // current group's products
         // Two register sets alternate (software pipeline without copies):
         // the next group's loads are issued before the current group's
         // products.  Lanes past the selection load the first selected
-        // triangle's record (always in bounds); their rows are ignored
-        // through `valid`.  Record offsets are 32-bit byte offsets from the
-        // view's record base (a view's records are smaller than 4 GiB).
+        // triangle's record (always in bounds).  Record offsets are 32-bit
+        // byte offsets from the view's record base.
         struct Group {
             float a0, a1, d0, d1, d2, d3;
             v4f c;
@@ -744,8 +809,8 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
         const char *vbase = reinterpret_cast<const char *>(vrec);
         auto load_group = [&](Group &G, int g) {
             const int ia = 4 * g + ga, ic = 4 * g + kq;
-            const uint32_t oa = (uint32_t)s_sel[ia < nbuf ? ia : 0] * (uint32_t)(RL::W * 4);
-            const uint32_t oc = (uint32_t)s_sel[ic < nbuf ? ic : 0] * (uint32_t)(RL::W * 4);
+            const uint32_t oa = (uint32_t)s_sel[ia < nbuf ? ia : 0] << 4;
+            const uint32_t oc = (uint32_t)s_sel[ic < nbuf ? ic : 0] << 4;
             G.a0 = *reinterpret_cast<const float *>(vbase + oa + 4 * aoff);
             G.a1 = ROLL ? *reinterpret_cast<const float *>(vbase + oa + 4 * (16 + aoff)) : 0.0f;
             G.valid = ic < nbuf;
@@ -774,14 +839,16 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
             for (int b = 0; b < 4; ++b) {
                 const float lo = fminf(fminf(acc[b][0], acc[b][1]), acc[b][2]);
                 const float hi = fmaxf(fmaxf(acc[b][0], acc[b][1]), acc[b][2]);
-                if (G.valid & ((lo >= 0.0f) | (hi <= 0.0f))) {   // skipped when no lane passes
+                // rows past the selection repeat the first selected triangle
+                // (same keys), so only the counts need `valid`
+                if ((!COUNT | G.valid) & ((lo >= 0.0f) | (hi <= 0.0f))) {   // skipped when no lane passes
                     const float t = tb[b];
                     const float D = ROLL ? fmaf(t, fmaf(t, fmaf(t, G.d3, G.d2), G.d1), G.d0) : G.d0;
                     const float z = D * __builtin_amdgcn_rcpf(acc[b][3]);
-                    const bool hit = (z >= znear) & (z <= 3.0e38f);
+                    const bool hit = z >= znear;   // (and key < kFar: finite)
                     const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | G.id;
-                    best[b] = hit & (key < best[b]) ? key : best[b];
-                    if (COUNT) hits += hit;
+                    best[b] = (hit & (key < best[b])) ? key : best[b];
+                    if (COUNT) hits += hit & (key < kFar) & G.valid;
                 }
             }
         };
@@ -818,7 +885,7 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
     const int px = cx0 + (lane & 7), py = cy0 + (lane >> 3);
     if (px < pc.W && py < pc.H) {
         const int64_t p = (int64_t)py * pc.W + px;
-        const bool miss = mine == ~0ull;
+        const bool miss = mine == kFar;
         out_id[p] = miss ? -1 : (int32_t)(uint32_t)(mine & 0xffffffffu);
         out_depth[p] = miss ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(mine >> 32));
     }
