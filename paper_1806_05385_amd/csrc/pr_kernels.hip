@@ -376,14 +376,19 @@ struct Pairs {
     uint32_t *entry;   // list entry (triangle index | quadrant mask)
 };
 
-// Each round gives every thread kBinPer consecutive candidates (mostly of
-// one or two triangles, found with one binary search over the block's
-// candidate prefix).  A thread keeps its candidates' quadrant masks in a
-// register (4 bits each), the block reserves space for all survivors of the
-// round with one global atomic, and each survivor takes its slot in its
-// tile's list with an atomic on the tile's count.  A survivor's list entry
-// carries its quadrant mask above the triangle index.
+// Each round gives every thread up to kBinPer consecutive candidates
+// (mostly of one or two triangles, found with one binary search over the
+// block's candidate prefix).  A thread keeps its candidates' quadrant masks
+// in a register (4 bits each); the round's survivors are counted per tile in
+// LDS and reserve their places in the tiles' lists with one global atomic
+// per tile.  A survivor's list entry carries its quadrant mask above the
+// triangle index.
 constexpr int kBinPer = 8;
+// LDS table of a round's survivors per tile: 2^kBinHashBits entries,
+// kBinProbe linear probes.
+constexpr int kBinHashBits = 10;
+constexpr int kBinHash = 1 << kBinHashBits;
+constexpr int kBinProbe = 8;
 
 // A thread's walk over its consecutive candidates: triangle q of the block,
 // candidate `local` of its tile rectangle, the rectangle column lx and the
@@ -438,7 +443,14 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
     __shared__ int s_rect[kBinTris][5];
     __shared__ int s_pref[kBinTris + 1];
     __shared__ int s_tmp[72];
+    // survivors per tile of the current round (open addressing on the tile)
+    __shared__ int32_t s_hkey[kBinHash];
+    __shared__ uint32_t s_hcnt[kBinHash], s_hbase[kBinHash];
     const int j = threadIdx.x;
+    for (int e = j; e < kBinHash; e += 256) {
+        s_hkey[e] = -1;
+        s_hcnt[e] = 0u;
+    }
     {
         const int v = find_view(T->tri_block0, T->nv, blockIdx.x);
         const ViewDev &vd = T->v[v];
@@ -533,38 +545,75 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
                     masks |= (uint32_t)mask << (4 * k);
                 }
             }
-            // every candidate owns a pair slot (boff: the block's first); a
-            // survivor takes its place in its tile's list with an atomic on
-            // the tile's count.  All of the thread's atomics are issued
-            // before any result is used (unrolled, fixed register slots), so
-            // their latencies overlap.
-            if (myn > 0) {
-                const int64_t base = s_off + my0;
-                BinCursor cur = bin_start(vd, s_rect, s_pref, q0, l0);
-                int ptile[kBinPer];
-                uint32_t pslot[kBinPer], pent[kBinPer];
+            // Every candidate owns a pair slot (boff: the block's first).  A
+            // survivor's place in its tile's list: the round's survivors are
+            // counted per tile in LDS (LDS atomics give each its rank), one
+            // global atomic per tile and round reserves the tile's places
+            // (a survivor that finds no table entry takes its place with its
+            // own global atomic).
+            int ptile[kBinPer], hslot[kBinPer];
+            uint32_t pslot[kBinPer], pent[kBinPer];
+            {
+                BinCursor cur{0, 0, 0, 0};
+                if (myn > 0) cur = bin_start(vd, s_rect, s_pref, q0, l0);
 #pragma unroll
                 for (int k = 0; k < kBinPer; ++k) {
                     ptile[k] = -1;
+                    hslot[k] = -1;
                     pslot[k] = 0u;
                     pent[k] = 0u;
                     if (k < myn) {
                         if (k > 0) bin_step(cur, vd, s_rect, s_pref);
                         const uint32_t m = (masks >> (4 * k)) & 0xFu;
                         if (m) {
-                            ptile[k] = cur.gt;
-                            pslot[k] = atomicAdd(&tcount[cur.gt], 1u);
+                            const int gt = cur.gt;
+                            ptile[k] = gt;
+                            int h = (int)(((uint32_t)gt * 2654435761u) >> (32 - kBinHashBits));
+                            for (int probe = 0; probe < kBinProbe; ++probe) {
+                                const int old = atomicCAS(&s_hkey[h], -1, gt);
+                                if (old == -1 || old == gt) {
+                                    hslot[k] = h;
+                                    break;
+                                }
+                                h = (h + 1) & (kBinHash - 1);
+                            }
+                            pslot[k] = hslot[k] >= 0 ? atomicAdd(&s_hcnt[hslot[k]], 1u) : atomicAdd(&tcount[gt], 1u);
                         }
                         pent[k] = (uint32_t)(f0 + cur.q) | (m << kListTriBits);
                     }
                 }
-                // one wait for all returned slots, then the stores (a store
-                // interleaved with the waits would be waited for as well)
-                asm volatile("" ::"v"(pslot[0]), "v"(pslot[1]), "v"(pslot[2]), "v"(pslot[3]), "v"(pslot[4]),
-                             "v"(pslot[5]), "v"(pslot[6]), "v"(pslot[7]));
-                static_assert(kBinPer == 8, "one operand per slot");
+            }
+            __syncthreads();
+            {
+                // one global atomic per used entry (issued together), then
+                // the entry is cleared for the next round
+                constexpr int kPerThread = kBinHash / 256;
+                uint32_t eb[kPerThread];
+#pragma unroll
+                for (int i = 0; i < kPerThread; ++i) {
+                    const int e = j + 256 * i;
+                    const int key = s_hkey[e];
+                    eb[i] = 0u;
+                    if (key >= 0) eb[i] = atomicAdd(&tcount[key], s_hcnt[e]);
+                }
+#pragma unroll
+                for (int i = 0; i < kPerThread; ++i) {
+                    const int e = j + 256 * i;
+                    if (s_hkey[e] >= 0) {
+                        s_hbase[e] = eb[i];
+                        s_hkey[e] = -1;
+                        s_hcnt[e] = 0u;
+                    }
+                }
+            }
+            __syncthreads();
+            if (myn > 0) {
+#pragma unroll
+                for (int k = 0; k < kBinPer; ++k)
+                    if (hslot[k] >= 0) pslot[k] += s_hbase[hslot[k]];
                 // slots past the capacity are dropped (the overflow is
                 // reported); one set of addresses with immediate offsets
+                const int64_t base = s_off + my0;
                 const int nw = (int)min<int64_t>((int64_t)myn, cap - base);
                 int32_t *pt = pairs.tile + base;
                 uint32_t *ps = pairs.slot + base, *pe = pairs.entry + base;
