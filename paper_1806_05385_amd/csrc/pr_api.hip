@@ -214,7 +214,6 @@ void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, D
     }
     Sched *S = at<Sched>(ws, L.sched);
     const int nb = (L.total_tiles + 255) / 256;
-    fill_u32(S->cursor, 0u, kBuckets, s);
     hipLaunchKernelGGL(k_sched_scatter, dim3(nb), dim3(256), 0, s, T, at<uint32_t>(ws, L.toff), L.total_tiles, S,
                        at<int4>(ws, L.order), st);
     static int resident = 0;
@@ -222,7 +221,7 @@ void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, D
     const int nitems = ray_items<TILE>(L.total_tiles);
     const int grid = std::max(1, std::min(nitems, resident));
     hipLaunchKernelGGL((k_raycast_queue<TILE, COUNT>), dim3(grid), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
-                       at<uint32_t>(ws, L.lists), out, st, at<int4>(ws, L.order), nitems);
+                       at<uint32_t>(ws, L.lists), out, st, at<int4>(ws, L.order), nitems, S);
 }
 
 template <int TILE>

@@ -303,7 +303,10 @@ __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, 
     const bool valid = gt < T->total_tiles;
     // clear the counters the binning pass accumulates into
     if (q == 0 && gt <= T->total_tiles) tcount[gt] = 0u;
-    if (gid < kBuckets) S->count[gid] = 0u;
+    if (gid < kBuckets) {
+        S->count[gid] = 0u;
+        S->cursor[gid] = 0u;
+    }
     if (blockIdx.x < (T->total_tri_blocks + 255) / 256) {
         // the binning blocks' candidate slots: local exclusive scan of 256
         // block totals here; k_bin adds the totals of the chunks before
@@ -1032,7 +1035,8 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
 // the order with a static stride, so the longest lists start first.
 // Tile order of the persistent ray cast: longest lists first, by
 // power-of-two length bucket (counting sort on the histogram k_scan_apply
-// built; S->cursor cleared before the launch).
+// built; S->cursor is zero on entry: cleared by k_tiles and again by each
+// k_raycast_queue).
 __global__ __launch_bounds__(256) void k_sched_scatter(const ViewTable *__restrict__ T, const uint32_t *__restrict__ toff,
                                                        int n, Sched *__restrict__ S, int4 *__restrict__ order,
                                                        const DevStatus *__restrict__ st) {
@@ -1063,8 +1067,11 @@ __global__ __launch_bounds__(256) void k_sched_scatter(const ViewTable *__restri
 template <int TILE, bool COUNT>
 __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast_queue(
     const ViewTable *__restrict__ T, const float4 *__restrict__ rec, const uint32_t *__restrict__ lists, RayOut out,
-    DevStatus *__restrict__ st, const int4 *__restrict__ order, int nitems) {
+    DevStatus *__restrict__ st, const int4 *__restrict__ order, int nitems, Sched *__restrict__ S) {
     __shared__ int32_t s_sel[4 * kSelCap];
+    // k_sched_scatter has finished with the bucket cursors: clear them for
+    // the next ray cast over the same lists (k_tiles clears them per frame)
+    if (blockIdx.x == 0 && threadIdx.x < kBuckets) S->cursor[threadIdx.x] = 0u;
     // block b takes items b, b + grid, b + 2 grid, ... of the longest-first
     // order (the first round holds the longest lists, no queue atomics).
     // While an item is cast, the tile record two items ahead and the first
