@@ -120,9 +120,8 @@ def main():
         r.bound()
         r.bin()
         ev[k][0].record(stream)
-        r.raycast()
+        r.raycast_shade(rgba8=True, rgb32=False)   # ray cast with the shading fused in
         ev[k][1].record(stream)
-        r.shade(rgba8=True, rgb32=False)
     t1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -159,8 +158,7 @@ def main():
             f0.record(stream)
             gr.bound()
             gr.bin()
-            gr.raycast()
-            gr.shade(rgba8=False, rgb32=True)
+            gr.raycast_shade(rgba8=False, rgb32=True)
             f1.record(stream)
             gr.backward(dl)
             b1.record(stream)
@@ -199,8 +197,7 @@ def main():
             for rr in seq:
                 rr.bound()
                 rr.bin()
-                rr.raycast()
-                rr.shade(rgba8=True, rgb32=False)
+                rr.raycast_shade(rgba8=True, rgb32=False)
         seq_round()
         torch.cuda.synchronize()
         e0.record(stream)
@@ -231,8 +228,7 @@ def main():
         for _ in range(nl):
             lr.bound()
             lr.bin()
-            lr.raycast()
-            lr.shade(rgba8=True, rgb32=False)
+            lr.raycast_shade(rgba8=True, rgb32=False)
         e1.record(stream)
         torch.cuda.synchronize()
         assert not lr.status().overflow
@@ -274,7 +270,7 @@ def main():
                    'views': len(sc.views), 'width': sc.views[0].width, 'height': sc.views[0].height,
                    'tile': args.tile},
         'frames_per_s': round(1e3 / ms_step, 1),
-        'raycast_ms': round(ray_ms_avg, 4),
+        'raycast_shade_ms': round(ray_ms_avg, 4),
         'tests_per_frame': tests,
         'tests_per_s': round(tests / (ray_ms_avg * 1e-3), 1),
         'ste': round(hits / max(tests, 1), 4),
@@ -287,7 +283,8 @@ def main():
         'wall_s': round(wall, 3),
         'roofline': {'bound': 'mfma', 'achieved': round(achieved, 3), 'peak': PEAK_FP32_TFLOPS,
                      'unit': 'TFLOP/s', 'frac': round(achieved / PEAK_FP32_TFLOPS, 4), 'traffic': traffic,
-                     'kernel': 'k_raycast_queue' if args.persistent else 'k_raycast', 'flop_per_test': flop_test},
+                     'kernel': ('k_raycast_queue (shading fused)' if args.persistent else 'k_raycast + k_shade'),
+                     'flop_per_test': flop_test},
         'cpu_baseline': cpu,
     }
     print(json.dumps(out), flush=True)

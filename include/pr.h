@@ -194,6 +194,19 @@ int pr_shade(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const 
              void *ws, size_t ws_bytes, const int32_t *const *tri_id, const pr_light *light,
              const float *const *albedo, uint8_t *const *rgba8, float *const *rgb32, void *stream);
 
+/* pr_raycast followed by pr_shade of the ids it resolves, in one pass: the
+ * persistent ray cast (PR_FLAG_PERSISTENT) shades each 8x8 cell right after
+ * resolving it, which overlaps the shading's gathers with the ray cast's
+ * arithmetic; otherwise the two kernels run in turn.  Arguments and outputs
+ * as for the two calls (tri_id and depth required; rgba8 / rgb32 may be
+ * NULL or hold NULL entries, and with no shaded output this is pr_raycast).
+ * The outputs are bitwise those of pr_raycast then pr_shade.  Needs pr_bin
+ * first. */
+int pr_raycast_shade(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
+                     void *ws, size_t ws_bytes, int32_t *const *tri_id, float *const *depth,
+                     const pr_light *light, const float *const *albedo, uint8_t *const *rgba8,
+                     float *const *rgb32, void *stream);
+
 /* Gradient of a loss L(rgb32) with visibility fixed to tri_id: given
  * dL/drgb[v] (float32 [H][W][3]), writes dL/dv0 and dL/dv1 (float32 [nv][3]
  * per mesh, summed over the views that use the mesh) and dL/dpose0,
@@ -206,10 +219,10 @@ int pr_backward(const pr_mesh *meshes, int nm, const pr_view *views, int nv, con
 
 /* BATCHED FORM.  A batch renders many views (eyes, frames, scenes) of
  * uneven size and triangle count as one frame: every pass is one launch over
- * all views, the ray cast is one resident grid pulling (view, tile) items
- * longest-first from a device queue, and the whole frame (bound, bin,
- * raycast, shade) is captured once into a hipGraph that pr_batch_launch
- * replays.
+ * all views, the ray cast (with the shading fused in) is one resident grid
+ * walking the (view, tile) items longest list first, and the whole frame
+ * (bound, bin, ray cast and shade) is captured once into a hipGraph that
+ * pr_batch_launch replays.
  *
  * pr_batch_create: meshes / views / light / albedo / outputs as for the
  * per-call functions (device pointers; outputs tri_id and depth required,

@@ -65,6 +65,7 @@ SIGNATURES = {
     'pr_bin': (ctypes.c_int, _FRAME + [ctypes.c_void_p]),
     'pr_raycast': (ctypes.c_int, _FRAME + [_PP, _PP, ctypes.c_void_p]),
     'pr_shade': (ctypes.c_int, _FRAME + [_PP, ctypes.POINTER(PrLight), _PP, _PP, _PP, ctypes.c_void_p]),
+    'pr_raycast_shade': (ctypes.c_int, _FRAME + [_PP, _PP, ctypes.POINTER(PrLight), _PP, _PP, _PP, ctypes.c_void_p]),
     'pr_backward': (ctypes.c_int, _FRAME + [_PP, ctypes.POINTER(PrLight), _PP, _PP, _PP, _PP, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p]),
     'pr_status_read': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(PrStatus), ctypes.c_void_p]),

@@ -202,14 +202,19 @@ int resident_blocks(K kernel, int threads) {
     return per_cu * prop.multiProcessorCount;
 }
 
-template <int TILE, bool COUNT>
-void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, DevStatus *st, ViewTable *T,
-                      hipStream_t s) {
+// The ray cast; with SHADE the resolved pixels are also shaded (fused into
+// the persistent ray cast; the one-block-per-item form runs k_shade after).
+template <int TILE, bool COUNT, bool SHADE>
+void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, const ShadeIO &sio,
+                      const pr_light &light, DevStatus *st, ViewTable *T, hipStream_t s) {
     using C = RayCfg<TILE>;
     if (!(flags & PR_FLAG_PERSISTENT)) {
         hipLaunchKernelGGL((k_raycast<TILE, COUNT>), dim3(ray_items<TILE>(L.total_tiles)), dim3(C::NT), 0, s, T,
                            at<float4>(ws, L.rec),
                            at<uint32_t>(ws, L.toff), at<uint32_t>(ws, L.lists), out, st);
+        if (SHADE)
+            hipLaunchKernelGGL(k_shade, dim3(L.total_pix_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec), sio,
+                               light);
         return;
     }
     Sched *S = at<Sched>(ws, L.sched);
@@ -217,18 +222,56 @@ void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, D
     hipLaunchKernelGGL(k_sched_scatter, dim3(nb), dim3(256), 0, s, T, at<uint32_t>(ws, L.toff), L.total_tiles, S,
                        at<int4>(ws, L.order), st);
     static int resident = 0;
-    if (!resident) resident = resident_blocks(k_raycast_queue<TILE, COUNT>, C::NT);
+    if (!resident) resident = resident_blocks(k_raycast_queue<TILE, COUNT, SHADE>, C::NT);
     const int nitems = ray_items<TILE>(L.total_tiles);
     const int grid = std::max(1, std::min(nitems, resident));
-    hipLaunchKernelGGL((k_raycast_queue<TILE, COUNT>), dim3(grid), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
-                       at<uint32_t>(ws, L.lists), out, st, at<int4>(ws, L.order), nitems, S);
+    hipLaunchKernelGGL((k_raycast_queue<TILE, COUNT, SHADE>), dim3(grid), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
+                       at<uint32_t>(ws, L.lists), out, st, at<int4>(ws, L.order), nitems, S, sio, light);
 }
 
-template <int TILE>
-void launch_raycast(int flags, const Layout &L, void *ws, const RayOut &out, DevStatus *st, ViewTable *T,
-                    hipStream_t s) {
-    if (flags & PR_FLAG_COUNT) launch_raycast_t<TILE, true>(flags, L, ws, out, st, T, s);
-    else launch_raycast_t<TILE, false>(flags, L, ws, out, st, T, s);
+template <int TILE, bool SHADE>
+void launch_raycast(int flags, const Layout &L, void *ws, const RayOut &out, const ShadeIO &sio,
+                    const pr_light &light, DevStatus *st, ViewTable *T, hipStream_t s) {
+    if (flags & PR_FLAG_COUNT) launch_raycast_t<TILE, true, SHADE>(flags, L, ws, out, sio, light, st, T, s);
+    else launch_raycast_t<TILE, false, SHADE>(flags, L, ws, out, sio, light, st, T, s);
+}
+
+template <bool SHADE>
+void launch_raycast_any(int tile, int flags, const Layout &L, void *ws, const RayOut &out, const ShadeIO &sio,
+                        const pr_light &light, DevStatus *st, ViewTable *T, hipStream_t s) {
+    if (tile == 8) launch_raycast<8, SHADE>(flags, L, ws, out, sio, light, st, T, s);
+    else if (tile == 16) launch_raycast<16, SHADE>(flags, L, ws, out, sio, light, st, T, s);
+    else launch_raycast<32, SHADE>(flags, L, ws, out, sio, light, st, T, s);
+}
+
+// Checks the shading arguments and fills io (ids from tri_id, may be NULL
+// when the ids come from the ray cast); *any: some view has an output.
+int shade_args(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const int32_t *const *tri_id,
+               const pr_light *light, const float *const *albedo, uint8_t *const *rgba8, float *const *rgb32,
+               ShadeIO &io, bool &any) {
+    if (!light || !albedo || !views || nv < 1 || nv > PR_MAX_VIEWS) return PR_ERR_INVALID;
+    if (!isfinite(light->ambient) || !isfinite(light->dir_world[0]) || !isfinite(light->dir_world[1]) ||
+        !isfinite(light->dir_world[2]))
+        return PR_ERR_INVALID;
+    if (tri_id)
+        for (int v = 0; v < nv; ++v)
+            if (!tri_id[v]) return PR_ERR_INVALID;
+    if (meshes)
+        for (int v = 0; v < nv; ++v) {
+            int m = views[v].mesh;
+            if (m >= 0 && m < nm && meshes[m].nt > 0 && !albedo[m]) return PR_ERR_INVALID;
+        }
+    memset(&io, 0, sizeof(io));
+    any = false;
+    for (int v = 0; v < nv; ++v) {
+        const int m = views[v].mesh;
+        io.id[v] = tri_id ? tri_id[v] : nullptr;
+        io.rgba8[v] = rgba8 ? rgba8[v] : nullptr;
+        io.rgb32[v] = rgb32 ? rgb32[v] : nullptr;
+        io.albedo[v] = (m >= 0 && m < nm) ? albedo[m] : nullptr;
+        any = any || io.rgba8[v] || io.rgb32[v];
+    }
+    return PR_OK;
 }
 
 }  // namespace
@@ -302,39 +345,46 @@ int pr_raycast(const pr_mesh *meshes, int nm, const pr_view *views, int nv, cons
         out.id[v] = tri_id[v];
         out.depth[v] = depth[v];
     }
-    if (tuning->tile == 8) launch_raycast<8>(tuning->flags, L, ws, out, st, T, s);
-    else if (tuning->tile == 16) launch_raycast<16>(tuning->flags, L, ws, out, st, T, s);
-    else launch_raycast<32>(tuning->flags, L, ws, out, st, T, s);
+    ShadeIO io;
+    memset(&io, 0, sizeof(io));
+    const pr_light none{};
+    launch_raycast_any<false>(tuning->tile, tuning->flags, L, ws, out, io, none, st, T, s);
     return launched();
 }
 
 int pr_shade(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning, void *ws,
              size_t ws_bytes, const int32_t *const *tri_id, const pr_light *light, const float *const *albedo,
              uint8_t *const *rgba8, float *const *rgb32, void *stream) {
-    if (!tri_id || !light || !albedo) return PR_ERR_INVALID;
-    if (!isfinite(light->ambient) || !isfinite(light->dir_world[0]) || !isfinite(light->dir_world[1]) ||
-        !isfinite(light->dir_world[2]))
-        return PR_ERR_INVALID;
-    for (int v = 0; v < nv && v < PR_MAX_VIEWS; ++v)
-        if (!tri_id[v]) return PR_ERR_INVALID;
-    if (meshes)
-        for (int v = 0; v < nv && v < PR_MAX_VIEWS && views; ++v) {
-            int m = views[v].mesh;
-            if (m >= 0 && m < nm && meshes[m].nt > 0 && !albedo[m]) return PR_ERR_INVALID;
-        }
-    PR_PREP();
+    if (!tri_id) return PR_ERR_INVALID;
     ShadeIO io;
-    memset(&io, 0, sizeof(io));
     bool any = false;
-    for (int v = 0; v < nv; ++v) {
-        io.id[v] = tri_id[v];
-        io.rgba8[v] = rgba8 ? rgba8[v] : nullptr;
-        io.rgb32[v] = rgb32 ? rgb32[v] : nullptr;
-        io.albedo[v] = albedo[views[v].mesh];
-        any = any || io.rgba8[v] || io.rgb32[v];
-    }
+    int rc = shade_args(meshes, nm, views, nv, tri_id, light, albedo, rgba8, rgb32, io, any);
+    if (rc) return rc;
+    PR_PREP();
     if (!any) return PR_OK;
     hipLaunchKernelGGL(k_shade, dim3(L.total_pix_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec), io, *light);
+    return launched();
+}
+
+int pr_raycast_shade(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning, void *ws,
+                     size_t ws_bytes, int32_t *const *tri_id, float *const *depth, const pr_light *light,
+                     const float *const *albedo, uint8_t *const *rgba8, float *const *rgb32, void *stream) {
+    if (!tri_id || !depth) return PR_ERR_INVALID;
+    for (int v = 0; v < nv && v < PR_MAX_VIEWS; ++v)
+        if (!tri_id[v] || !depth[v]) return PR_ERR_INVALID;
+    ShadeIO io;
+    bool any = false;
+    int rc = shade_args(meshes, nm, views, nv, tri_id, light, albedo, rgba8, rgb32, io, any);
+    if (rc) return rc;
+    PR_PREP();
+    RayOut out;
+    memset(&out, 0, sizeof(out));
+    for (int v = 0; v < nv; ++v) {
+        out.id[v] = tri_id[v];
+        out.depth[v] = depth[v];
+    }
+    if (any) launch_raycast_any<true>(tuning->tile, tuning->flags, L, ws, out, io, *light, st, T, s);
+    else launch_raycast_any<false>(tuning->tile, tuning->flags, L, ws, out, io, *light, st, T, s);
     return launched();
 }
 
@@ -528,12 +578,10 @@ int batch_frame(pr_batch *b, hipStream_t s) {
     const pr_view *V = b->views.data();
     int rc = pr_bound(M, nm, V, nv, &b->tuning, b->ws, b->ws_bytes, s);
     if (!rc) rc = pr_bin(M, nm, V, nv, &b->tuning, b->ws, b->ws_bytes, s);
-    if (!rc) rc = pr_raycast(M, nm, V, nv, &b->tuning, b->ws, b->ws_bytes, b->ids.data(), b->depth.data(), s);
-    bool shade = false;
-    for (int v = 0; v < nv; ++v) shade = shade || b->rgba8[v] || b->rgb32[v];
-    if (!rc && shade)
-        rc = pr_shade(M, nm, V, nv, &b->tuning, b->ws, b->ws_bytes, (const int32_t *const *)b->ids.data(), &b->light,
-                      b->albedo.data(), b->rgba8.data(), b->rgb32.data(), s);
+    // ray cast and shading in one pass (plain ray cast when nothing is shaded)
+    if (!rc)
+        rc = pr_raycast_shade(M, nm, V, nv, &b->tuning, b->ws, b->ws_bytes, b->ids.data(), b->depth.data(), &b->light,
+                              b->albedo.data(), b->rgba8.data(), b->rgb32.data(), s);
     return rc;
 }
 

@@ -726,6 +726,85 @@ __device__ __forceinline__ void pixel_setup(const PixelConst &pc, int px, int py
 }
 
 // Ray terms of one pixel: w = (rx, ry, t rx, t ry, t, t^2 rx, t^2 ry, t^2).
+// Shading of one resolved pixel (k_shade, and the ray cast's fused form).
+// Edge-plane normals c_k(t), face normal N(t) of triangle id at time t.
+__device__ __forceinline__ void record_at(const ViewDev &vd, const float4 *__restrict__ rec, int id, float t,
+                                          float ck[3][3], float N[3]) {
+    // c_o(t) = (M0 + t M2 + t^2 M5, M1 + t M3 + t^2 M6, K + t M4 + t^2 M7)
+    if (vd.rolling) {
+        const float *R = reinterpret_cast<const float *>(rec + vd.rec_off + (int64_t)id * kRecRoll);
+        for (int o = 0; o < 4; ++o) {
+            float *dst = o < 3 ? ck[o] : N;
+            dst[0] = fmaf(t, fmaf(t, R[20 + o], R[8 + o]), R[o]);
+            dst[1] = fmaf(t, fmaf(t, R[24 + o], R[12 + o]), R[4 + o]);
+            dst[2] = fmaf(t, fmaf(t, R[28 + o], R[16 + o]), R[32 + o]);
+        }
+    } else {
+        const float *R = reinterpret_cast<const float *>(rec + vd.rec_off + (int64_t)id * kRecStatic);
+        for (int o = 0; o < 4; ++o) {
+            float *dst = o < 3 ? ck[o] : N;
+            dst[0] = R[o];
+            dst[1] = R[4 + o];
+            dst[2] = R[16 + o];
+        }
+    }
+}
+
+// Rolling Lambert colour of triangle id (0 <= id < nt) at pixel (px, py).
+__device__ __forceinline__ void shade_pixel(const ViewDev &vd, const float4 *__restrict__ rec,
+                                            const float *__restrict__ alb, const pr_light &light, int px, int py,
+                                            int id, float c[3]) {
+    const PixelConst &pc = vd.pc;
+    const float ambient = light.ambient;
+    float t, rx, ry;
+    pixel_setup(pc, px, py, t, rx, ry);
+    float ck[3][3], N[3];
+    record_at(vd, rec, id, t, ck, N);
+    float e[3];
+    for (int k = 0; k < 3; ++k) e[k] = fmaf(ry, ck[k][1], fmaf(rx, ck[k][0], ck[k][2]));
+    float S = e[0] + e[1] + e[2];
+    float inn = rsqrtf(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+    float sg = (N[0] * rx + N[1] * ry + N[2]) > 0.0f ? -inn : inn;
+    // light direction in camera space at the pixel's time
+    float L[3];
+    for (int r = 0; r < 3; ++r) {
+        const float l0 = vd.R0f[3 * r] * light.dir_world[0] + vd.R0f[3 * r + 1] * light.dir_world[1] +
+                         vd.R0f[3 * r + 2] * light.dir_world[2];
+        const float l1 = vd.R1f[3 * r] * light.dir_world[0] + vd.R1f[3 * r + 1] * light.dir_world[1] +
+                         vd.R1f[3 * r + 2] * light.dir_world[2];
+        L[r] = fmaf(t, l1 - l0, l0);
+    }
+    float inl = rsqrtf(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
+    float ndl = sg * inl * (N[0] * L[0] + N[1] * L[1] + N[2] * L[2]);
+    float s = ambient + (1.0f - ambient) * fmaxf(ndl, 0.0f);
+    float invS = 1.0f / S;
+    c[0] = c[1] = c[2] = 0.0f;
+    for (int k = 0; k < 3; ++k) {
+        int vi = vd.mesh.tri[3 * (int64_t)id + k];
+        float mu = e[k] * invS;
+        for (int ch = 0; ch < 3; ++ch) c[ch] = fmaf(mu, alb[3 * (int64_t)vi + ch], c[ch]);
+    }
+    for (int ch = 0; ch < 3; ++ch) c[ch] *= s;
+}
+
+// The shaded outputs of pixel p of view v (id < 0: a miss, colour 0).
+__device__ __forceinline__ void store_shade(const ShadeIO &io, int v, int64_t p, const float c[3], int id) {
+    if (io.rgb32[v]) {
+        float *o = io.rgb32[v];
+        o[3 * p] = c[0];
+        o[3 * p + 1] = c[1];
+        o[3 * p + 2] = c[2];
+    }
+    if (io.rgba8[v]) {
+        uchar4 o;
+        o.x = (uint8_t)floorf(fminf(fmaxf(c[0], 0.0f), 1.0f) * 255.0f + 0.5f);
+        o.y = (uint8_t)floorf(fminf(fmaxf(c[1], 0.0f), 1.0f) * 255.0f + 0.5f);
+        o.z = (uint8_t)floorf(fminf(fmaxf(c[2], 0.0f), 1.0f) * 255.0f + 0.5f);
+        o.w = id >= 0 ? 255 : 0;
+        reinterpret_cast<uchar4 *>(io.rgba8[v])[p] = o;
+    }
+}
+
 __device__ __forceinline__ void ray_terms(const PixelConst &pc, int px, int py, float w[8]) {
     float t, rx, ry;
     pixel_setup(pc, px, py, t, rx, ry);
@@ -785,11 +864,21 @@ struct RecLayout {
 
 // One 8x8 cell of one view.  (cx0, cy0): its first pixel; q: the quadrant
 // bit its list entries must carry (-1: no filter).
-template <bool ROLL, bool COUNT>
+// SHADE: the cell's pixels are shaded right after they are resolved
+// (pixel colours as k_shade gives them for the same ids).
+struct ShadeArgs {
+    const ShadeIO *io;
+    const pr_light *light;
+    const float4 *rec;
+    int v;
+};
+
+template <bool ROLL, bool COUNT, bool SHADE>
 __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0, int q, const float *__restrict__ vrec,
                                              int beg, int end, const uint32_t *__restrict__ lists, uint32_t ent0,
                                              int32_t *__restrict__ out_id, float *__restrict__ out_depth,
-                                             unsigned long long *__restrict__ cnt, int32_t *s_sel) {
+                                             unsigned long long *__restrict__ cnt, int32_t *s_sel,
+                                             const ShadeArgs &sa) {
     using RL = RecLayout<ROLL>;
     const PixelConst &pc = vd.pc;
     const int lane = __lane_id();
@@ -938,8 +1027,14 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
     if (px < pc.W && py < pc.H) {
         const int64_t p = (int64_t)py * pc.W + px;
         const bool miss = mine == kFar;
-        out_id[p] = miss ? -1 : (int32_t)(uint32_t)(mine & 0xffffffffu);
+        const int32_t id = miss ? -1 : (int32_t)(uint32_t)(mine & 0xffffffffu);
+        out_id[p] = id;
         out_depth[p] = miss ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(mine >> 32));
+        if (SHADE) {
+            float c[3] = {0.0f, 0.0f, 0.0f};
+            if (id >= 0) shade_pixel(vd, sa.rec, sa.io->albedo[sa.v], *sa.light, px, py, id, c);
+            store_shade(*sa.io, sa.v, p, c, id);
+        }
     }
     if (COUNT) {
         unsigned long long h = hits;
@@ -974,11 +1069,11 @@ __device__ __forceinline__ uint32_t first_entries(const uint32_t *__restrict__ l
 
 // Block item -> the wave's 8x8 cell of tile record tr (ent0: the lane's
 // first list entry).
-template <int TILE, bool COUNT>
+template <int TILE, bool COUNT, bool SHADE>
 __device__ __forceinline__ void raycast_item(const ViewTable *__restrict__ T, const float4 *__restrict__ rec,
                                              const uint32_t *__restrict__ lists, const RayOut &out,
                                              DevStatus *__restrict__ st, int item, int4 tr, uint32_t ent0,
-                                             int32_t *s_sel_block) {
+                                             int32_t *s_sel_block, const ShadeIO *sio, const pr_light *light) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (tr.x < 0) return;
     const int gt = tr.x, v = tr.y;
@@ -999,10 +1094,13 @@ __device__ __forceinline__ void raycast_item(const ViewTable *__restrict__ T, co
     const float *vrec = reinterpret_cast<const float *>(rec + vd.rec_off);
     unsigned long long *cnt = &st->cnt[blockIdx.x & (kCountSlots - 1)][0];
     int32_t *s_sel = s_sel_block + wv * kSelCap;
+    const ShadeArgs sa{sio, light, rec, v};
     if (vd.rolling)
-        raycast_cell<true, COUNT>(vd, cx0, cy0, q, vrec, tr.z, tr.w, lists, ent0, out.id[v], out.depth[v], cnt, s_sel);
+        raycast_cell<true, COUNT, SHADE>(vd, cx0, cy0, q, vrec, tr.z, tr.w, lists, ent0, out.id[v], out.depth[v], cnt,
+                                         s_sel, sa);
     else
-        raycast_cell<false, COUNT>(vd, cx0, cy0, q, vrec, tr.z, tr.w, lists, ent0, out.id[v], out.depth[v], cnt, s_sel);
+        raycast_cell<false, COUNT, SHADE>(vd, cx0, cy0, q, vrec, tr.z, tr.w, lists, ent0, out.id[v], out.depth[v], cnt,
+                                          s_sel, sa);
 }
 
 // Block b -> item: consecutive blocks go to the eight XCDs in turn, so XCD
@@ -1023,7 +1121,8 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
     const int item = xcd_item(blockIdx.x, gridDim.x);
     const int k = item_tile<TILE>(item, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
     const int4 tr = k < T->total_tiles ? tile_rec(T, toff, k, st->overflow != 0) : make_int4(-1, 0, 0, 0);
-    raycast_item<TILE, COUNT>(T, rec, lists, out, st, item, tr, first_entries(lists, tr), s_sel);
+    raycast_item<TILE, COUNT, false>(T, rec, lists, out, st, item, tr, first_entries(lists, tr), s_sel, nullptr,
+                                     nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1064,10 +1163,12 @@ __global__ __launch_bounds__(256) void k_sched_scatter(const ViewTable *__restri
     if (i < n) order[base[b] + rank] = tile_rec(T, toff, i, st->overflow != 0);
 }
 
-template <int TILE, bool COUNT>
-__global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast_queue(
+// Six waves per SIMD (80 VGPRs, a few spilled) run faster than five.
+template <int TILE, bool COUNT, bool SHADE>
+__global__ __launch_bounds__((RayCfg<TILE>::NT)) __attribute__((amdgpu_waves_per_eu(6))) void k_raycast_queue(
     const ViewTable *__restrict__ T, const float4 *__restrict__ rec, const uint32_t *__restrict__ lists, RayOut out,
-    DevStatus *__restrict__ st, const int4 *__restrict__ order, int nitems, Sched *__restrict__ S) {
+    DevStatus *__restrict__ st, const int4 *__restrict__ order, int nitems, Sched *__restrict__ S, ShadeIO sio,
+    pr_light light) {
     __shared__ int32_t s_sel[4 * kSelCap];
     // k_sched_scatter has finished with the bucket cursors: clear them for
     // the next ray cast over the same lists (k_tiles clears them per frame)
@@ -1089,7 +1190,7 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast_queue(
     while (item < nitems) {
         const int4 nx2 = fetch(item + 2 * G);
         const uint32_t enx = first_entries(lists, nx1);
-        raycast_item<TILE, COUNT>(T, rec, lists, out, st, item, cur, ecur, s_sel);
+        raycast_item<TILE, COUNT, SHADE>(T, rec, lists, out, st, item, cur, ecur, s_sel, &sio, &light);
         item += G;
         cur = nx1;
         nx1 = nx2;
@@ -1100,32 +1201,8 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast_queue(
 // ---------------------------------------------------------------------------
 // shade
 // ---------------------------------------------------------------------------
-// Edge-plane normals c_k(t), face normal N(t) of triangle id at time t.
-__device__ __forceinline__ void record_at(const ViewDev &vd, const float4 *__restrict__ rec, int id, float t,
-                                          float ck[3][3], float N[3]) {
-    // c_o(t) = (M0 + t M2 + t^2 M5, M1 + t M3 + t^2 M6, K + t M4 + t^2 M7)
-    if (vd.rolling) {
-        const float *R = reinterpret_cast<const float *>(rec + vd.rec_off + (int64_t)id * kRecRoll);
-        for (int o = 0; o < 4; ++o) {
-            float *dst = o < 3 ? ck[o] : N;
-            dst[0] = fmaf(t, fmaf(t, R[20 + o], R[8 + o]), R[o]);
-            dst[1] = fmaf(t, fmaf(t, R[24 + o], R[12 + o]), R[4 + o]);
-            dst[2] = fmaf(t, fmaf(t, R[28 + o], R[16 + o]), R[32 + o]);
-        }
-    } else {
-        const float *R = reinterpret_cast<const float *>(rec + vd.rec_off + (int64_t)id * kRecStatic);
-        for (int o = 0; o < 4; ++o) {
-            float *dst = o < 3 ? ck[o] : N;
-            dst[0] = R[o];
-            dst[1] = R[4 + o];
-            dst[2] = R[16 + o];
-        }
-    }
-}
-
 __global__ __launch_bounds__(256) void k_shade(const ViewTable *__restrict__ T, const float4 *__restrict__ rec,
                                                ShadeIO io, pr_light light) {
-    const float ambient = light.ambient;
     const int v = find_view(T->pix_block0, T->nv, blockIdx.x);
     const ViewDev &vd = T->v[v];
     const PixelConst &pc = vd.pc;
@@ -1134,52 +1211,8 @@ __global__ __launch_bounds__(256) void k_shade(const ViewTable *__restrict__ T, 
     int id = io.id[v][p];
     if (id >= vd.mesh.nt) id = -1;   // ids outside the mesh shade as misses
     float c[3] = {0.0f, 0.0f, 0.0f};
-    if (id >= 0) {
-        int px = (int)(p % pc.W), py = (int)(p / pc.W);
-        float t, rx, ry;
-        pixel_setup(pc, px, py, t, rx, ry);
-        float ck[3][3], N[3];
-        record_at(vd, rec, id, t, ck, N);
-        float e[3];
-        for (int k = 0; k < 3; ++k) e[k] = fmaf(ry, ck[k][1], fmaf(rx, ck[k][0], ck[k][2]));
-        float S = e[0] + e[1] + e[2];
-        float inn = rsqrtf(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
-        float sg = (N[0] * rx + N[1] * ry + N[2]) > 0.0f ? -inn : inn;
-        // light direction in camera space at the pixel's time
-        float L[3];
-        for (int r = 0; r < 3; ++r) {
-            const float l0 = vd.R0f[3 * r] * light.dir_world[0] + vd.R0f[3 * r + 1] * light.dir_world[1] +
-                             vd.R0f[3 * r + 2] * light.dir_world[2];
-            const float l1 = vd.R1f[3 * r] * light.dir_world[0] + vd.R1f[3 * r + 1] * light.dir_world[1] +
-                             vd.R1f[3 * r + 2] * light.dir_world[2];
-            L[r] = fmaf(t, l1 - l0, l0);
-        }
-        float inl = rsqrtf(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
-        float ndl = sg * inl * (N[0] * L[0] + N[1] * L[1] + N[2] * L[2]);
-        float s = ambient + (1.0f - ambient) * fmaxf(ndl, 0.0f);
-        float invS = 1.0f / S;
-        const float *alb = io.albedo[v];
-        for (int k = 0; k < 3; ++k) {
-            int vi = vd.mesh.tri[3 * (int64_t)id + k];
-            float mu = e[k] * invS;
-            for (int ch = 0; ch < 3; ++ch) c[ch] = fmaf(mu, alb[3 * (int64_t)vi + ch], c[ch]);
-        }
-        for (int ch = 0; ch < 3; ++ch) c[ch] *= s;
-    }
-    if (io.rgb32[v]) {
-        float *o = io.rgb32[v];
-        o[3 * p] = c[0];
-        o[3 * p + 1] = c[1];
-        o[3 * p + 2] = c[2];
-    }
-    if (io.rgba8[v]) {
-        uchar4 o;
-        o.x = (uint8_t)floorf(fminf(fmaxf(c[0], 0.0f), 1.0f) * 255.0f + 0.5f);
-        o.y = (uint8_t)floorf(fminf(fmaxf(c[1], 0.0f), 1.0f) * 255.0f + 0.5f);
-        o.z = (uint8_t)floorf(fminf(fmaxf(c[2], 0.0f), 1.0f) * 255.0f + 0.5f);
-        o.w = id >= 0 ? 255 : 0;
-        reinterpret_cast<uchar4 *>(io.rgba8[v])[p] = o;
-    }
+    if (id >= 0) shade_pixel(vd, rec, io.albedo[v], light, (int)(p % pc.W), (int)(p / pc.W), id, c);
+    store_shade(io, v, p, c, id);
 }
 
 // ---------------------------------------------------------------------------

@@ -42,8 +42,9 @@ def _stream_handle() -> int:
 class Renderer:
     """One frame pipeline over a fixed set of meshes and views.
 
-    ``frame()`` enqueues pr_bound, pr_bin, pr_raycast and (optionally)
-    pr_shade on the current torch stream and returns the output tensors.
+    ``frame()`` enqueues pr_bound, pr_bin and pr_raycast_shade (pr_raycast
+    when ``shade=False``) on the current torch stream and returns the output
+    tensors.
     The workspace is a torch uint8 tensor sized by pr_workspace_size; on a
     tile-list overflow (checked only when ``check=True``) the capacity is
     raised to what the device reported and the frame is run again."""
@@ -106,6 +107,16 @@ class Renderer:
         B.check('pr_shade', self.L.pr_shade(*self._args(), idp, ctypes.byref(self.light), alb, o8, o32,
                                             ctypes.c_void_p(_stream_handle())))
 
+    def raycast_shade(self, rgba8: bool = True, rgb32: bool = True):
+        """pr_raycast_shade: the ray cast with the shading of its ids fused in."""
+        ids = B.ptr_array([o['id'].data_ptr() for o in self.outputs])
+        deps = B.ptr_array([o['depth'].data_ptr() for o in self.outputs])
+        alb = B.ptr_array([m.albedo.data_ptr() for m in self.meshes])
+        o8 = B.ptr_array([o['rgba8'].data_ptr() for o in self.outputs]) if rgba8 else None
+        o32 = B.ptr_array([o['rgb32'].data_ptr() for o in self.outputs]) if rgb32 else None
+        B.check('pr_raycast_shade', self.L.pr_raycast_shade(*self._args(), ids, deps, ctypes.byref(self.light), alb,
+                                                            o8, o32, ctypes.c_void_p(_stream_handle())))
+
     def backward(self, dl_drgb, ids=None):
         """pr_backward: dL/drgb per view (float32 [H,W,3] cuda) -> (dv0, dv1)
         per mesh ([V,3] cuda) and (dpose0, dpose1) [n_views, 6] cuda, with
@@ -158,9 +169,10 @@ class Renderer:
         for _ in range(4):
             self.bound()
             self.bin()
-            self.raycast()
             if shade:
-                self.shade()
+                self.raycast_shade()
+            else:
+                self.raycast()
             if not check:
                 break
             st = self.status()

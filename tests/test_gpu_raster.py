@@ -185,6 +185,32 @@ def test_nonfinite_vertex_and_empty_mesh():
     assert (e[0]['id'] == -1).all() and np.isinf(e[0]['depth']).all() and (e[0]['rgba8'] == 0).all()
 
 
+@pytest.mark.parametrize('tile', [8, 16, 32])
+@pytest.mark.parametrize('flags', [0, 2])
+def test_fused_shading_matches_separate_calls(tile, flags):
+    """pr_raycast_shade (shading fused into the persistent ray cast, flags 2;
+    two kernels in turn, flags 0) writes bitwise the ids, depths and colours
+    of pr_raycast followed by pr_shade."""
+    torch = _torch()
+    from paper_1806_05385_amd.render import Renderer
+    sc = scenegen.make_moving_soup(seed=34, n_tris=1500, width=203, height=171, alpha=2.0, roll=(1.0, 0.0),
+                                   yaw_deg_s=1500.0, obj_speed=10.0, side=(0.03, 0.5))
+    r = Renderer(sc.meshes, sc.views, tile=tile, light=sc.light_dir, ambient=sc.ambient, flags=flags)
+    r.frame(shade=False)
+    r.shade(rgba8=True, rgb32=True)
+    sep = {k: v.cpu().numpy().copy() for k, v in r.outputs[0].items()}
+    for o in r.outputs:
+        for t in o.values():
+            t.zero_()
+    r.bound()
+    r.bin()
+    r.raycast_shade(rgba8=True, rgb32=True)
+    fused = {k: v.cpu().numpy() for k, v in r.outputs[0].items()}
+    assert (sep['id'] >= 0).sum() > 5000
+    for k in ('id', 'depth', 'rgba8', 'rgb32'):
+        assert np.array_equal(sep[k].view(np.uint8), fused[k].view(np.uint8)), k
+
+
 def test_shading_matches_oracle():
     """RGBA8 within 1 LSB of the FP64 rolling Lambert shading, both on the
     GPU's own ids and when the GPU shades the oracle's ids."""
