@@ -25,6 +25,7 @@ struct Geom {
     double R0[9], T0[3], R1[9], T1[3];
     double fx, fy, cx, cy, znear;
     double fov[2], alpha, rad;   // fovea, exponent, normalising radius
+    double inv_alpha, inv_rad;   // 1 / alpha, 1 / rad
     double roll[2];
     int W, H;
     bool rolling;
@@ -117,6 +118,8 @@ PRG void make_geom(const pr_view &v, Geom &g) {
     g.fov[0] = v.fovea[0]; g.fov[1] = v.fovea[1];
     g.alpha = v.alpha;
     g.rad = fovea_radius(g.fov[0], g.fov[1]);
+    g.inv_alpha = 1.0 / g.alpha;
+    g.inv_rad = 1.0 / g.rad;
     g.roll[0] = v.roll_dir[0]; g.roll[1] = v.roll_dir[1];
     g.rolling = (v.roll_dir[0] != 0.0f) || (v.roll_dir[1] != 0.0f);
     g.W = v.width; g.H = v.height;
@@ -129,9 +132,8 @@ PRG void radial_map(const Geom &g, double e, double x0, double x1, double &o0, d
     double d0 = x0 - g.fov[0], d1 = x1 - g.fov[1];
     double rho = sqrt(d0 * d0 + d1 * d1);
     if (rho == 0.0 || e == 1.0) { o0 = x0; o1 = x1; return; }
-    double q = rho / g.rad;
     // (rho/R)^(e-1); the square-law density (e = 2 or 1/2) avoids pow
-    double s = e == 2.0 ? q : (e == 0.5 ? sqrt(1.0 / q) : pow(q, e - 1.0));
+    double s = e == 2.0 ? rho * g.inv_rad : (e == 0.5 ? sqrt(g.rad / rho) : pow(rho * g.inv_rad, e - 1.0));
     o0 = g.fov[0] + d0 * s;
     o1 = g.fov[1] + d1 * s;
 }
@@ -347,7 +349,8 @@ PRG void display_box(const Geom &g, const double Ps[3][3], const double Pe[3][3]
     box[0] = box[2] = 1e300;
     box[1] = box[3] = -1e300;
     auto add = [&](const double *P) {
-        double x = g.fx * P[0] / P[2] + g.cx, y = g.fy * P[1] / P[2] + g.cy;
+        const double iz = 1.0 / P[2];
+        double x = g.fx * P[0] * iz + g.cx, y = g.fy * P[1] * iz + g.cy;
         box[0] = dmin(box[0], x); box[1] = dmax(box[1], x);
         box[2] = dmin(box[2], y); box[3] = dmax(box[3], y);
     };
@@ -405,7 +408,7 @@ PRG bool tile_rect(const Geom &g, const double box[4], int tile, int rect[4]) {
     double b0 = dmax(box[2], -1.0), b1 = dmin(box[3], 1.0);
     if (!(a0 <= a1 && b0 <= b1)) return false;
     double fb[4];
-    radial_bbox(g, 1.0 / g.alpha, a0, a1, b0, b1, fb);
+    radial_bbox(g, g.inv_alpha, a0, a1, b0, b1, fb);
     for (int k = 0; k < 4; ++k) {
         double m = kSlackNdc * (1.0 + fabs(fb[k]));
         fb[k] += (k & 1) ? m : -m;
@@ -413,7 +416,12 @@ PRG bool tile_rect(const Geom &g, const double box[4], int tile, int rect[4]) {
     int i0, i1, j0, j1;
     if (!pixel_range(fb[0], fb[1], g.W, false, i0, i1)) return false;
     if (!pixel_range(fb[2], fb[3], g.H, true, j0, j1)) return false;
-    rect[0] = i0 / tile; rect[1] = j0 / tile; rect[2] = i1 / tile; rect[3] = j1 / tile;
+    if ((tile & (tile - 1)) == 0) {   // power of two (every supported size): shifts
+        const int sh = __builtin_ctz((unsigned)tile);
+        rect[0] = i0 >> sh; rect[1] = j0 >> sh; rect[2] = i1 >> sh; rect[3] = j1 >> sh;
+    } else {
+        rect[0] = i0 / tile; rect[1] = j0 / tile; rect[2] = i1 / tile; rect[3] = j1 / tile;
+    }
     return true;
 }
 

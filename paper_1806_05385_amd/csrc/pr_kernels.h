@@ -38,6 +38,7 @@ struct TriBound {
     int32_t kind;      // prg::kCulled / kWindow / kClipped
     int32_t pad;
     double w[4];       // kWindow: time window w[0..1]; kClipped: display box
+    int32_t pad2[2];   // to 4 float4 (coalesced stores)
 };
 
 // Display-space box of a tile's pixel centres and its frame-time window;

@@ -142,8 +142,37 @@ __device__ inline double ddot(const double a[3], const double b[3]) { return a[0
 
 // Per-triangle bound and record of one triangle (k_bound).  Returns the
 // number of (triangle, tile) candidates of its tile rectangle.
-__device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, float4 *__restrict__ rec,
-                                         TriBound *__restrict__ tb, DevStatus *__restrict__ st) {
+// Coalesced stores of per-lane rows: lane j holds rows [r0, r0 + n) (n <= 4)
+// of item j of the wave, item j's rows at base + j * stride + r0.  The rows
+// pass through the wave's 256-float4 LDS buffer so that each store
+// instruction writes 64-byte runs (four rows of one item) instead of one
+// row per lane; items whose bit of `valid` is clear are not written.
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N>
+__device__ __forceinline__ void wave_rows(float4 *__restrict__ base, int stride, int r0, const float4 *v,
+                                          unsigned long long valid, float4 *s_buf) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int q = 0; q < N; ++q) s_buf[4 * lane + q] = v[q];
+    wave_fence();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k = 64 * i + lane, j = k >> 2, q = k & 3;
+        if (q < N && ((valid >> j) & 1ull)) base[(int64_t)j * stride + r0 + q] = s_buf[k];
+    }
+    wave_fence();
+}
+
+// Triangle f of the view (every lane of the wave calls it; lanes with valid
+// false compute on an in-range triangle and store nothing); f0: the wave's
+// first triangle (wave-uniform; lane j's triangle is f0 + j).
+__device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, bool valid, int f0, float4 *__restrict__ rec,
+                                         TriBound *__restrict__ tb, DevStatus *__restrict__ st, float4 *s_buf) {
     const prg::Geom &g = vd.g;
     double Ps[3][3], Pe[3][3];
     int32_t idx[3];
@@ -152,9 +181,10 @@ __device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, float4 *__res
     b.rect[0] = 1; b.rect[1] = 1; b.rect[2] = 0; b.rect[3] = 0;
     b.kind = prg::kCulled;
     b.pad = 0;
+    b.pad2[0] = b.pad2[1] = 0;
     for (int k = 0; k < 4; ++k) b.w[k] = 0.0;
     if (!ok) {
-        atomicAdd(&st->nonfinite, 1);
+        if (valid) atomicAdd(&st->nonfinite, 1);
     } else {
         double win[2];
         int kind = prg::time_window(g, Ps, Pe, win);
@@ -170,7 +200,13 @@ __device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, float4 *__res
             }
         }
     }
-    tb[vd.tri_off + f] = b;
+    const unsigned long long vmask = __ballot(valid);
+    {
+        float4 w[4];
+        static_assert(sizeof(TriBound) == sizeof(w), "TriBound is 4 float4");
+        __builtin_memcpy(w, &b, sizeof(w));
+        wave_rows<4>(reinterpret_cast<float4 *>(tb + vd.tri_off + f0), 4, 0, w, vmask, s_buf);
+    }
 
     // Intersection record.  Edge k joins vertices a = k+1, b = k+2.  Its
     // plane normal is computed from the lower-indexed mesh vertex as
@@ -247,9 +283,13 @@ __device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, float4 *__res
         out[36] = (float)d0; out[37] = (float)d1; out[38] = (float)d2; out[39] = (float)d3;
         out[40] = __int_as_float(f);
         out[41] = out[42] = out[43] = 0.0f;
-        float4 *dst = rec + vd.rec_off + (int64_t)f * kRecRoll;
+        float4 w[kRecRoll];
 #pragma unroll
-        for (int q = 0; q < kRecRoll; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+        for (int q = 0; q < kRecRoll; ++q) w[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+        float4 *dst = rec + vd.rec_off + (int64_t)f0 * kRecRoll;
+        wave_rows<4>(dst, kRecRoll, 0, w, vmask, s_buf);
+        wave_rows<4>(dst, kRecRoll, 4, w + 4, vmask, s_buf);
+        wave_rows<3>(dst, kRecRoll, 8, w + 8, vmask, s_buf);
     } else {
         float out[24];
 #pragma unroll
@@ -263,11 +303,14 @@ __device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, float4 *__res
         out[20] = (float)d0;
         out[21] = __int_as_float(f);
         out[22] = out[23] = 0.0f;
-        float4 *dst = rec + vd.rec_off + (int64_t)f * kRecStatic;
+        float4 w[kRecStatic];
 #pragma unroll
-        for (int q = 0; q < kRecStatic; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+        for (int q = 0; q < kRecStatic; ++q) w[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+        float4 *dst = rec + vd.rec_off + (int64_t)f0 * kRecStatic;
+        wave_rows<4>(dst, kRecStatic, 0, w, vmask, s_buf);
+        wave_rows<2>(dst, kRecStatic, 4, w + 4, vmask, s_buf);
     }
-    return b.kind == prg::kCulled ? 0 : (b.rect[2] - b.rect[0] + 1) * (b.rect[3] - b.rect[1] + 1);
+    return (!valid || b.kind == prg::kCulled) ? 0 : (b.rect[2] - b.rect[0] + 1) * (b.rect[3] - b.rect[1] + 1);
 }
 
 // One lane per triangle; the block's candidate total (the binning block of
@@ -276,10 +319,15 @@ __global__ __launch_bounds__(256) void k_bound(const ViewTable *__restrict__ T, 
                                                TriBound *__restrict__ tb, DevStatus *__restrict__ st,
                                                int32_t *__restrict__ bcand) {
     __shared__ int s_tmp[72];
+    __shared__ float4 s_rows[4][256];   // per-wave store staging
     const int v = find_view(T->tri_block0, T->nv, blockIdx.x);
     const ViewDev &vd = T->v[v];
     const int f = (blockIdx.x - vd.tri_block0) * 256 + threadIdx.x;
-    const int cnt = f < vd.mesh.nt ? bound_tri(vd, f, rec, tb, st) : 0;
+    // every lane takes part in the wave's coalesced stores; lanes past the
+    // mesh work on triangle 0 (a block exists only for nt >= 1)
+    const bool valid = f < vd.mesh.nt;
+    const int fw0 = (blockIdx.x - vd.tri_block0) * 256 + (int)(threadIdx.x & ~63u);
+    const int cnt = bound_tri(vd, valid ? f : 0, valid, fw0, rec, tb, st, s_rows[threadIdx.x >> 6]);
     int total;
     block_excl_scan(cnt, s_tmp, total);
     if (threadIdx.x == 0) bcand[blockIdx.x] = total;
