@@ -315,7 +315,7 @@ __device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, bool valid, i
 
 // One lane per triangle; the block's candidate total (the binning block of
 // the same 256 triangles) goes to bcand[block].
-__global__ __launch_bounds__(256) void k_bound(const ViewTable *__restrict__ T, float4 *__restrict__ rec,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_bound(const ViewTable *__restrict__ T, float4 *__restrict__ rec,
                                                TriBound *__restrict__ tb, DevStatus *__restrict__ st,
                                                int32_t *__restrict__ bcand) {
     __shared__ int s_tmp[72];
