@@ -53,6 +53,39 @@ def measured_traffic():
         return None
 
 
+def grad_leg(args, stream):
+    """Backward / forward on the differentiation workload (100,820 triangles,
+    512x512, rolling + foveated, moving camera): forward = bound + bin + ray
+    cast with fp32 rgb shading, backward = pr_backward.  Median ms of each."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_1806_05385_amd.render import Renderer
+    gsc = scenegen.make_grad()
+    gr = Renderer(gsc.meshes, gsc.views, tile=args.tile, light=gsc.light_dir, ambient=gsc.ambient)
+    gr.frame(check=True)
+    dl = [torch.ones_like(gr.outputs[0]['rgb32'])]
+    for _ in range(3):
+        gr.frame(check=False)
+        gr.backward(dl)
+    nrep = max(10, args.steps)
+    f0, f1, b1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    fwd_ms, bwd_ms = [], []
+    for _ in range(nrep):
+        f0.record(stream)
+        gr.bound()
+        gr.bin()
+        gr.raycast_shade(rgba8=False, rgb32=True)
+        f1.record(stream)
+        gr.backward(dl)
+        b1.record(stream)
+        torch.cuda.synchronize()
+        fwd_ms.append(f0.elapsed_time(f1))
+        bwd_ms.append(f1.elapsed_time(b1))
+    return float(np.median(fwd_ms)), float(np.median(bwd_ms))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -63,8 +96,9 @@ def main():
                     help='one block per tile item instead of the longest-first persistent ray cast')
     ap.add_argument('--cpu-pixels', type=int, default=49152)
     ap.add_argument('--no-cpu-baseline', action='store_true')
-    ap.add_argument('--only', choices=['all', 'hmd'], default='all',
-                    help='hmd: only the headline frame (no backward, batch or CPU legs; for profiling)')
+    ap.add_argument('--only', choices=['all', 'hmd', 'grad'], default='all',
+                    help='hmd: only the headline frame (no backward, batch or CPU legs; for profiling); '
+                         'grad: only the backward / forward leg (prints that leg\'s line; for profiling)')
     ap.add_argument('--source-sha', action='store_true', help='print the kernel source hash and exit')
     ap.add_argument('--copy-bytes', type=int, default=0,
                     help='only run a plain device copy of this many bytes 10 times (counter calibration)')
@@ -92,23 +126,29 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({'copy_bytes': args.copy_bytes, 'launches': 10}))
         return
+    if args.only == 'grad':
+        fwd_med, bwd_med = grad_leg(args, torch.cuda.current_stream())
+        print(json.dumps({'grad_workload': {'triangles': 100820, 'size': 512, 'fwd_ms': round(fwd_med, 4),
+                                            'bwd_ms': round(bwd_med, 4)}, 'bwd_fwd': round(bwd_med / fwd_med, 3)}))
+        return
     sc = scenegen.make_hmd()
     mesh = sc.meshes[0]
     r = Renderer(sc.meshes, sc.views, tile=args.tile, light=sc.light_dir, ambient=sc.ambient)
-    r.frame(check=True)            # sizes the tile-list capacity
+    # every frame shades RGBA8 only, as the timed ones do
+    r.frame(check=True, rgb32=False)            # sizes the tile-list capacity
     # one counting frame (not timed): ray-triangle tests and hits
     r.flags = B.PR_FLAG_COUNT | (B.PR_FLAG_PERSISTENT if args.persistent else 0)
     r._prepare()
-    r.frame(check=True)
+    r.frame(check=True, rgb32=False)
     st = r.status()
     tests, hits = int(st.tests), int(st.hits)
     r.flags = B.PR_FLAG_PERSISTENT if args.persistent else 0
     r._prepare()
-    r.frame(check=True)
+    r.frame(check=True, rgb32=False)
 
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
-        r.frame(check=False)
+        r.frame(check=False, rgb32=False)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = torch.cuda.Event(enable_timing=True)
@@ -138,34 +178,10 @@ def main():
 
     if args.only == 'hmd':
         args.no_cpu_baseline = True
-    # backward / forward on the differentiation workload (100,820 triangles,
-    # 512x512, rolling + foveated, moving camera): forward = bound + bin +
-    # raycast + shade (fp32 rgb), backward = pr_backward
     fwd_med = bwd_med = float('nan')
     batch_out = large_out = None
     if args.only == 'all':
-        gsc = scenegen.make_grad()
-        gr = Renderer(gsc.meshes, gsc.views, tile=args.tile, light=gsc.light_dir, ambient=gsc.ambient)
-        gr.frame(check=True)
-        dl = [torch.ones_like(gr.outputs[0]['rgb32'])]
-        for _ in range(3):
-            gr.frame(check=False)
-            gr.backward(dl)
-        nrep = max(10, args.steps)
-        f0, f1, b1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-        fwd_ms, bwd_ms = [], []
-        for _ in range(nrep):
-            f0.record(stream)
-            gr.bound()
-            gr.bin()
-            gr.raycast_shade(rgba8=False, rgb32=True)
-            f1.record(stream)
-            gr.backward(dl)
-            b1.record(stream)
-            torch.cuda.synchronize()
-            fwd_ms.append(f0.elapsed_time(f1))
-            bwd_ms.append(f1.elapsed_time(b1))
-        fwd_med, bwd_med = float(np.median(fwd_ms)), float(np.median(bwd_ms))
+        fwd_med, bwd_med = grad_leg(args, stream)
 
         # batched form: 64 views (log-uniform 128..2048 px, 1k..500k triangles)
         # in one autotuned hipGraph frame vs 64 sequential plain frames

@@ -149,7 +149,7 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     L.pairs = off; off = up(off + (size_t)L.cap * 12);   // Pairs: tile, slot, entry arrays
     L.lists = off; off = up(off + (size_t)L.cap * 4);
     L.gacc = off; off = up(off + (size_t)gacc * 4);
-    L.pacc = off; off = up(off + (size_t)PR_MAX_VIEWS * kPoseAcc * 8);
+    L.pacc = off; off = up(off + ((size_t)pix_blocks + 1) * kPoseAcc * 8);   // per pixel block (backward)
     L.sched = off; off = up(off + sizeof(Sched));
     L.order = off; off = up(off + (size_t)tiles * 16);
     L.bytes = off;
@@ -424,13 +424,13 @@ int pr_backward(const pr_mesh *meshes, int nm, const pr_view *views, int nv, con
         }
     }
     fill_u32(at<void>(ws, L.gacc), 0u, L.total_gacc, s);
-    fill_u32(at<void>(ws, L.pacc), 0u, (int64_t)PR_MAX_VIEWS * kPoseAcc * 2, s);
     hipLaunchKernelGGL(k_view_light, dim3(1), dim3(64), 0, s, T, *light);
     hipLaunchKernelGGL(k_bwd_pixel, dim3(L.total_pix_blocks), dim3(256), 0, s, T, io, light->ambient,
                        at<float>(ws, L.gacc), at<double>(ws, L.pacc));
     if (L.total_vtx_blocks > 0)
         hipLaunchKernelGGL(k_bwd_vertex, dim3(L.total_vtx_blocks), dim3(256), 0, s, T, at<float>(ws, L.gacc), out);
-    hipLaunchKernelGGL(k_bwd_pose, dim3(1), dim3(64), 0, s, T, at<double>(ws, L.pacc), *light, dpose0, dpose1);
+    hipLaunchKernelGGL(k_bwd_pose, dim3(nv), dim3(kPoseThreads), 0, s, T, at<double>(ws, L.pacc), *light, dpose0,
+                       dpose1);
     return launched();
 }
 

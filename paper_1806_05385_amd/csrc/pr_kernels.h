@@ -92,7 +92,8 @@ struct ViewDev {
     prg::Geom g;           // FP64 camera geometry (written by k_write_views)
 };
 
-// Per-view backward partial sums (FP64): [0..2] sum (1-t) dL/dLw,
+// Backward partial sums (FP64) of one pixel block, stored per block and
+// added per view by k_bwd_pose: [0..2] sum (1-t) dL/dLw,
 // [3..5] sum t dL/dLw (light direction before normalisation), [6..8] dL/dT0,
 // [9..17] dL/dR0 (vertex part), [18..20] dL/dT1, [21..29] dL/dR1, 2 pad.
 constexpr int kPoseAcc = 32;

@@ -1306,8 +1306,24 @@ __device__ __forceinline__ void pixel_setup_d(const prg::Geom &g, int px, int py
 // grazing incidence (ray almost in the triangle's plane) the barycentric
 // terms scale like 1/S^2 and FP32 rounding of the ray alone would move
 // them by 2^-24 / cos(incidence).
+// Vertex gradients of a block's pixels are summed per vertex in an LDS
+// table (open addressing on the vertex index, kBwdProbe probes) and added to
+// the global accumulators once per vertex and block; a pixel whose vertex
+// finds no entry adds directly.
+constexpr int kBwdHashBits = 9;
+constexpr int kBwdHash = 1 << kBwdHashBits;
+constexpr int kBwdProbe = 8;
+
 __global__ __launch_bounds__(256) void k_bwd_pixel(const ViewTable *__restrict__ T, BwdIO io, float ka,
-                                                   float *__restrict__ gacc, double *__restrict__ pacc) {
+                                                   float *__restrict__ gacc, double *__restrict__ pblk) {
+    __shared__ int32_t s_vkey[kBwdHash];
+    __shared__ float s_vg[kBwdHash][7];   // start xyz, end xyz (odd stride)
+    __shared__ double s_pp[4][30];
+    for (int e = threadIdx.x; e < kBwdHash; e += 256) {
+        s_vkey[e] = -1;
+        for (int c = 0; c < 6; ++c) s_vg[e][c] = 0.0f;
+    }
+    __syncthreads();
     const int v = find_view(T->pix_block0, T->nv, blockIdx.x);
     const ViewDev &vd = T->v[v];
     const prg::Geom &g = vd.g;
@@ -1411,11 +1427,27 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(const ViewTable *__restrict__
         }
         float *gs_ = gacc + vd.gacc_off;
         float *ge_ = gs_ + 3 * (int64_t)vd.mesh.nv;
-        for (int k = 0; k < 3; ++k)
-            for (int q = 0; q < 3; ++q) {
-                atomicAdd(&gs_[3 * (int64_t)vi[k] + q], (float)((1.0 - t) * gP[k][q]));
-                atomicAdd(&ge_[3 * (int64_t)vi[k] + q], (float)(t * gP[k][q]));
+        for (int k = 0; k < 3; ++k) {
+            int h = (int)(((uint32_t)vi[k] * 2654435761u) >> (32 - kBwdHashBits)), slot = -1;
+            for (int probe = 0; probe < kBwdProbe; ++probe) {
+                const int old = atomicCAS(&s_vkey[h], -1, vi[k]);
+                if (old == -1 || old == vi[k]) {
+                    slot = h;
+                    break;
+                }
+                h = (h + 1) & (kBwdHash - 1);
             }
+            for (int q = 0; q < 3; ++q) {
+                const float a = (float)((1.0 - t) * gP[k][q]), b = (float)(t * gP[k][q]);
+                if (slot >= 0) {
+                    atomicAdd(&s_vg[slot][q], a);
+                    atomicAdd(&s_vg[slot][3 + q], b);
+                } else {
+                    atomicAdd(&gs_[3 * (int64_t)vi[k] + q], a);
+                    atomicAdd(&ge_[3 * (int64_t)vi[k] + q], b);
+                }
+            }
+        }
         // Pose partials of this pixel: dL/dT = sum_k w gP_k = w gd and
         // dL/dR = sum_k w gP_k v_k^T = w (gd v_0^T + gE1 (v_1 - v_0)^T +
         // gE2 (v_2 - v_0)^T), w = 1-t (start) or t (end).
@@ -1431,11 +1463,29 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(const ViewTable *__restrict__
             }
         }
     }
-    // pose and light partials: FP64 wave sums, one FP64 atomic per wave and value
+    // pose and light partials: FP64 wave sums, then the block's sums stored
+    // (k_bwd_pose adds the blocks of each view)
     for (int q = 0; q < 30; ++q) {
         double x = part[q];
         for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-        if (__lane_id() == 0 && x != 0.0) atomicAdd(&pacc[kPoseAcc * v + q], x);
+        if (__lane_id() == 0) s_pp[threadIdx.x >> 6][q] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < kPoseAcc) {
+        const int q = threadIdx.x;
+        pblk[(int64_t)blockIdx.x * kPoseAcc + q] =
+            q < 30 ? ((s_pp[0][q] + s_pp[1][q]) + s_pp[2][q]) + s_pp[3][q] : 0.0;
+    }
+    // the block's vertex sums
+    float *gs_ = gacc + vd.gacc_off;
+    float *ge_ = gs_ + 3 * (int64_t)vd.mesh.nv;
+    for (int e = threadIdx.x; e < kBwdHash; e += 256) {
+        const int key = s_vkey[e];
+        if (key < 0) continue;
+        for (int q = 0; q < 3; ++q) {
+            atomicAdd(&gs_[3 * (int64_t)key + q], s_vg[e][q]);
+            atomicAdd(&ge_[3 * (int64_t)key + q], s_vg[e][3 + q]);
+        }
     }
 }
 
@@ -1461,12 +1511,38 @@ __global__ __launch_bounds__(256) void k_bwd_vertex(const ViewTable *__restrict_
 
 // Per view: dL/dR = vertex part + light part (sum (1-t) dL/dLw) l^T, then the
 // rotation-vector gradient through Rodrigues' Jacobian.
-__global__ void k_bwd_pose(const ViewTable *__restrict__ T, const double *__restrict__ pacc, pr_light light,
-                           float *__restrict__ dpose0, float *__restrict__ dpose1) {
-    const int v = threadIdx.x;
+// One block per view: the view's pixel blocks' partial sums are added (in a
+// fixed order: deterministic), then turned into the pose gradients.
+constexpr int kPoseThreads = 1024;
+
+__global__ __launch_bounds__(kPoseThreads) void k_bwd_pose(const ViewTable *__restrict__ T,
+                                                           const double *__restrict__ pblk, pr_light light,
+                                                           float *__restrict__ dpose0, float *__restrict__ dpose1) {
+    constexpr int kRows = kPoseThreads / kPoseAcc;   // blocks read at once
+    __shared__ double s_w[kPoseThreads];
+    __shared__ double a[kPoseAcc];
+    const int v = blockIdx.x;
     if (v >= T->nv) return;
     const ViewDev &vd = T->v[v];
-    const double *a = pacc + kPoseAcc * v;
+    const int b0 = T->pix_block0[v], b1 = T->pix_block0[v + 1];
+    // thread t adds value t % 32 of blocks b0 + t / 32, + kRows, ... with
+    // four independent partial sums (coalesced: the view's partials are read
+    // as one array)
+    const int q = threadIdx.x & (kPoseAcc - 1);
+    double x[4] = {0.0, 0.0, 0.0, 0.0};
+    int b = b0 + (int)(threadIdx.x / kPoseAcc);
+    for (; b + 3 * kRows < b1; b += 4 * kRows)
+        for (int k = 0; k < 4; ++k) x[k] += pblk[(int64_t)(b + k * kRows) * kPoseAcc + q];
+    for (; b < b1; b += kRows) x[0] += pblk[(int64_t)b * kPoseAcc + q];
+    s_w[threadIdx.x] = (x[0] + x[1]) + (x[2] + x[3]);
+    __syncthreads();
+    if (threadIdx.x < kPoseAcc) {
+        double y = 0.0;
+        for (int k = 0; k < kRows; ++k) y += s_w[k * kPoseAcc + q];
+        a[q] = y;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     const double lw[3] = {light.dir_world[0], light.dir_world[1], light.dir_world[2]};
     for (int e = 0; e < 2; ++e) {
         double gR[9];

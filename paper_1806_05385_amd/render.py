@@ -165,12 +165,12 @@ class Renderer:
                                                         ctypes.byref(st), ctypes.c_void_p(_stream_handle())))
         return st
 
-    def frame(self, shade: bool = True, check: bool = True):
+    def frame(self, shade: bool = True, check: bool = True, rgb32: bool = True):
         for _ in range(4):
             self.bound()
             self.bin()
             if shade:
-                self.raycast_shade()
+                self.raycast_shade(rgba8=True, rgb32=rgb32)
             else:
                 self.raycast()
             if not check:
