@@ -10,17 +10,19 @@
 //   k_tiles    four lanes per tile: display box of its pixel centres (and of
 //              each quadrant's) and its frame-time window
 //   k_bin      one block per 256 triangles: every (triangle, tile) candidate
-//              of the block's rectangles tested conservatively, survivors
-//              compacted with one reservation per round and a slot in their
-//              tile's list
-//   k_scan_*   exclusive scan of per-tile counts (three phases)
+//              of the block's rectangles tested conservatively; the round's
+//              survivors counted per tile in LDS take their list places with
+//              one global atomic per tile
+//   k_scan_*   exclusive scan of per-tile counts
 //   k_scatter  pairs -> per-tile triangle lists
-//   k_raycast  one four-wave block per tile: every pixel's ray (foveated
-//              position, rolling time) tested against the triangles of the
-//              tile's list, read as wave-uniform scalar loads; nearest packed
-//              (depth bits << 32 | id) kept in registers (Sec. 3.2
-//              "Intersection")
+//   k_raycast  one wave per 8x8 cell: every pixel's ray (foveated position,
+//   (_queue)   rolling time) tested against the cell's triangles of the tile
+//              list on the matrix cores, four triangles x 64 pixels per
+//              group; nearest packed (depth bits << 32 | id) kept in
+//              registers (Sec. 3.2 "Intersection"); the persistent form
+//              walks the tiles longest list first and may shade each cell
 //   k_shade    rolling Lambert shading of resolved ids (Sec. 3.2 "Shading")
+//   k_bwd_*    frozen-visibility gradient of the shaded image
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
