@@ -217,16 +217,12 @@ void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, c
                                light);
         return;
     }
-    Sched *S = at<Sched>(ws, L.sched);
-    const int nb = (L.total_tiles + 255) / 256;
-    hipLaunchKernelGGL(k_sched_scatter, dim3(nb), dim3(256), 0, s, T, at<uint32_t>(ws, L.toff), L.total_tiles, S,
-                       at<int4>(ws, L.order), st);
     static int resident = 0;
     if (!resident) resident = resident_blocks(k_raycast_queue<TILE, COUNT, SHADE>, C::NT);
     const int nitems = ray_items<TILE>(L.total_tiles);
     const int grid = std::max(1, std::min(nitems, resident));
     hipLaunchKernelGGL((k_raycast_queue<TILE, COUNT, SHADE>), dim3(grid), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
-                       at<uint32_t>(ws, L.lists), out, st, at<int4>(ws, L.order), nitems, S, sio, light);
+                       at<uint32_t>(ws, L.lists), out, st, at<int4>(ws, L.order), nitems, sio, light);
 }
 
 template <int TILE, bool SHADE>
@@ -327,9 +323,13 @@ int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
                        at<uint32_t>(ws, L.part));
     hipLaunchKernelGGL(k_scan_apply, dim3(L.nparts), dim3(256), 0, s, at<uint32_t>(ws, L.tcount), n, L.total_tiles,
                        at<uint32_t>(ws, L.part), at<uint32_t>(ws, L.toff), at<Sched>(ws, L.sched));
+    // pairs (grid-stride) and the persistent ray cast's tile order (one
+    // block per 256 tiles)
     int sb = (int)std::min<int64_t>(std::max<int64_t>((L.cap + 255) / 256, 1), 2048);
-    hipLaunchKernelGGL(k_scatter, dim3(sb), dim3(256), 0, s, pairs_at(L, ws), at<uint32_t>(ws, L.toff),
-                       at<int32_t>(ws, L.lists), L.cap, L.total_tiles, st);
+    sb = std::max(sb, (L.total_tiles + 255) / 256);
+    hipLaunchKernelGGL(k_scatter, dim3(sb), dim3(256), 0, s, T, pairs_at(L, ws), at<uint32_t>(ws, L.toff),
+                       at<int32_t>(ws, L.lists), L.cap, L.total_tiles, st, at<Sched>(ws, L.sched),
+                       at<int4>(ws, L.order));
     return launched();
 }
 

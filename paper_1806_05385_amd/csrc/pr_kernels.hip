@@ -739,15 +739,53 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
 // ---------------------------------------------------------------------------
 // scatter pairs into tile lists (slot order within a list is arbitrary)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_scatter(Pairs pairs, const uint32_t *__restrict__ toff,
-                                                 int32_t *__restrict__ lists, int64_t cap, int ntiles,
-                                                 DevStatus *__restrict__ st) {
+// A tile as the ray cast takes it: global tile, view, list begin and end
+// (x < 0: none).
+__device__ __forceinline__ int4 tile_rec(const ViewTable *__restrict__ T, const uint32_t *__restrict__ toff,
+                                         int gt, bool ovf) {
+    const int v = find_view(T->tile_base, T->nv, gt);
+    return ovf ? make_int4(gt, v, 0, 0) : make_int4(gt, v, (int)toff[gt], (int)toff[gt + 1]);
+}
+
+// Pairs -> lists.  Blocks below ceil(ntiles / 256) also write the tile
+// order of the persistent ray cast: longest lists first, by power-of-two
+// length bucket (counting sort on the histogram k_scan_apply built; S->cursor
+// cleared by k_tiles).
+__global__ __launch_bounds__(256) void k_scatter(const ViewTable *__restrict__ T, Pairs pairs,
+                                                 const uint32_t *__restrict__ toff, int32_t *__restrict__ lists,
+                                                 int64_t cap, int ntiles, DevStatus *__restrict__ st,
+                                                 Sched *__restrict__ S, int4 *__restrict__ order) {
     const int64_t n = (int64_t)st->pairs_required;
+    const bool ovf = n > cap;   // overflow: the ray cast writes misses
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->pairs_total = toff[ntiles];
-        if (n > cap) st->overflow = 1;
+        if (ovf) st->overflow = 1;
     }
-    if (n > cap) return;   // overflow: the ray cast writes misses
+    if (blockIdx.x < (ntiles + 255) / 256) {
+        __shared__ uint32_t h[kBuckets], base[kBuckets], first[kBuckets];
+        if (threadIdx.x == 0) {
+            uint32_t sum = 0;
+            for (int b = kBuckets - 1; b >= 0; --b) {   // longest lists first
+                first[b] = sum;
+                sum += S->count[b];
+            }
+        }
+        if (threadIdx.x < kBuckets) h[threadIdx.x] = 0u;
+        __syncthreads();
+        const int i = blockIdx.x * 256 + threadIdx.x;
+        int b = 0;
+        uint32_t rank = 0;
+        if (i < ntiles) {
+            b = len_bucket(toff[i + 1] - toff[i]);
+            rank = atomicAdd(&h[b], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < kBuckets && h[threadIdx.x])
+            base[threadIdx.x] = first[threadIdx.x] + atomicAdd(&S->cursor[threadIdx.x], h[threadIdx.x]);
+        __syncthreads();
+        if (i < ntiles) order[base[b] + rank] = tile_rec(T, toff, i, ovf);
+    }
+    if (ovf) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t tile = pairs.tile[i];
         if (tile >= 0) lists[toff[tile] + pairs.slot[i]] = (int32_t)pairs.entry[i];
@@ -1096,14 +1134,6 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
     }
 }
 
-// A tile as the ray cast takes it: global tile, view, list begin and end
-// (x < 0: none).
-__device__ __forceinline__ int4 tile_rec(const ViewTable *__restrict__ T, const uint32_t *__restrict__ toff,
-                                         int gt, bool ovf) {
-    const int v = find_view(T->tile_base, T->nv, gt);
-    return ovf ? make_int4(gt, v, 0, 0) : make_int4(gt, v, (int)toff[gt], (int)toff[gt + 1]);
-}
-
 // The wave's tile index of a block item: 8x8 tiles: four tiles per item;
 // 16x16: one; 32x32: one quadrant of a tile per item.
 template <int TILE>
@@ -1178,51 +1208,14 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
 // ---------------------------------------------------------------------------
 // persistent ray cast over a longest-list-first tile queue
 // ---------------------------------------------------------------------------
-// Tiles are ordered by list length, longest first, in power-of-two buckets
-// (a counting sort: per-block histograms in LDS, one global atomic per
-// block and bucket); a grid sized to the device's resident blocks then walks
-// the order with a static stride, so the longest lists start first.
-// Tile order of the persistent ray cast: longest lists first, by
-// power-of-two length bucket (counting sort on the histogram k_scan_apply
-// built; S->cursor is zero on entry: cleared by k_tiles and again by each
-// k_raycast_queue).
-__global__ __launch_bounds__(256) void k_sched_scatter(const ViewTable *__restrict__ T, const uint32_t *__restrict__ toff,
-                                                       int n, Sched *__restrict__ S, int4 *__restrict__ order,
-                                                       const DevStatus *__restrict__ st) {
-    __shared__ uint32_t h[kBuckets], base[kBuckets], first[kBuckets];
-    if (threadIdx.x == 0) {
-        uint32_t sum = 0;
-        for (int b = kBuckets - 1; b >= 0; --b) {   // longest lists first
-            first[b] = sum;
-            sum += S->count[b];
-        }
-    }
-    if (threadIdx.x < kBuckets) h[threadIdx.x] = 0u;
-    __syncthreads();
-    int i = blockIdx.x * 256 + threadIdx.x;
-    int b = 0;
-    uint32_t rank = 0;
-    if (i < n) {
-        b = len_bucket(toff[i + 1] - toff[i]);
-        rank = atomicAdd(&h[b], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x < kBuckets && h[threadIdx.x])
-        base[threadIdx.x] = first[threadIdx.x] + atomicAdd(&S->cursor[threadIdx.x], h[threadIdx.x]);
-    __syncthreads();
-    if (i < n) order[base[b] + rank] = tile_rec(T, toff, i, st->overflow != 0);
-}
-
-// Six waves per SIMD (80 VGPRs, a few spilled) run faster than five.
+// A grid sized to the device's resident blocks walks the longest-first tile
+// order (written by k_scatter) with a static stride, so the longest lists
+// start first.
 template <int TILE, bool COUNT, bool SHADE>
 __global__ __launch_bounds__((RayCfg<TILE>::NT)) __attribute__((amdgpu_waves_per_eu(6))) void k_raycast_queue(
     const ViewTable *__restrict__ T, const float4 *__restrict__ rec, const uint32_t *__restrict__ lists, RayOut out,
-    DevStatus *__restrict__ st, const int4 *__restrict__ order, int nitems, Sched *__restrict__ S, ShadeIO sio,
-    pr_light light) {
+    DevStatus *__restrict__ st, const int4 *__restrict__ order, int nitems, ShadeIO sio, pr_light light) {
     __shared__ int32_t s_sel[4 * kSelCap];
-    // k_sched_scatter has finished with the bucket cursors: clear them for
-    // the next ray cast over the same lists (k_tiles clears them per frame)
-    if (blockIdx.x == 0 && threadIdx.x < kBuckets) S->cursor[threadIdx.x] = 0u;
     // block b takes items b, b + grid, b + 2 grid, ... of the longest-first
     // order (the first round holds the longest lists, no queue atomics).
     // While an item is cast, the tile record two items ahead and the first
