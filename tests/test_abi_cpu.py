@@ -76,6 +76,22 @@ def test_workspace_size_and_argument_checks():
     assert L.pr_workspace_size(nullmesh, 1, views, 1, ctypes.byref(tu), ctypes.byref(size)) == B.PR_ERR_INVALID
 
 
+def test_triangle_count_limit():
+    """A view's records (176 B each) are addressed with 32-bit byte offsets:
+    the largest accepted mesh has 24,403,223 triangles (records < 4 GiB); one
+    more is rejected before anything is allocated or launched."""
+    L = B.lib()
+    _, views, tu, _ = _frame()
+    size = ctypes.c_size_t(0)
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced by pr_workspace_size
+    for nt, want in ((24_403_223, B.PR_OK), (24_403_224, B.PR_ERR_INVALID), (1 << 28, B.PR_ERR_INVALID)):
+        mesh = (B.PrMesh * 1)(B.PrMesh(fake, fake, fake, 100, nt))
+        assert L.pr_workspace_size(mesh, 1, views, 1, ctypes.byref(tu), ctypes.byref(size)) == want, nt
+    mesh = (B.PrMesh * 1)(B.PrMesh(fake, fake, fake, 100, 24_403_223))
+    L.pr_workspace_size(mesh, 1, views, 1, ctypes.byref(tu), ctypes.byref(size))
+    assert size.value > 24_403_223 * (96 + 64)   # static records (this view rolls not) + triangle bounds
+
+
 def test_calls_reject_bad_workspace_before_launch():
     """Workspace and pointer checks run on the host before any HIP call, so
     they answer the same with or without a GPU."""
