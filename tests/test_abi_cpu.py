@@ -89,7 +89,7 @@ def test_triangle_count_limit():
         assert L.pr_workspace_size(mesh, 1, views, 1, ctypes.byref(tu), ctypes.byref(size)) == want, nt
     mesh = (B.PrMesh * 1)(B.PrMesh(fake, fake, fake, 100, 24_403_223))
     L.pr_workspace_size(mesh, 1, views, 1, ctypes.byref(tu), ctypes.byref(size))
-    assert size.value > 24_403_223 * (96 + 64)   # static records (this view rolls not) + triangle bounds
+    assert size.value > 24_403_223 * (96 + 64)   # static view: 96-byte records, 64-byte bounds
 
 
 def test_calls_reject_bad_workspace_before_launch():
