@@ -739,12 +739,14 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
 // ---------------------------------------------------------------------------
 // scatter pairs into tile lists (slot order within a list is arbitrary)
 // ---------------------------------------------------------------------------
-// A tile as the ray cast takes it: global tile, view, list begin and end
-// (x < 0: none).
+// A tile as the ray cast takes it: tile coordinates in its view (tx | ty <<
+// 16), view, list begin and end (x < 0: none).
 __device__ __forceinline__ int4 tile_rec(const ViewTable *__restrict__ T, const uint32_t *__restrict__ toff,
                                          int gt, bool ovf) {
     const int v = find_view(T->tile_base, T->nv, gt);
-    return ovf ? make_int4(gt, v, 0, 0) : make_int4(gt, v, (int)toff[gt], (int)toff[gt + 1]);
+    const int lt = gt - T->v[v].tile_base, tx = lt % T->v[v].tiles_x, ty = lt / T->v[v].tiles_x;
+    const int xy = tx | (ty << 16);   // tile coordinates in the view (below 2^16)
+    return ovf ? make_int4(xy, v, 0, 0) : make_int4(xy, v, (int)toff[gt], (int)toff[gt + 1]);
 }
 
 // Pairs -> lists.  Blocks below ceil(ntiles / 256) also write the tile
@@ -803,7 +805,7 @@ __device__ __forceinline__ void pixel_setup(const PixelConst &pc, int px, int py
     float d0 = y0 - pc.fov0, d1 = y1 - pc.fov1;
     float s = 1.0f;
     if (pc.mode != 0) {
-        float rho = sqrtf(d0 * d0 + d1 * d1);
+        float rho = __builtin_amdgcn_sqrtf(d0 * d0 + d1 * d1);   // hardware square root (1 ulp)
         s = pc.mode == 1 ? rho * pc.invR : (rho > 0.0f ? powf(rho * pc.invR, pc.alpha - 1.0f) : 0.0f);
     }
     float x0 = pc.fov0 + d0 * s, x1 = pc.fov1 + d1 * s;
@@ -1156,10 +1158,9 @@ __device__ __forceinline__ void raycast_item(const ViewTable *__restrict__ T, co
                                              int32_t *s_sel_block, const ShadeIO *sio, const pr_light *light) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (tr.x < 0) return;
-    const int gt = tr.x, v = tr.y;
+    const int v = tr.y;
     const ViewDev &vd = T->v[v];
-    const int lt = gt - vd.tile_base;
-    const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
+    const int tx = tr.x & 0xFFFF, ty = tr.x >> 16;
     int cx0 = tx * TILE, cy0 = ty * TILE, q = -1;
     if (TILE == 16) {
         q = wv;
