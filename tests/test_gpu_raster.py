@@ -61,6 +61,28 @@ def test_moving_soup_full_frame(alpha, roll, fovea, tile):
     _full_parity(sc, tile)
 
 
+@pytest.mark.parametrize('tile', [8, 16, 32])
+def test_screen_filling_triangles_full_frame(tile):
+    """A soup plus four triangles that each cover the whole image (thousands
+    of tiles): the binning block holding them runs several rounds, and one
+    round's survivors fall on more distinct tiles than its LDS table holds
+    (the overflow path of the per-tile counting)."""
+    sc = scenegen.make_moving_soup(seed=35, n_tris=300, width=1024, height=768, alpha=2.0, roll=(1.0, 0.0),
+                                   yaw_deg_s=500.0, obj_speed=5.0, side=(0.03, 0.4))
+    m = sc.meshes[0]
+    big = np.array([[-30, -30, 6.0], [30, -30, 6.0], [0, 30, 6.0],
+                    [-30, -30, 3.0], [30, -30, 9.0], [-30, 30, 9.0],
+                    [30, 30, 2.5], [-30, 30, 12.0], [30, -30, 12.0],
+                    [-30, 0, 4.0], [30, 10, 4.5], [0, -30, 5.0]], np.float32)
+    nv = m.v0.shape[0]
+    v0 = np.concatenate([m.v0, big])
+    v1 = np.concatenate([m.v1, big + np.float32([0.05, 0.0, 0.0])])
+    tri = np.concatenate([m.tri, nv + np.arange(12, dtype=np.int32).reshape(4, 3)])
+    alb = np.concatenate([m.albedo, np.full((12, 3), 0.5, np.float32)])
+    sc2 = scenegen.Scene('big', [scenegen.Mesh(v0, v1, tri, alb)], sc.views)
+    _full_parity(sc2, tile)
+
+
 def test_hmd_reduced_full_frame():
     """The HMD workload's recipe at reduced size (sphere f=24, 60 boxes,
     2 eyes at 302x336), brute force over every pixel."""
