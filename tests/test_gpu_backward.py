@@ -42,10 +42,14 @@ def _close(g, ref, floor_frac=1e-3):
 
 
 def _case(size, f):
+    sc = scenegen.make_grad(seed=5, size=size, f=f)
+    return _case_scene(sc, sc.extra['target'])
+
+
+def _case_scene(sc, target):
     torch = _torch()
     from paper_1806_05385_amd.render import Renderer
-    sc = scenegen.make_grad(seed=5, size=size, f=f)
-    mesh, view, target = sc.meshes[0], sc.views[0], sc.extra['target']
+    mesh, view = sc.meshes[0], sc.views[0]
     light = oracle.light_block(sc)
     orc_t = oracle.Oracle(target, view)
     tgt = orc_t.shade(orc_t.render()['id'], light)
@@ -70,11 +74,31 @@ def _case(size, f):
                 r=r, sc=sc, oid=oid, tgt=tgt, near=near)
 
 
-@pytest.mark.parametrize('size,f', [(96, 16), (512, 71)])
-def test_gradients_match_fp64_reference(size, f):
-    """(96, f=16): small; (512, f=71): the differentiation workload at full
-    size (100,820 triangles, 512x512, rolling + foveated, moving camera)."""
-    c = _case(size, f)
+def _soup_case():
+    """40,000 disjoint triangles of about one pixel (own vertices each) over
+    64x64: a block of 256 pixels sees up to 234 distinct triangles (702
+    vertices), more than the backward's 512-entry LDS table holds, so part
+    of its vertex gradients take the direct-atomic path."""
+    sc = scenegen.make_moving_soup(seed=36, n_tris=40000, width=64, height=64, alpha=2.0, roll=(1.0, 0.0),
+                                   yaw_deg_s=300.0, obj_speed=2.0, side=(0.05, 0.12),
+                                   centre_lo=(-2.0, -2.0, 2.0), centre_hi=(2.0, 2.0, 3.0))
+    m = sc.meshes[0]
+    rng = np.random.default_rng(37)
+    noise = rng.normal(0.0, 0.003, size=m.v0.shape).astype(np.float32)
+    target = scenegen.Mesh(m.v0 + noise, m.v1 + noise, m.tri, m.albedo)
+    return _case_scene(sc, target)
+
+
+@pytest.mark.parametrize('case', ['grad96', 'grad512', 'soup64'])
+def test_gradients_match_fp64_reference(case):
+    """grad96 (f=16, 96x96): small; grad512 (f=71, 512x512): the
+    differentiation workload at full size (100,820 triangles, rolling +
+    foveated, moving camera); soup64: see _soup_case."""
+    c = {'grad96': lambda: _case(96, 16), 'grad512': lambda: _case(512, 71), 'soup64': _soup_case}[case]()
+    if case == 'soup64':
+        ids, tri = c['oid'], c['sc'].meshes[0].tri
+        most = max(len(np.unique(tri[seg[seg >= 0]])) for seg in np.split(ids, len(ids) // 256))
+        assert most > 512, most
     assert abs(c['gpu_L'] - c['L']) <= 1e-4 * c['L']
     for name, g, ref in [('dv0', c['dv0'], c['g0']), ('dv1', c['dv1'], c['g1']),
                          ('dpose0', c['dp0'], c['gp0']), ('dpose1', c['dp1'], c['gp1'])]:
