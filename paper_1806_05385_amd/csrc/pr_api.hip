@@ -315,7 +315,7 @@ int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
                        at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<Sched>(ws, L.sched),
                        at<int32_t>(ws, L.bcand), at<int32_t>(ws, L.boff), at<uint32_t>(ws, L.bpart), st);
     if (L.total_tri_blocks > 0)
-        hipLaunchKernelGGL(k_bin, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<TriBound>(ws, L.tb),
+        hipLaunchKernelGGL(k_bin, dim3(L.total_tri_blocks), dim3(kBinThreads), 0, s, T, at<TriBound>(ws, L.tb),
                            at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<int32_t>(ws, L.boff),
                            at<uint32_t>(ws, L.bpart), pairs_at(L, ws), L.cap);
     int n = L.total_tiles + 1;

@@ -485,8 +485,11 @@ __device__ __forceinline__ void bin_step(BinCursor &c, const ViewDev &vd, const 
 // every thread `per` consecutive candidates, per = ceil(candidates / 256) up
 // to kBinPer, tested in FP32 against the tile's FP32 boxes.
 constexpr int kBinTris = 256;
+// threads of a binning block: the triangles' records are built by the
+// first kBinTris, the candidates are shared by all
+constexpr int kBinThreads = 512;
 
-__global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, const TriBound *__restrict__ tb,
+__global__ __launch_bounds__(kBinThreads) void k_bin(const ViewTable *__restrict__ T, const TriBound *__restrict__ tb,
                                              const TileInfo *__restrict__ ti, uint32_t *__restrict__ tcount,
                                              const int32_t *__restrict__ boff, const uint32_t *__restrict__ bpart,
                                              Pairs pairs, int64_t cap) {
@@ -500,7 +503,7 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
     __shared__ int32_t s_hkey[kBinHash];
     __shared__ uint32_t s_hcnt[kBinHash], s_hbase[kBinHash];
     const int j = threadIdx.x;
-    for (int e = j; e < kBinHash; e += 256) {
+    for (int e = j; e < kBinHash; e += kBinThreads) {
         s_hkey[e] = -1;
         s_hcnt[e] = 0u;
     }
@@ -514,7 +517,7 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
             // (FP64, once per triangle)
             const int f = f0 + j;
             int cnt = 0;
-            if (f < vd.mesh.nt) {
+            if (j < kBinTris && f < vd.mesh.nt) {
                 const TriBound b = tb[vd.tri_off + f];
                 if (b.kind != prg::kCulled && b.rect[0] <= b.rect[2] && b.rect[1] <= b.rect[3]) {
                     cnt = (b.rect[2] - b.rect[0] + 1) * (b.rect[3] - b.rect[1] + 1);
@@ -533,20 +536,20 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
             }
             int total;
             const int ex = block_excl_scan(cnt, s_tmp, total);
-            s_pref[j] = ex;
+            if (j < kBinTris) s_pref[j] = ex;
             if (j == kBinTris - 1) s_pref[kBinTris] = total;
         }
         // the block's first candidate slot: its offset in its chunk of 256
         // blocks plus the totals of the chunks before
         int cpre = 0;
-        for (int i = j; i < (int)(blockIdx.x >> 8); i += 256) cpre += (int)bpart[i];
+        for (int i = j; i < (int)(blockIdx.x >> 8); i += kBinThreads) cpre += (int)bpart[i];
         int ctot;
         block_excl_scan(cpre, s_tmp, ctot);
         const int64_t s_off = (int64_t)boff[blockIdx.x] + ctot;
         const int total = s_pref[kBinTris];
-        const int per = min(kBinPer, max(1, (total + 255) >> 8));
+        const int per = min(kBinPer, max(1, (total + kBinThreads - 1) / kBinThreads));
         const bool split = prg::split_quads(vd.tile);
-        for (int c0 = 0; c0 < total; c0 += 256 * per) {
+        for (int c0 = 0; c0 < total; c0 += kBinThreads * per) {
             const int my0 = c0 + j * per;
             const int myn = max(0, min(per, total - my0));
             int q0 = 0, l0 = 0;
@@ -640,18 +643,18 @@ __global__ __launch_bounds__(256) void k_bin(const ViewTable *__restrict__ T, co
             {
                 // one global atomic per used entry (issued together), then
                 // the entry is cleared for the next round
-                constexpr int kPerThread = kBinHash / 256;
+                constexpr int kPerThread = kBinHash / kBinThreads;
                 uint32_t eb[kPerThread];
 #pragma unroll
                 for (int i = 0; i < kPerThread; ++i) {
-                    const int e = j + 256 * i;
+                    const int e = j + kBinThreads * i;
                     const int key = s_hkey[e];
                     eb[i] = 0u;
                     if (key >= 0) eb[i] = atomicAdd(&tcount[key], s_hcnt[e]);
                 }
 #pragma unroll
                 for (int i = 0; i < kPerThread; ++i) {
-                    const int e = j + 256 * i;
+                    const int e = j + kBinThreads * i;
                     if (s_hkey[e] >= 0) {
                         s_hbase[e] = eb[i];
                         s_hkey[e] = -1;
@@ -1234,6 +1237,15 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) __attribute__((amdgpu_waves_per
     while (item < nitems) {
         const int4 nx2 = fetch(item + 2 * G);
         const uint32_t enx = first_entries(lists, nx1);
+        // Waves of equal priority issue oldest first, so the blocks
+        // dispatched last fall behind and end up running alone; a wave in
+        // the first quarter of its items runs at priority 3, in the last at
+        // 0, so lagging waves are issued first and the grid drains evenly.
+        const int quarter = 4 * ((item - (int)blockIdx.x) / G) / ((nitems - 1 - (int)blockIdx.x) / G + 1);
+        if (quarter == 0) __builtin_amdgcn_s_setprio(3);
+        else if (quarter == 1) __builtin_amdgcn_s_setprio(2);
+        else if (quarter == 2) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
         raycast_item<TILE, COUNT, SHADE>(T, rec, lists, out, st, item, cur, ecur, s_sel, &sio, &light);
         item += G;
         cur = nx1;
