@@ -849,6 +849,13 @@ __device__ __forceinline__ void shade_pixel(const ViewDev &vd, const float4 *__r
                                             int id, float c[3]) {
     const PixelConst &pc = vd.pc;
     const float ambient = light.ambient;
+    // gathers first (vertex indices, then all nine albedo values), so their
+    // latencies overlap each other and the arithmetic below
+    int32_t vi[3];
+    for (int k = 0; k < 3; ++k) vi[k] = vd.mesh.tri[3 * (int64_t)id + k];
+    float a[3][3];
+    for (int k = 0; k < 3; ++k)
+        for (int ch = 0; ch < 3; ++ch) a[k][ch] = alb[3 * (int64_t)vi[k] + ch];
     float t, rx, ry;
     pixel_setup(pc, px, py, t, rx, ry);
     float ck[3][3], N[3];
@@ -873,9 +880,8 @@ __device__ __forceinline__ void shade_pixel(const ViewDev &vd, const float4 *__r
     float invS = 1.0f / S;
     c[0] = c[1] = c[2] = 0.0f;
     for (int k = 0; k < 3; ++k) {
-        int vi = vd.mesh.tri[3 * (int64_t)id + k];
         float mu = e[k] * invS;
-        for (int ch = 0; ch < 3; ++ch) c[ch] = fmaf(mu, alb[3 * (int64_t)vi + ch], c[ch]);
+        for (int ch = 0; ch < 3; ++ch) c[ch] = fmaf(mu, a[k][ch], c[ch]);
     }
     for (int ch = 0; ch < 3; ++ch) c[ch] *= s;
 }
@@ -889,12 +895,11 @@ __device__ __forceinline__ void store_shade(const ShadeIO &io, int v, int64_t p,
         o[3 * p + 2] = c[2];
     }
     if (io.rgba8[v]) {
-        uchar4 o;
-        o.x = (uint8_t)floorf(fminf(fmaxf(c[0], 0.0f), 1.0f) * 255.0f + 0.5f);
-        o.y = (uint8_t)floorf(fminf(fmaxf(c[1], 0.0f), 1.0f) * 255.0f + 0.5f);
-        o.z = (uint8_t)floorf(fminf(fmaxf(c[2], 0.0f), 1.0f) * 255.0f + 0.5f);
-        o.w = id >= 0 ? 255 : 0;
-        reinterpret_cast<uchar4 *>(io.rgba8[v])[p] = o;
+        // one 32-bit store of the four bytes (R in the lowest address)
+        uint32_t o = id >= 0 ? 0xFF000000u : 0u;
+        for (int ch = 0; ch < 3; ++ch)
+            o |= (uint32_t)floorf(fminf(fmaxf(c[ch], 0.0f), 1.0f) * 255.0f + 0.5f) << (8 * ch);
+        reinterpret_cast<uint32_t *>(io.rgba8[v])[p] = o;
     }
 }
 
