@@ -843,11 +843,11 @@ __device__ __forceinline__ void record_at(const ViewDev &vd, const float4 *__res
     }
 }
 
-// Rolling Lambert colour of triangle id (0 <= id < nt) at pixel (px, py).
-__device__ __forceinline__ void shade_pixel(const ViewDev &vd, const float4 *__restrict__ rec,
-                                            const float *__restrict__ alb, const pr_light &light, int px, int py,
-                                            int id, float c[3]) {
-    const PixelConst &pc = vd.pc;
+// Rolling Lambert colour of triangle id (0 <= id < nt) at a pixel whose
+// time and ray pixel_setup gave as (t, rx, ry).
+__device__ __forceinline__ void shade_pixel_at(const ViewDev &vd, const float4 *__restrict__ rec,
+                                               const float *__restrict__ alb, const pr_light &light, float t,
+                                               float rx, float ry, int id, float c[3]) {
     const float ambient = light.ambient;
     // gathers first (vertex indices, then all nine albedo values), so their
     // latencies overlap each other and the arithmetic below
@@ -856,8 +856,6 @@ __device__ __forceinline__ void shade_pixel(const ViewDev &vd, const float4 *__r
     float a[3][3];
     for (int k = 0; k < 3; ++k)
         for (int ch = 0; ch < 3; ++ch) a[k][ch] = alb[3 * (int64_t)vi[k] + ch];
-    float t, rx, ry;
-    pixel_setup(pc, px, py, t, rx, ry);
     float ck[3][3], N[3];
     record_at(vd, rec, id, t, ck, N);
     float e[3];
@@ -884,6 +882,15 @@ __device__ __forceinline__ void shade_pixel(const ViewDev &vd, const float4 *__r
         for (int ch = 0; ch < 3; ++ch) c[ch] = fmaf(mu, a[k][ch], c[ch]);
     }
     for (int ch = 0; ch < 3; ++ch) c[ch] *= s;
+}
+
+// Rolling Lambert colour of triangle id (0 <= id < nt) at pixel (px, py).
+__device__ __forceinline__ void shade_pixel(const ViewDev &vd, const float4 *__restrict__ rec,
+                                            const float *__restrict__ alb, const pr_light &light, int px, int py,
+                                            int id, float c[3]) {
+    float t, rx, ry;
+    pixel_setup(vd.pc, px, py, t, rx, ry);
+    shade_pixel_at(vd, rec, alb, light, t, rx, ry, id, c);
 }
 
 // The shaded outputs of pixel p of view v (id < 0: a miss, colour 0).
@@ -984,8 +991,8 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
     // B operands: ray terms kq and kq + 4 of pixel 16 b + jl of the cell.
     // Lane l sets up pixel l; the others fetch its (t, rx, ry).
     float bt0[4], bt1[4], tb[4];
+    float t, rx, ry;   // lane l's own pixel l (shaded by lane l at the end)
     {
-        float t, rx, ry;
         pixel_setup(pc, cx0 + (lane & 7), cy0 + (lane >> 3), t, rx, ry);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
@@ -1130,7 +1137,7 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
         out_depth[p] = miss ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(mine >> 32));
         if (SHADE) {
             float c[3] = {0.0f, 0.0f, 0.0f};
-            if (id >= 0) shade_pixel(vd, sa.rec, sa.io->albedo[sa.v], *sa.light, px, py, id, c);
+            if (id >= 0) shade_pixel_at(vd, sa.rec, sa.io->albedo[sa.v], *sa.light, t, rx, ry, id, c);
             store_shade(*sa.io, sa.v, p, c, id);
         }
     }
