@@ -29,7 +29,7 @@ struct Layout {
     ViewDev vd[PR_MAX_VIEWS];
     int total_tiles, total_tri_blocks, total_pix_blocks, total_vtx_blocks, nparts;
     int64_t cap, total_rec4, total_tris, total_gacc;
-    size_t table, tinfo, rec, tb, bcand, boff, bpart, tcount, toff, part, pairs, lists, gacc, pacc, sched, order, bytes;
+    size_t table, tinfo, rec, tb, bcand, bperm, boff, bpart, tcount, toff, part, pairs, lists, gacc, pacc, sched, order, bytes;
 };
 
 bool finite_all(const float *p, int n) {
@@ -141,6 +141,7 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     L.rec = off; off = up(off + (size_t)rec4 * sizeof(float4));
     L.tb = off; off = up(off + (size_t)tris * sizeof(TriBound));
     L.bcand = off; off = up(off + ((size_t)tri_blocks + 1) * 4);
+    L.bperm = off; off = up(off + ((size_t)tri_blocks + 1) * 4);
     L.boff = off; off = up(off + ((size_t)tri_blocks + 1) * 4);
     L.bpart = off; off = up(off + ((size_t)tri_blocks / 256 + 1) * 4);
     L.tcount = off; off = up(off + ((size_t)tiles + 1) * 4);
@@ -311,13 +312,16 @@ int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     PR_PREP();
     const int tile_blocks = ((L.total_tiles + 1) * 4 + 255) / 256;
     const int chunk_blocks = (L.total_tri_blocks + 255) / 256;
-    hipLaunchKernelGGL(k_tiles, dim3(std::max(tile_blocks, chunk_blocks)), dim3(256), 0, s, T,
+    // one block more than the tiles and chunks need: the last orders the
+    // binning blocks
+    hipLaunchKernelGGL(k_tiles, dim3(std::max(tile_blocks, chunk_blocks) + 1), dim3(256), 0, s, T,
                        at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<Sched>(ws, L.sched),
-                       at<int32_t>(ws, L.bcand), at<int32_t>(ws, L.boff), at<uint32_t>(ws, L.bpart), st);
+                       at<int32_t>(ws, L.bcand), at<int32_t>(ws, L.boff), at<uint32_t>(ws, L.bpart), st,
+                       at<int32_t>(ws, L.bperm));
     if (L.total_tri_blocks > 0)
         hipLaunchKernelGGL(k_bin, dim3(L.total_tri_blocks), dim3(kBinThreads), 0, s, T, at<TriBound>(ws, L.tb),
                            at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<int32_t>(ws, L.boff),
-                           at<uint32_t>(ws, L.bpart), pairs_at(L, ws), L.cap);
+                           at<uint32_t>(ws, L.bpart), pairs_at(L, ws), L.cap, at<int32_t>(ws, L.bperm));
     int n = L.total_tiles + 1;
     hipLaunchKernelGGL(k_scan_reduce, dim3(L.nparts), dim3(256), 0, s, at<uint32_t>(ws, L.tcount), n,
                        at<uint32_t>(ws, L.part));

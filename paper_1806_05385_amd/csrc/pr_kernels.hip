@@ -343,10 +343,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // in its quadrant's box), an unsplit tile's box is computed by lane 0.  The
 // kernel also clears the binning counters and scans the binning blocks'
 // candidate totals in chunks of 256 (grid: at least one block per chunk).
+// Binning blocks with at least this many candidates are dispatched first.
+constexpr int kHeavyCand = 1024;
+constexpr int kPermItems = 8;
+
 __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, TileInfo *__restrict__ ti,
                                                uint32_t *__restrict__ tcount, Sched *__restrict__ S, const int32_t *__restrict__ bcand,
                                                int32_t *__restrict__ boff, uint32_t *__restrict__ part,
-                                               DevStatus *__restrict__ st) {
+                                               DevStatus *__restrict__ st, int32_t *__restrict__ bperm) {
     __shared__ int s_tmp[72];
     const int gid = blockIdx.x * 256 + threadIdx.x;
     const int gt = gid >> 2, q = gid & 3;
@@ -369,6 +373,48 @@ __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, 
         if (threadIdx.x == 0) {
             part[blockIdx.x] = (uint32_t)tot;
             atomicAdd(&st->pairs_required, (unsigned long long)tot);
+        }
+    }
+    if (blockIdx.x == gridDim.x - 1) {
+        // (the grid's extra last block, which has no tiles and runs beside
+        // the others) Dispatch order of the binning blocks: the few with
+        // many candidates (large triangles near the eye) first, the others
+        // in index order; started last, the heavy ones would set the
+        // binning's end.  A stable partition: heavy block i goes to place
+        // (heavy blocks before it), light block i to nheavy + (light blocks
+        // before it).  One pass when the blocks fit one round of the scan
+        // (its total is then nheavy), else a counting pass first.
+        const int nb = T->total_tri_blocks;
+        int nheavy = 0;
+        for (int b0 = 0; nb > 256 * kPermItems && b0 < nb; b0 += 256 * kPermItems) {
+            const int i0 = b0 + (int)threadIdx.x * kPermItems;
+            int cnt = 0;
+#pragma unroll
+            for (int k = 0; k < kPermItems; ++k) cnt += i0 + k < nb && bcand[i0 + k] >= kHeavyCand;
+            int tot;
+            block_excl_scan(cnt, s_tmp, tot);
+            nheavy += tot;
+        }
+        int hbase = 0;
+        for (int b0 = 0; b0 < nb; b0 += 256 * kPermItems) {
+            const int i0 = b0 + (int)threadIdx.x * kPermItems;
+            bool fl[kPermItems];
+            int cnt = 0;
+#pragma unroll
+            for (int k = 0; k < kPermItems; ++k) {
+                fl[k] = i0 + k < nb && bcand[i0 + k] >= kHeavyCand;
+                cnt += fl[k];
+            }
+            int tot;
+            int hp = block_excl_scan(cnt, s_tmp, tot) + hbase;
+            if (nb <= 256 * kPermItems) nheavy = tot;
+#pragma unroll
+            for (int k = 0; k < kPermItems; ++k) {
+                const int i = i0 + k;
+                if (i < nb) bperm[fl[k] ? hp : nheavy + (i - hp)] = i;
+                hp += fl[k];
+            }
+            hbase += tot;
         }
     }
     const int v = find_view(T->tile_base, T->nv, valid ? gt : 0);
@@ -492,7 +538,7 @@ constexpr int kBinThreads = 512;
 __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewTable *__restrict__ T, const TriBound *__restrict__ tb,
                                              const TileInfo *__restrict__ ti, uint32_t *__restrict__ tcount,
                                              const int32_t *__restrict__ boff, const uint32_t *__restrict__ bpart,
-                                             Pairs pairs, int64_t cap) {
+                                             Pairs pairs, int64_t cap, const int32_t *__restrict__ bperm) {
     // odd row strides (33 and 5 words) keep lanes reading different
     // triangles on different LDS banks
     __shared__ uint32_t s_sat[kBinTris][33];
@@ -508,10 +554,11 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewTable *__restrict
         s_hcnt[e] = 0u;
     }
     {
-        const int v = find_view(T->tri_block0, T->nv, blockIdx.x);
+        const int bb = bperm[blockIdx.x];   // this block's 256 triangles (heavy blocks first)
+        const int v = find_view(T->tri_block0, T->nv, bb);
         const ViewDev &vd = T->v[v];
         const prg::Geom &g = vd.g;
-        const int f0 = (blockIdx.x - vd.tri_block0) * kBinTris;
+        const int f0 = (bb - vd.tri_block0) * kBinTris;
         {
             // one lane per triangle: its tile rectangle and its test record
             // (FP64, once per triangle)
@@ -542,10 +589,10 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewTable *__restrict
         // the block's first candidate slot: its offset in its chunk of 256
         // blocks plus the totals of the chunks before
         int cpre = 0;
-        for (int i = j; i < (int)(blockIdx.x >> 8); i += kBinThreads) cpre += (int)bpart[i];
+        for (int i = j; i < (bb >> 8); i += kBinThreads) cpre += (int)bpart[i];
         int ctot;
         block_excl_scan(cpre, s_tmp, ctot);
-        const int64_t s_off = (int64_t)boff[blockIdx.x] + ctot;
+        const int64_t s_off = (int64_t)boff[bb] + ctot;
         const int total = s_pref[kBinTris];
         const int per = min(kBinPer, max(1, (total + kBinThreads - 1) / kBinThreads));
         const bool split = prg::split_quads(vd.tile);
