@@ -344,7 +344,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // kernel also clears the binning counters and scans the binning blocks'
 // candidate totals in chunks of 256 (grid: at least one block per chunk).
 // Binning blocks with at least this many candidates are dispatched first.
-constexpr int kHeavyCand = 1024;
+constexpr int kHeavyCand = 512;
 constexpr int kPermItems = 8;
 
 __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, TileInfo *__restrict__ ti,
