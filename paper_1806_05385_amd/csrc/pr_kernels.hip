@@ -338,15 +338,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // ---------------------------------------------------------------------------
 // per-tile display boxes
 // ---------------------------------------------------------------------------
-// Four lanes per tile, lane q computing quadrant q's box; a split tile's box
-// is the union of its quadrants' boxes (every pixel centre of the tile lies
-// in its quadrant's box), an unsplit tile's box is computed by lane 0.  The
-// kernel also clears the binning counters and scans the binning blocks'
-// candidate totals in chunks of 256 (grid: at least one block per chunk).
 // Binning blocks with at least this many candidates are dispatched first.
 constexpr int kHeavyCand = 512;
 constexpr int kPermItems = 8;
 
+// Four lanes per tile, lane q computing quadrant q's box; a split tile's box
+// is the union of its quadrants' boxes (every pixel centre of the tile lies
+// in its quadrant's box), an unsplit tile's box is computed by lane 0.  The
+// kernel also clears the binning counters and scans the binning blocks'
+// candidate totals in chunks of 256; its last block (one more than the
+// tiles and chunks need) writes the binning blocks' dispatch order.
 __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, TileInfo *__restrict__ ti,
                                                uint32_t *__restrict__ tcount, Sched *__restrict__ S, const int32_t *__restrict__ bcand,
                                                int32_t *__restrict__ boff, uint32_t *__restrict__ part,
@@ -527,9 +528,9 @@ __device__ __forceinline__ void bin_step(BinCursor &c, const ViewDev &vd, const 
 }
 
 // One block per kBinTris triangles.  Each triangle's test record is built
-// once (FP64, rounded outwards to FP32) into LDS; each round gives
-// every thread `per` consecutive candidates, per = ceil(candidates / 256) up
-// to kBinPer, tested in FP32 against the tile's FP32 boxes.
+// once (FP64, rounded outwards to FP32) into LDS; each round gives every
+// thread `per` consecutive candidates, per = ceil(candidates / kBinThreads)
+// up to kBinPer, tested in FP32 against the tile's FP32 boxes.
 constexpr int kBinTris = 256;
 // threads of a binning block: the triangles' records are built by the
 // first kBinTris, the candidates are shared by all
