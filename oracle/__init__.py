@@ -7,9 +7,10 @@ two share no code: the only common module is the seeded input generator
 
 ``pr_oracle.c`` is the brute-force definition (every triangle at every pixel,
 the paper's "correct, but slow" solution, Sec. 3); this module compiles it
-with gcc (OpenMP) and wraps it with ctypes.  ``classic.py`` holds the
-independent textbook half-space rasteriser used to pin it, ``bounds.py`` the
-FP64 rolling-time bound pieces (Sec. 4.2) that are pinned by bisection.
+with gcc (OpenMP) and wraps it with ctypes.  ``orc_render_fast`` computes
+the same render bit for bit with a conservative display-space grid of its
+own (pinned against the brute force); ``classic.py`` holds the independent
+textbook half-space rasteriser used to pin the brute force.
 """
 from __future__ import annotations
 
@@ -63,6 +64,7 @@ def lib():
         L.orc_get_threads.restype = ctypes.c_int
         mesh = [dp, dp, ctypes.c_int, ip, ctypes.c_int]
         L.orc_render.argtypes = [dp] + mesh + [lp, i64, ip, dp, dp, ip, dp]
+        L.orc_render_fast.argtypes = [dp] + mesh + [lp, i64, ip, dp, dp, ip, dp, ctypes.c_int]
         L.orc_eval.argtypes = [dp] + mesh + [i64, ctypes.c_int, dp]
         L.orc_eval.restype = ctypes.c_int
         L.orc_eval_many.argtypes = [dp] + mesh + [lp, ip, i64, ip, dp, dp, dp]
@@ -127,6 +129,22 @@ class Oracle:
                           _p(out['id'], ctypes.c_int32), _p(out['z'], ctypes.c_double),
                           _p(out['ehat'], ctypes.c_double), _p(out['id2'], ctypes.c_int32),
                           _p(out['z2'], ctypes.c_double))
+        return out
+
+    def render_fast(self, pix=None, grid: int = 0):
+        """The same as render() (bit for bit) through a conservative
+        display-space grid of grid x grid cells (0: from the image size)."""
+        n = self.W * self.H if pix is None else len(pix)
+        if grid <= 0:
+            grid = int(min(1024, max(16, (self.W * self.H) ** 0.5 / 4)))
+        pp = None if pix is None else np.ascontiguousarray(pix, dtype=np.int64)
+        out = dict(id=np.empty(n, np.int32), z=np.empty(n), ehat=np.empty(n),
+                   id2=np.empty(n, np.int32), z2=np.empty(n))
+        self.L.orc_render_fast(_p(self.vp, ctypes.c_double), *self._m(),
+                               None if pp is None else _p(pp, ctypes.c_int64), n,
+                               _p(out['id'], ctypes.c_int32), _p(out['z'], ctypes.c_double),
+                               _p(out['ehat'], ctypes.c_double), _p(out['id2'], ctypes.c_int32),
+                               _p(out['z2'], ctypes.c_double), grid)
         return out
 
     def eval_many(self, pix, fid, with_cos: bool = False):

@@ -386,6 +386,130 @@ int64_t orc_all_hits(const double *vp, const double *v0, const double *v1, int n
 }
 
 /* ------------------------------------------------------------------------- */
+/* the same render with a conservative display-space grid (oracle_fast)       */
+/* ------------------------------------------------------------------------- */
+
+/* Keeps the two smallest (z, f) pairs in lexicographic order: exactly the
+ * winner and runner-up of orc_render whatever order triangles arrive in. */
+static void keep_two(double z, int32_t f, double eh, double *bz, int32_t *bid, double *beh, double *bz2,
+                     int32_t *bid2) {
+    if (z < *bz || (z == *bz && f < *bid)) {
+        *bz2 = *bz; *bid2 = *bid;
+        *bz = z; *bid = f; *beh = eh;
+    } else if (z < *bz2 || (z == *bz2 && f < *bid2)) {
+        *bz2 = z; *bid2 = f;
+    }
+}
+
+/* Grid cell of a display coordinate: [-1, 1] split into g equal cells,
+ * clamped (monotone, so a clamped box still contains every clamped point
+ * of it). */
+static int grid_cell(double x, int g) {
+    double u = (x + 1.0) * 0.5 * g;
+    if (!(u > 0.0)) return 0;
+    if (u >= g) return g - 1;
+    return (int)u;
+}
+
+/* orc_render with the same outputs, bit for bit, computed faster: a
+ * triangle can only be hit at a pixel whose display point lies in the
+ * projection of the triangle at the pixel's time, which lies in the convex
+ * hull of the six projected start and end vertices when all six are in
+ * front of the near plane (every point of the triangle at any time in
+ * [0, 1] is a convex combination of them, and projection keeps convex
+ * hulls in front of the eye); so each such triangle is listed in the cells
+ * of a g x g grid over the display square that its six points' box
+ * (padded) touches.  A triangle with every space-time vertex behind the
+ * near plane can never be hit (its points all have z < znear); one with
+ * some in front and some behind is tested at every pixel.  Per pixel the
+ * same ray_tri test as orc_render runs on the triangles of its display
+ * point's cell, and the pixel keeps the same winner and runner-up. */
+void orc_render_fast(const double *vp, const double *v0, const double *v1, int nv, const int32_t *tri, int nt,
+                     const int64_t *pix, int64_t npix, int32_t *out_id, double *out_z, double *out_ehat,
+                     int32_t *out_id2, double *out_z2, int g) {
+    orc_cam cam;
+    cam_init(&cam, vp, v0, v1, nv);
+    if (!pix) npix = (int64_t)vp[ORC_W] * (int64_t)vp[ORC_H];
+    if (g < 1) g = 1;
+    const double znear = vp[ORC_ZNEAR];
+    int *rect = (int *)malloc(sizeof(int) * 4 * (size_t)(nt > 0 ? nt : 1));
+    unsigned char *kind = (unsigned char *)malloc((size_t)(nt > 0 ? nt : 1));   /* 0 never, 1 grid, 2 everywhere */
+    int64_t *cnt = (int64_t *)calloc((size_t)g * g + 1, sizeof(int64_t));
+    int64_t nglob = 0;
+    for (int f = 0; f < nt; ++f) {
+        double pts[6][3];
+        int n_in = 0;
+        for (int k = 0; k < 3; ++k) {
+            int64_t v = tri[3 * (int64_t)f + k];
+            for (int d = 0; d < 3; ++d) {
+                pts[k][d] = cam.Ps[3 * v + d];
+                pts[3 + k][d] = cam.Pe[3 * v + d];
+            }
+        }
+        for (int i = 0; i < 6; ++i) n_in += pts[i][2] >= znear;
+        if (n_in == 0) { kind[f] = 0; continue; }
+        if (n_in < 6) { kind[f] = 2; ++nglob; continue; }
+        double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
+        for (int i = 0; i < 6; ++i) {
+            double q[2] = {vp[ORC_FX] * pts[i][0] / pts[i][2] + vp[ORC_CX], vp[ORC_FY] * pts[i][1] / pts[i][2] + vp[ORC_CY]};
+            for (int a = 0; a < 2; ++a) {
+                if (q[a] < lo[a]) lo[a] = q[a];
+                if (q[a] > hi[a]) hi[a] = q[a];
+            }
+        }
+        for (int a = 0; a < 2; ++a) {   /* far above the rounding of the projections */
+            lo[a] -= 1e-9 * (1.0 + fabs(lo[a]));
+            hi[a] += 1e-9 * (1.0 + fabs(hi[a]));
+        }
+        kind[f] = 1;
+        int *r = rect + 4 * (size_t)f;
+        r[0] = grid_cell(lo[0], g); r[1] = grid_cell(hi[0], g);
+        r[2] = grid_cell(lo[1], g); r[3] = grid_cell(hi[1], g);
+        for (int cy = r[2]; cy <= r[3]; ++cy)
+            for (int cx = r[0]; cx <= r[1]; ++cx) ++cnt[(size_t)cy * g + cx + 1];
+    }
+    for (size_t c = 0; c < (size_t)g * g; ++c) cnt[c + 1] += cnt[c];
+    int32_t *list = (int32_t *)malloc(sizeof(int32_t) * (size_t)(cnt[(size_t)g * g] > 0 ? cnt[(size_t)g * g] : 1));
+    int32_t *glob = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nglob > 0 ? nglob : 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)g * g);
+    memcpy(fill, cnt, sizeof(int64_t) * (size_t)g * g);
+    nglob = 0;
+    for (int f = 0; f < nt; ++f) {
+        if (kind[f] == 2) glob[nglob++] = f;
+        if (kind[f] != 1) continue;
+        const int *r = rect + 4 * (size_t)f;
+        for (int cy = r[2]; cy <= r[3]; ++cy)
+            for (int cx = r[0]; cx <= r[1]; ++cx) list[fill[(size_t)cy * g + cx]++] = f;
+    }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t q = 0; q < npix; ++q) {
+        int64_t p = pix ? pix[q] : q;
+        double y[2], x[2], t, r[3];
+        orc_pixel_setup(vp, p, y, x, &t, r);
+        double bz = INFINITY, bz2 = INFINITY, beh = 0;
+        int32_t bid = -1, bid2 = -1;
+        size_t c = (size_t)grid_cell(x[1], g) * g + grid_cell(x[0], g);
+        for (int pass = 0; pass < 2; ++pass) {
+            const int32_t *L = pass ? glob : list + cnt[c];
+            int64_t n = pass ? nglob : cnt[c + 1] - cnt[c];
+            for (int64_t i = 0; i < n; ++i) {
+                double P[3][3], z, eh, e[3];
+                tri_at(&cam, tri, L[i], t, P);
+                if (!ray_tri(P, r, znear, &z, &eh, e)) continue;
+                keep_two(z, L[i], eh, &bz, &bid, &beh, &bz2, &bid2);
+            }
+        }
+        if (out_id) out_id[q] = bid;
+        if (out_z) out_z[q] = bz;
+        if (out_ehat) out_ehat[q] = bid >= 0 ? beh : INFINITY;
+        if (out_id2) out_id2[q] = bid2;
+        if (out_z2) out_z2[q] = bz2;
+    }
+    free(rect); free(kind); free(cnt); free(list); free(glob); free(fill);
+    cam_free(&cam);
+}
+
+/* ------------------------------------------------------------------------- */
 /* rolling Lambert shading and its gradient (frozen visibility)              */
 /* ------------------------------------------------------------------------- */
 

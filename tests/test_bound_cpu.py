@@ -86,12 +86,15 @@ def _quad_mesh(pts0, pts1=None):
 
 
 @pytest.mark.parametrize('case', ['over_fovea', 'screen_filling', 'near_crossing', 'behind_eye_vertex',
-                                  'sweeps_frame', 'offscreen_vertices', 'eye_in_plane'])
+                                  'sweeps_frame', 'offscreen_vertices', 'eye_in_plane', 'zero_area_collinear',
+                                  'zero_area_point', 'zero_area_at_start'])
 def test_adversarial_triangles(case):
     """Single triangles that stress the bound: covering the fovea, filling the
     screen, crossing the near plane, a vertex behind the eye, sweeping the
     whole display within one frame, vertices far off-screen, the eye in the
-    triangle's plane."""
+    triangle's plane, zero area (collinear vertices, one point, and a
+    triangle collapsed to a segment at the frame's start that opens up by its
+    end, so it is hit only late in the frame)."""
     T = {
         'over_fovea': ([[-0.05, -0.05, 1.0], [0.06, -0.04, 1.0], [0.0, 0.07, 1.1]], None),
         'screen_filling': ([[-9, -9, 2.0], [9, -9, 2.0], [0, 9, 2.5]], None),
@@ -101,6 +104,10 @@ def test_adversarial_triangles(case):
                          [[3.0, -0.2, 2.0], [3.2, -0.1, 2.0], [3.1, 0.2, 2.0]]),
         'offscreen_vertices': ([[-40, -1, 3.0], [40, -0.5, 3.0], [0.0, 30, 3.0]], None),
         'eye_in_plane': ([[-1, 0.0, 1.0], [1, 0.0, 1.0], [0.0, 0.0, 3.0]], None),
+        'zero_area_collinear': ([[-0.5, -0.3, 2.0], [0.5, 0.3, 2.0], [0.0, 0.0, 2.0]], None),
+        'zero_area_point': ([[0.1, 0.1, 2.0], [0.1, 0.1, 2.0], [0.1, 0.1, 2.0]], None),
+        'zero_area_at_start': ([[-0.5, -0.3, 2.0], [0.5, 0.3, 2.0], [0.0, 0.0, 2.0]],
+                               [[-0.5, -0.3, 2.0], [0.5, 0.3, 2.0], [0.3, -0.6, 2.0]]),
     }[case]
     mesh = _quad_mesh(*T)
     for roll in [(1.0, 0.0), (0.0, 0.0)]:
@@ -109,6 +116,8 @@ def test_adversarial_triangles(case):
             sc = scenegen.Scene('adv', [mesh], [view])
             n, missed, _ = _check_hits(sc, 8)
             assert not missed, (case, roll, missed[:3])
+            if case == 'zero_area_at_start' and roll == (1.0, 0.0):
+                assert n > 20   # covered in the frame's later columns
 
 
 def test_bound_is_tight_enough_to_reject_pairs():

@@ -45,6 +45,18 @@ MUTANTS = {
                             'double v = cn > 0 ? fabs(e[k]) / cn : 0.0;'),
     'cosinc_not_normalised': ('cosinc[q] = nn > 0 ? fabs(dot3(N, r)) / nn : 0.0;',
                               'cosinc[q] = nn > 0 ? fabs(dot3(N, r)) / norm3(N) : 0.0;'),
+    # the bound invariant's checker: every hit, occluded or not
+    'all_hits_first_only': ('out_ehat[count] = eh; }\n            ++count;',
+                            'out_ehat[count] = eh; }\n            ++count;\n            break;'),
+    'all_hits_position_not_pixel': ('if (count < cap) { out_pix[count] = p;', 'if (count < cap) { out_pix[count] = q;'),
+    # the grid render
+    'fast_box_start_vertices_only': ('for (int i = 0; i < 6; ++i) {\n            double q[2]',
+                                     'for (int i = 0; i < 3; ++i) {\n            double q[2]'),
+    'fast_near_plane_crossing_culled': ('if (n_in < 6) { kind[f] = 2; ++nglob; continue; }',
+                                        'if (n_in < 6) { kind[f] = 0; continue; }'),
+    'fast_tie_to_higher_index': ('if (z < *bz || (z == *bz && f < *bid)) {', 'if (z < *bz || (z == *bz && f > *bid)) {'),
+    'fast_cell_axes_swapped': ('size_t c = (size_t)grid_cell(x[1], g) * g + grid_cell(x[0], g);',
+                               'size_t c = (size_t)grid_cell(x[0], g) * g + grid_cell(x[1], g);'),
 }
 
 

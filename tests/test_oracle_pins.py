@@ -445,3 +445,99 @@ def test_edge_metric_and_incidence_cosine_closed_forms():
             assert abs(o['ehat'][p] - eh[0]) < 1e-15
             checked += 1
     assert checked == 16
+
+
+# --------------------------------------------------------------------------
+# every hit (the bound invariant's checker) and the grid-accelerated render
+# --------------------------------------------------------------------------
+
+def _soup(seed=41, n=300, w=48, h=40, **kw):
+    base = dict(alpha=2.0, roll=(1.0, 0.0), yaw_deg_s=3000.0, obj_speed=30.0, side=(0.05, 0.6))
+    base.update(kw)
+    return scenegen.make_moving_soup(seed=seed, n_tris=n, width=w, height=h, **base)
+
+
+def _near_plane_scene():
+    """A soup plus triangles that cross the near plane (some space-time
+    vertices behind z = znear, one behind the eye) and cover many pixels,
+    and one triangle entirely behind the eye."""
+    sc = _soup(seed=43, n=200, w=56, h=44)
+    m = sc.meshes[0]
+    extra0 = np.array([[-2.0, -1.5, 0.01], [2.5, -1.0, 4.0], [0.0, 2.0, 3.0],
+                       [-1.0, 1.0, -0.5], [1.5, 1.5, 2.0], [1.0, -2.0, 0.04],
+                       [-1.0, -1.0, -1.0], [1.0, -1.0, -2.0], [0.0, 1.0, -1.5]], np.float32)
+    extra1 = extra0 + np.float32([0.02, 0.0, 0.06])
+    nv = m.v0.shape[0]
+    v0 = np.concatenate([m.v0, extra0])
+    v1 = np.concatenate([m.v1, extra1])
+    tri = np.concatenate([m.tri, nv + np.arange(9, dtype=np.int32).reshape(3, 3)])
+    alb = np.concatenate([m.albedo, np.full((9, 3), 0.5, np.float32)])
+    return scenegen.Scene('near', [scenegen.Mesh(v0, v1, tri, alb)], sc.views)
+
+
+def test_all_hits_equals_pairwise_evaluation():
+    """orc_all_hits (the checker of the bound invariant: every covered
+    fragment, occluded or not) returns exactly the (pixel, triangle) pairs
+    the per-pair evaluation calls hits, over every pair of a small moving
+    scene, with the same edge metric; it contains every winner and
+    runner-up of the render; with a pixel subset it reports the given pixel
+    indices."""
+    for sc in (_soup(), _near_plane_scene()):
+        v = sc.views[0]
+        orc = oracle.Oracle(sc.meshes[0], v)
+        npx, nt = v.width * v.height, sc.meshes[0].nt
+        hp, ht, he = orc.all_hits()
+        pp = np.repeat(np.arange(npx), nt)
+        ff = np.tile(np.arange(nt, dtype=np.int32), npx)
+        hit, _, eh = orc.eval_many(pp, ff)
+        ref = set(zip(pp[hit].tolist(), ff[hit].tolist()))
+        got = list(zip(hp.tolist(), ht.tolist()))
+        assert len(got) == len(set(got)) == len(ref) and set(got) == ref
+        # many pixels see more than one triangle (occluded hits are kept)
+        assert np.bincount(hp, minlength=npx).max() >= 3
+        ehref = dict(zip(zip(pp[hit].tolist(), ff[hit].tolist()), eh[hit].tolist()))
+        assert all(ehref[k] == e for k, e in zip(got, he.tolist()))
+        o = orc.render()
+        for key in ('id', 'id2'):
+            win = np.nonzero(o[key] >= 0)[0]
+            assert set(zip(win.tolist(), o[key][win].tolist())) <= ref
+        sub = np.random.default_rng(5).permutation(npx)[: npx // 3]
+        sp, st, _ = orc.all_hits(sub)
+        subset = set(sub.tolist())
+        assert set(zip(sp.tolist(), st.tolist())) == {k for k in ref if k[0] in subset}
+
+
+@pytest.mark.parametrize('grid', [0, 1, 7, 64])
+def test_fast_render_equals_brute_force(grid):
+    """orc_render_fast gives orc_render's outputs bit for bit (winner and
+    runner-up ids, depths, edge metric): moving soups under fast yaw with
+    foveation and rolling, triangles crossing the near plane or behind the
+    eye, rolling off, ragged sizes, full frames and pixel subsets."""
+    scenes = [_soup(), _soup(seed=44, n=400, w=61, h=37, alpha=3.0, roll=(0.0, 0.9), fovea=(-0.2, 0.2)),
+              _soup(seed=45, n=250, w=40, h=52, alpha=1.0, roll=(0.0, 0.0)), _near_plane_scene()]
+    for sc in scenes:
+        v = sc.views[0]
+        orc = oracle.Oracle(sc.meshes[0], v)
+        a, b = orc.render(), orc.render_fast(grid=grid)
+        assert (a['id'] >= 0).sum() > 200
+        for k in a:
+            assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), (sc.name, grid, k)
+        pix = np.random.default_rng(6).permutation(v.width * v.height)[:500]
+        a, b = orc.render(pix), orc.render_fast(pix, grid=grid)
+        for k in a:
+            assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), (sc.name, grid, k)
+
+
+def test_fast_render_exact_ties():
+    """The grid render keeps the brute force's tie order: coincident
+    triangles tie exactly in depth and resolve to the lower index, the other
+    copy being the runner-up."""
+    v = np.array([[-1, -1, 2], [1, -1, 2], [0, 1, 2.5]], np.float32)
+    v = np.concatenate([v, v, v + np.float32([0, 0, 1])])
+    tri = np.array([[6, 7, 8], [3, 4, 5], [0, 1, 2]], np.int32)
+    mesh = scenegen.Mesh(v, v.copy(), tri, np.ones_like(v))
+    view = scenegen.View(24, 24, np.zeros(6, np.float32), np.zeros(6, np.float32), alpha=2.0, roll_dir=(1, 0))
+    o = oracle.Oracle(mesh, view).render_fast(grid=4)
+    hit = o['id'] >= 0
+    assert hit.sum() > 50
+    assert (o['id'][hit] == 1).all() and (o['id2'][hit] == 2).all()
