@@ -211,7 +211,11 @@ int pr_raycast_shade(const pr_mesh *meshes, int nm, const pr_view *views, int nv
  * dL/drgb[v] (float32 [H][W][3]), writes dL/dv0 and dL/dv1 (float32 [nv][3]
  * per mesh, summed over the views that use the mesh) and dL/dpose0,
  * dL/dpose1 (float32 [nv_views][6]: rotation vector then translation).
- * Needs pr_bound of the same frame. */
+ * The shading is differentiated at this call's own vertices and poses
+ * (meshes, views): the call rewrites the workspace's view table from them
+ * and needs no earlier pass, so a forward frame run after the one that
+ * produced tri_id does not change the result.  The status block is left
+ * as it is. */
 int pr_backward(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
                 void *ws, size_t ws_bytes, const int32_t *const *tri_id, const pr_light *light,
                 const float *const *albedo, const float *const *dl_drgb, float *const *dv0,

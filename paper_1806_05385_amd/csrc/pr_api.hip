@@ -142,8 +142,8 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     L.tb = off; off = up(off + (size_t)tris * sizeof(TriBound));
     L.bcand = off; off = up(off + ((size_t)tri_blocks + 1) * 4);
     L.bperm = off; off = up(off + ((size_t)tri_blocks + 1) * 4);
-    L.boff = off; off = up(off + ((size_t)tri_blocks + 1) * 4);
-    L.bpart = off; off = up(off + ((size_t)tri_blocks / 256 + 1) * 4);
+    L.boff = off; off = up(off + ((size_t)tri_blocks + 1) * 8);
+    L.bpart = off; off = up(off + ((size_t)tri_blocks / 256 + 1) * 8);
     L.tcount = off; off = up(off + ((size_t)tiles + 1) * 4);
     L.toff = off; off = up(off + ((size_t)tiles + 1) * 4);
     L.part = off; off = up(off + (size_t)L.nparts * 4);
@@ -191,6 +191,26 @@ void fill_u32(void *p, uint32_t v, int64_t n, hipStream_t s) {
     hipStream_t s = (hipStream_t)stream;                                  \
     DevStatus *st = at<DevStatus>(ws, 0);                                 \
     ViewTable *T = at<ViewTable>(ws, L.table);
+
+// The workspace's view table from the call's own meshes and views (FP64
+// camera geometry computed on the device); reset_status: also clear the
+// status block (the frame's first pass).
+void write_views(const Layout &L, ViewTable *T, DevStatus *st, bool reset_status, hipStream_t s) {
+    for (int first = 0; first < L.nv; first += kViewsPerWrite) {
+        ViewPack p;
+        memset(&p, 0, sizeof(p));
+        p.first = first;
+        p.count = std::min(kViewsPerWrite, L.nv - first);
+        p.nv = L.nv;
+        p.total_tiles = L.total_tiles;
+        p.total_tri_blocks = L.total_tri_blocks;
+        p.total_pix_blocks = L.total_pix_blocks;
+        p.total_vtx_blocks = L.total_vtx_blocks;
+        p.reset_status = reset_status ? 1 : 0;
+        for (int i = 0; i < p.count; ++i) p.v[i] = L.vd[first + i];
+        hipLaunchKernelGGL(k_write_views, dim3(1), dim3(64), 0, s, p, T, st);
+    }
+}
 
 // Blocks of a kernel the whole device keeps resident (persistent grids).
 template <typename K>
@@ -288,19 +308,7 @@ int pr_workspace_size(const pr_mesh *meshes, int nm, const pr_view *views, int n
 int pr_bound(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning, void *ws,
              size_t ws_bytes, void *stream) {
     PR_PREP();
-    for (int first = 0; first < nv; first += kViewsPerWrite) {
-        ViewPack p;
-        memset(&p, 0, sizeof(p));
-        p.first = first;
-        p.count = std::min(kViewsPerWrite, nv - first);
-        p.nv = nv;
-        p.total_tiles = L.total_tiles;
-        p.total_tri_blocks = L.total_tri_blocks;
-        p.total_pix_blocks = L.total_pix_blocks;
-        p.total_vtx_blocks = L.total_vtx_blocks;
-        for (int i = 0; i < p.count; ++i) p.v[i] = L.vd[first + i];
-        hipLaunchKernelGGL(k_write_views, dim3(1), dim3(64), 0, s, p, T, st);
-    }
+    write_views(L, T, st, true, s);
     if (L.total_tri_blocks > 0)
         hipLaunchKernelGGL(k_bound, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec),
                            at<TriBound>(ws, L.tb), st, at<int32_t>(ws, L.bcand));
@@ -316,12 +324,12 @@ int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     // binning blocks
     hipLaunchKernelGGL(k_tiles, dim3(std::max(tile_blocks, chunk_blocks) + 1), dim3(256), 0, s, T,
                        at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<Sched>(ws, L.sched),
-                       at<int32_t>(ws, L.bcand), at<int32_t>(ws, L.boff), at<uint32_t>(ws, L.bpart), st,
+                       at<int32_t>(ws, L.bcand), at<int64_t>(ws, L.boff), at<int64_t>(ws, L.bpart), st,
                        at<int32_t>(ws, L.bperm));
     if (L.total_tri_blocks > 0)
         hipLaunchKernelGGL(k_bin, dim3(L.total_tri_blocks), dim3(kBinThreads), 0, s, T, at<TriBound>(ws, L.tb),
-                           at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<int32_t>(ws, L.boff),
-                           at<uint32_t>(ws, L.bpart), pairs_at(L, ws), L.cap, at<int32_t>(ws, L.bperm));
+                           at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<int64_t>(ws, L.boff),
+                           at<int64_t>(ws, L.bpart), pairs_at(L, ws), L.cap, at<int32_t>(ws, L.bperm), st);
     int n = L.total_tiles + 1;
     hipLaunchKernelGGL(k_scan_reduce, dim3(L.nparts), dim3(256), 0, s, at<uint32_t>(ws, L.tcount), n,
                        at<uint32_t>(ws, L.part));
@@ -428,6 +436,9 @@ int pr_backward(const pr_mesh *meshes, int nm, const pr_view *views, int nv, con
         }
     }
     fill_u32(at<void>(ws, L.gacc), 0u, L.total_gacc, s);
+    // the geometry and poses are this call's own (the view table of the
+    // frame's pr_bound may hold another frame's by now)
+    write_views(L, T, st, false, s);
     hipLaunchKernelGGL(k_view_light, dim3(1), dim3(64), 0, s, T, *light);
     hipLaunchKernelGGL(k_bwd_pixel, dim3(L.total_pix_blocks), dim3(256), 0, s, T, io, light->ambient,
                        at<float>(ws, L.gacc), at<double>(ws, L.pacc));

@@ -112,7 +112,8 @@ struct ViewTable {
 // Views written per k_write_views launch (kernel-argument size).
 constexpr int kViewsPerWrite = 2;
 struct ViewPack {
-    int32_t first, count, nv, total_tiles, total_tri_blocks, total_pix_blocks, total_vtx_blocks, pad;
+    int32_t first, count, nv, total_tiles, total_tri_blocks, total_pix_blocks, total_vtx_blocks;
+    int32_t reset_status;   // the frame's first launch clears the status block (pr_bound, not pr_backward)
     ViewDev v[kViewsPerWrite];
 };
 

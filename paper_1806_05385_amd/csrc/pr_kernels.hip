@@ -68,6 +68,36 @@ __device__ inline int block_excl_scan(int v, int *lds, int &total) {
     return out;
 }
 
+// The same in 64 bits (candidate slot offsets: a frame's candidates may
+// exceed 2^31 before the capacity check rejects it).
+__device__ inline long long wave_incl_scan64(long long v) {
+    int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        long long n = __shfl_up(v, o, 64);
+        if (lane >= o) v += n;
+    }
+    return v;
+}
+
+__device__ inline long long block_excl_scan64(long long v, long long *lds, long long &total) {
+    int lane = __lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    long long inc = wave_incl_scan64(v);
+    if (lane == 63) lds[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        long long w = threadIdx.x < nw ? lds[threadIdx.x] : 0;
+        long long wi = wave_incl_scan64(w);
+        if (threadIdx.x < nw) lds[32 + threadIdx.x] = wi - w;
+        if (threadIdx.x == nw - 1) lds[64] = wi;
+    }
+    __syncthreads();
+    long long out = inc - v + lds[32 + wid];
+    total = lds[64];
+    __syncthreads();
+    return out;
+}
+
 // ---------------------------------------------------------------------------
 // small fills (used instead of hipMemsetAsync so the frame can be captured)
 // ---------------------------------------------------------------------------
@@ -91,7 +121,7 @@ __device__ __forceinline__ int find_view(const int32_t *base, int nv, int key) {
 
 __global__ void k_write_views(ViewPack p, ViewTable *__restrict__ T, DevStatus *__restrict__ st) {
     int i = threadIdx.x;
-    if (p.first == 0) {   // the frame's first launch resets the status block
+    if (p.first == 0 && p.reset_status) {   // the frame's first launch resets the status block
         uint32_t *w = reinterpret_cast<uint32_t *>(st);
         for (int k = i; k < (int)(sizeof(DevStatus) / 4); k += blockDim.x) w[k] = 0u;
     }
@@ -350,9 +380,10 @@ constexpr int kPermItems = 8;
 // tiles and chunks need) writes the binning blocks' dispatch order.
 __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, TileInfo *__restrict__ ti,
                                                uint32_t *__restrict__ tcount, Sched *__restrict__ S, const int32_t *__restrict__ bcand,
-                                               int32_t *__restrict__ boff, uint32_t *__restrict__ part,
+                                               int64_t *__restrict__ boff, int64_t *__restrict__ part,
                                                DevStatus *__restrict__ st, int32_t *__restrict__ bperm) {
     __shared__ int s_tmp[72];
+    __shared__ long long s_tmp64[72];
     const int gid = blockIdx.x * 256 + threadIdx.x;
     const int gt = gid >> 2, q = gid & 3;
     const bool valid = gt < T->total_tiles;
@@ -364,15 +395,17 @@ __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, 
     }
     if (blockIdx.x < (T->total_tri_blocks + 255) / 256) {
         // the binning blocks' candidate slots: local exclusive scan of 256
-        // block totals here; k_bin adds the totals of the chunks before
+        // block totals here; k_bin adds the totals of the chunks before.
+        // A block's total fits 32 bits (256 rectangles of at most 2^22
+        // tiles), a chunk's does not.
         const int nb = T->total_tri_blocks;
         const int b = blockIdx.x * 256 + threadIdx.x;
-        const int c = b < nb ? bcand[b] : 0;
-        int tot;
-        const int ex = block_excl_scan(c, s_tmp, tot);
+        const long long c = b < nb ? bcand[b] : 0;
+        long long tot;
+        const long long ex = block_excl_scan64(c, s_tmp64, tot);
         if (b < nb) boff[b] = ex;
         if (threadIdx.x == 0) {
-            part[blockIdx.x] = (uint32_t)tot;
+            part[blockIdx.x] = tot;
             atomicAdd(&st->pairs_required, (unsigned long long)tot);
         }
     }
@@ -538,14 +571,20 @@ constexpr int kBinThreads = 512;
 
 __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewTable *__restrict__ T, const TriBound *__restrict__ tb,
                                              const TileInfo *__restrict__ ti, uint32_t *__restrict__ tcount,
-                                             const int32_t *__restrict__ boff, const uint32_t *__restrict__ bpart,
-                                             Pairs pairs, int64_t cap, const int32_t *__restrict__ bperm) {
+                                             const int64_t *__restrict__ boff, const int64_t *__restrict__ bpart,
+                                             Pairs pairs, int64_t cap, const int32_t *__restrict__ bperm,
+                                             const DevStatus *__restrict__ st) {
+    // A frame whose candidates exceed the capacity (k_tiles summed them) is
+    // not binned at all: its pairs would not fit, the overflow is reported
+    // and the ray cast writes misses.
+    if ((int64_t)st->pairs_required > cap) return;
     // odd row strides (33 and 5 words) keep lanes reading different
     // triangles on different LDS banks
     __shared__ uint32_t s_sat[kBinTris][33];
     __shared__ int s_rect[kBinTris][5];
     __shared__ int s_pref[kBinTris + 1];
     __shared__ int s_tmp[72];
+    __shared__ long long s_tmp64[72];
     // survivors per tile of the current round (open addressing on the tile)
     __shared__ int32_t s_hkey[kBinHash];
     __shared__ uint32_t s_hcnt[kBinHash], s_hbase[kBinHash];
@@ -589,11 +628,11 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewTable *__restrict
         }
         // the block's first candidate slot: its offset in its chunk of 256
         // blocks plus the totals of the chunks before
-        int cpre = 0;
-        for (int i = j; i < (bb >> 8); i += kBinThreads) cpre += (int)bpart[i];
-        int ctot;
-        block_excl_scan(cpre, s_tmp, ctot);
-        const int64_t s_off = (int64_t)boff[bb] + ctot;
+        long long cpre = 0;
+        for (int i = j; i < (bb >> 8); i += kBinThreads) cpre += bpart[i];
+        long long ctot;
+        block_excl_scan64(cpre, s_tmp64, ctot);
+        const int64_t s_off = boff[bb] + ctot;
         const int total = s_pref[kBinTris];
         const int per = min(kBinPer, max(1, (total + kBinThreads - 1) / kBinThreads));
         const bool split = prg::split_quads(vd.tile);

@@ -289,20 +289,31 @@ class PerceptualRender(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, renderer, v0, v1, pose0, pose1):
-        renderer.set_geometry(0, v0, v1)
+        v0c, v1c = v0.detach().contiguous(), v1.detach().contiguous()
         p0 = pose0.detach().cpu().tolist()
         p1 = pose1.detach().cpu().tolist()
+        renderer.set_geometry(0, v0c, v1c)
         for i in range(len(renderer.views)):
             renderer.set_poses(i, p0[i], p1[i])
         out = renderer.frame(shade=True)
         ctx.renderer = renderer
         ctx.ids = [o['id'].clone() for o in out]
+        # this forward's own geometry and poses: another forward on the same
+        # renderer (a second loss term, a target render) may run before the
+        # backward and re-point the renderer
+        ctx.save_for_backward(v0c, v1c)
+        ctx.poses = (p0, p1)
         ctx.pose_devices = (pose0.device, pose1.device)
         return torch.stack([o['rgb32'] for o in out]).clone()
 
     @staticmethod
     def backward(ctx, grad_rgb):
         r = ctx.renderer
+        v0c, v1c = ctx.saved_tensors
+        p0, p1 = ctx.poses
+        r.set_geometry(0, v0c, v1c)
+        for i in range(len(r.views)):
+            r.set_poses(i, p0[i], p1[i])
         dl = [grad_rgb[i].contiguous().float() for i in range(grad_rgb.shape[0])]
         dv0, dv1, dp0, dp1 = r.backward(dl, ids=ctx.ids)
         return None, dv0[0], dv1[0], dp0.to(ctx.pose_devices[0]), dp1.to(ctx.pose_devices[1])

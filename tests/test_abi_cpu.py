@@ -109,3 +109,37 @@ def test_calls_reject_bad_workspace_before_launch():
                       None) == B.PR_ERR_INVALID
     st = B.PrStatus()
     assert L.pr_status_read(None, 1024, ctypes.byref(st), None) == B.PR_ERR_INVALID
+
+
+def huge_candidate_scene(n_tris: int = 520):
+    """A 16384 x 16384 view at tile 8 (2048 x 2048 tiles) and n_tris
+    triangles that each cover the whole display: every triangle's tile
+    rectangle is the whole grid, 4,194,304 candidates each."""
+    import numpy as np
+    import scenegen
+    base = np.array([[-40.0, -40.0, 2.0], [40.0, -40.0, 2.0], [0.0, 40.0, 2.0]], np.float32)
+    v = np.concatenate([base + np.float32([0.0, 0.0, 0.001 * k]) for k in range(n_tris)])
+    tri = np.arange(3 * n_tris, dtype=np.int32).reshape(n_tris, 3)
+    mesh = scenegen.Mesh(v, v.copy(), tri, np.full_like(v, 0.5))
+    view = scenegen.View(16384, 16384, np.zeros(6, np.float32), np.zeros(6, np.float32), alpha=1.0,
+                         roll_dir=(0.0, 0.0))
+    return scenegen.Scene('huge_candidates', [mesh], [view])
+
+
+def test_candidate_count_beyond_int32():
+    """The candidate count of huge_candidate_scene exceeds 2^31 - 1 (the
+    binning's slot offsets are 64-bit; the GPU test checks the frame reports
+    exactly this count as an overflow): each triangle's tile rectangle,
+    from the host build of the bound, is the full 2048 x 2048 grid."""
+    sc = huge_candidate_scene()
+    mesh, view = sc.meshes[0], sc.views[0]
+    L = B.lib()
+    hm = B.host_mesh(mesh.v0, mesh.v1, mesh.tri)
+    pv = B.make_view(view)
+    rect = (ctypes.c_int32 * 4)()
+    total = 0
+    for f in range(mesh.nt):
+        assert L.pr_host_tile_rect(ctypes.byref(hm), f, ctypes.byref(pv), 8, rect) == 1
+        assert tuple(rect) == (0, 0, 2047, 2047)
+        total += (rect[2] - rect[0] + 1) * (rect[3] - rect[1] + 1)
+    assert total == 520 * 2048 * 2048 == 2_181_038_080 > 2 ** 31 - 1

@@ -8,12 +8,9 @@ pixels whose FP32 forward colour differs from the FP64 one by ~1e-4 would
 otherwise move the pose sums by more than the backward's own error (the
 forward colours are checked separately, to 1 LSB in RGBA8).
 
-Tolerance: |g - g_ref| <= 1e-3 max(|g_ref|, 1e-3 max|g_ref|) per component,
-except for listed near-edge vertices: a vertex that receives a contribution
-from a pixel whose ray passes within 1e-4 rad of an edge plane of its
-triangle (normalised edge magnitude < 1e-4).  There the barycentric of the
-opposite vertex is tiny and rounding the ray to FP32 (2^-24) alone changes
-it by 2^-24 / ehat relative, so those vertices are checked at 5e-2."""
+Tolerance: |g - g_ref| <= 1e-3 max(|g_ref|, 1e-3 max|g_ref|) for every
+component (the backward sets up each pixel's ray and the shading chain in
+FP64, so no component is exempt)."""
 import numpy as np
 import pytest
 
@@ -65,13 +62,9 @@ def _case_scene(sc, target):
     c_ref = orc.shade(oid, light)
     dl = torch.as_tensor(2.0 * (c_ref - tgt).reshape(view.height, view.width, 3), dtype=torch.float32).cuda()
     dv0, dv1, dp0, dp1 = r.backward([dl], ids=[ids])
-    o = orc.render()
-    edge_px = (o['id'] >= 0) & (o['ehat'] < 1e-4)
-    near = np.zeros(mesh.nv, bool)
-    near[np.unique(mesh.tri[o['id'][edge_px]].ravel())] = True
     return dict(L=L, g0=g0, g1=g1, gp0=gp0, gp1=gp1, dv0=dv0[0].cpu().numpy(), dv1=dv1[0].cpu().numpy(),
                 dp0=dp0[0].cpu().numpy(), dp1=dp1[0].cpu().numpy(), gpu_L=float(((rgb - tg) ** 2).sum()),
-                r=r, sc=sc, oid=oid, tgt=tgt, near=near)
+                r=r, sc=sc, oid=oid, tgt=tgt)
 
 
 def _soup_case():
@@ -104,15 +97,9 @@ def test_gradients_match_fp64_reference(case):
                          ('dpose0', c['dp0'], c['gp0']), ('dpose1', c['dp1'], c['gp1'])]:
         bad, rel = _close(g, ref)
         nz = np.abs(ref) > 1e-3 * np.abs(ref).max()
-        listed = 0
-        if name.startswith('dv'):
-            near = np.repeat(c['near'][:, None], 3, axis=1)
-            listed = int((bad & near).sum())
-            loose = np.abs(g - ref) <= 5e-2 * np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
-            assert (loose | ~near).all(), (name, np.argwhere(near & ~loose)[:5])
-            bad = bad & ~near
-        print(f'\n{name}: {bad.sum()} of {bad.size} outside tolerance, {listed} listed near-edge; '
-              f'median rel err of significant components {np.median(rel[nz]):.2e}', flush=True)
+        print(f'\n{name}: {bad.sum()} of {bad.size} outside tolerance; '
+              f'median rel err of significant components {np.median(rel[nz]):.2e}, max {rel[nz].max():.2e}',
+              flush=True)
         assert np.abs(ref).max() > 0
         assert not bad.any(), (name, np.argwhere(bad)[:5], g[bad][:5], ref[bad][:5])
 
@@ -147,3 +134,42 @@ def test_translation_identity_on_device():
     lhs = c['dv0'].astype(np.float64).sum(0)
     rhs = R0.T @ c['dp0'][3:].astype(np.float64)
     assert np.abs(lhs - rhs).max() <= 1e-4 * np.abs(rhs).max()
+
+
+def test_backward_after_a_second_forward():
+    """A second forward on the same renderer with other poses and vertices
+    (a target render, a second loss term) runs before the backward of the
+    first: the gradients are still those of the first forward's own
+    geometry and poses, checked against the FP64 reference at the 1e-3
+    rule.  The loss is linear, sum(w * rgb), so both sides take the same
+    upstream gradient w (the oracle's L2 loss with target c - w/2)."""
+    torch = _torch()
+    from paper_1806_05385_amd.render import PerceptualRender, Renderer
+    sc = scenegen.make_grad(seed=5, size=96, f=16)
+    mesh, view = sc.meshes[0], sc.views[0]
+    r = Renderer(sc.meshes, sc.views, tile=16, light=sc.light_dir, ambient=sc.ambient)
+    m = r.meshes[0]
+    v0 = m.v0.clone().requires_grad_(True)
+    v1 = m.v1.clone().requires_grad_(True)
+    p0 = torch.tensor(np.array([view.pose0]), dtype=torch.float32, requires_grad=True)
+    p1 = torch.tensor(np.array([view.pose1]), dtype=torch.float32, requires_grad=True)
+    rgb = PerceptualRender.apply(r, v0, v1, p0, p1)
+    ids = r.outputs[0]['id'].cpu().numpy().ravel().copy()
+    # the second forward: shifted vertices and poses
+    q0 = (p0.detach() + torch.tensor([[0.01, -0.02, 0.0, 0.05, 0.0, 0.1]])).requires_grad_(True)
+    q1 = (p1.detach() + torch.tensor([[0.0, 0.02, 0.01, -0.05, 0.02, 0.0]])).requires_grad_(True)
+    rgb2 = PerceptualRender.apply(r, v0.detach() * 1.01, v1.detach() * 0.99, q0, q1)
+    assert not torch.equal(rgb, rgb2)
+    w = torch.rand(rgb.shape, generator=torch.Generator(device='cuda').manual_seed(3), device='cuda')
+    (rgb * w).sum().backward()
+    light = oracle.light_block(sc)
+    orc = oracle.Oracle(mesh, view)
+    c_ref = orc.shade(ids, light)
+    wn = w[0].detach().cpu().numpy().astype(np.float64).reshape(-1, 3)
+    _, g0, g1, gp0, gp1 = orc.loss_grad(ids, light, c_ref - 0.5 * wn)
+    assert (ids >= 0).sum() > 2000
+    for name, g, ref in [('dv0', v0.grad, g0), ('dv1', v1.grad, g1), ('dpose0', p0.grad[0], gp0),
+                         ('dpose1', p1.grad[0], gp1)]:
+        bad, _ = _close(g.detach().cpu().numpy(), ref)
+        assert np.abs(ref).max() > 0
+        assert not bad.any(), (name, np.argwhere(bad)[:5])

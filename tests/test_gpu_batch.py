@@ -94,3 +94,37 @@ def test_autotuner_chooses_and_caches(tmp_path, monkeypatch):
         assert np.array_equal(a['id'].cpu().numpy(), b['id'].cpu().numpy())
     bt.close()
     bt2.close()
+
+
+def test_full_batch_parity_with_oracle():
+    """The benchmark's batch (64 views, sides log-uniform 128..2048, scenes
+    log-uniform 1k..500k triangles, each view with its own fovea, poses,
+    foveation and rolling), autotuned and replayed from its hipGraph as the
+    benchmark runs it: every pixel of every view against the oracle
+    (orc_render_fast, re-checked by the brute force on 200 sampled pixels
+    per view)."""
+    _torch()
+    from paper_1806_05385_amd.render import Batch
+    sc = scenegen.make_batch()
+    assert len(sc.views) == 64
+    bt = Batch(sc.meshes, sc.views, tile=0, light=sc.light_dir, ambient=sc.ambient, rgba8=True)
+    bt.launch()
+    out = bt.launch()
+    st = bt.status()
+    assert st.overflow == 0
+    total = exempt = 0
+    for v, view in enumerate(sc.views):
+        orc = oracle.Oracle(sc.meshes[view.mesh], view)
+        o = orc.render_fast()
+        pix = scenegen.sample_pixels(4100 + v, view, 200)
+        bf = orc.render(pix)
+        assert np.array_equal(bf['id'], o['id'][pix]) and np.array_equal(bf['z'].view(np.uint8),
+                                                                           o['z'][pix].view(np.uint8))
+        allpix = np.arange(view.width * view.height)
+        rep = compare(orc, o, out[v]['id'].cpu().numpy().ravel(), out[v]['depth'].cpu().numpy().ravel(), allpix,
+                      view.znear)
+        total += len(allpix)
+        exempt += rep['mismatch'] + rep['grazing']
+        assert_parity(rep)
+    print(f"\nbatch: 64 views, {total} pixels, tile {bt.info()['tile']}, {exempt} exempt pixels", flush=True)
+    bt.close()
