@@ -7,8 +7,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,6 +22,7 @@ using namespace prk;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxDevices = 64;   // devices a process may drive (per-device caches)
 size_t up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // Workspace: [status | view table | tile infos | records | triangle bounds |
@@ -238,10 +241,19 @@ void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, c
                                light);
         return;
     }
-    static int resident = 0;
-    if (!resident) resident = resident_blocks(k_raycast_queue<TILE, COUNT, SHADE>, C::NT);
+    // resident blocks per device (each instantiation its own cache; a race
+    // between threads only computes the same value twice)
+    static std::atomic<int> resident[kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+    int res = resident[dev].load(std::memory_order_relaxed);
+    if (!res) {
+        res = resident_blocks(k_raycast_queue<TILE, COUNT, SHADE>, C::NT);
+        resident[dev].store(res, std::memory_order_relaxed);
+    }
+    const int resident_n = res;
     const int nitems = ray_items<TILE>(L.total_tiles);
-    const int grid = std::max(1, std::min(nitems, resident));
+    const int grid = std::max(1, std::min(nitems, resident_n));
     hipLaunchKernelGGL((k_raycast_queue<TILE, COUNT, SHADE>), dim3(grid), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
                        at<uint32_t>(ws, L.lists), out, st, at<int4>(ws, L.order), nitems, sio, light);
 }
