@@ -75,6 +75,13 @@ def lib():
         L.orc_loss.restype = ctypes.c_double
         L.orc_loss_grad.argtypes = [dp] + mesh + [dp, dp, ip, dp, dp, dp, dp, dp]
         L.orc_loss_grad.restype = ctypes.c_double
+        L.orc_unfov_coord.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.orc_unfov_lod.argtypes = [dp]
+        L.orc_unfov_lod.restype = ctypes.c_double
+        L.orc_unfoveate_image.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                          lp, i64, dp]
+        L.orc_mip_level.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ip, ip]
+        L.orc_mip_level.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -246,3 +253,61 @@ def pixel_setup(view, pix: int):
     lib().orc_pixel_setup(_p(vp, ctypes.c_double), pix, _p(y, ctypes.c_double), _p(x, ctypes.c_double),
                           ctypes.byref(t), _p(r, ctypes.c_double))
     return y, x, t.value, r
+
+
+# --------------------------------------------------------------------------
+# display unfoveation (Sec. 3.1.1 "Display")
+# --------------------------------------------------------------------------
+UNFOV_MIP = 0
+UNFOV_FILTER = 1
+
+
+def _rgba01(img) -> np.ndarray:
+    """Foveated image as float64 RGBA in [0, 1] ([H, W, 4]; uint8 / 255)."""
+    a = np.asarray(img)
+    if a.dtype == np.uint8:
+        return np.ascontiguousarray(a, dtype=np.float64) / 255.0
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def unfoveate_image(view, fov, width: int, height: int, mode: int = UNFOV_MIP, sigma: float = 0.5,
+                    pix=None) -> np.ndarray:
+    """Display image (float64 RGBA, [height*width, 4] or [len(pix), 4]) of
+    the foveated image ``fov`` ([view.height, view.width, 4]) of ``view``."""
+    vp = view_params(view)
+    f = _rgba01(fov)
+    assert f.shape == (view.height, view.width, 4)
+    n = width * height if pix is None else len(pix)
+    pp = None if pix is None else np.ascontiguousarray(pix, dtype=np.int64)
+    out = np.empty((n, 4))
+    lib().orc_unfoveate_image(_p(vp, ctypes.c_double), _p(f, ctypes.c_double), width, height, mode, sigma,
+                              None if pp is None else _p(pp, ctypes.c_int64), n, _p(out, ctypes.c_double))
+    return out
+
+
+def unfov_coord(view, width: int, height: int, a: float, b: float):
+    """Continuous foveated pixel coordinates u of display pixel (a, b) and
+    the Jacobian du/d(a, b) (2x2), and the level of detail."""
+    vp = view_params(view)
+    u, J = np.empty(2), np.empty(4)
+    lib().orc_unfov_coord(_p(vp, ctypes.c_double), width, height, a, b, _p(u, ctypes.c_double),
+                          _p(J, ctypes.c_double))
+    return u, J.reshape(2, 2), lib().orc_unfov_lod(_p(J, ctypes.c_double))
+
+
+def mip_level(fov, k: int):
+    """Level k of the oracle's MIP pyramid (float64 [h, w, 4]) and the number
+    of levels."""
+    f = _rgba01(fov)
+    H, W = f.shape[:2]
+    w, h = ctypes.c_int(0), ctypes.c_int(0)
+    n = lib().orc_mip_level(_p(f, ctypes.c_double), W, H, k, None, ctypes.byref(w), ctypes.byref(h))
+    out = np.empty((h.value, w.value, 4))
+    lib().orc_mip_level(_p(f, ctypes.c_double), W, H, k, _p(out, ctypes.c_double), ctypes.byref(w),
+                        ctypes.byref(h))
+    return out, n
+
+
+def to_rgba8(c) -> np.ndarray:
+    """floor(clamp(c, 0, 1) * 255 + 1/2) as uint8."""
+    return np.floor(np.clip(c, 0.0, 1.0) * 255.0 + 0.5).astype(np.uint8)

@@ -746,3 +746,230 @@ double orc_loss_grad(const double *vp, const double *v0, const double *v1, int n
     cam_free(&cam);
     return L;
 }
+
+/* ------------------------------------------------------------------------- */
+/* display unfoveation (Sec. 3.1.1 "Display")                                 */
+/* ------------------------------------------------------------------------- */
+/* The foveated image I_f (W x H, its pixel grid in the foveated domain) is
+ * resampled to the display's regular grid (Wd x Hd): display pixel (a, b)
+ * has display NDC x = (2(a+1/2)/Wd - 1, 1 - 2(b+1/2)/Hd), foveated NDC
+ * y = foveate(x), and continuous foveated pixel coordinates
+ * u = ((y0+1)/2 W - 1/2, (1-y1)/2 H - 1/2) (texel centres at integers).
+ *
+ * Fast form: a MIP pyramid of I_f (level k+1 = 2x2 box mean of level k,
+ * sizes halved rounding up, the last row / column repeated where a level
+ * is odd) sampled at u with level of detail lambda = log2 of the longer
+ * image of a display pixel step in foveated pixels: lambda <= 0 (the
+ * display magnifies, the periphery) a separable cubic interpolation
+ * (Catmull-Rom) of level 0; 0 < lambda < 1 its linear blend with the
+ * bilinear sample of level 1; lambda >= 1 trilinear (bilinear at levels
+ * floor(lambda) and floor(lambda)+1, linear between them), the top level
+ * held past the pyramid.  Level k is addressed at u_k = (u + 1/2)/2^k - 1/2,
+ * edges clamped.
+ *
+ * Reconstruction-filter form: the 5 x 5 foveated pixels around the nearest
+ * one to u, each weighted by a Gaussian of its distance to the display
+ * pixel measured in display pixels after unfoveating its centre,
+ * exp(-d^2 / (2 sigma^2)), normalised by the sum of the weights; pixels
+ * outside the image are skipped.
+ *
+ * Images: RGBA in [0,1], row-major [rows][cols][4] doubles. */
+
+/* u of display pixel (a, b) and the 2x2 Jacobian du/d(a, b) (J[0] = du0/da,
+ * J[1] = du0/db, J[2] = du1/da, J[3] = du1/db).  The foveation is the radial
+ * power map y = f + (x - f) s, s = (|x - f|/R)^(1/alpha - 1); its Jacobian
+ * is s I + (1/alpha - 1) s (x - f)(x - f)^T / |x - f|^2.  At the fovea
+ * itself (alpha > 1) the map's derivative is unbounded: lambda = +inf. */
+void orc_unfov_coord(const double *vp, int Wd, int Hd, double a, double b, double u[2], double J[4]) {
+    int W = (int)vp[ORC_W], H = (int)vp[ORC_H];
+    double x[2] = {2.0 * (a + 0.5) / Wd - 1.0, 1.0 - 2.0 * (b + 0.5) / Hd};
+    double y[2];
+    orc_foveate(vp, x, y);
+    u[0] = (y[0] + 1.0) * 0.5 * W - 0.5;
+    u[1] = (1.0 - y[1]) * 0.5 * H - 0.5;
+    double d[2] = {x[0] - vp[ORC_FOV], x[1] - vp[ORC_FOV + 1]};
+    double rho2 = d[0] * d[0] + d[1] * d[1];
+    double e = 1.0 / vp[ORC_ALPHA];
+    double JF[4];
+    if (rho2 == 0.0) {
+        double v = e == 1.0 ? 1.0 : INFINITY;
+        JF[0] = v; JF[1] = 0.0; JF[2] = 0.0; JF[3] = v;
+    } else {
+        double s = pow(sqrt(rho2) / orc_fovea_radius(vp), e - 1.0);
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) JF[2 * r + c] = (r == c ? s : 0.0) + (e - 1.0) * s * d[r] * d[c] / rho2;
+    }
+    /* u = diag(W/2, -H/2) y + const, x = diag(2/Wd, -2/Hd) (a, b) + const */
+    double su[2] = {0.5 * W, -0.5 * H}, sx[2] = {2.0 / Wd, -2.0 / Hd};
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) J[2 * r + c] = su[r] * JF[2 * r + c] * sx[c];
+}
+
+typedef struct {
+    int n;               /* levels */
+    int w[32], h[32];
+    double *lev[32];     /* [h][w][4] */
+} orc_mip;
+
+static void mip_build(orc_mip *m, const double *img, int W, int H) {
+    m->n = 0;
+    int w = W, h = H;
+    const double *src = img;
+    for (;;) {
+        double *dst = (double *)malloc(sizeof(double) * 4 * (size_t)w * h);
+        if (m->n == 0) {
+            memcpy(dst, img, sizeof(double) * 4 * (size_t)w * h);
+        } else {
+            int pw = m->w[m->n - 1], ph = m->h[m->n - 1];
+            for (int j = 0; j < h; ++j)
+                for (int i = 0; i < w; ++i)
+                    for (int c = 0; c < 4; ++c) {
+                        double s = 0.0;
+                        for (int dj = 0; dj < 2; ++dj)
+                            for (int di = 0; di < 2; ++di) {
+                                int ii = 2 * i + di, jj = 2 * j + dj;
+                                if (ii > pw - 1) ii = pw - 1;
+                                if (jj > ph - 1) jj = ph - 1;
+                                s += src[4 * ((size_t)jj * pw + ii) + c];
+                            }
+                        dst[4 * ((size_t)j * w + i) + c] = 0.25 * s;
+                    }
+        }
+        m->w[m->n] = w; m->h[m->n] = h; m->lev[m->n] = dst;
+        src = dst;
+        ++m->n;
+        if ((w == 1 && h == 1) || m->n == 32) break;
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+    }
+}
+
+static void mip_free(orc_mip *m) {
+    for (int k = 0; k < m->n; ++k) free(m->lev[k]);
+}
+
+static double texel(const orc_mip *m, int k, int i, int j, int c) {
+    int w = m->w[k], h = m->h[k];
+    if (i < 0) i = 0;
+    if (i > w - 1) i = w - 1;
+    if (j < 0) j = 0;
+    if (j > h - 1) j = h - 1;
+    return m->lev[k][4 * ((size_t)j * w + i) + c];
+}
+
+static void bilinear(const orc_mip *m, int k, const double u[2], double out[4]) {
+    double sc = ldexp(1.0, -k);
+    double uk0 = (u[0] + 0.5) * sc - 0.5, uk1 = (u[1] + 0.5) * sc - 0.5;
+    double fi = floor(uk0), fj = floor(uk1);
+    double ti = uk0 - fi, tj = uk1 - fj;
+    int i = (int)fi, j = (int)fj;
+    for (int c = 0; c < 4; ++c)
+        out[c] = (1 - tj) * ((1 - ti) * texel(m, k, i, j, c) + ti * texel(m, k, i + 1, j, c)) +
+                 tj * ((1 - ti) * texel(m, k, i, j + 1, c) + ti * texel(m, k, i + 1, j + 1, c));
+}
+
+/* Catmull-Rom weights of the taps at offsets -1, 0, 1, 2 from floor(u). */
+static void catmull_rom_w(double t, double w[4]) {
+    w[0] = 0.5 * (-t + 2 * t * t - t * t * t);
+    w[1] = 0.5 * (2 - 5 * t * t + 3 * t * t * t);
+    w[2] = 0.5 * (t + 4 * t * t - 3 * t * t * t);
+    w[3] = 0.5 * (-t * t + t * t * t);
+}
+
+static void cubic0(const orc_mip *m, const double u[2], double out[4]) {
+    double fi = floor(u[0]), fj = floor(u[1]);
+    double wi[4], wj[4];
+    catmull_rom_w(u[0] - fi, wi);
+    catmull_rom_w(u[1] - fj, wj);
+    for (int c = 0; c < 4; ++c) {
+        double s = 0.0;
+        for (int b = 0; b < 4; ++b)
+            for (int a = 0; a < 4; ++a) s += wj[b] * wi[a] * texel(m, 0, (int)fi - 1 + a, (int)fj - 1 + b, c);
+        out[c] = s;
+    }
+}
+
+/* The MIP form's value at continuous foveated coordinates u with level of
+ * detail lam. */
+static void mip_sample(const orc_mip *m, const double u[2], double lam, double out[4]) {
+    double a[4], b[4];
+    int top = m->n - 1;
+    if (!(lam > 0.0)) {
+        cubic0(m, u, out);
+    } else if (lam < 1.0) {
+        cubic0(m, u, a);
+        bilinear(m, top >= 1 ? 1 : 0, u, b);
+        for (int c = 0; c < 4; ++c) out[c] = (1.0 - lam) * a[c] + lam * b[c];
+    } else {
+        double k = floor(lam), fr = lam - k;
+        if (k >= top) {
+            bilinear(m, top, u, out);
+        } else {
+            bilinear(m, (int)k, u, a);
+            bilinear(m, (int)k + 1, u, b);
+            for (int c = 0; c < 4; ++c) out[c] = (1.0 - fr) * a[c] + fr * b[c];
+        }
+    }
+}
+
+/* Level of detail from the Jacobian: log2 of the longer column. */
+double orc_unfov_lod(const double J[4]) {
+    double c0 = sqrt(J[0] * J[0] + J[2] * J[2]), c1 = sqrt(J[1] * J[1] + J[3] * J[3]);
+    double l = c0 > c1 ? c0 : c1;
+    return log2(l);
+}
+
+/* Display image of the MIP form (mode 0) or the reconstruction filter
+ * (mode 1, Gaussian sigma in display pixels).  fov: [H][W][4], out:
+ * [Hd][Wd][4].  pix (nullable) selects display pixels (row-major indices);
+ * out then holds npix entries. */
+void orc_unfoveate_image(const double *vp, const double *fov, int Wd, int Hd, int mode, double sigma,
+                         const int64_t *pix, int64_t npix, double *out) {
+    int W = (int)vp[ORC_W], H = (int)vp[ORC_H];
+    orc_mip m;
+    mip_build(&m, fov, W, H);
+    if (!pix) npix = (int64_t)Wd * Hd;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t q = 0; q < npix; ++q) {
+        int64_t p = pix ? pix[q] : q;
+        double a = (double)(p % Wd), b = (double)(p / Wd);
+        double u[2], J[4], c[4];
+        orc_unfov_coord(vp, Wd, Hd, a, b, u, J);
+        if (mode == 0) {
+            mip_sample(&m, u, orc_unfov_lod(J), c);
+        } else {
+            int i0 = (int)floor(u[0] + 0.5), j0 = (int)floor(u[1] + 0.5);
+            double acc[4] = {0, 0, 0, 0}, ws = 0.0;
+            for (int dj = -2; dj <= 2; ++dj)
+                for (int di = -2; di <= 2; ++di) {
+                    int i = i0 + di, j = j0 + dj;
+                    if (i < 0 || i >= W || j < 0 || j >= H) continue;
+                    double yv[2] = {2.0 * (i + 0.5) / W - 1.0, 1.0 - 2.0 * (j + 0.5) / H}, xv[2];
+                    orc_unfoveate(vp, yv, xv);
+                    double da = (xv[0] + 1.0) * 0.5 * Wd - 0.5 - a, db = (1.0 - xv[1]) * 0.5 * Hd - 0.5 - b;
+                    double w = exp(-(da * da + db * db) / (2.0 * sigma * sigma));
+                    ws += w;
+                    for (int ch = 0; ch < 4; ++ch) acc[ch] += w * fov[4 * ((size_t)j * W + i) + ch];
+                }
+            int ic = i0 < 0 ? 0 : (i0 > W - 1 ? W - 1 : i0), jc = j0 < 0 ? 0 : (j0 > H - 1 ? H - 1 : j0);
+            for (int ch = 0; ch < 4; ++ch) c[ch] = ws > 0.0 ? acc[ch] / ws : fov[4 * ((size_t)jc * W + ic) + ch];
+        }
+        for (int ch = 0; ch < 4; ++ch) out[4 * q + ch] = c[ch];
+    }
+    mip_free(&m);
+}
+
+/* The MIP pyramid itself (tests): level k into out (w_k x h_k x 4), returns
+ * the number of levels; *w, *h receive level k's size. */
+int orc_mip_level(const double *fov, int W, int H, int k, double *out, int *w, int *h) {
+    orc_mip m;
+    mip_build(&m, fov, W, H);
+    int n = m.n;
+    if (k >= 0 && k < n) {
+        *w = m.w[k];
+        *h = m.h[k];
+        if (out) memcpy(out, m.lev[k], sizeof(double) * 4 * (size_t)m.w[k] * m.h[k]);
+    }
+    mip_free(&m);
+    return n;
+}

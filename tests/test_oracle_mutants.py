@@ -2,7 +2,8 @@
 
 Each case copies oracle/pr_oracle.c, plants one plausible mistake (a dropped
 term, a wrong sign or index, a swapped operand), builds the copy with gcc and
-runs tests/test_oracle_pins.py against it; the pins must fail.  Runs on the
+runs tests/test_oracle_pins.py and tests/test_oracle_display_pins.py
+against it; the pins must fail.  Runs on the
 CPU only.
 """
 import os
@@ -57,6 +58,17 @@ MUTANTS = {
     'fast_tie_to_higher_index': ('if (z < *bz || (z == *bz && f < *bid)) {', 'if (z < *bz || (z == *bz && f > *bid)) {'),
     'fast_cell_axes_swapped': ('size_t c = (size_t)grid_cell(x[1], g) * g + grid_cell(x[0], g);',
                                'size_t c = (size_t)grid_cell(x[0], g) * g + grid_cell(x[1], g);'),
+    # display unfoveation
+    'mip_texel_centre_shift': ('double uk0 = (u[0] + 0.5) * sc - 0.5, uk1 = (u[1] + 0.5) * sc - 0.5;',
+                               'double uk0 = u[0] * sc, uk1 = u[1] * sc;'),
+    'mip_box_mean_weight': ('dst[4 * ((size_t)j * w + i) + c] = 0.25 * s;', 'dst[4 * ((size_t)j * w + i) + c] = 0.3 * s;'),
+    'mip_odd_edge_wraps': ('if (ii > pw - 1) ii = pw - 1;', 'if (ii > pw - 1) ii = 0;'),
+    'lod_shorter_column': ('double l = c0 > c1 ? c0 : c1;', 'double l = c0 < c1 ? c0 : c1;'),
+    'catmull_rom_weight': ('w[1] = 0.5 * (2 - 5 * t * t + 3 * t * t * t);', 'w[1] = 0.5 * (2 - 4 * t * t + 3 * t * t * t);'),
+    'level_blend_reversed': ('out[c] = (1.0 - fr) * a[c] + fr * b[c];', 'out[c] = fr * a[c] + (1.0 - fr) * b[c];'),
+    'filter_distance_foveated': ('orc_unfoveate(vp, yv, xv);', 'xv[0] = yv[0]; xv[1] = yv[1];'),
+    'unfov_jacobian_sign': ('(e - 1.0) * s * d[r] * d[c] / rho2', '(1.0 - e) * s * d[r] * d[c] / rho2'),
+    'unfov_row_not_flipped': ('u[1] = (1.0 - y[1]) * 0.5 * H - 0.5;', 'u[1] = (y[1] + 1.0) * 0.5 * H - 0.5;'),
 }
 
 
@@ -72,7 +84,8 @@ def _run(name, tmp):
     subprocess.check_call(['gcc', '-O2', '-fopenmp', '-fPIC', '-shared', '-std=c11', '-o', so, c, '-lm'])
     env = dict(os.environ, PR_ORACLE_LIB=so, OMP_NUM_THREADS='2')
     r = subprocess.run([sys.executable, '-m', 'pytest', '-x', '-q', '-p', 'no:cacheprovider',
-                        os.path.join(ROOT, 'tests', 'test_oracle_pins.py')],
+                        os.path.join(ROOT, 'tests', 'test_oracle_pins.py'),
+                        os.path.join(ROOT, 'tests', 'test_oracle_display_pins.py')],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode
 
