@@ -86,6 +86,120 @@ def grad_leg(args, stream):
     return float(np.median(fwd_ms)), float(np.median(bwd_ms))
 
 
+def frame_distribution(r, stream, n):
+    """Per-frame times (ms) of n frames timed one by one with HIP events on
+    the frame's stream (bound, bin, ray cast with fused shading)."""
+    import numpy as np
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        r.bound()
+        r.bin()
+        r.raycast_shade(rgba8=True, rgb32=False)
+        b.record(stream)
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in ev])
+
+
+def sequential_eyes(sc, args, stream, n):
+    """The frame with each eye rendered by its own calls, one after the
+    other (two single-view renderers): mean ms over n frames."""
+    import torch
+
+    import scenegen
+    from paper_1806_05385_amd.render import Renderer
+    rs = []
+    for v in sc.views:
+        vv = scenegen.View(**{**v.__dict__, 'mesh': 0})
+        rr = Renderer([sc.meshes[v.mesh]], [vv], tile=args.tile, light=sc.light_dir, ambient=sc.ambient)
+        rr.frame(check=True, rgb32=False)
+        rs.append(rr)
+    for _ in range(3):
+        for rr in rs:
+            rr.frame(check=False, rgb32=False)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(n):
+        for rr in rs:
+            rr.bound()
+            rr.bin()
+            rr.raycast_shade(rgba8=True, rgb32=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def display_leg(sc, r, stream, n):
+    """Display unfoveation of the HMD frame (both eyes, displays of the
+    foveated images' size) in both forms: median ms, and HBM GB/s of the
+    algorithmic bytes (4 B read per foveated pixel, 4 B written per display
+    pixel) against 8 TB/s."""
+    import numpy as np
+    import torch
+
+    from paper_1806_05385_amd import binding as B
+    from paper_1806_05385_amd.render import Display
+    fov = [o['rgba8'] for o in r.outputs]
+    out = {}
+    for name, mode in (('mip', B.PR_UNFOV_MIP), ('filter', B.PR_UNFOV_FILTER)):
+        d = Display(sc.views, mode=mode, sigma=0.7)
+        for _ in range(3):
+            d.run(fov)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(stream)
+            d.run(fov)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        px = sum(v.width * v.height for v in sc.views)
+        nbytes = 8 * px
+        out[name] = {'ms': round(ms, 4), 'algorithmic_bytes': nbytes, 'GBps': round(nbytes / (ms * 1e-3) / 1e9, 1),
+                     'frac_of_hbm_peak': round(nbytes / (ms * 1e-3) / 8e12, 4)}
+    return out
+
+
+def bound_ablation(sc, args, stream, n):
+    """The HMD frame under each rolling bound of Sec. 4.2 (Zenon, Adaptive,
+    Hull, Quad): listed pairs, ray-triangle tests, sample test efficiency
+    (hits / tests, counted in a separate frame) and the mean frame time."""
+    import torch
+
+    from paper_1806_05385_amd import binding as B
+    from paper_1806_05385_amd.render import Renderer
+    out = {}
+    for name, mode in (('zenon', B.PR_BOUND_ZENON), ('adaptive', B.PR_BOUND_ADAPTIVE), ('hull', B.PR_BOUND_HULL),
+                       ('quad', B.PR_BOUND_QUAD)):
+        rr = Renderer(sc.meshes, sc.views, tile=args.tile, light=sc.light_dir, ambient=sc.ambient, bound=mode)
+        rr.frame(check=True, rgb32=False)
+        rr.flags = B.PR_FLAG_COUNT | B.PR_FLAG_PERSISTENT
+        rr._prepare()
+        rr.frame(check=True, rgb32=False)
+        st = rr.status()
+        rr.flags = B.PR_FLAG_PERSISTENT
+        rr._prepare()
+        for _ in range(3):
+            rr.frame(check=False, rgb32=False)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(n):
+            rr.bound()
+            rr.bin()
+            rr.raycast_shade(rgba8=True, rgb32=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = {'frame_ms': round(e0.elapsed_time(e1) / n, 4), 'pairs': int(st.pairs_total),
+                     'candidates': int(st.pairs_required), 'tests': int(st.tests),
+                     'ste': round(int(st.hits) / max(int(st.tests), 1), 4)}
+        del rr
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -170,6 +284,10 @@ def main():
     ms_step = t0.elapsed_time(t1) / args.steps
     ray_ms = np.array([a.elapsed_time(b) for a, b in ev])
     ray_ms_avg = float(ray_ms.mean())
+    # the frame's distribution, timed frame by frame (not the headline)
+    dist = frame_distribution(r, stream, max(200, args.steps))
+    px_total = sum(v.width * v.height for v in sc.views)
+    fb_bytes = 12 * px_total     # id, depth and RGBA8 written once per pixel
 
     rolling = any(v.roll_dir[0] or v.roll_dir[1] for v in sc.views)
     flop_test = FLOP_PER_TEST_MOVING if rolling else FLOP_PER_TEST_STATIC
@@ -179,8 +297,11 @@ def main():
     if args.only == 'hmd':
         args.no_cpu_baseline = True
     fwd_med = bwd_med = float('nan')
-    batch_out = large_out = None
+    batch_out = large_out = seq_eyes_ms = display_out = ablation_out = None
     if args.only == 'all':
+        seq_eyes_ms = sequential_eyes(sc, args, stream, 50)
+        display_out = display_leg(sc, r, stream, 50)
+        ablation_out = bound_ablation(sc, args, stream, 20)
         fwd_med, bwd_med = grad_leg(args, stream)
 
         # batched form: 64 views (log-uniform 128..2048 px, 1k..500k triangles)
@@ -216,19 +337,44 @@ def main():
                 rr.raycast_shade(rgba8=True, rgb32=False)
         seq_round()
         torch.cuda.synchronize()
+        h0 = time.perf_counter()
         e0.record(stream)
         for _ in range(nb):
             seq_round()
         e1.record(stream)
+        h1 = time.perf_counter()
         torch.cuda.synchronize()
         seq_ms = e0.elapsed_time(e1) / nb
+        seq_enqueue_ms = (h1 - h0) * 1e3 / nb
+        # the same 64 plain frames captured once into a graph and replayed:
+        # their GPU time without the host's launch overhead
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            seq_round()
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g, stream=side):
+                seq_round()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(nb):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        seq_graph_ms = e0.elapsed_time(e1) / nb
         n_views = len(bsc.views)
         batch_out = {'views': n_views, 'pixels': int(sum(v.width * v.height for v in bsc.views)),
                      'triangles': int(sum(bsc.meshes[v.mesh].nt for v in bsc.views)), 'tile': binfo['tile'],
                      'trial_ms': binfo['trial_ms'], 'batched_ms': round(batch_ms, 4), 'sequential_ms': round(seq_ms, 4),
                      'batched_views_per_s': round(n_views / (batch_ms * 1e-3), 1),
                      'sequential_views_per_s': round(n_views / (seq_ms * 1e-3), 1),
-                     'speedup': round(seq_ms / batch_ms, 3)}
+                     'speedup': round(seq_ms / batch_ms, 3),
+                     'sequential_host_enqueue_ms': round(seq_enqueue_ms, 4),
+                     'sequential_graph_ms': round(seq_graph_ms, 4),
+                     'speedup_vs_sequential_graph': round(seq_graph_ms / batch_ms, 3)}
         bt.close()
         del seq
 
@@ -262,7 +408,6 @@ def main():
         c0 = time.perf_counter()
         orc.render(pix)
         c1 = time.perf_counter()
-        px_total = sum(v.width * v.height for v in sc.views)
         cpu_ms = (c1 - c0) / len(pix) * px_total * 1e3
         cpu = {'value': round(cpu_ms, 1), 'unit': 'ms/frame', 'cores': threads, 'kind': 'oracle',
                'sample': f'{len(pix)} pixels of eye 0 (half within 0.1 NDC of the fovea) x {mesh.nt} triangles, '
@@ -286,6 +431,14 @@ def main():
                    'views': len(sc.views), 'width': sc.views[0].width, 'height': sc.views[0].height,
                    'tile': args.tile},
         'frames_per_s': round(1e3 / ms_step, 1),
+        'frame_ms_dist': {'frames': int(len(dist)), 'median': round(float(np.median(dist)), 4),
+                          'p10': round(float(np.percentile(dist, 10)), 4),
+                          'p90': round(float(np.percentile(dist, 90)), 4)},
+        'sequential_eyes_ms': round(seq_eyes_ms, 4) if seq_eyes_ms is not None else None,
+        'framebuffer': {'bytes': fb_bytes, 'GBps': round(fb_bytes / (ray_ms_avg * 1e-3) / 1e9, 1),
+                        'frac_of_hbm_peak': round(fb_bytes / (ray_ms_avg * 1e-3) / 8e12, 4)},
+        'display': display_out,
+        'bound_ablation': ablation_out,
         'raycast_shade_ms': round(ray_ms_avg, 4),
         'tests_per_frame': tests,
         'tests_per_s': round(tests / (ray_ms_avg * 1e-3), 1),

@@ -123,6 +123,15 @@ typedef struct pr_light {
 } pr_light;
 
 /* tile: square tile side in pixels, one of 8, 16, 32.
+ * bound: the rolling bound (Sec. 4.2), PR_BOUND_ZENON (default, 0): the
+ *   exact frame-time window in which the rolling scan catches up with the
+ *   moving triangle, hull of the triangle at its ends; PR_BOUND_ADAPTIVE:
+ *   the window spanned by the scan times of the six projected start / end
+ *   vertices, hull at its ends; PR_BOUND_HULL: the whole frame, hull of the
+ *   six projected vertices; PR_BOUND_QUAD: the whole frame, their bounding
+ *   box.  All are conservative (no covered pixel is dropped) and give the
+ *   same images; they differ in the pairs and tests a frame spends.  Views
+ *   without rolling use one instant whatever the bound.
  * bin_capacity: (triangle, tile) candidate pairs a frame can hold (all
  *   views; each candidate of a triangle's tile rectangle takes one slot,
  *   and the tile lists hold the candidates that survive the tile test).
@@ -135,11 +144,16 @@ typedef struct pr_tuning {
     int32_t tile;
     int32_t bin_capacity;
     int32_t flags;
-    int32_t reserved;
+    int32_t bound;
 } pr_tuning;
 
 #define PR_FLAG_COUNT 1
 #define PR_FLAG_PERSISTENT 2
+
+#define PR_BOUND_ZENON 0
+#define PR_BOUND_ADAPTIVE 1
+#define PR_BOUND_HULL 2
+#define PR_BOUND_QUAD 3
 
 /* Device-side conditions of the last frame (all views). */
 typedef struct pr_status {
@@ -221,6 +235,56 @@ int pr_backward(const pr_mesh *meshes, int nm, const pr_view *views, int nv, con
                 const float *const *albedo, const float *const *dl_drgb, float *const *dv0,
                 float *const *dv1, float *dpose0, float *dpose1, void *stream);
 
+/* DISPLAY UNFOVEATION (Sec. 3.1.1 "Display").  The foveated image of each
+ * view (the ray cast's RGBA8 output: its pixel grid lives in the foveated
+ * domain) is resampled to the display's regular pixel grid.  Display pixel
+ * (a, b) of a width x height display has display NDC x = (2(a+1/2)/width -
+ * 1, 1 - 2(b+1/2)/height); it samples the foveated image at the foveated
+ * position of x (the inverse of the view's unfoveate map, same fovea,
+ * alpha and normalising radius), in continuous foveated pixel coordinates
+ * u = ((y0+1)/2 W - 1/2, (1-y1)/2 H - 1/2), edges clamped.
+ *   PR_UNFOV_MIP: a MIP pyramid of the foveated image (2x2 box means,
+ *     sizes halved rounding up, the last row / column repeated) sampled
+ *     with level of detail log2 of the longer image of a display pixel step
+ *     in foveated pixels: Catmull-Rom interpolation of the finest level
+ *     where the display magnifies (lod <= 0), blended linearly into the
+ *     bilinear sample of level 1 for 0 < lod < 1, trilinear above.
+ *   PR_UNFOV_FILTER: the 5 x 5 foveated pixels around the nearest one, each
+ *     weighted by exp(-d^2 / (2 sigma^2)), d its distance in display pixels
+ *     from the display pixel after unfoveating its centre, normalised
+ *     (the paper's reconstruction filter r, Gaussian).
+ * Display pixels whose foveated position lies beyond the foveated image
+ * (the power map leaves parts of the display uncovered when the fovea is
+ * not at the centre) take the image's edge.  Arithmetic in FP32; output
+ * RGBA8 = floor(clamp(c, 0, 1) 255 + 1/2) per channel (alpha filtered too).
+ */
+#define PR_UNFOV_MIP 0
+#define PR_UNFOV_FILTER 1
+
+/* The display of one view: its size (1..16384 pixels each way), the form,
+ * and for PR_UNFOV_FILTER the Gaussian's sigma in display pixels (> 0). */
+typedef struct pr_display {
+    int32_t width, height;
+    int32_t mode;
+    float sigma;
+} pr_display;
+
+/* Bytes of workspace pr_unfoveate needs (the pyramids of the MIP views:
+ * about 16/3 bytes per foveated pixel).  Returns PR_OK or PR_ERR_INVALID. */
+int pr_unfoveate_workspace_size(const pr_view *views, int nv, const pr_display *disp, size_t *bytes);
+
+/* Display unfoveation of nv views (one launch per pass over all views).
+ * views: the views whose foveated images are given (width, height, fovea,
+ * alpha are used); disp[v]: view v's display; fov_rgba8[v]: uint8
+ * [H][W][4] device (read only); disp_rgba8[v]: uint8 [height][width][4]
+ * device (fully overwritten); ws: device workspace of at least
+ * pr_unfoveate_workspace_size bytes, 256-byte aligned (contents need no
+ * initialisation).  Stream-ordered, allocates nothing.  Returns PR_OK,
+ * PR_ERR_INVALID, PR_ERR_WORKSPACE or PR_ERR_HIP; arguments are checked
+ * before anything is enqueued. */
+int pr_unfoveate(const pr_view *views, int nv, const pr_display *disp, const uint8_t *const *fov_rgba8,
+                 uint8_t *const *disp_rgba8, void *ws, size_t ws_bytes, void *stream);
+
 /* BATCHED FORM.  A batch renders many views (eyes, frames, scenes) of
  * uneven size and triangle count as one frame: every pass is one launch over
  * all views, the ray cast (with the shading fused in) is one resident grid
@@ -276,7 +340,8 @@ int pr_debug_tile_lists(const pr_mesh *meshes, int nm, const pr_view *views, int
 
 /* Host evaluation of the bound pieces, for CPU tests of their
  * conservativeness without a GPU (the same code the kernels run).  `mesh`
- * holds HOST pointers here.
+ * holds HOST pointers here; bound is a PR_BOUND_* mode (-1 for another
+ * value).
  * pr_host_time_interval: the frame-time window of triangle f in `view`;
  *   returns 0 (culled: never visible), 1 (window t[0..1]) or 2 (the near
  *   plane cuts the triangle; the window is the whole frame).
@@ -285,10 +350,11 @@ int pr_debug_tile_lists(const pr_mesh *meshes, int nm, const pr_view *views, int
  * pr_host_tile_test: the quadrant mask binning gives the pair (triangle f,
  *   tile (tx, ty)) (as in pr_debug_tile_lists); 0 if the pair is rejected
  *   (or the triangle is culled). */
-int pr_host_time_interval(const pr_mesh *mesh, int32_t f, const pr_view *view, double *t);
-int pr_host_tile_rect(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t tile, int32_t *rect);
-int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t tile, int32_t tx,
-                      int32_t ty);
+int pr_host_time_interval(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, double *t);
+int pr_host_tile_rect(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, int32_t tile,
+                      int32_t *rect);
+int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, int32_t tile,
+                      int32_t tx, int32_t ty);
 
 #ifdef __cplusplus
 }

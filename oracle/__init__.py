@@ -82,6 +82,8 @@ def lib():
                                           lp, i64, dp]
         L.orc_mip_level.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ip, ip]
         L.orc_mip_level.restype = ctypes.c_int
+        L.orc_unfov_filter_at.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
         _lib = L
     return _lib
 
@@ -311,3 +313,15 @@ def mip_level(fov, k: int):
 def to_rgba8(c) -> np.ndarray:
     """floor(clamp(c, 0, 1) * 255 + 1/2) as uint8."""
     return np.floor(np.clip(c, 0.0, 1.0) * 255.0 + 0.5).astype(np.uint8)
+
+
+def unfov_filter_at(view, fov, width: int, height: int, a: int, b: int, i0: int, j0: int,
+                    sigma: float) -> np.ndarray:
+    """The reconstruction filter at display pixel (a, b) with its 5 x 5
+    window centred on foveated pixel (i0, j0)."""
+    vp = view_params(view)
+    f = _rgba01(fov)
+    out = np.empty(4)
+    lib().orc_unfov_filter_at(_p(vp, ctypes.c_double), _p(f, ctypes.c_double), width, height, a, b, i0, j0, sigma,
+                              _p(out, ctypes.c_double))
+    return out

@@ -919,15 +919,37 @@ double orc_unfov_lod(const double J[4]) {
     return log2(l);
 }
 
+/* The reconstruction filter at display pixel (a, b) with its 5 x 5 window
+ * centred on foveated pixel (i0, j0) (the nearest one to u in the
+ * definition; tests evaluate the neighbouring windows where the nearest is
+ * a floating-point tie).  fov: [H][W][4]; out: 4 doubles. */
+void orc_unfov_filter_at(const double *vp, const double *fov, int Wd, int Hd, int a, int b, int i0, int j0,
+                         double sigma, double out[4]) {
+    int W = (int)vp[ORC_W], H = (int)vp[ORC_H];
+    double acc[4] = {0, 0, 0, 0}, ws = 0.0;
+    for (int dj = -2; dj <= 2; ++dj)
+        for (int di = -2; di <= 2; ++di) {
+            int i = i0 + di, j = j0 + dj;
+            if (i < 0 || i >= W || j < 0 || j >= H) continue;
+            double yv[2] = {2.0 * (i + 0.5) / W - 1.0, 1.0 - 2.0 * (j + 0.5) / H}, xv[2];
+            orc_unfoveate(vp, yv, xv);
+            double da = (xv[0] + 1.0) * 0.5 * Wd - 0.5 - a, db = (1.0 - xv[1]) * 0.5 * Hd - 0.5 - b;
+            double w = exp(-(da * da + db * db) / (2.0 * sigma * sigma));
+            ws += w;
+            for (int ch = 0; ch < 4; ++ch) acc[ch] += w * fov[4 * ((size_t)j * W + i) + ch];
+        }
+    int ic = i0 < 0 ? 0 : (i0 > W - 1 ? W - 1 : i0), jc = j0 < 0 ? 0 : (j0 > H - 1 ? H - 1 : j0);
+    for (int ch = 0; ch < 4; ++ch) out[ch] = ws > 0.0 ? acc[ch] / ws : fov[4 * ((size_t)jc * W + ic) + ch];
+}
+
 /* Display image of the MIP form (mode 0) or the reconstruction filter
  * (mode 1, Gaussian sigma in display pixels).  fov: [H][W][4], out:
  * [Hd][Wd][4].  pix (nullable) selects display pixels (row-major indices);
  * out then holds npix entries. */
 void orc_unfoveate_image(const double *vp, const double *fov, int Wd, int Hd, int mode, double sigma,
                          const int64_t *pix, int64_t npix, double *out) {
-    int W = (int)vp[ORC_W], H = (int)vp[ORC_H];
     orc_mip m;
-    mip_build(&m, fov, W, H);
+    mip_build(&m, fov, (int)vp[ORC_W], (int)vp[ORC_H]);
     if (!pix) npix = (int64_t)Wd * Hd;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t q = 0; q < npix; ++q) {
@@ -939,20 +961,7 @@ void orc_unfoveate_image(const double *vp, const double *fov, int Wd, int Hd, in
             mip_sample(&m, u, orc_unfov_lod(J), c);
         } else {
             int i0 = (int)floor(u[0] + 0.5), j0 = (int)floor(u[1] + 0.5);
-            double acc[4] = {0, 0, 0, 0}, ws = 0.0;
-            for (int dj = -2; dj <= 2; ++dj)
-                for (int di = -2; di <= 2; ++di) {
-                    int i = i0 + di, j = j0 + dj;
-                    if (i < 0 || i >= W || j < 0 || j >= H) continue;
-                    double yv[2] = {2.0 * (i + 0.5) / W - 1.0, 1.0 - 2.0 * (j + 0.5) / H}, xv[2];
-                    orc_unfoveate(vp, yv, xv);
-                    double da = (xv[0] + 1.0) * 0.5 * Wd - 0.5 - a, db = (1.0 - xv[1]) * 0.5 * Hd - 0.5 - b;
-                    double w = exp(-(da * da + db * db) / (2.0 * sigma * sigma));
-                    ws += w;
-                    for (int ch = 0; ch < 4; ++ch) acc[ch] += w * fov[4 * ((size_t)j * W + i) + ch];
-                }
-            int ic = i0 < 0 ? 0 : (i0 > W - 1 ? W - 1 : i0), jc = j0 < 0 ? 0 : (j0 > H - 1 ? H - 1 : j0);
-            for (int ch = 0; ch < 4; ++ch) c[ch] = ws > 0.0 ? acc[ch] / ws : fov[4 * ((size_t)jc * W + ic) + ch];
+            orc_unfov_filter_at(vp, fov, Wd, Hd, (int)a, (int)b, i0, j0, sigma, c);
         }
         for (int ch = 0; ch < 4; ++ch) out[4 * q + ch] = c[ch];
     }

@@ -17,6 +17,12 @@ PR_ERR_HIP = -4
 PR_MAX_VIEWS = 64
 PR_FLAG_COUNT = 1
 PR_FLAG_PERSISTENT = 2
+PR_BOUND_ZENON = 0
+PR_BOUND_ADAPTIVE = 1
+PR_BOUND_HULL = 2
+PR_BOUND_QUAD = 3
+PR_UNFOV_MIP = 0
+PR_UNFOV_FILTER = 1
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
 c_int32_p = ctypes.POINTER(ctypes.c_int32)
@@ -41,7 +47,12 @@ class PrLight(ctypes.Structure):
 
 class PrTuning(ctypes.Structure):
     _fields_ = [('tile', ctypes.c_int32), ('bin_capacity', ctypes.c_int32), ('flags', ctypes.c_int32),
-                ('reserved', ctypes.c_int32)]
+                ('bound', ctypes.c_int32)]
+
+
+class PrDisplay(ctypes.Structure):
+    _fields_ = [('width', ctypes.c_int32), ('height', ctypes.c_int32), ('mode', ctypes.c_int32),
+                ('sigma', ctypes.c_float)]
 
 
 class PrStatus(ctypes.Structure):
@@ -68,6 +79,10 @@ SIGNATURES = {
     'pr_raycast_shade': (ctypes.c_int, _FRAME + [_PP, _PP, ctypes.POINTER(PrLight), _PP, _PP, _PP, ctypes.c_void_p]),
     'pr_backward': (ctypes.c_int, _FRAME + [_PP, ctypes.POINTER(PrLight), _PP, _PP, _PP, _PP, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p]),
+    'pr_unfoveate_workspace_size': (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(PrDisplay),
+                                                   ctypes.POINTER(ctypes.c_size_t)]),
+    'pr_unfoveate': (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(PrDisplay), _PP, _PP, ctypes.c_void_p,
+                                    ctypes.c_size_t, ctypes.c_void_p]),
     'pr_status_read': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(PrStatus), ctypes.c_void_p]),
     'pr_status_string': (ctypes.c_char_p, [ctypes.c_int]),
     'pr_debug_tile_lists': (ctypes.c_int, _FRAME[:5] + [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, c_int32_p,
@@ -80,9 +95,10 @@ SIGNATURES = {
                                      ctypes.POINTER(ctypes.c_double)]),
     'pr_batch_status': (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PrStatus), ctypes.c_void_p]),
     'pr_batch_destroy': (ctypes.c_int, [ctypes.c_void_p]),
-    'pr_host_time_interval': (ctypes.c_int, [_MP, ctypes.c_int32, _VP, ctypes.POINTER(ctypes.c_double)]),
-    'pr_host_tile_rect': (ctypes.c_int, [_MP, ctypes.c_int32, _VP, ctypes.c_int32, c_int32_p]),
-    'pr_host_tile_test': (ctypes.c_int, [_MP, ctypes.c_int32, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    'pr_host_time_interval': (ctypes.c_int, [_MP, ctypes.c_int32, _VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    'pr_host_tile_rect': (ctypes.c_int, [_MP, ctypes.c_int32, _VP, ctypes.c_int32, ctypes.c_int32, c_int32_p]),
+    'pr_host_tile_test': (ctypes.c_int, [_MP, ctypes.c_int32, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32]),
 }
 
 _lib = None

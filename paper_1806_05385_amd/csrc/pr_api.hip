@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "pr.h"
+#include "pr_display.hip"
 #include "pr_kernels.hip"
 
 using namespace prk;
@@ -65,6 +66,7 @@ int check_args(const pr_mesh *meshes, int nm, const pr_view *views, int nv, cons
     }
     if (tu->tile != 8 && tu->tile != 16 && tu->tile != 32) return PR_ERR_UNSUPPORTED;
     if (tu->bin_capacity < 1) return PR_ERR_INVALID;
+    if (tu->bound < PR_BOUND_ZENON || tu->bound > PR_BOUND_QUAD) return PR_ERR_INVALID;
     return PR_OK;
 }
 
@@ -113,6 +115,7 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
         d.tri_block0 = (int32_t)tri_blocks;
         d.pix_block0 = (int32_t)pix_blocks;
         d.rolling = rolling(V) ? 1 : 0;
+        d.bound = tu->bound;
         d.rec_w = d.rolling ? kRecRoll : kRecStatic;
         d.rec_off = rec4;
         d.tri_off = tris;
@@ -155,7 +158,7 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     L.gacc = off; off = up(off + (size_t)gacc * 4);
     L.pacc = off; off = up(off + ((size_t)pix_blocks + 1) * kPoseAcc * 8);   // per pixel block (backward)
     L.sched = off; off = up(off + sizeof(Sched));
-    L.order = off; off = up(off + (size_t)tiles * 16);
+    L.order = off; off = up(off + (size_t)tiles * 16 * kXcds);   // one tile order per XCD share
     L.bytes = off;
     return PR_OK;
 }
@@ -251,11 +254,14 @@ void launch_raycast_t(int flags, const Layout &L, void *ws, const RayOut &out, c
         res = resident_blocks(k_raycast_queue<TILE, COUNT, SHADE>, C::NT);
         resident[dev].store(res, std::memory_order_relaxed);
     }
-    const int resident_n = res;
-    const int nitems = ray_items<TILE>(L.total_tiles);
-    const int grid = std::max(1, std::min(nitems, resident_n));
+    // items: at most every tile in one XCD share (the device knows the
+    // exact count); the grid a multiple of the XCD count
+    const int64_t bound_items = (int64_t)kXcds * share_items(TILE, L.total_tiles);
+    int grid = (int)std::min<int64_t>(bound_items, (int64_t)std::max(res, kXcds));
+    grid = std::max(kXcds, grid - grid % kXcds);
     hipLaunchKernelGGL((k_raycast_queue<TILE, COUNT, SHADE>), dim3(grid), dim3(C::NT), 0, s, T, at<float4>(ws, L.rec),
-                       at<uint32_t>(ws, L.lists), out, st, at<int4>(ws, L.order), nitems, sio, light);
+                       at<uint32_t>(ws, L.lists), out, st, at<int4>(ws, L.order), at<Sched>(ws, L.sched), sio,
+                       light);
 }
 
 template <int TILE, bool SHADE>
@@ -345,8 +351,8 @@ int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     int n = L.total_tiles + 1;
     hipLaunchKernelGGL(k_scan_reduce, dim3(L.nparts), dim3(256), 0, s, at<uint32_t>(ws, L.tcount), n,
                        at<uint32_t>(ws, L.part));
-    hipLaunchKernelGGL(k_scan_apply, dim3(L.nparts), dim3(256), 0, s, at<uint32_t>(ws, L.tcount), n, L.total_tiles,
-                       at<uint32_t>(ws, L.part), at<uint32_t>(ws, L.toff), at<Sched>(ws, L.sched));
+    hipLaunchKernelGGL(k_scan_apply, dim3(L.nparts), dim3(256), 0, s, T, at<uint32_t>(ws, L.tcount), n,
+                       L.total_tiles, at<uint32_t>(ws, L.part), at<uint32_t>(ws, L.toff), at<Sched>(ws, L.sched));
     // pairs (grid-stride) and the persistent ray cast's tile order (one
     // block per 256 tiles)
     int sb = (int)std::min<int64_t>(std::max<int64_t>((L.cap + 255) / 256, 1), 2048);
@@ -529,24 +535,26 @@ int pr_debug_tile_lists(const pr_mesh *meshes, int nm, const pr_view *views, int
 // ---------------------------------------------------------------------------
 // host evaluation of the bound (tests)
 // ---------------------------------------------------------------------------
-int pr_host_time_interval(const pr_mesh *mesh, int32_t f, const pr_view *view, double *t) {
-    if (!mesh || !view || !t || f < 0 || f >= mesh->nt) return -1;
+int pr_host_time_interval(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, double *t) {
+    if (!mesh || !view || !t || f < 0 || f >= mesh->nt || bound < 0 || bound > PR_BOUND_QUAD) return -1;
     prg::Geom g;
     prg::make_geom(*view, g);
     double Ps[3][3], Pe[3][3];
     int32_t idx[3];
     if (!prg::load_tri(mesh->v0, mesh->v1, mesh->tri, mesh->nv, f, g, Ps, Pe, idx)) return 0;
-    return prg::time_window(g, Ps, Pe, t);
+    return prg::time_window(g, Ps, Pe, t, bound);
 }
 
-int pr_host_tile_rect(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t tile, int32_t *rect) {
-    if (!mesh || !view || !rect || f < 0 || f >= mesh->nt || tile < 1) return -1;
+int pr_host_tile_rect(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, int32_t tile,
+                      int32_t *rect) {
+    if (!mesh || !view || !rect || f < 0 || f >= mesh->nt || tile < 1 || bound < 0 || bound > PR_BOUND_QUAD)
+        return -1;
     prg::Geom g;
     prg::make_geom(*view, g);
     double Ps[3][3], Pe[3][3], win[2], box[4];
     int32_t idx[3];
     if (!prg::load_tri(mesh->v0, mesh->v1, mesh->tri, mesh->nv, f, g, Ps, Pe, idx)) return 0;
-    int kind = prg::time_window(g, Ps, Pe, win);
+    int kind = prg::time_window(g, Ps, Pe, win, bound);
     if (kind == prg::kCulled) return 0;
     prg::display_box(g, Ps, Pe, win[0], win[1], kind, box);
     int r[4];
@@ -555,14 +563,15 @@ int pr_host_tile_rect(const pr_mesh *mesh, int32_t f, const pr_view *view, int32
     return 1;
 }
 
-int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t tile, int32_t tx, int32_t ty) {
-    if (!mesh || !view || f < 0 || f >= mesh->nt || tile < 1) return -1;
+int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, int32_t tile, int32_t tx,
+                      int32_t ty) {
+    if (!mesh || !view || f < 0 || f >= mesh->nt || tile < 1 || bound < 0 || bound > PR_BOUND_QUAD) return -1;
     prg::Geom g;
     prg::make_geom(*view, g);
     double Ps[3][3], Pe[3][3], win[2], box[4];
     int32_t idx[3];
     if (!prg::load_tri(mesh->v0, mesh->v1, mesh->tri, mesh->nv, f, g, Ps, Pe, idx)) return 0;
-    int kind = prg::time_window(g, Ps, Pe, win);
+    int kind = prg::time_window(g, Ps, Pe, win, bound);
     if (kind == prg::kCulled) return 0;
     prg::display_box(g, Ps, Pe, win[0], win[1], kind, box);
     int r[4];
@@ -571,10 +580,129 @@ int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32
     double w[4];
     if (kind == prg::kWindow) { w[0] = win[0]; w[1] = win[1]; w[2] = w[3] = 0.0; }
     else for (int k = 0; k < 4; ++k) w[k] = box[k];
-    return prg::tile_mask(g, Ps, Pe, kind, w, tile, tx, ty);
+    return prg::tile_mask(g, Ps, Pe, kind, w, tile, tx, ty, bound);
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// display unfoveation
+// ---------------------------------------------------------------------------
+namespace {
+
+struct DispLayout {
+    int nv;
+    prd::DispView v[PR_MAX_VIEWS];
+    int total_blocks, total_tiles, max_levels;
+    bool any_mip;
+    size_t pyr, bytes;
+};
+
+int disp_layout(const pr_view *views, int nv, const pr_display *disp, DispLayout &L) {
+    if (!views || !disp || nv < 1 || nv > PR_MAX_VIEWS) return PR_ERR_INVALID;
+    L.nv = nv;
+    int64_t blocks = 0, tiles = 0, f4 = 0;
+    L.max_levels = 1;
+    L.any_mip = false;
+    for (int i = 0; i < nv; ++i) {
+        const pr_view &V = views[i];
+        const pr_display &D = disp[i];
+        if (V.width < 1 || V.height < 1 || V.width > 16384 || V.height > 16384) return PR_ERR_INVALID;
+        if (D.width < 1 || D.height < 1 || D.width > 16384 || D.height > 16384) return PR_ERR_INVALID;
+        float misc[4] = {V.fovea[0], V.fovea[1], V.alpha, D.sigma};
+        if (!finite_all(misc, 3)) return PR_ERR_INVALID;
+        if (!(V.alpha >= 1.0f) || V.alpha > 16.0f) return PR_ERR_INVALID;
+        if (fabsf(V.fovea[0]) > 1.0f || fabsf(V.fovea[1]) > 1.0f) return PR_ERR_INVALID;
+        if (D.mode != PR_UNFOV_MIP && D.mode != PR_UNFOV_FILTER) return PR_ERR_INVALID;
+        if (D.mode == PR_UNFOV_FILTER && !(isfinite(D.sigma) && D.sigma > 0.0f)) return PR_ERR_INVALID;
+        prd::DispView &d = L.v[i];
+        memset(&d, 0, sizeof(d));
+        d.W = V.width; d.H = V.height; d.Wd = D.width; d.Hd = D.height;
+        d.mode = D.mode;
+        d.fov0 = V.fovea[0]; d.fov1 = V.fovea[1];
+        d.e = (float)(1.0 / (double)V.alpha);
+        d.invR = (float)(1.0 / prg::fovea_radius(V.fovea[0], V.fovea[1]));
+        d.powmode = V.alpha == 1.0f ? 0 : (V.alpha == 2.0f ? 1 : 2);
+        if (D.mode == PR_UNFOV_FILTER) d.inv2s2 = (float)(1.0 / (2.0 * (double)D.sigma * D.sigma));
+        d.blk0 = (int32_t)blocks;
+        blocks += (int64_t)((D.width + 31) / 32) * ((D.height + 7) / 8);
+        d.tile0 = (int32_t)tiles;
+        int w = V.width, h = V.height, n = 0;
+        for (;;) {
+            d.lw[n] = w;
+            d.lh[n] = h;
+            ++n;
+            if (w == 1 && h == 1) break;
+            w = (w + 1) / 2;
+            h = (h + 1) / 2;
+        }
+        d.nlev = n;
+        if (D.mode == PR_UNFOV_MIP) {
+            L.any_mip = true;
+            L.max_levels = std::max(L.max_levels, n);
+            d.tiles_x = (V.width + 31) / 32;
+            d.tiles_y = (V.height + 31) / 32;
+            tiles += (int64_t)d.tiles_x * d.tiles_y;
+            for (int k = 1; k < n; ++k) {   // each level on its own 256-byte lines
+                d.loff[k] = f4;
+                f4 += ((int64_t)d.lw[k] * d.lh[k] + 15) & ~(int64_t)15;
+            }
+        }
+    }
+    if (blocks > INT32_MAX / 2 || tiles > INT32_MAX / 2) return PR_ERR_INVALID;
+    L.total_blocks = (int)blocks;
+    L.total_tiles = (int)tiles;
+    L.pyr = up(sizeof(prd::DispTable));
+    L.bytes = up(L.pyr + (size_t)f4 * 16);
+    return PR_OK;
+}
+
+}  // namespace
+
+extern "C" int pr_unfoveate_workspace_size(const pr_view *views, int nv, const pr_display *disp, size_t *bytes) {
+    if (!bytes) return PR_ERR_INVALID;
+    static thread_local DispLayout L;
+    int rc = disp_layout(views, nv, disp, L);
+    if (rc) return rc;
+    *bytes = L.bytes;
+    return PR_OK;
+}
+
+extern "C" int pr_unfoveate(const pr_view *views, int nv, const pr_display *disp, const uint8_t *const *fov_rgba8,
+                            uint8_t *const *disp_rgba8, void *ws, size_t ws_bytes, void *stream) {
+    static thread_local DispLayout L;
+    int rc = disp_layout(views, nv, disp, L);
+    if (rc) return rc;
+    rc = check_ws(ws, ws_bytes, L.bytes);
+    if (rc) return rc;
+    if (!fov_rgba8 || !disp_rgba8) return PR_ERR_INVALID;
+    prd::DispIO io;
+    memset(&io, 0, sizeof(io));
+    for (int v = 0; v < nv; ++v) {
+        if (!fov_rgba8[v] || !disp_rgba8[v]) return PR_ERR_INVALID;
+        io.fov[v] = fov_rgba8[v];
+        io.out[v] = disp_rgba8[v];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    prd::DispTable *T = at<prd::DispTable>(ws, 0);
+    float4 *pyr = at<float4>(ws, L.pyr);
+    for (int first = 0; first < nv; first += prd::kDispViewsPerWrite) {
+        prd::DispPack p;
+        memset(&p, 0, sizeof(p));
+        p.first = first;
+        p.count = std::min(prd::kDispViewsPerWrite, nv - first);
+        p.nv = nv;
+        p.total_blocks = L.total_blocks;
+        p.total_tiles = L.total_tiles;
+        for (int i = 0; i < p.count; ++i) p.v[i] = L.v[first + i];
+        hipLaunchKernelGGL(prd::k_disp_views, dim3(1), dim3(64), 0, s, p, T);
+    }
+    if (L.any_mip && L.total_tiles > 0)
+        hipLaunchKernelGGL(prd::k_mip_tile, dim3(L.total_tiles), dim3(256), 0, s, T, io, pyr);
+    if (L.max_levels > prd::kTileLevels + 1) hipLaunchKernelGGL(prd::k_mip_top, dim3(nv), dim3(1024), 0, s, T, pyr);
+    if (L.total_blocks > 0) hipLaunchKernelGGL(prd::k_unfov, dim3(L.total_blocks), dim3(256), 0, s, T, io, pyr);
+    return launched();
+}
 
 // ---------------------------------------------------------------------------
 // batched form: hipGraph of one frame over all views, autotuned

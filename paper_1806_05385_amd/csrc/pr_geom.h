@@ -243,6 +243,19 @@ PRG void sort8(double v[8]) {
 
 enum { kCulled = 0, kWindow = 1, kClipped = 2 };
 
+// Rolling bound modes (Sec. 4.2): the frame-time window and the display
+// region the per-tile test uses.
+//  kBoundZenon    the exact window in which the scan catches up with the
+//                 moving triangle (Sec. 4.2.4, made exact), hull at its ends
+//  kBoundAdaptive the window spanned by the scan times of the six projected
+//                 start / end vertices (Sec. 4.2.3), hull at its ends
+//  kBoundHull     the whole frame, hull of the six projected vertices
+//                 (Sec. 4.2.2)
+//  kBoundQuad     the whole frame, bounding box of the six (Sec. 4.2.1)
+// Every mode is conservative; the hull is the separating-axis test on the
+// edges of the two end triangles (any axis separates validly).
+enum { kBoundZenon = 0, kBoundAdaptive = 1, kBoundHull = 2, kBoundQuad = 3 };
+
 // Frame-time window in which the triangle can affect a pixel.
 //  kCulled : never (every space-time vertex behind the near plane, or the
 //            rolling scan never meets the triangle).
@@ -261,7 +274,8 @@ enum { kCulled = 0, kWindow = 1, kClipped = 2 };
 // t = 0 pixels with u <= 0 count, at t = 1 pixels with u >= 1.  Between the
 // roots of the h_k no sign changes, so testing each root and each gap's
 // midpoint gives the window exactly.
-PRG int time_window(const Geom &g, const double Ps[3][3], const double Pe[3][3], double win[2]) {
+PRG int time_window(const Geom &g, const double Ps[3][3], const double Pe[3][3], double win[2],
+                    int mode = kBoundZenon) {
     int n_in = 0, n_pts = g.rolling ? 6 : 3;
     for (int k = 0; k < 3; ++k) {
         n_in += Ps[k][2] >= g.znear;
@@ -275,6 +289,25 @@ PRG int time_window(const Geom &g, const double Ps[3][3], const double Pe[3][3],
     }
     if (!g.rolling) {
         win[0] = win[1] = 0.0;
+        return kWindow;
+    }
+    if (mode == kBoundHull || mode == kBoundQuad) {
+        win[0] = 0.0;
+        win[1] = 1.0;
+        return kWindow;
+    }
+    if (mode == kBoundAdaptive) {
+        // every covered display point lies in the hull of the six projected
+        // vertices, and its (unclamped) scan time is linear in the point:
+        // its frame time lies between the vertices' extreme scan times
+        double lo = 1e300, hi = -1e300;
+        for (int k = 0; k < 3; ++k) {
+            const double a = scan_numer(g, Ps[k]) / Ps[k][2], b = scan_numer(g, Pe[k]) / Pe[k][2];
+            lo = dmin(lo, dmin(a, b));
+            hi = dmax(hi, dmax(a, b));
+        }
+        win[0] = clamp01(lo - kSlackTime);
+        win[1] = clamp01(hi + kSlackTime);
         return kWindow;
     }
     double hc[3][3];  // h_k = hc[k][0] + hc[k][1] t + hc[k][2] t^2
@@ -496,9 +529,20 @@ struct SatRec {
 PRG float f32_clamp(float x) { return x < -1e30f ? -1e30f : (x > 1e30f ? 1e30f : x); }
 
 PRG void sat_build(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double w[4],
-                   SatRec &R) {
+                   SatRec &R, int mode = kBoundZenon) {
     R.kind = kind;
     R.pad = 0;
+    if (kind == kWindow && mode == kBoundQuad) {
+        // the box alone: the display box of the window ends, no edge axes
+        double box[4];
+        display_box(g, Ps, Pe, w[0], w[1], kind, box);
+        R.ext[0] = f32_clamp(f32_down(box[0])); R.ext[1] = f32_clamp(f32_up(box[1]));
+        R.ext[2] = f32_clamp(f32_down(box[2])); R.ext[3] = f32_clamp(f32_up(box[3]));
+        R.win[0] = f32_down(w[0]);
+        R.win[1] = f32_up(w[1]);
+        for (int a = 0; a < 6; ++a) { R.ax[a][0] = R.ax[a][1] = 0.0f; R.ax[a][2] = -1.0f; R.ax[a][3] = 1.0f; }
+        return;
+    }
     if (kind != kWindow) {
         R.ext[0] = f32_down(w[0]); R.ext[1] = f32_up(w[1]);
         R.ext[2] = f32_down(w[2]); R.ext[3] = f32_up(w[3]);
@@ -582,7 +626,7 @@ PRG bool split_quads(int tile) { return tile >= 16; }
 // and window built and rounded as the device builds them: a split tile's
 // box is the union of its quadrants' boxes.
 PRG int tile_mask(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double w[4],
-                  int tile, int tx, int ty) {
+                  int tile, int tx, int ty, int mode = kBoundZenon) {
     double tb[4], tw[2], qb[4][4];
     int qvalid = 0;
     if (!split_quads(tile)) {
@@ -607,7 +651,7 @@ PRG int tile_mask(const Geom &g, const double Ps[3][3], const double Pe[3][3], i
         fqb[k][2] = ok ? f32_down(qb[k][2]) : 0.0f; fqb[k][3] = ok ? f32_up(qb[k][3]) : 0.0f;
     }
     SatRec R;
-    sat_build(g, Ps, Pe, kind, w, R);
+    sat_build(g, Ps, Pe, kind, w, R, mode);
     return sat_mask(R, ftb, ftw, split_quads(tile) ? fqb : nullptr, qvalid);
 }
 

@@ -80,7 +80,7 @@ struct ViewDev {
     int32_t pix_block0;    // first 256-pixel block (shade and backward grids)
     int32_t rec_w;         // float4 per record
     int32_t rolling;
-    int32_t pad;
+    int32_t bound;         // rolling bound mode (prg::kBound*; pr_tuning.bound)
     int64_t rec_off;       // float4 offset of the view's first record
     int64_t tri_off;       // TriBound index of the view's first triangle
     int32_t vtx_block0;    // first 256-vertex block (backward vertex pass)
@@ -129,13 +129,19 @@ struct DevStatus {
     unsigned long long cnt[kCountSlots][2];   // ray-cast tests, hits, spread over slots
 };
 
-// Tile queue of the persistent ray cast: power-of-two list-length buckets.
+// Schedule of the persistent ray cast.  Every tile belongs to one XCD's
+// share (64 x 64-pixel super-tiles spread over the XCDs, so the tiles that
+// read a triangle's record mostly run on one XCD and share its L2); each
+// share is walked longest list first (counting sort by power-of-two list
+// length bucket).
 constexpr int kBuckets = 33;
+constexpr int kXcds = 8;
+constexpr int kSchedCounters = 2 * kXcds * kBuckets + kXcds + 1;   // cleared by k_tiles
 struct Sched {
-    uint32_t queue;
-    uint32_t pad[3];
-    uint32_t count[kBuckets];
-    uint32_t cursor[kBuckets];
+    uint32_t count[kXcds][kBuckets];    // tiles per (XCD share, bucket)
+    uint32_t cursor[kXcds][kBuckets];
+    uint32_t ntile[kXcds];              // tiles of each share
+    uint32_t nitems;                    // items of the persistent grid (8 x the largest share's)
 };
 
 // Output / input pointers of the per-pixel passes, indexed by view.

@@ -219,7 +219,7 @@ __device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, bool valid, i
         if (valid) atomicAdd(&st->nonfinite, 1);
     } else {
         double win[2];
-        int kind = prg::time_window(g, Ps, Pe, win);
+        int kind = prg::time_window(g, Ps, Pe, win, vd.bound);
         if (kind != prg::kCulled) {
             double box[4];
             prg::display_box(g, Ps, Pe, win[0], win[1], kind, box);
@@ -389,10 +389,7 @@ __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, 
     const bool valid = gt < T->total_tiles;
     // clear the counters the binning pass accumulates into
     if (q == 0 && gt <= T->total_tiles) tcount[gt] = 0u;
-    if (gid < kBuckets) {
-        S->count[gid] = 0u;
-        S->cursor[gid] = 0u;
-    }
+    for (int e = gid; e < kSchedCounters; e += (int)gridDim.x * 256) reinterpret_cast<uint32_t *>(S)[e] = 0u;
     if (blockIdx.x < (T->total_tri_blocks + 255) / 256) {
         // the binning blocks' candidate slots: local exclusive scan of 256
         // block totals here; k_bin adds the totals of the chunks before.
@@ -612,7 +609,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewTable *__restrict
                     int32_t idx[3];
                     prg::load_tri(vd.mesh.v0, vd.mesh.v1, vd.mesh.tri, vd.mesh.nv, f, g, Ps, Pe, idx);
                     prg::SatRec R;
-                    prg::sat_build(g, Ps, Pe, b.kind, b.w, R);
+                    prg::sat_build(g, Ps, Pe, b.kind, b.w, R, vd.bound);
                     uint32_t rw[32];   // the record's words (memcpy: no type punning)
                     static_assert(sizeof(R) == sizeof(rw), "SatRec is 32 words");
                     __builtin_memcpy(rw, &R, sizeof(rw));
@@ -792,16 +789,26 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict_
 
 // Exclusive scan of the per-tile counts: the block's offset is the sum of
 // the partial sums of the blocks before it (few: one per 2048 tiles).  The
-// block also adds its tiles' list-length buckets to the persistent ray
-// cast's histogram (S->count, cleared by k_tiles).
+// block also adds its tiles' (XCD share, list-length bucket) pairs to the
+// persistent ray cast's histogram (S->count, cleared by k_tiles).
 __device__ __forceinline__ int len_bucket(uint32_t len) { return len == 0u ? 0 : 32 - __clz(len); }
 
-__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__ in, int n, int ntiles,
-                                                    const uint32_t *__restrict__ part, uint32_t *__restrict__ out,
-                                                    Sched *__restrict__ S) {
+// The XCD share of global tile gt: its view's 64 x 64-pixel super-tile
+// (tile / 64 is a power of two) on a diagonal pattern over the XCDs.
+__device__ __forceinline__ int tile_xcd(const ViewTable *__restrict__ T, int gt) {
+    const int v = find_view(T->tile_base, T->nv, gt);
+    const ViewDev &vd = T->v[v];
+    const int lt = gt - vd.tile_base, tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
+    const int per = vd.tile >= 64 ? 1 : 64 / vd.tile;
+    return (tx / per + 3 * (ty / per) + 5 * v) & (kXcds - 1);
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const ViewTable *__restrict__ T, const uint32_t *__restrict__ in,
+                                                    int n, int ntiles, const uint32_t *__restrict__ part,
+                                                    uint32_t *__restrict__ out, Sched *__restrict__ S) {
     __shared__ int s_tmp[72];
-    __shared__ uint32_t h[kBuckets];
-    if (threadIdx.x < kBuckets) h[threadIdx.x] = 0u;
+    __shared__ uint32_t h[kXcds * kBuckets];
+    for (int e = threadIdx.x; e < kXcds * kBuckets; e += 256) h[e] = 0u;
     int pre = 0;
     for (int i = threadIdx.x; i < (int)blockIdx.x; i += 256) pre += (int)part[i];
     int total;
@@ -819,11 +826,12 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n) out[base + k] = (uint32_t)ex;
-        if (base + k < ntiles) atomicAdd(&h[len_bucket((uint32_t)v[k])], 1u);
+        if (base + k < ntiles) atomicAdd(&h[tile_xcd(T, base + k) * kBuckets + len_bucket((uint32_t)v[k])], 1u);
         ex += v[k];
     }
     __syncthreads();
-    if (threadIdx.x < kBuckets && h[threadIdx.x]) atomicAdd(&S->count[threadIdx.x], h[threadIdx.x]);
+    for (int e = threadIdx.x; e < kXcds * kBuckets; e += 256)
+        if (h[e]) atomicAdd(&S->count[e / kBuckets][e % kBuckets], h[e]);
 }
 
 // ---------------------------------------------------------------------------
@@ -839,10 +847,16 @@ __device__ __forceinline__ int4 tile_rec(const ViewTable *__restrict__ T, const 
     return ovf ? make_int4(xy, v, 0, 0) : make_int4(xy, v, (int)toff[gt], (int)toff[gt + 1]);
 }
 
+// Items of the persistent ray cast for n tiles of a share: 8x8 tiles run
+// four per item, 16x16 one, 32x32 one quadrant per item.
+__host__ __device__ __forceinline__ int share_items(int tile, int n) {
+    return tile == 8 ? (n + 3) / 4 : (tile == 16 ? n : 4 * n);
+}
+
 // Pairs -> lists.  Blocks below ceil(ntiles / 256) also write the tile
-// order of the persistent ray cast: longest lists first, by power-of-two
-// length bucket (counting sort on the histogram k_scan_apply built; S->cursor
-// cleared by k_tiles).
+// orders of the persistent ray cast: XCD share x's tiles at order[x ntiles
+// ...], longest lists first by power-of-two length bucket (counting sort on
+// the histogram k_scan_apply built; S->cursor cleared by k_tiles).
 __global__ __launch_bounds__(256) void k_scatter(const ViewTable *__restrict__ T, Pairs pairs,
                                                  const uint32_t *__restrict__ toff, int32_t *__restrict__ lists,
                                                  int64_t cap, int ntiles, DevStatus *__restrict__ st,
@@ -852,30 +866,38 @@ __global__ __launch_bounds__(256) void k_scatter(const ViewTable *__restrict__ T
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->pairs_total = toff[ntiles];
         if (ovf) st->overflow = 1;
+        int most = 0;
+        for (int x = 0; x < kXcds; ++x) {
+            uint32_t nt = 0;
+            for (int b = 0; b < kBuckets; ++b) nt += S->count[x][b];
+            S->ntile[x] = nt;
+            most = max(most, share_items(T->v[0].tile, (int)nt));
+        }
+        S->nitems = (uint32_t)(kXcds * most);
     }
     if (blockIdx.x < (ntiles + 255) / 256) {
-        __shared__ uint32_t h[kBuckets], base[kBuckets], first[kBuckets];
-        if (threadIdx.x == 0) {
+        __shared__ uint32_t h[kXcds * kBuckets], base[kXcds * kBuckets], first[kXcds * kBuckets];
+        if (threadIdx.x < kXcds) {
             uint32_t sum = 0;
             for (int b = kBuckets - 1; b >= 0; --b) {   // longest lists first
-                first[b] = sum;
-                sum += S->count[b];
+                first[threadIdx.x * kBuckets + b] = sum;
+                sum += S->count[threadIdx.x][b];
             }
         }
-        if (threadIdx.x < kBuckets) h[threadIdx.x] = 0u;
+        for (int e = threadIdx.x; e < kXcds * kBuckets; e += 256) h[e] = 0u;
         __syncthreads();
         const int i = blockIdx.x * 256 + threadIdx.x;
-        int b = 0;
+        int key = 0;
         uint32_t rank = 0;
         if (i < ntiles) {
-            b = len_bucket(toff[i + 1] - toff[i]);
-            rank = atomicAdd(&h[b], 1u);
+            key = tile_xcd(T, i) * kBuckets + len_bucket(toff[i + 1] - toff[i]);
+            rank = atomicAdd(&h[key], 1u);
         }
         __syncthreads();
-        if (threadIdx.x < kBuckets && h[threadIdx.x])
-            base[threadIdx.x] = first[threadIdx.x] + atomicAdd(&S->cursor[threadIdx.x], h[threadIdx.x]);
+        for (int e = threadIdx.x; e < kXcds * kBuckets; e += 256)
+            if (h[e]) base[e] = first[e] + atomicAdd(&S->cursor[e / kBuckets][e % kBuckets], h[e]);
         __syncthreads();
-        if (i < ntiles) order[base[b] + rank] = tile_rec(T, toff, i, ovf);
+        if (i < ntiles) order[(int64_t)(key / kBuckets) * ntiles + base[key] + rank] = tile_rec(T, toff, i, ovf);
     }
     if (ovf) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -1252,11 +1274,11 @@ __device__ __forceinline__ uint32_t first_entries(const uint32_t *__restrict__ l
 }
 
 // Block item -> the wave's 8x8 cell of tile record tr (ent0: the lane's
-// first list entry).
+// first list entry; quad: the item's quadrant of a 32x32 tile).
 template <int TILE, bool COUNT, bool SHADE>
 __device__ __forceinline__ void raycast_item(const ViewTable *__restrict__ T, const float4 *__restrict__ rec,
                                              const uint32_t *__restrict__ lists, const RayOut &out,
-                                             DevStatus *__restrict__ st, int item, int4 tr, uint32_t ent0,
+                                             DevStatus *__restrict__ st, int quad, int4 tr, uint32_t ent0,
                                              int32_t *s_sel_block, const ShadeIO *sio, const pr_light *light) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (tr.x < 0) return;
@@ -1269,7 +1291,7 @@ __device__ __forceinline__ void raycast_item(const ViewTable *__restrict__ T, co
         cx0 += (q & 1) * 8;
         cy0 += (q >> 1) * 8;
     } else if (TILE == 32) {
-        q = item & 3;
+        q = quad;
         cx0 += (q & 1) * 16 + (wv & 1) * 8;
         cy0 += (q >> 1) * 16 + (wv >> 1) * 8;
     }
@@ -1304,7 +1326,7 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
     const int item = xcd_item(blockIdx.x, gridDim.x);
     const int k = item_tile<TILE>(item, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
     const int4 tr = k < T->total_tiles ? tile_rec(T, toff, k, st->overflow != 0) : make_int4(-1, 0, 0, 0);
-    raycast_item<TILE, COUNT, false>(T, rec, lists, out, st, item, tr, first_entries(lists, tr), s_sel, nullptr,
+    raycast_item<TILE, COUNT, false>(T, rec, lists, out, st, item & 3, tr, first_entries(lists, tr), s_sel, nullptr,
                                      nullptr);
 }
 
@@ -1317,24 +1339,31 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
 template <int TILE, bool COUNT, bool SHADE>
 __global__ __launch_bounds__((RayCfg<TILE>::NT)) __attribute__((amdgpu_waves_per_eu(6))) void k_raycast_queue(
     const ViewTable *__restrict__ T, const float4 *__restrict__ rec, const uint32_t *__restrict__ lists, RayOut out,
-    DevStatus *__restrict__ st, const int4 *__restrict__ order, int nitems, ShadeIO sio, pr_light light) {
+    DevStatus *__restrict__ st, const int4 *__restrict__ order, const Sched *__restrict__ S, ShadeIO sio,
+    pr_light light) {
     __shared__ int32_t s_sel[4 * kSelCap];
-    // block b takes items b, b + grid, b + 2 grid, ... of the longest-first
-    // order (the first round holds the longest lists, no queue atomics).
-    // While an item is cast, the tile record two items ahead and the first
-    // list entries of the next item are loaded.
+    // Block b takes items b, b + grid, b + 2 grid, ... (no queue atomics).
+    // Blocks are dispatched to the XCDs in turn and the grid is a multiple
+    // of their count, so item i runs on XCD i % 8: it is position i / 8 of
+    // that XCD's share, walked longest list first (the first round holds
+    // the longest lists).  While an item is cast, the tile record two items
+    // ahead and the first list entries of the next item are loaded.
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ntiles = T->total_tiles;
     const int G = gridDim.x;
-    auto fetch = [&](int it) {
-        const int k = item_tile<TILE>(it, wv);
-        return it < nitems && k < ntiles ? order[k] : make_int4(-1, 0, 0, 0);
+    const int nitems = (int)S->nitems;
+    auto fetch = [&](int it, int &quad) {
+        const int x = it & (kXcds - 1), j = it >> 3;
+        const int pos = TILE == 8 ? 4 * j + wv : (TILE == 16 ? j : j >> 2);
+        quad = j & 3;
+        return it < nitems && pos < (int)S->ntile[x] ? order[(int64_t)x * ntiles + pos] : make_int4(-1, 0, 0, 0);
     };
     int item = blockIdx.x;
-    int4 cur = fetch(item), nx1 = fetch(item + G);
+    int qcur, qn1, qn2;
+    int4 cur = fetch(item, qcur), nx1 = fetch(item + G, qn1);
     uint32_t ecur = first_entries(lists, cur);
     while (item < nitems) {
-        const int4 nx2 = fetch(item + 2 * G);
+        const int4 nx2 = fetch(item + 2 * G, qn2);
         const uint32_t enx = first_entries(lists, nx1);
         // Waves of equal priority issue oldest first, so the blocks
         // dispatched last fall behind and end up running alone; a wave in
@@ -1345,10 +1374,12 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) __attribute__((amdgpu_waves_per
         else if (quarter == 1) __builtin_amdgcn_s_setprio(2);
         else if (quarter == 2) __builtin_amdgcn_s_setprio(1);
         else __builtin_amdgcn_s_setprio(0);
-        raycast_item<TILE, COUNT, SHADE>(T, rec, lists, out, st, item, cur, ecur, s_sel, &sio, &light);
+        raycast_item<TILE, COUNT, SHADE>(T, rec, lists, out, st, qcur, cur, ecur, s_sel, &sio, &light);
         item += G;
         cur = nx1;
+        qcur = qn1;
         nx1 = nx2;
+        qn1 = qn2;
         ecur = enx;
     }
 }

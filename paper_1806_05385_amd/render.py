@@ -50,8 +50,9 @@ class Renderer:
     raised to what the device reported and the frame is run again."""
 
     def __init__(self, meshes, views, tile: int = 16, bin_capacity: int = 0, light=None, ambient: float = 0.1,
-                 flags: int = B.PR_FLAG_PERSISTENT, device='cuda'):
+                 flags: int = B.PR_FLAG_PERSISTENT, device='cuda', bound: int = B.PR_BOUND_ZENON):
         self.L = B.lib()
+        self.bound_mode = int(bound)
         self.device = torch.device(device)
         self.meshes = [m if isinstance(m, DeviceMesh) else DeviceMesh.from_numpy(m, device) for m in meshes]
         self.views = [copy.copy(v) for v in views]
@@ -75,7 +76,7 @@ class Renderer:
         nm = len(self.meshes)
         self.c_meshes = (B.PrMesh * nm)(*[m.pr() for m in self.meshes])
         self.c_views = (B.PrView * len(self.views))(*[B.make_view(v) for v in self.views])
-        self.tuning = B.PrTuning(self.tile, self.cap, self.flags, 0)
+        self.tuning = B.PrTuning(self.tile, self.cap, self.flags, self.bound_mode)
         size = ctypes.c_size_t(0)
         B.check('pr_workspace_size', self.L.pr_workspace_size(self.c_meshes, nm, self.c_views, len(self.views),
                                                               ctypes.byref(self.tuning), ctypes.byref(size)))
@@ -267,6 +268,41 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Display:
+    """Display unfoveation (pr_unfoveate): each view's foveated RGBA8 image
+    resampled to its display's regular grid.  ``sizes``: display (width,
+    height) per view (default: the view's own size); ``mode``:
+    B.PR_UNFOV_MIP or B.PR_UNFOV_FILTER (Gaussian ``sigma`` in display
+    pixels)."""
+
+    def __init__(self, views, sizes=None, mode: int = B.PR_UNFOV_MIP, sigma: float = 0.5, device='cuda'):
+        self.L = B.lib()
+        self.device = torch.device(device)
+        self.views = [copy.copy(v) for v in views]
+        n = len(self.views)
+        sizes = sizes or [(v.width, v.height) for v in self.views]
+        self.c_views = (B.PrView * n)(*[B.make_view(v, 0) for v in self.views])
+        self.c_disp = (B.PrDisplay * n)(*[B.PrDisplay(int(w), int(h), int(mode), float(sigma)) for w, h in sizes])
+        size = ctypes.c_size_t(0)
+        B.check('pr_unfoveate_workspace_size', self.L.pr_unfoveate_workspace_size(self.c_views, n, self.c_disp,
+                                                                                  ctypes.byref(size)))
+        self.ws_bytes = size.value
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        self.ws_ptr = (self.ws.data_ptr() + 255) & ~255
+        self.outputs = [torch.empty((h, w, 4), dtype=torch.uint8, device=self.device) for w, h in sizes]
+
+    def run(self, fov_rgba8):
+        """fov_rgba8: per view uint8 [H, W, 4] cuda tensors (contiguous)."""
+        for f, v in zip(fov_rgba8, self.views):
+            assert f.is_cuda and f.dtype == torch.uint8 and f.is_contiguous() and tuple(f.shape) == (v.height,
+                                                                                                    v.width, 4)
+        B.check('pr_unfoveate', self.L.pr_unfoveate(
+            self.c_views, len(self.views), self.c_disp, B.ptr_array([f.data_ptr() for f in fov_rgba8]),
+            B.ptr_array([o.data_ptr() for o in self.outputs]), ctypes.c_void_p(self.ws_ptr), self.ws_bytes,
+            ctypes.c_void_p(_stream_handle())))
+        return self.outputs
 
 
 def render_scene(scene, tile: int = 16, shade: bool = True, flags: int = B.PR_FLAG_PERSISTENT, device='cuda'):

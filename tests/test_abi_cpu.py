@@ -139,7 +139,38 @@ def test_candidate_count_beyond_int32():
     rect = (ctypes.c_int32 * 4)()
     total = 0
     for f in range(mesh.nt):
-        assert L.pr_host_tile_rect(ctypes.byref(hm), f, ctypes.byref(pv), 8, rect) == 1
+        assert L.pr_host_tile_rect(ctypes.byref(hm), f, ctypes.byref(pv), 0, 8, rect) == 1
         assert tuple(rect) == (0, 0, 2047, 2047)
         total += (rect[2] - rect[0] + 1) * (rect[3] - rect[1] + 1)
     assert total == 520 * 2048 * 2048 == 2_181_038_080 > 2 ** 31 - 1
+
+
+def test_unfoveate_arguments_checked_before_launch():
+    """pr_unfoveate's sizes and checks are host-side: bad displays, views or
+    workspaces are rejected before any HIP call; the workspace holds the MIP
+    views' pyramids (about a third of a float4 per foveated pixel) and nothing
+    for the filter form."""
+    L = B.lib()
+    v = scenegen.View(64, 48, np.zeros(6, np.float32), np.zeros(6, np.float32), fovea=(0.1, 0.0), alpha=2.0)
+    views = (B.PrView * 1)(B.make_view(v))
+    size = ctypes.c_size_t(0)
+
+    def ws_size(w, h, mode, sigma, vv=views):
+        d = (B.PrDisplay * 1)(B.PrDisplay(w, h, mode, sigma))
+        return L.pr_unfoveate_workspace_size(vv, 1, d, ctypes.byref(size)), size.value
+
+    rc, mip = ws_size(80, 60, B.PR_UNFOV_MIP, 0.0)
+    assert rc == B.PR_OK and mip >= 16 * (32 * 24 + 16 * 12 + 8 * 6 + 4 * 3 + 2 * 2 + 1)
+    rc, filt = ws_size(80, 60, B.PR_UNFOV_FILTER, 0.5)
+    assert rc == B.PR_OK and filt < mip
+    for bad in [(0, 60, B.PR_UNFOV_MIP, 0.5), (80, 16385, B.PR_UNFOV_MIP, 0.5), (80, 60, 7, 0.5),
+                (80, 60, B.PR_UNFOV_FILTER, 0.0), (80, 60, B.PR_UNFOV_FILTER, float('nan'))]:
+        assert ws_size(*bad)[0] == B.PR_ERR_INVALID, bad
+    v.alpha = 0.5
+    assert ws_size(80, 60, B.PR_UNFOV_MIP, 0.5, (B.PrView * 1)(B.make_view(v)))[0] == B.PR_ERR_INVALID
+    d = (B.PrDisplay * 1)(B.PrDisplay(80, 60, B.PR_UNFOV_MIP, 0.5))
+    arr = B.ptr_array([1 << 20])
+    assert L.pr_unfoveate(views, 1, d, arr, arr, None, mip, None) == B.PR_ERR_WORKSPACE
+    assert L.pr_unfoveate(views, 1, d, arr, arr, ctypes.c_void_p(256 * 1000), mip - 1, None) == B.PR_ERR_WORKSPACE
+    assert L.pr_unfoveate(views, 1, d, None, arr, ctypes.c_void_p(256 * 1000), mip, None) == B.PR_ERR_INVALID
+    assert L.pr_unfoveate(views, 0, d, arr, arr, ctypes.c_void_p(256 * 1000), mip, None) == B.PR_ERR_INVALID

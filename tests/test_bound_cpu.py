@@ -20,7 +20,7 @@ import scenegen
 from paper_1806_05385_amd import binding as B
 
 
-def _check_hits(scene, tile, max_pix=None, seed=0):
+def _check_hits(scene, tile, max_pix=None, seed=0, bound=0):
     L = B.lib()
     mesh, view = scene.meshes[0], scene.views[0]
     W, H = view.width, view.height
@@ -37,9 +37,9 @@ def _check_hits(scene, tile, max_pix=None, seed=0):
     missed = []
     for p, f in zip(hp.tolist(), ht.tolist()):
         if f not in cache:
-            kind = L.pr_host_time_interval(ctypes.byref(hm), f, ctypes.byref(pv),
+            kind = L.pr_host_time_interval(ctypes.byref(hm), f, ctypes.byref(pv), bound,
                                            win.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
-            ok = L.pr_host_tile_rect(ctypes.byref(hm), f, ctypes.byref(pv), tile, rect)
+            ok = L.pr_host_tile_rect(ctypes.byref(hm), f, ctypes.byref(pv), bound, tile, rect)
             cache[f] = (kind, win.copy(), tuple(rect) if ok == 1 else None)
         kind, w, r = cache[f]
         i, j = p % W, p // W
@@ -47,7 +47,7 @@ def _check_hits(scene, tile, max_pix=None, seed=0):
         t = oracle.pixel_setup(view, p)[2]
         ok = kind in (1, 2) and r is not None and r[0] <= tx <= r[2] and r[1] <= ty <= r[3]
         ok = ok and (kind == 2 or w[0] <= t <= w[1])
-        mask = L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), tile, tx, ty)
+        mask = L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), bound, tile, tx, ty)
         if tile >= 16:   # the pixel's quadrant of its tile must be in the pair's mask
             h = tile // 2
             quad = int(i % tile >= h) + 2 * int(j % tile >= h)
@@ -132,12 +132,12 @@ def test_bound_is_tight_enough_to_reject_pairs():
     rect = (ctypes.c_int32 * 4)()
     cand = kept = 0
     for f in range(mesh.nt):
-        if L.pr_host_tile_rect(ctypes.byref(hm), f, ctypes.byref(pv), 8, rect) != 1:
+        if L.pr_host_tile_rect(ctypes.byref(hm), f, ctypes.byref(pv), 0, 8, rect) != 1:
             continue
         for ty in range(rect[1], rect[3] + 1):
             for tx in range(rect[0], rect[2] + 1):
                 cand += 1
-                kept += L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), 8, tx, ty) != 0
+                kept += L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), 0, 8, tx, ty) != 0
     tiles = 16 * 16
     assert cand < 0.1 * tiles * mesh.nt
     assert kept <= cand
@@ -145,11 +145,11 @@ def test_bound_is_tight_enough_to_reject_pairs():
     # tiles x 4, and most kept pairs skip at least one quadrant
     quads = pairs = 0
     for f in range(mesh.nt):
-        if L.pr_host_tile_rect(ctypes.byref(hm), f, ctypes.byref(pv), 16, rect) != 1:
+        if L.pr_host_tile_rect(ctypes.byref(hm), f, ctypes.byref(pv), 0, 16, rect) != 1:
             continue
         for ty in range(rect[1], rect[3] + 1):
             for tx in range(rect[0], rect[2] + 1):
-                m = L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), 16, tx, ty)
+                m = L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), 0, 16, tx, ty)
                 assert 0 <= m <= 0xF
                 if m:
                     pairs += 1
@@ -191,7 +191,7 @@ def test_time_window_matches_dense_sampling():
     w = np.empty(2)
     n_win = n_narrow = 0
     for f in range(mesh.nt):
-        kind = L.pr_host_time_interval(ctypes.byref(hm), f, ctypes.byref(pv),
+        kind = L.pr_host_time_interval(ctypes.byref(hm), f, ctypes.byref(pv), 0,
                                        w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         if kind == 2:
             continue
@@ -204,3 +204,49 @@ def test_time_window_matches_dense_sampling():
         assert w[0] >= b[0] - 1e-4 - 1e-6 and w[1] <= b[1] + 1e-4 + 1e-6, (f, w, b)
         n_narrow += (w[1] - w[0]) < 0.5
     assert n_win > 100 and n_narrow > 0.5 * n_win
+
+
+BOUNDS = {'zenon': B.PR_BOUND_ZENON, 'adaptive': B.PR_BOUND_ADAPTIVE, 'hull': B.PR_BOUND_HULL,
+          'quad': B.PR_BOUND_QUAD}
+
+
+@pytest.mark.parametrize('bound', sorted(BOUNDS))
+@pytest.mark.parametrize('roll', [(1.0, 0.0), (0.0, 0.9)])
+def test_every_bound_mode_is_conservative(bound, roll):
+    """Each rolling bound of Sec. 4.2 (Quad, Hull, Adaptive, Zenon) keeps
+    every (pixel, triangle) hit of a fast-moving, rolling, foveated soup in
+    its time window, tile rectangle and quadrant mask."""
+    sc = scenegen.make_moving_soup(seed=24, n_tris=300, width=80, height=72, alpha=2.0, roll=roll,
+                                   yaw_deg_s=3000.0, obj_speed=40.0, fovea=(0.1, -0.1), side=(0.05, 0.6))
+    n, missed, _ = _check_hits(sc, 16, bound=BOUNDS[bound])
+    assert n > 1000
+    assert not missed, missed[:5]
+
+
+def test_bound_modes_order_by_tightness():
+    """On the HMD scene's recipe (reduced: sphere f=24, 60 boxes, one eye at
+    302x336), the pairs each bound keeps order as Sec. 4.2 says they should:
+    the box (Quad) keeps the most, the hull fewer, the Adaptive window fewer
+    again and the exact catch-up window (Zenon) the fewest; every pair a
+    tighter bound keeps, the looser ones keep too."""
+    sc = scenegen.make_hmd(seed=2, width=302, height=336, sphere_f=24, n_boxes=60)
+    mesh, view = sc.meshes[0], sc.views[0]
+    L = B.lib()
+    hm = B.host_mesh(mesh.v0, mesh.v1, mesh.tri)
+    pv = B.make_view(view)
+    rect = (ctypes.c_int32 * 4)()
+    kept = {}
+    for name in ('quad', 'hull', 'adaptive', 'zenon'):
+        pairs = set()
+        for f in range(0, mesh.nt, 7):
+            if L.pr_host_tile_rect(ctypes.byref(hm), f, ctypes.byref(pv), BOUNDS[name], 16, rect) != 1:
+                continue
+            for ty in range(rect[1], rect[3] + 1):
+                for tx in range(rect[0], rect[2] + 1):
+                    if L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), BOUNDS[name], 16, tx, ty):
+                        pairs.add((f, tx, ty))
+        kept[name] = pairs
+    n = {k: len(v) for k, v in kept.items()}
+    print(n)
+    assert n['quad'] > n['hull'] > n['adaptive'] >= n['zenon'] > 0
+    assert kept['zenon'] <= kept['adaptive'] <= kept['hull'] <= kept['quad']

@@ -131,14 +131,19 @@ def test_large_full_size_full_frame():
     _full_size_parity(sc, r, out, 'large', 0.05, 500, 300)
 
 
-def test_bound_invariant_on_device_lists():
+BOUNDS = {'zenon': 0, 'adaptive': 1, 'hull': 2, 'quad': 3}
+
+
+@pytest.mark.parametrize('bound', sorted(BOUNDS))
+def test_bound_invariant_on_device_lists(bound):
     """Every oracle hit (occluded or not) lies in a tile whose device-built
     list holds the triangle, with the pixel's quadrant in the entry's mask
-    (the bound never drops a covered fragment)."""
+    (the bound never drops a covered fragment), under each rolling bound of
+    Sec. 4.2 (Zenon, Adaptive, Hull, Quad)."""
     sc = scenegen.make_moving_soup(seed=32, n_tris=800, width=160, height=144, alpha=2.0, roll=(1.0, 0.0),
                                    yaw_deg_s=3000.0, obj_speed=30.0, side=(0.03, 0.5))
     for tile in (8, 16, 32):
-        r, out = _render(sc, tile)
+        r, out = _render(sc, tile, bound=BOUNDS[bound])
         off, lst, qm = r.tile_lists(0)
         v = sc.views[0]
         hp, ht, he = oracle.Oracle(sc.meshes[0], v).all_hits()
@@ -161,6 +166,19 @@ def test_bound_invariant_on_device_lists():
         for t in range(len(off) - 1):
             seg = lst[off[t]:off[t + 1]]
             assert len(np.unique(seg)) == len(seg)
+
+
+@pytest.mark.parametrize('bound', sorted(BOUNDS))
+def test_every_bound_mode_full_frame(bound):
+    """Full-frame parity under each rolling bound (moving soup, fast yaw,
+    foveated, rolling), and the looser bounds never list fewer pairs."""
+    sc = scenegen.make_moving_soup(seed=31, n_tris=1500, width=203, height=171, alpha=2.0, roll=(1.0, 0.0),
+                                   yaw_deg_s=2000.0, obj_speed=20.0, fovea=(0.1, -0.15), side=(0.03, 0.5))
+    r, _, _, _ = _full_parity(sc, 16, bound=BOUNDS[bound])
+    pairs = r.status().pairs_total
+    if bound != 'zenon':
+        r0, _ = _render(sc, 16)
+        assert pairs >= r0.status().pairs_total
 
 
 def test_deterministic_and_static_rolling_equivalence():
