@@ -318,6 +318,26 @@ int pr_batch_status(const pr_batch *batch, pr_status *out, void *stream);
 /* Frees everything the batch owns.  NULL is allowed. */
 int pr_batch_destroy(pr_batch *batch);
 
+/* ALLOCATION-FREE FRAME, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  pr_frame_static runs pr_bound, pr_bin and pr_raycast_shade
+ * with the same arguments (minus the workspace) and writes the same outputs
+ * bitwise, using as workspace a static device array of
+ * PR_STATIC_SCRATCH_BYTES that the library holds on each device it runs on
+ * until the process ends; it calls no hipMalloc, hipFree or other
+ * allocating routine.  A frame whose pr_workspace_size exceeds
+ * PR_STATIC_SCRATCH_BYTES is rejected with PR_ERR_WORKSPACE before anything
+ * is enqueued.  The array keeps the last call's contents (the frame's
+ * passes clear what they need); every call on one device shares it, so
+ * calls that overlap on one device (other streams, other threads) race and
+ * must be serialised by the caller.  Device-side conditions (tile-list
+ * overflow: misses written) stay in the array and are not returned; size
+ * bin_capacity with the allocating path first. */
+#define PR_STATIC_SCRATCH_BYTES (256u << 20)
+int pr_frame_static(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
+                    int32_t *const *tri_id, float *const *depth, const pr_light *light, const float *const *albedo,
+                    uint8_t *const *rgba8, float *const *rgb32, void *stream);
+
 /* Waits for `stream`, copies the workspace's status block into *out.
  * Returns PR_OK, PR_ERR_INVALID or PR_ERR_HIP. */
 int pr_status_read(const void *ws, size_t ws_bytes, pr_status *out, void *stream);

@@ -17,6 +17,7 @@ PR_ERR_HIP = -4
 PR_MAX_VIEWS = 64
 PR_FLAG_COUNT = 1
 PR_FLAG_PERSISTENT = 2
+PR_STATIC_SCRATCH_BYTES = 256 << 20
 PR_BOUND_ZENON = 0
 PR_BOUND_ADAPTIVE = 1
 PR_BOUND_HULL = 2
@@ -79,6 +80,7 @@ SIGNATURES = {
     'pr_raycast_shade': (ctypes.c_int, _FRAME + [_PP, _PP, ctypes.POINTER(PrLight), _PP, _PP, _PP, ctypes.c_void_p]),
     'pr_backward': (ctypes.c_int, _FRAME + [_PP, ctypes.POINTER(PrLight), _PP, _PP, _PP, _PP, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p]),
+    'pr_frame_static': (ctypes.c_int, _FRAME[:5] + [_PP, _PP, ctypes.POINTER(PrLight), _PP, _PP, _PP, ctypes.c_void_p]),
     'pr_unfoveate_workspace_size': (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(PrDisplay),
                                                    ctypes.POINTER(ctypes.c_size_t)]),
     'pr_unfoveate': (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(PrDisplay), _PP, _PP, ctypes.c_void_p,

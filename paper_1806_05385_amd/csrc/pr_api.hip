@@ -705,6 +705,67 @@ extern "C" int pr_unfoveate(const pr_view *views, int nv, const pr_display *disp
 }
 
 // ---------------------------------------------------------------------------
+// the frame on a static scratch array (callers that cannot allocate)
+// ---------------------------------------------------------------------------
+// Workspace of pr_frame_static: a file-scope device array, one per device
+// the library runs on, held until the process ends.  Host code never passes
+// this name to a kernel or a copy (on the host it is only a stand-in for the
+// symbol): it takes the array's device address from hipGetSymbolAddress,
+// once per device, and uses that.
+static __device__ __align__(256) unsigned char scratch[PR_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up on the device's first
+// call, with that device current).
+int static_scratch(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PR_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PR_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PR_OK;
+}
+
+}  // namespace
+
+extern "C" int pr_frame_static(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
+                               int32_t *const *tri_id, float *const *depth, const pr_light *light,
+                               const float *const *albedo, uint8_t *const *rgba8, float *const *rgb32,
+                               void *stream) {
+    // every argument is checked before anything is enqueued
+    size_t need = 0;
+    int rc = pr_workspace_size(meshes, nm, views, nv, tuning, &need);
+    if (rc) return rc;
+    if (need > (size_t)PR_STATIC_SCRATCH_BYTES) return PR_ERR_WORKSPACE;
+    if (!tri_id || !depth) return PR_ERR_INVALID;
+    for (int v = 0; v < nv; ++v)
+        if (!tri_id[v] || !depth[v]) return PR_ERR_INVALID;
+    ShadeIO io;
+    bool any = false;
+    rc = shade_args(meshes, nm, views, nv, tri_id, light, albedo, rgba8, rgb32, io, any);
+    if (rc) return rc;
+    void *ws = nullptr;
+    rc = static_scratch(&ws);
+    if (rc) return rc;
+    // the frame's passes clear what they accumulate into (status block,
+    // counters, cursors), so the array's previous contents do not matter
+    rc = pr_bound(meshes, nm, views, nv, tuning, ws, PR_STATIC_SCRATCH_BYTES, stream);
+    if (!rc) rc = pr_bin(meshes, nm, views, nv, tuning, ws, PR_STATIC_SCRATCH_BYTES, stream);
+    if (!rc)
+        rc = pr_raycast_shade(meshes, nm, views, nv, tuning, ws, PR_STATIC_SCRATCH_BYTES, tri_id, depth, light,
+                              albedo, rgba8, rgb32, stream);
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
 // batched form: hipGraph of one frame over all views, autotuned
 // ---------------------------------------------------------------------------
 struct pr_batch {

@@ -174,3 +174,19 @@ def test_unfoveate_arguments_checked_before_launch():
     assert L.pr_unfoveate(views, 1, d, arr, arr, ctypes.c_void_p(256 * 1000), mip - 1, None) == B.PR_ERR_WORKSPACE
     assert L.pr_unfoveate(views, 1, d, None, arr, ctypes.c_void_p(256 * 1000), mip, None) == B.PR_ERR_INVALID
     assert L.pr_unfoveate(views, 0, d, arr, arr, ctypes.c_void_p(256 * 1000), mip, None) == B.PR_ERR_INVALID
+
+
+def test_static_frame_rejects_large_frames_before_launch():
+    """pr_frame_static checks its sizes on the host: a frame whose workspace
+    exceeds PR_STATIC_SCRATCH_BYTES returns PR_ERR_WORKSPACE before any HIP
+    call (so the answer is the same without a GPU)."""
+    L = B.lib()
+    meshes, views, _, sc = _frame(cap=1 << 24)
+    tu = B.PrTuning(16, 1 << 24, B.PR_FLAG_PERSISTENT, 0)
+    size = ctypes.c_size_t(0)
+    assert L.pr_workspace_size(meshes, 1, views, 1, ctypes.byref(tu), ctypes.byref(size)) == B.PR_OK
+    assert size.value > B.PR_STATIC_SCRATCH_BYTES
+    fake = B.ptr_array([1 << 20])
+    light = B.make_light(sc.light_dir, sc.ambient)
+    assert L.pr_frame_static(meshes, 1, views, 1, ctypes.byref(tu), fake, fake, ctypes.byref(light), fake, None,
+                             None, None) == B.PR_ERR_WORKSPACE
