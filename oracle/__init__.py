@@ -75,6 +75,8 @@ def lib():
         L.orc_loss.restype = ctypes.c_double
         L.orc_loss_grad.argtypes = [dp] + mesh + [dp, dp, ip, dp, dp, dp, dp, dp]
         L.orc_loss_grad.restype = ctypes.c_double
+        L.orc_gbuffer.argtypes = [dp] + mesh + [lp, i64, ip, dp, dp, dp]
+        L.orc_foveate_jac.argtypes = [dp, dp, dp]
         L.orc_unfov_coord.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
         L.orc_unfov_lod.argtypes = [dp]
         L.orc_unfov_lod.restype = ctypes.c_double
@@ -185,7 +187,7 @@ class Oracle:
         n = self.W * self.H if pix is None else len(pix)
         pp = None if pix is None else np.ascontiguousarray(pix, dtype=np.int64)
         ids = np.ascontiguousarray(ids, dtype=np.int32)
-        lt = _d(light)
+        lt = _light6(light)
         out = np.empty((n, 3))
         self.L.orc_shade(_p(self.vp, ctypes.c_double), *self._m(), _p(self.albedo, ctypes.c_double),
                          _p(lt, ctypes.c_double), None if pp is None else _p(pp, ctypes.c_int64), n,
@@ -194,13 +196,13 @@ class Oracle:
 
     def loss(self, ids, light, target):
         ids = np.ascontiguousarray(ids, dtype=np.int32)
-        lt, tg = _d(light), _d(target)
+        lt, tg = _light6(light), _d(target)
         return self.L.orc_loss(_p(self.vp, ctypes.c_double), *self._m(), _p(self.albedo, ctypes.c_double),
                                _p(lt, ctypes.c_double), _p(ids, ctypes.c_int32), _p(tg, ctypes.c_double))
 
     def loss_grad(self, ids, light, target):
         ids = np.ascontiguousarray(ids, dtype=np.int32)
-        lt, tg = _d(light), _d(target)
+        lt, tg = _light6(light), _d(target)
         nv = self.v0.shape[0]
         g0, g1 = np.zeros((nv, 3)), np.zeros((nv, 3))
         gp0, gp1 = np.zeros(6), np.zeros(6)
@@ -211,8 +213,32 @@ class Oracle:
         return L, g0, g1, gp0, gp1
 
 
-def light_block(scene) -> np.ndarray:
-    return np.array([*scene.light_dir, scene.ambient], np.float64)
+    def gbuffer(self, ids, pix=None):
+        """Per pixel: unit normal (turned to the eye) and barycentrics
+        (mu_1, mu_2) of its id (zeros for misses), and the pixel density."""
+        n = self.W * self.H if pix is None else len(pix)
+        pp = None if pix is None else np.ascontiguousarray(pix, dtype=np.int64)
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        out = dict(normal=np.empty((n, 3)), bary=np.empty((n, 2)), density=np.empty(n))
+        self.L.orc_gbuffer(_p(self.vp, ctypes.c_double), *self._m(),
+                           None if pp is None else _p(pp, ctypes.c_int64), n, _p(ids, ctypes.c_int32),
+                           _p(out['normal'], ctypes.c_double), _p(out['bary'], ctypes.c_double),
+                           _p(out['density'], ctypes.c_double))
+        return out
+
+
+def _light6(light) -> np.ndarray:
+    """(l_w[3], k_a[, k_s, m]) -> the oracle's six-entry light (k_s = 0: no
+    highlight)."""
+    lt = np.asarray(light, np.float64).ravel()
+    if lt.size == 4:
+        lt = np.concatenate([lt, [0.0, 1.0]])
+    assert lt.size == 6, 'light: (dir[3], ambient) or (dir[3], ambient, specular, shininess)'
+    return np.ascontiguousarray(lt)
+
+
+def light_block(scene, specular: float = 0.0, shininess: float = 1.0) -> np.ndarray:
+    return np.array([*scene.light_dir, scene.ambient, specular, shininess], np.float64)
 
 
 def rodrigues(w) -> np.ndarray:

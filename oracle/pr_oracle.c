@@ -18,8 +18,11 @@
  *   - intersection (Sec. 3.2, "Intersection"): the triangle is linearly
  *     interpolated to the pixel's time in camera space and intersected with
  *     the pixel's ray; the nearest hit wins;
- *   - shading (Sec. 3.2, "Shading"): light direction interpolated to the
- *     pixel's time, Lambert with one directional light.
+ *   - shading (Sec. 3.2, "Shading"): light direction and eye interpolated
+ *     to the pixel's time, Lambert with one directional light plus a
+ *     Blinn-Phong highlight (Sec. 5.1 "Rolling Shading");
+ *   - the G-buffer of the resolved pixels (normals, barycentrics) and the
+ *     foveation's pixel density (Sec. 7 "Screen-space effects").
  * Plus the analytic gradient of an L2 image loss with visibility held fixed
  * (an AI-systems form of the method; pinned by central differences).
  *
@@ -513,10 +516,25 @@ void orc_render_fast(const double *vp, const double *v0, const double *v1, int n
 /* rolling Lambert shading and its gradient (frozen visibility)              */
 /* ------------------------------------------------------------------------- */
 
-/* Shade one pixel whose visible triangle is f.  light = (l_w[3], k_a).
+/* Rolling highlight (Sec. 3.2 "Shading": the eye position rolls like the
+ * light; Sec. 5.1 "Rolling Shading"): in the camera frame at the pixel's
+ * time the eye is the origin, so the direction from the surface towards it
+ * is v = -r/|r|.  Blinn-Phong, white: h = normalize(l + v),
+ * sigma = k_s (n.h)^m where n.l > 0 and n.h > 0, else 0 (also when l = -v). */
+static double highlight(const double n[3], const double l[3], const double r[3], double ks, double m) {
+    if (ks == 0.0 || dot3(n, l) <= 0.0) return 0.0;
+    double rn = norm3(r);
+    double H[3] = {l[0] - r[0] / rn, l[1] - r[1] / rn, l[2] - r[2] / rn};
+    double hn = norm3(H);
+    if (hn == 0.0) return 0.0;
+    double ndh = dot3(n, H) / hn;
+    return ndh > 0.0 ? ks * pow(ndh, m) : 0.0;
+}
+
+/* Shade one pixel whose visible triangle is f.  light = (l_w[3], k_a, k_s, m).
  * n = face normal flipped to face the eye; l(t) = normalize((1-t) R0 l_w +
  * t R1 l_w); albedo = barycentric (mu_k = e_k/S) blend of per-vertex albedo;
- * c = albedo * (k_a + (1-k_a) max(0, n.l)). */
+ * c = albedo * (k_a + (1-k_a) max(0, n.l)) + highlight(n, l, r). */
 static void shade_px(const orc_cam *cam, const double *vp, const int32_t *tri, const double *albedo,
                      const double *light, int64_t p, int f, double c[3]) {
     double y[2], x[2], t, r[3], P[3][3];
@@ -541,10 +559,12 @@ static void shade_px(const orc_cam *cam, const double *vp, const int32_t *tri, c
     double ln = norm3(L);
     double ndl = dot3(n, L) / ln;
     double s = light[3] + (1.0 - light[3]) * (ndl > 0 ? ndl : 0.0);
+    double l[3] = {L[0] / ln, L[1] / ln, L[2] / ln};
+    double sigma = highlight(n, l, r, light[4], light[5]);
     for (int ch = 0; ch < 3; ++ch) {
         double a = 0;
         for (int k = 0; k < 3; ++k) a += e[k] / S * albedo[3 * (size_t)tri[3 * f + k] + ch];
-        c[ch] = a * s;
+        c[ch] = a * s + sigma;
     }
 }
 
@@ -648,12 +668,13 @@ double orc_loss_grad(const double *vp, const double *v0, const double *v1, int n
             double l[3] = {Lw[0] / lnorm, Lw[1] / lnorm, Lw[2] / lnorm};
             double ndl = dot3(n, l);
             double s = ka + (1.0 - ka) * (ndl > 0 ? ndl : 0.0);
+            double sigma = highlight(n, l, r, light[4], light[5]);
             double a[3];
             const int32_t *tv = tri + 3 * (size_t)f;
             for (int ch = 0; ch < 3; ++ch) {
                 a[ch] = 0;
                 for (int k = 0; k < 3; ++k) a[ch] += mu[k] * albedo[3 * (size_t)tv[k] + ch];
-                c[ch] = a[ch] * s;
+                c[ch] = a[ch] * s + sigma;
             }
             double gc[3];
             for (int ch = 0; ch < 3; ++ch) {
@@ -671,6 +692,21 @@ double orc_loss_grad(const double *vp, const double *v0, const double *v1, int n
             double gndl = ndl > 0 ? gs * (1.0 - ka) : 0.0;
             double gn[3] = {gndl * l[0], gndl * l[1], gndl * l[2]};
             double gl[3] = {gndl * n[0], gndl * n[1], gndl * n[2]};
+            /* sigma = k_s (n.h)^m (each channel), h = H/|H|, H = l - r/|r|:
+             * dsigma/dn = k_s m (n.h)^(m-1) h, dsigma/dh = k_s m (n.h)^(m-1) n */
+            if (sigma > 0.0) {
+                double rn = norm3(r);
+                double H[3] = {l[0] - r[0] / rn, l[1] - r[1] / rn, l[2] - r[2] / rn};
+                double hn = norm3(H);
+                double h[3] = {H[0] / hn, H[1] / hn, H[2] / hn};
+                double gsig = (gc[0] + gc[1] + gc[2]) * light[4] * light[5] * pow(dot3(n, h), light[5] - 1.0);
+                double gh[3] = {gsig * n[0], gsig * n[1], gsig * n[2]};
+                double hg = dot3(h, gh);
+                for (int d = 0; d < 3; ++d) {
+                    gn[d] += gsig * h[d];
+                    gl[d] += (gh[d] - h[d] * hg) / hn;
+                }
+            }
             /* n = sg N/|N| */
             double gm[3] = {sg * gn[0], sg * gn[1], sg * gn[2]};
             double mg = dot3(m, gm);
@@ -748,6 +784,58 @@ double orc_loss_grad(const double *vp, const double *v0, const double *v1, int n
 }
 
 /* ------------------------------------------------------------------------- */
+/* G-buffer (Sec. 3.2 "Pipeline": the deferred shading buffer; Sec. 7         */
+/* "Screen-space effects": image distances scaled by the pixel density)       */
+/* ------------------------------------------------------------------------- */
+void orc_foveate_jac(const double *vp, const double x[2], double JF[4]);
+
+/* Per pixel: the visible triangle's unit face normal at the pixel's time in
+ * the camera frame, turned towards the eye; the barycentrics mu_1, mu_2 of
+ * the ray's hit (mu_k = e_k / S); the pixel density, the square root of the
+ * Jacobian determinant of the foveate map at the pixel's display point (how
+ * much a short display-space length grows in the foveated image).  Misses
+ * give zero normal and barycentrics; the density is written for every pixel. */
+void orc_gbuffer(const double *vp, const double *v0, const double *v1, int nv, const int32_t *tri, int nt,
+                 const int64_t *pix, int64_t npix, const int32_t *ids, double *out_normal, double *out_bary,
+                 double *out_density) {
+    (void)nt;
+    orc_cam cam;
+    cam_init(&cam, vp, v0, v1, nv);
+    if (!pix) npix = (int64_t)vp[ORC_W] * (int64_t)vp[ORC_H];
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < npix; ++q) {
+        int64_t p = pix ? pix[q] : q;
+        double y[2], x[2], t, r[3];
+        orc_pixel_setup(vp, p, y, x, &t, r);
+        double JF[4];
+        orc_foveate_jac(vp, x, JF);
+        out_density[q] = sqrt(fabs(JF[0] * JF[3] - JF[1] * JF[2]));
+        double n[3] = {0, 0, 0}, mu[3] = {0, 0, 0};
+        int f = ids[q];
+        if (f >= 0) {
+            double P[3][3], e[3], ck[3];
+            tri_at(&cam, tri, f, t, P);
+            for (int k = 0; k < 3; ++k) {
+                cross3(P[(k + 1) % 3], P[(k + 2) % 3], ck);
+                e[k] = dot3(r, ck);
+            }
+            double S = e[0] + e[1] + e[2];
+            for (int k = 0; k < 3; ++k) mu[k] = e[k] / S;
+            double e1[3], e2[3], N[3];
+            for (int d = 0; d < 3; ++d) { e1[d] = P[1][d] - P[0][d]; e2[d] = P[2][d] - P[0][d]; }
+            cross3(e1, e2, N);
+            double nn = norm3(N);
+            for (int d = 0; d < 3; ++d) n[d] = N[d] / nn;
+            if (dot3(n, r) > 0) { n[0] = -n[0]; n[1] = -n[1]; n[2] = -n[2]; }
+        }
+        for (int d = 0; d < 3; ++d) out_normal[3 * q + d] = n[d];
+        out_bary[2 * q] = mu[1];
+        out_bary[2 * q + 1] = mu[2];
+    }
+    cam_free(&cam);
+}
+
+/* ------------------------------------------------------------------------- */
 /* display unfoveation (Sec. 3.1.1 "Display")                                 */
 /* ------------------------------------------------------------------------- */
 /* The foveated image I_f (W x H, its pixel grid in the foveated domain) is
@@ -780,17 +868,11 @@ double orc_loss_grad(const double *vp, const double *v0, const double *v1, int n
  * power map y = f + (x - f) s, s = (|x - f|/R)^(1/alpha - 1); its Jacobian
  * is s I + (1/alpha - 1) s (x - f)(x - f)^T / |x - f|^2.  At the fovea
  * itself (alpha > 1) the map's derivative is unbounded: lambda = +inf. */
-void orc_unfov_coord(const double *vp, int Wd, int Hd, double a, double b, double u[2], double J[4]) {
-    int W = (int)vp[ORC_W], H = (int)vp[ORC_H];
-    double x[2] = {2.0 * (a + 0.5) / Wd - 1.0, 1.0 - 2.0 * (b + 0.5) / Hd};
-    double y[2];
-    orc_foveate(vp, x, y);
-    u[0] = (y[0] + 1.0) * 0.5 * W - 0.5;
-    u[1] = (1.0 - y[1]) * 0.5 * H - 0.5;
+/* Jacobian dy/dx of the foveate map at display NDC x (row-major 2x2). */
+void orc_foveate_jac(const double *vp, const double x[2], double JF[4]) {
     double d[2] = {x[0] - vp[ORC_FOV], x[1] - vp[ORC_FOV + 1]};
     double rho2 = d[0] * d[0] + d[1] * d[1];
     double e = 1.0 / vp[ORC_ALPHA];
-    double JF[4];
     if (rho2 == 0.0) {
         double v = e == 1.0 ? 1.0 : INFINITY;
         JF[0] = v; JF[1] = 0.0; JF[2] = 0.0; JF[3] = v;
@@ -799,6 +881,17 @@ void orc_unfov_coord(const double *vp, int Wd, int Hd, double a, double b, doubl
         for (int r = 0; r < 2; ++r)
             for (int c = 0; c < 2; ++c) JF[2 * r + c] = (r == c ? s : 0.0) + (e - 1.0) * s * d[r] * d[c] / rho2;
     }
+}
+
+void orc_unfov_coord(const double *vp, int Wd, int Hd, double a, double b, double u[2], double J[4]) {
+    int W = (int)vp[ORC_W], H = (int)vp[ORC_H];
+    double x[2] = {2.0 * (a + 0.5) / Wd - 1.0, 1.0 - 2.0 * (b + 0.5) / Hd};
+    double y[2];
+    orc_foveate(vp, x, y);
+    u[0] = (y[0] + 1.0) * 0.5 * W - 0.5;
+    u[1] = (1.0 - y[1]) * 0.5 * H - 0.5;
+    double JF[4];
+    orc_foveate_jac(vp, x, JF);
     /* u = diag(W/2, -H/2) y + const, x = diag(2/Wd, -2/Hd) (a, b) + const */
     double su[2] = {0.5 * W, -0.5 * H}, sx[2] = {2.0 / Wd, -2.0 / Hd};
     for (int r = 0; r < 2; ++r)

@@ -2,8 +2,8 @@
 
 Each case copies oracle/pr_oracle.c, plants one plausible mistake (a dropped
 term, a wrong sign or index, a swapped operand), builds the copy with gcc and
-runs tests/test_oracle_pins.py and tests/test_oracle_display_pins.py
-against it; the pins must fail.  Runs on the
+runs tests/test_oracle_pins.py, tests/test_oracle_display_pins.py and
+tests/test_oracle_shading_pins.py against it; the pins must fail.  Runs on the
 CPU only.
 """
 import os
@@ -34,7 +34,8 @@ MUTANTS = {
                            'double s = light[3] + (ndl > 0 ? ndl : 0.0);'),
     'light_not_rolling': ('for (int d = 0; d < 3; ++d) L[d] = (1.0 - t) * l0[d] + t * l1[d];',
                           'for (int d = 0; d < 3; ++d) L[d] = l0[d];'),
-    'normal_not_flipped': ('if (dot3(n, r) > 0) { n[0] = -n[0]; n[1] = -n[1]; n[2] = -n[2]; }', ''),
+    'normal_not_flipped': ('    if (dot3(n, r) > 0) { n[0] = -n[0]; n[1] = -n[1]; n[2] = -n[2]; }\n    double l0[3]',
+                           '    double l0[3]'),
     'grad_end_weight': ('mPe[3 * (size_t)tv[k] + d] += t * gP[k][d];',
                         'mPe[3 * (size_t)tv[k] + d] += (1.0 - t) * gP[k][d];'),
     'grad_cross_order': ('cross3(P[ib], g, ta);', 'cross3(g, P[ib], ta);'),
@@ -58,6 +59,23 @@ MUTANTS = {
     'fast_tie_to_higher_index': ('if (z < *bz || (z == *bz && f < *bid)) {', 'if (z < *bz || (z == *bz && f > *bid)) {'),
     'fast_cell_axes_swapped': ('size_t c = (size_t)grid_cell(x[1], g) * g + grid_cell(x[0], g);',
                                'size_t c = (size_t)grid_cell(x[0], g) * g + grid_cell(x[1], g);'),
+    # rolling highlight and G-buffer
+    'highlight_eye_sign': ('if (ks == 0.0 || dot3(n, l) <= 0.0) return 0.0;\n    double rn = norm3(r);',
+                           'if (ks == 0.0 || dot3(n, l) <= 0.0) return 0.0;\n    double rn = -norm3(r);'),
+    'highlight_not_gated': ('if (ks == 0.0 || dot3(n, l) <= 0.0) return 0.0;', 'if (ks == 0.0) return 0.0;'),
+    'highlight_exponent': ('return ndh > 0.0 ? ks * pow(ndh, m) : 0.0;', 'return ndh > 0.0 ? ks * pow(ndh, m - 1.0) : 0.0;'),
+    'highlight_half_vector_unnormalised': ('double ndh = dot3(n, H) / hn;', 'double ndh = dot3(n, H);'),
+    'highlight_eye_unnormalised': ('    double H[3] = {l[0] - r[0] / rn, l[1] - r[1] / rn, l[2] - r[2] / rn};\n    double hn',
+                                   '    double H[3] = {l[0] - r[0], l[1] - r[1], l[2] - r[2]};\n    double hn'),
+    'grad_highlight_normal_dropped': ('gn[d] += gsig * h[d];', 'gn[d] += 0.0 * h[d];'),
+    'grad_highlight_light_dropped': ('gl[d] += (gh[d] - h[d] * hg) / hn;', 'gl[d] += gh[d] / hn;'),
+    'gbuffer_bary_vertex': ('out_bary[2 * q] = mu[1];', 'out_bary[2 * q] = mu[0];'),
+    'gbuffer_normal_not_flipped': ('            if (dot3(n, r) > 0) { n[0] = -n[0]; n[1] = -n[1]; n[2] = -n[2]; }\n        }',
+                                   '        }'),
+    'gbuffer_density_not_sqrt': ('out_density[q] = sqrt(fabs(JF[0] * JF[3] - JF[1] * JF[2]));',
+                                 'out_density[q] = fabs(JF[0] * JF[3] - JF[1] * JF[2]);'),
+    'gbuffer_density_display_distance': ('    double JF[4];\n        orc_foveate_jac(vp, x, JF);',
+                                         '    double JF[4];\n        orc_foveate_jac(vp, y, JF);'),
     # display unfoveation
     'mip_texel_centre_shift': ('double uk0 = (u[0] + 0.5) * sc - 0.5, uk1 = (u[1] + 0.5) * sc - 0.5;',
                                'double uk0 = u[0] * sc, uk1 = u[1] * sc;'),
@@ -85,7 +103,8 @@ def _run(name, tmp):
     env = dict(os.environ, PR_ORACLE_LIB=so, OMP_NUM_THREADS='2')
     r = subprocess.run([sys.executable, '-m', 'pytest', '-x', '-q', '-p', 'no:cacheprovider',
                         os.path.join(ROOT, 'tests', 'test_oracle_pins.py'),
-                        os.path.join(ROOT, 'tests', 'test_oracle_display_pins.py')],
+                        os.path.join(ROOT, 'tests', 'test_oracle_display_pins.py'),
+                        os.path.join(ROOT, 'tests', 'test_oracle_shading_pins.py')],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode
 
