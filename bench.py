@@ -200,6 +200,48 @@ def bound_ablation(sc, args, stream, n):
     return out
 
 
+def shading_leg(sc, args, stream, n):
+    """Richer rolling shading on the HMD frame: the fused ray cast with the
+    Blinn-Phong highlight (eye at each pixel's time) against the Lambert-only
+    one, and the G-buffer pass (normal, barycentrics, density: 24 B written
+    and 4 B of id read per pixel, plus the record gathers) with its HBM rate
+    on the algorithmic bytes."""
+    import torch
+
+    from paper_1806_05385_amd import binding as B
+    from paper_1806_05385_amd.render import Renderer
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    out = {}
+    for name, ks in (('lambert', 0.0), ('highlight', 0.6)):
+        rr = Renderer(sc.meshes, sc.views, tile=args.tile, light=sc.light_dir, ambient=sc.ambient, specular=ks,
+                      shininess=24.0, flags=B.PR_FLAG_PERSISTENT)
+        rr.frame(check=True, rgb32=False)
+        out[name + '_raycast_shade_ms'] = round(timed(lambda: rr.raycast_shade(rgba8=True, rgb32=False)), 4)
+        if ks > 0:
+            g = rr.gbuffer()
+            px = sum(v.width * v.height for v in sc.views)
+            ms = timed(lambda: rr.gbuffer())
+            nbytes = 28 * px
+            out['gbuffer_ms'] = round(ms, 4)
+            out['gbuffer_GBps'] = round(nbytes / (ms * 1e-3) / 1e9, 1)
+            out['gbuffer_frac_of_hbm_peak'] = round(nbytes / (ms * 1e-3) / 8e12, 4)
+            del g
+        del rr
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -297,9 +339,10 @@ def main():
     if args.only == 'hmd':
         args.no_cpu_baseline = True
     fwd_med = bwd_med = float('nan')
-    batch_out = large_out = seq_eyes_ms = display_out = ablation_out = None
+    batch_out = large_out = seq_eyes_ms = display_out = ablation_out = shading_out = None
     if args.only == 'all':
         seq_eyes_ms = sequential_eyes(sc, args, stream, 50)
+        shading_out = shading_leg(sc, args, stream, 50)
         display_out = display_leg(sc, r, stream, 50)
         ablation_out = bound_ablation(sc, args, stream, 20)
         fwd_med, bwd_med = grad_leg(args, stream)
@@ -439,6 +482,7 @@ def main():
                         'frac_of_hbm_peak': round(fb_bytes / (ray_ms_avg * 1e-3) / 8e12, 4)},
         'display': display_out,
         'bound_ablation': ablation_out,
+        'shading': shading_out,
         'raycast_shade_ms': round(ray_ms_avg, 4),
         'tests_per_frame': tests,
         'tests_per_s': round(tests / (ray_ms_avg * 1e-3), 1),

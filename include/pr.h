@@ -21,7 +21,8 @@
  *               (replaces the fixed-function rasterisation of the bound)
  *   pr_raycast  per-pixel ray at the pixel's foveated position and time,
  *               ray-triangle test, nearest-depth resolve (Sec. 3.2)
- *   pr_shade    rolling Lambert shading of the resolved ids (Sec. 3.2)
+ *   pr_shade    rolling shading of the resolved ids (Sec. 3.2)
+ *   pr_gbuffer  normals, barycentrics and pixel density of the resolved ids
  * and, for differentiable rendering,
  *   pr_backward gradient of an image loss w.r.t. vertex positions and the
  *               start/end camera poses with visibility held fixed.
@@ -116,10 +117,18 @@ typedef struct pr_view {
 } pr_view;
 
 /* Directional light: dir_world points towards the light (need not be unit);
- * ambient = k_a in c = albedo (k_a + (1 - k_a) max(0, n.l)). */
+ * ambient = k_a in c = albedo (k_a + (1 - k_a) max(0, n.l)).
+ * specular = k_s >= 0 and shininess = m >= 1 add a white Blinn-Phong
+ * highlight k_s max(0, n.h)^m to every channel where n.l > 0, with the
+ * half vector h = normalize(l + v) of the light and the direction v = -ray
+ * towards the eye; k_s = 0 is pure Lambert.  Like the light, the eye rolls:
+ * v is taken in the camera frame at the pixel's own time (Sec. 3.2
+ * "Shading", Sec. 5.1 "Rolling Shading"). */
 typedef struct pr_light {
     float dir_world[3];
     float ambient;
+    float specular;
+    float shininess;
 } pr_light;
 
 /* tile: square tile side in pixels, one of 8, 16, 32.
@@ -198,10 +207,11 @@ int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
 int pr_raycast(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
                void *ws, size_t ws_bytes, int32_t *const *tri_id, float *const *depth, void *stream);
 
-/* Rolling Lambert shading (Sec. 3.2 "Shading"): light direction
+/* Rolling shading (Sec. 3.2 "Shading"): light direction
  * normalize((1-t) R0 l + t R1 l) at the pixel's time t, face normal turned
  * towards the eye, per-vertex albedo (float32 [nv][3] per mesh) blended with
- * the perspective-correct barycentrics of the hit.  rgba8[v] (uint8
+ * the perspective-correct barycentrics of the hit, Lambert plus the rolling
+ * Blinn-Phong highlight of pr_light (eye direction at the pixel's time).  rgba8[v] (uint8
  * [H][W][4]) and rgb32[v] (float32 [H][W][3]) may each be NULL (or hold NULL
  * entries).  Needs pr_bound of the same frame. */
 int pr_shade(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
@@ -220,6 +230,31 @@ int pr_raycast_shade(const pr_mesh *meshes, int nm, const pr_view *views, int nv
                      void *ws, size_t ws_bytes, int32_t *const *tri_id, float *const *depth,
                      const pr_light *light, const float *const *albedo, uint8_t *const *rgba8,
                      float *const *rgb32, void *stream);
+
+/* G-buffer of the resolved ids (the deferred-shading buffer of Sec. 3.2
+ * "Pipeline", for screen-space effects, Sec. 7 "Screen-space effects").
+ * Per pixel of view v:
+ *   normal[v]  float32 [H][W][3]: the triangle's unit face normal in the
+ *              camera frame at the pixel's time, turned towards the eye
+ *              (0 for misses);
+ *   bary[v]    float32 [H][W][2]: the perspective-correct barycentrics
+ *              (mu_1, mu_2) of the hit (mu_0 = 1 - mu_1 - mu_2; 0 for
+ *              misses), which interpolate any per-vertex attribute such as
+ *              texture coordinates;
+ *   density[v] float32 [H][W]: the foveation's pixel density at the pixel,
+ *              the factor by which a short distance in the display grows in
+ *              the foveated image: the square root of the Jacobian
+ *              determinant of the foveate map at the pixel's display point,
+ *              alpha^(-1/2) (rho/R)^(1-alpha) with rho the pixel's foveated
+ *              distance to the fovea (1 for alpha = 1, +inf at the fovea
+ *              itself); written for every pixel.
+ * Screen-space effects that measure distances in display pixels (an SSAO
+ * radius) multiply them by density.  tri_id as pr_raycast wrote it; any
+ * output array may be NULL or hold NULL entries.  Needs pr_bound of the
+ * same frame. */
+int pr_gbuffer(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning,
+               void *ws, size_t ws_bytes, const int32_t *const *tri_id, float *const *normal,
+               float *const *bary, float *const *density, void *stream);
 
 /* Gradient of a loss L(rgb32) with visibility fixed to tri_id: given
  * dL/drgb[v] (float32 [H][W][3]), writes dL/dv0 and dL/dv1 (float32 [nv][3]

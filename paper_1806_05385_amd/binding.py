@@ -43,7 +43,8 @@ class PrView(ctypes.Structure):
 
 
 class PrLight(ctypes.Structure):
-    _fields_ = [('dir_world', ctypes.c_float * 3), ('ambient', ctypes.c_float)]
+    _fields_ = [('dir_world', ctypes.c_float * 3), ('ambient', ctypes.c_float), ('specular', ctypes.c_float),
+                ('shininess', ctypes.c_float)]
 
 
 class PrTuning(ctypes.Structure):
@@ -78,6 +79,7 @@ SIGNATURES = {
     'pr_raycast': (ctypes.c_int, _FRAME + [_PP, _PP, ctypes.c_void_p]),
     'pr_shade': (ctypes.c_int, _FRAME + [_PP, ctypes.POINTER(PrLight), _PP, _PP, _PP, ctypes.c_void_p]),
     'pr_raycast_shade': (ctypes.c_int, _FRAME + [_PP, _PP, ctypes.POINTER(PrLight), _PP, _PP, _PP, ctypes.c_void_p]),
+    'pr_gbuffer': (ctypes.c_int, _FRAME + [_PP, _PP, _PP, _PP, ctypes.c_void_p]),
     'pr_backward': (ctypes.c_int, _FRAME + [_PP, ctypes.POINTER(PrLight), _PP, _PP, _PP, _PP, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p]),
     'pr_frame_static': (ctypes.c_int, _FRAME[:5] + [_PP, _PP, ctypes.POINTER(PrLight), _PP, _PP, _PP, ctypes.c_void_p]),
@@ -143,11 +145,13 @@ def make_view(v, mesh_index: int = None) -> PrView:
     return pv
 
 
-def make_light(direction, ambient: float) -> PrLight:
+def make_light(direction, ambient: float, specular: float = 0.0, shininess: float = 1.0) -> PrLight:
     pl = PrLight()
     for k in range(3):
         pl.dir_world[k] = float(direction[k])
     pl.ambient = float(ambient)
+    pl.specular = float(specular)
+    pl.shininess = float(shininess)
     return pl
 
 

@@ -281,13 +281,19 @@ void launch_raycast_any(int tile, int flags, const Layout &L, void *ws, const Ra
 
 // Checks the shading arguments and fills io (ids from tri_id, may be NULL
 // when the ids come from the ray cast); *any: some view has an output.
+// A usable light: finite direction and ambient, highlight k_s >= 0 and
+// exponent m >= 1 (finite).
+bool light_ok(const pr_light *light) {
+    return light && isfinite(light->ambient) && isfinite(light->dir_world[0]) && isfinite(light->dir_world[1]) &&
+           isfinite(light->dir_world[2]) && isfinite(light->specular) && light->specular >= 0.0f &&
+           isfinite(light->shininess) && light->shininess >= 1.0f;
+}
+
 int shade_args(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const int32_t *const *tri_id,
                const pr_light *light, const float *const *albedo, uint8_t *const *rgba8, float *const *rgb32,
                ShadeIO &io, bool &any) {
     if (!light || !albedo || !views || nv < 1 || nv > PR_MAX_VIEWS) return PR_ERR_INVALID;
-    if (!isfinite(light->ambient) || !isfinite(light->dir_world[0]) || !isfinite(light->dir_world[1]) ||
-        !isfinite(light->dir_world[2]))
-        return PR_ERR_INVALID;
+    if (!light_ok(light)) return PR_ERR_INVALID;
     if (tri_id)
         for (int v = 0; v < nv; ++v)
             if (!tri_id[v]) return PR_ERR_INVALID;
@@ -396,6 +402,29 @@ int pr_shade(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const 
     return launched();
 }
 
+int pr_gbuffer(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning, void *ws,
+               size_t ws_bytes, const int32_t *const *tri_id, float *const *normal, float *const *bary,
+               float *const *density, void *stream) {
+    if (!tri_id || !views || nv < 1 || nv > PR_MAX_VIEWS) return PR_ERR_INVALID;
+    for (int v = 0; v < nv; ++v)
+        if (!tri_id[v]) return PR_ERR_INVALID;
+    GbufIO io;
+    memset(&io, 0, sizeof(io));
+    bool any = false;
+    for (int v = 0; v < nv; ++v) {
+        io.id[v] = tri_id[v];
+        io.normal[v] = normal ? normal[v] : nullptr;
+        io.bary[v] = bary ? bary[v] : nullptr;
+        io.density[v] = density ? density[v] : nullptr;
+        any |= io.normal[v] || io.bary[v] || io.density[v];
+    }
+    PR_PREP();
+    (void)st;
+    if (!any) return PR_OK;
+    hipLaunchKernelGGL(k_gbuffer, dim3(L.total_pix_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec), io);
+    return launched();
+}
+
 int pr_raycast_shade(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning, void *ws,
                      size_t ws_bytes, int32_t *const *tri_id, float *const *depth, const pr_light *light,
                      const float *const *albedo, uint8_t *const *rgba8, float *const *rgb32, void *stream) {
@@ -423,9 +452,7 @@ int pr_backward(const pr_mesh *meshes, int nm, const pr_view *views, int nv, con
                 const float *const *dl_drgb, float *const *dv0, float *const *dv1, float *dpose0, float *dpose1,
                 void *stream) {
     if (!tri_id || !light || !albedo || !dl_drgb || !dv0 || !dv1 || !dpose0 || !dpose1) return PR_ERR_INVALID;
-    if (!isfinite(light->ambient) || !isfinite(light->dir_world[0]) || !isfinite(light->dir_world[1]) ||
-        !isfinite(light->dir_world[2]))
-        return PR_ERR_INVALID;
+    if (!light_ok(light)) return PR_ERR_INVALID;
     if (!views || !meshes || nv < 1 || nv > PR_MAX_VIEWS || nm < 1 || nm > PR_MAX_VIEWS) return PR_ERR_INVALID;
     for (int v = 0; v < nv; ++v) {
         if (!tri_id[v] || !dl_drgb[v]) return PR_ERR_INVALID;
@@ -458,7 +485,7 @@ int pr_backward(const pr_mesh *meshes, int nm, const pr_view *views, int nv, con
     // frame's pr_bound may hold another frame's by now)
     write_views(L, T, st, false, s);
     hipLaunchKernelGGL(k_view_light, dim3(1), dim3(64), 0, s, T, *light);
-    hipLaunchKernelGGL(k_bwd_pixel, dim3(L.total_pix_blocks), dim3(256), 0, s, T, io, light->ambient,
+    hipLaunchKernelGGL(k_bwd_pixel, dim3(L.total_pix_blocks), dim3(256), 0, s, T, io, *light,
                        at<float>(ws, L.gacc), at<double>(ws, L.pacc));
     if (L.total_vtx_blocks > 0)
         hipLaunchKernelGGL(k_bwd_vertex, dim3(L.total_vtx_blocks), dim3(256), 0, s, T, at<float>(ws, L.gacc), out);
@@ -915,6 +942,7 @@ int pr_batch_create(const pr_mesh *meshes, int nm, const pr_view *views, int nv,
                     uint8_t *const *rgba8, float *const *rgb32, pr_batch **out) {
     if (!out || !tuning || !light || !albedo || !tri_id || !depth) return PR_ERR_INVALID;
     *out = nullptr;
+    if (!light_ok(light)) return PR_ERR_INVALID;
     pr_tuning probe = *tuning;
     if (probe.tile == 0) probe.tile = 16;
     if (probe.bin_capacity == 0) probe.bin_capacity = 1;

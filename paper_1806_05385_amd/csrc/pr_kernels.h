@@ -156,6 +156,13 @@ struct ShadeIO {
     const float *albedo[PR_MAX_VIEWS];   // per view (the albedo of its mesh)
 };
 
+struct GbufIO {
+    const int32_t *id[PR_MAX_VIEWS];
+    float *normal[PR_MAX_VIEWS];    // [H][W][3]
+    float *bary[PR_MAX_VIEWS];      // [H][W][2]
+    float *density[PR_MAX_VIEWS];   // [H][W]
+};
+
 struct BwdIO {
     const int32_t *id[PR_MAX_VIEWS];
     const float *dl[PR_MAX_VIEWS];       // dL/drgb [H][W][3]

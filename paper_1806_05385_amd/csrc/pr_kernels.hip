@@ -21,7 +21,9 @@
 //              group; nearest packed (depth bits << 32 | id) kept in
 //              registers (Sec. 3.2 "Intersection"); the persistent form
 //              walks the tiles longest list first and may shade each cell
-//   k_shade    rolling Lambert shading of resolved ids (Sec. 3.2 "Shading")
+//   k_shade    rolling shading of resolved ids (Sec. 3.2 "Shading"): Lambert
+//              and a Blinn-Phong highlight with the eye at the pixel's time
+//   k_gbuffer  normals, barycentrics and pixel density of resolved ids
 //   k_bwd_*    frozen-visibility gradient of the shaded image
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -952,8 +954,25 @@ __device__ __forceinline__ void record_at(const ViewDev &vd, const float4 *__res
     }
 }
 
-// Rolling Lambert colour of triangle id (0 <= id < nt) at a pixel whose
-// time and ray pixel_setup gave as (t, rx, ry).
+// Rolling Blinn-Phong highlight k_s (n.h)^m (white) of a pixel with ray
+// (rx, ry, 1): the eye is the camera's origin at the pixel's time, so the
+// direction towards it is -r; h = normalize(l + v).  Zero where n.l <= 0,
+// n.h <= 0 or l = -v.  n and l unit, ndl = n.l.
+__device__ __forceinline__ float specular_at(const pr_light &light, const float n[3], const float l[3], float ndl,
+                                             float rx, float ry) {
+    if (!(light.specular > 0.0f) || !(ndl > 0.0f)) return 0.0f;
+    const float ir = rsqrtf(fmaf(rx, rx, fmaf(ry, ry, 1.0f)));
+    const float H[3] = {fmaf(-rx, ir, l[0]), fmaf(-ry, ir, l[1]), l[2] - ir};
+    const float hh = H[0] * H[0] + H[1] * H[1] + H[2] * H[2];
+    if (!(hh > 0.0f)) return 0.0f;
+    const float ndh = (n[0] * H[0] + n[1] * H[1] + n[2] * H[2]) * rsqrtf(hh);
+    if (!(ndh > 0.0f)) return 0.0f;
+    // (n.h)^m = 2^(m log2(n.h)), n.h in (0, 1]
+    return light.specular * __builtin_amdgcn_exp2f(light.shininess * __builtin_amdgcn_logf(ndh));
+}
+
+// Rolling colour of triangle id (0 <= id < nt) at a pixel whose time and
+// ray pixel_setup gave as (t, rx, ry): Lambert plus the rolling highlight.
 __device__ __forceinline__ void shade_pixel_at(const ViewDev &vd, const float4 *__restrict__ rec,
                                                const float *__restrict__ alb, const pr_light &light, float t,
                                                float rx, float ry, int id, float c[3]) {
@@ -984,13 +1003,15 @@ __device__ __forceinline__ void shade_pixel_at(const ViewDev &vd, const float4 *
     float inl = rsqrtf(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
     float ndl = sg * inl * (N[0] * L[0] + N[1] * L[1] + N[2] * L[2]);
     float s = ambient + (1.0f - ambient) * fmaxf(ndl, 0.0f);
+    const float nu[3] = {sg * N[0], sg * N[1], sg * N[2]}, lu[3] = {inl * L[0], inl * L[1], inl * L[2]};
+    const float sp = specular_at(light, nu, lu, ndl, rx, ry);
     float invS = 1.0f / S;
     c[0] = c[1] = c[2] = 0.0f;
     for (int k = 0; k < 3; ++k) {
         float mu = e[k] * invS;
         for (int ch = 0; ch < 3; ++ch) c[ch] = fmaf(mu, a[k][ch], c[ch]);
     }
-    for (int ch = 0; ch < 3; ++ch) c[ch] *= s;
+    for (int ch = 0; ch < 3; ++ch) c[ch] = fmaf(c[ch], s, sp);
 }
 
 // Rolling Lambert colour of triangle id (0 <= id < nt) at pixel (px, py).
@@ -1402,6 +1423,64 @@ __global__ __launch_bounds__(256) void k_shade(const ViewTable *__restrict__ T, 
 }
 
 // ---------------------------------------------------------------------------
+// G-buffer
+// ---------------------------------------------------------------------------
+// Pixel density of the foveation at pixel (px, py): the linear scale of the
+// foveate map at the pixel's display point (square root of its Jacobian
+// determinant).  With display distance d = R (rho/R)^alpha of foveated
+// distance rho, the map's radial and tangential scales are
+// (1/alpha)(rho/R)^(1-alpha) and (rho/R)^(1-alpha), so the density is
+// alpha^(-1/2) (rho/R)^(1-alpha): 1 without foveation, +inf at the fovea.
+__device__ __forceinline__ float pixel_density(const PixelConst &pc, int px, int py) {
+    if (pc.mode == 0) return 1.0f;
+    const float y0 = (float)(2 * px + 1) * (0.5f * pc.invW2) - 1.0f;
+    const float y1 = 1.0f - (float)(2 * py + 1) * (0.5f * pc.invH2);
+    const float d0 = y0 - pc.fov0, d1 = y1 - pc.fov1;
+    const float rho = sqrtf(d0 * d0 + d1 * d1);
+    if (!(rho > 0.0f)) return INFINITY;
+    return rsqrtf(pc.alpha) * powf(rho * pc.invR, 1.0f - pc.alpha);
+}
+
+// One thread per pixel: for a resolved id the camera-space unit face normal
+// at the pixel's time turned towards the eye and the perspective-correct
+// barycentrics (mu_1, mu_2) (zeros for misses); the density for every pixel.
+__global__ __launch_bounds__(256) void k_gbuffer(const ViewTable *__restrict__ T, const float4 *__restrict__ rec,
+                                                 GbufIO io) {
+    const int v = find_view(T->pix_block0, T->nv, blockIdx.x);
+    const ViewDev &vd = T->v[v];
+    const PixelConst &pc = vd.pc;
+    const int64_t p = (int64_t)(blockIdx.x - vd.pix_block0) * 256 + threadIdx.x;
+    if (p >= (int64_t)pc.W * pc.H) return;
+    const int px = (int)(p % pc.W), py = (int)(p / pc.W);
+    int id = io.id[v][p];
+    if (id >= vd.mesh.nt) id = -1;
+    float n[3] = {0.0f, 0.0f, 0.0f}, mu1 = 0.0f, mu2 = 0.0f;
+    if (id >= 0) {
+        float t, rx, ry;
+        pixel_setup(pc, px, py, t, rx, ry);
+        float ck[3][3], N[3];
+        record_at(vd, rec, id, t, ck, N);
+        float e[3];
+        for (int k = 0; k < 3; ++k) e[k] = fmaf(ry, ck[k][1], fmaf(rx, ck[k][0], ck[k][2]));
+        const float invS = 1.0f / (e[0] + e[1] + e[2]);
+        mu1 = e[1] * invS;
+        mu2 = e[2] * invS;
+        const float inn = rsqrtf(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+        const float sg = (N[0] * rx + N[1] * ry + N[2]) > 0.0f ? -inn : inn;
+        for (int q = 0; q < 3; ++q) n[q] = sg * N[q];
+    }
+    if (io.normal[v]) {
+        float *o = io.normal[v] + 3 * p;
+        o[0] = n[0]; o[1] = n[1]; o[2] = n[2];
+    }
+    if (io.bary[v]) {
+        float *o = io.bary[v] + 2 * p;
+        o[0] = mu1; o[1] = mu2;
+    }
+    if (io.density[v]) io.density[v][p] = pixel_density(pc, px, py);
+}
+
+// ---------------------------------------------------------------------------
 // backward: gradient of a loss of the shaded image with visibility fixed
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void cross3f(const float a[3], const float b[3], float o[3]) {
@@ -1452,8 +1531,9 @@ constexpr int kBwdHashBits = 9;
 constexpr int kBwdHash = 1 << kBwdHashBits;
 constexpr int kBwdProbe = 8;
 
-__global__ __launch_bounds__(256) void k_bwd_pixel(const ViewTable *__restrict__ T, BwdIO io, float ka,
+__global__ __launch_bounds__(256) void k_bwd_pixel(const ViewTable *__restrict__ T, BwdIO io, pr_light light,
                                                    float *__restrict__ gacc, double *__restrict__ pblk) {
+    const double ka = light.ambient, ks = light.specular, shin = light.shininess;
     __shared__ int32_t s_vkey[kBwdHash];
     __shared__ float s_vg[kBwdHash][7];   // start xyz, end xyz (odd stride)
     __shared__ double s_pp[4][30];
@@ -1537,6 +1617,24 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(const ViewTable *__restrict__
         const double gndl = ndl > 0.0 ? gs * (1.0 - ka) : 0.0;
         double gm[3], gl[3];
         for (int q = 0; q < 3; ++q) { gm[q] = sg * gndl * l[q]; gl[q] = gndl * n[q]; }
+        // rolling highlight sigma = k_s (n.h)^m added to every channel:
+        // h = H / |H|, H = l + v, v = -r / |r| (the eye at the pixel's time)
+        if (ks > 0.0 && ndl > 0.0) {
+            const double ir = 1.0 / sqrt(dot(r, r));
+            double H[3] = {l[0] - r[0] * ir, l[1] - r[1] * ir, l[2] - r[2] * ir};
+            const double hn = sqrt(dot(H, H));
+            if (hn > 0.0) {
+                double h[3] = {H[0] / hn, H[1] / hn, H[2] / hn};
+                const double ndh = dot(n, h);
+                if (ndh > 0.0) {
+                    const double gsig = (gc[0] + gc[1] + gc[2]) * ks * shin * pow(ndh, shin - 1.0);
+                    double gh[3];
+                    for (int q = 0; q < 3; ++q) { gm[q] += sg * gsig * h[q]; gh[q] = gsig * n[q]; }
+                    const double hg = dot(h, gh);
+                    for (int q = 0; q < 3; ++q) gl[q] += (gh[q] - h[q] * hg) / hn;
+                }
+            }
+        }
         const double mg = dot(m, gm), lg = dot(l, gl);
         const double ge1 = gmu1 / S, ge2 = gmu2 / S;
         const double gS = -(gmu1 * mu1 + gmu2 * mu2) / S;

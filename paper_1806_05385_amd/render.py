@@ -50,7 +50,8 @@ class Renderer:
     raised to what the device reported and the frame is run again."""
 
     def __init__(self, meshes, views, tile: int = 16, bin_capacity: int = 0, light=None, ambient: float = 0.1,
-                 flags: int = B.PR_FLAG_PERSISTENT, device='cuda', bound: int = B.PR_BOUND_ZENON):
+                 flags: int = B.PR_FLAG_PERSISTENT, device='cuda', bound: int = B.PR_BOUND_ZENON,
+                 specular: float = 0.0, shininess: float = 1.0):
         self.L = B.lib()
         self.bound_mode = int(bound)
         self.device = torch.device(device)
@@ -61,7 +62,7 @@ class Renderer:
         if not bin_capacity:
             bin_capacity = max(1 << 16, 4 * sum(self.meshes[v.mesh].tri.shape[0] for v in self.views) // len(self.views))
         self.cap = int(bin_capacity)
-        self.light = B.make_light(light if light is not None else (0.0, 0.0, -1.0), ambient)
+        self.light = B.make_light(light if light is not None else (0.0, 0.0, -1.0), ambient, specular, shininess)
         self._prepare()
         self.outputs = []
         for v in self.views:
@@ -107,6 +108,20 @@ class Renderer:
         o32 = B.ptr_array([o['rgb32'].data_ptr() for o in self.outputs]) if rgb32 else None
         B.check('pr_shade', self.L.pr_shade(*self._args(), idp, ctypes.byref(self.light), alb, o8, o32,
                                             ctypes.c_void_p(_stream_handle())))
+
+    def gbuffer(self, ids=None):
+        """pr_gbuffer of this frame's ids (or ``ids``): per view a dict of
+        normal [H,W,3], bary [H,W,2] and density [H,W] float32 tensors."""
+        idp = B.ptr_array([(ids[i] if ids is not None else o['id']).data_ptr() for i, o in enumerate(self.outputs)])
+        out = [dict(normal=torch.empty((v.height, v.width, 3), dtype=torch.float32, device=self.device),
+                    bary=torch.empty((v.height, v.width, 2), dtype=torch.float32, device=self.device),
+                    density=torch.empty((v.height, v.width), dtype=torch.float32, device=self.device))
+               for v in self.views]
+        B.check('pr_gbuffer', self.L.pr_gbuffer(
+            *self._args(), idp, B.ptr_array([g['normal'].data_ptr() for g in out]),
+            B.ptr_array([g['bary'].data_ptr() for g in out]), B.ptr_array([g['density'].data_ptr() for g in out]),
+            ctypes.c_void_p(_stream_handle())))
+        return out
 
     def raycast_shade(self, rgba8: bool = True, rgb32: bool = True):
         """pr_raycast_shade: the ray cast with the shading of its ids fused in."""

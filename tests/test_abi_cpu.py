@@ -111,6 +111,27 @@ def test_calls_reject_bad_workspace_before_launch():
     assert L.pr_status_read(None, 1024, ctypes.byref(st), None) == B.PR_ERR_INVALID
 
 
+def test_light_and_gbuffer_arguments_checked_before_launch():
+    """A highlight needs k_s >= 0 and exponent m >= 1 (finite): pr_shade,
+    pr_raycast_shade and pr_backward reject other lights on the host;
+    pr_gbuffer checks its ids and workspace before any HIP call."""
+    L = B.lib()
+    meshes, views, tu, sc = _frame()
+    size = ctypes.c_size_t(0)
+    L.pr_workspace_size(meshes, 1, views, 1, ctypes.byref(tu), ctypes.byref(size))
+    args = (meshes, 1, views, 1, ctypes.byref(tu), ctypes.c_void_p(256 * 1000), size.value)
+    fake = B.ptr_array([1 << 20])
+    for ks, m in ((-0.1, 8.0), (0.5, 0.5), (float('nan'), 8.0), (0.5, float('inf'))):
+        bad = B.make_light(sc.light_dir, sc.ambient, ks, m)
+        assert L.pr_shade(*args, fake, ctypes.byref(bad), fake, fake, None, None) == B.PR_ERR_INVALID
+        assert L.pr_raycast_shade(*args, fake, fake, ctypes.byref(bad), fake, fake, None, None) == B.PR_ERR_INVALID
+        assert L.pr_backward(*args, fake, ctypes.byref(bad), fake, fake, fake, fake, ctypes.c_void_p(1 << 20),
+                             ctypes.c_void_p(1 << 20), None) == B.PR_ERR_INVALID
+    assert L.pr_gbuffer(*args, None, fake, fake, fake, None) == B.PR_ERR_INVALID
+    assert L.pr_gbuffer(*args, B.ptr_array([0]), fake, fake, fake, None) == B.PR_ERR_INVALID
+    assert L.pr_gbuffer(*args[:5], None, size.value, fake, fake, None, None, None) == B.PR_ERR_WORKSPACE
+
+
 def huge_candidate_scene(n_tris: int = 520):
     """A 16384 x 16384 view at tile 8 (2048 x 2048 tiles) and n_tris
     triangles that each cover the whole display: every triangle's tile
