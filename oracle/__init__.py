@@ -25,7 +25,8 @@ _SRC = os.path.join(_HERE, 'pr_oracle.c')
 _LIB = os.path.join(_HERE, '_pr_oracle.so')
 _lib = None
 
-NPARAM = 24
+NPARAM = 26 + 2 * 64
+PMAX = 64
 
 
 def build(force: bool = True) -> str:
@@ -56,6 +57,7 @@ def lib():
         L.orc_fovea_radius.argtypes = [dp]
         L.orc_fovea_radius.restype = ctypes.c_double
         L.orc_unfoveate.argtypes = [dp, dp, dp]
+        L.orc_undistort.argtypes = [dp, dp, dp]
         L.orc_foveate.argtypes = [dp, dp, dp]
         L.orc_pixel_time.argtypes = [dp, dp]
         L.orc_pixel_time.restype = ctypes.c_double
@@ -99,7 +101,7 @@ def _d(a):
 
 
 def view_params(view, pose0=None, pose1=None) -> np.ndarray:
-    """24-double parameter block of a scenegen.View (optionally overriding poses)."""
+    """Parameter block of a scenegen.View (optionally overriding poses)."""
     p = np.zeros(NPARAM)
     p[0], p[1] = view.width, view.height
     p[2:8] = view.pose0 if pose0 is None else pose0
@@ -108,6 +110,17 @@ def view_params(view, pose0=None, pose1=None) -> np.ndarray:
     p[19:21] = view.fovea
     p[21] = view.alpha
     p[22:24] = view.roll_dir
+    pc, pl = getattr(view, 'profile_c', None), getattr(view, 'profile_l', None)
+    if pc is not None:
+        pc = np.asarray(pc, np.float32).astype(np.float64)   # the float32 samples, exactly
+        assert 2 <= pc.size <= PMAX
+        p[24] = pc.size
+        p[26:26 + pc.size] = pc
+    if pl is not None:
+        pl = np.asarray(pl, np.float32).astype(np.float64)
+        assert 2 <= pl.size <= PMAX
+        p[25] = pl.size
+        p[26 + PMAX:26 + PMAX + pl.size] = pl
     return p
 
 
@@ -261,6 +274,16 @@ def unfoveate(view, y) -> np.ndarray:
     x = np.empty(2)
     lib().orc_unfoveate(_p(vp, ctypes.c_double), _p(y, ctypes.c_double), _p(x, ctypes.c_double))
     return x
+
+
+def undistort(view, x) -> np.ndarray:
+    """Panel point -> undistorted point (the view's lens inverted; identity
+    without a lens)."""
+    vp = view_params(view)
+    x = _d(x)
+    u = np.empty(2)
+    lib().orc_undistort(_p(vp, ctypes.c_double), _p(x, ctypes.c_double), _p(u, ctypes.c_double))
+    return u
 
 
 def foveate(view, x) -> np.ndarray:

@@ -28,9 +28,12 @@
  *
  * Everything is double precision; float32 inputs convert exactly.
  *
- * View parameter block (24 doubles), see ORC_* indices below:
+ * View parameter block (ORC_NPARAM doubles), see ORC_* indices below:
  *   width, height, pose0[6], pose1[6], fx, fy, cx, cy, znear,
- *   fovea[2], alpha, roll_dir[2]
+ *   fovea[2], alpha, roll_dir[2], n_c, n_l, p_c samples [64], p_l samples [64]
+ * n_c = 0: the power-law foveation of alpha; n_c >= 2: the tabulated
+ * foveation p_c (alpha unused); n_l >= 2: a tabulated lens distortion p_l
+ * composed before it (Sec. 5.1 "Lens Distortion"), 0: none.
  * A pose is a world->view rotation vector omega (3) then translation T (3):
  *   P = R(omega) v + T.
  * View space: x right, y up, +z forward.  NDC: x = fx X/Z + cx,
@@ -45,10 +48,12 @@
 #include <omp.h>
 #endif
 
+#define ORC_PMAX 64   /* samples of a tabulated profile */
 enum {
     ORC_W = 0, ORC_H = 1, ORC_POSE0 = 2, ORC_POSE1 = 8, ORC_FX = 14, ORC_FY = 15,
     ORC_CX = 16, ORC_CY = 17, ORC_ZNEAR = 18, ORC_FOV = 19, ORC_ALPHA = 21,
-    ORC_ROLL = 22, ORC_NPARAM = 24
+    ORC_ROLL = 22, ORC_NC = 24, ORC_NL = 25, ORC_PC = 26, ORC_PL = 26 + ORC_PMAX,
+    ORC_NPARAM = 26 + 2 * ORC_PMAX
 };
 
 /* ------------------------------------------------------------------------- */
@@ -155,28 +160,88 @@ double orc_fovea_radius(const double *vp) {
     return best;
 }
 
-/* Unfoveate (foveated NDC y -> display NDC x): radial power law about the
- * fovea, display distance = R (rho/R)^alpha.  alpha = 1 is the identity
- * (constant density, common rasterization). */
+/* Tabulated radial profile (Sec. 3.1.1 "Domain": p is arbitrary, only
+ * monotone, and may change every frame): a function g of normalised distance
+ * given by its samples tab[k] = g(k / (n-1)), tab[0] = 0, strictly
+ * increasing; linear between samples and continued past the last sample
+ * with the last segment's slope. */
+static double tab_eval(const double *tab, int n, double s) {
+    double h = 1.0 / (n - 1);
+    int k = (int)floor(s / h);
+    if (k < 0) k = 0;
+    if (k > n - 2) k = n - 2;
+    return tab[k] + (s - k * h) / h * (tab[k + 1] - tab[k]);
+}
+
+/* Slope of the segment that tab_eval uses at s. */
+static double tab_slope(const double *tab, int n, double s) {
+    double h = 1.0 / (n - 1);
+    int k = (int)floor(s / h);
+    if (k < 0) k = 0;
+    if (k > n - 2) k = n - 2;
+    return (tab[k + 1] - tab[k]) / h;
+}
+
+/* The numeric inverse of a tabulated profile: the segment whose end values
+ * bracket u (a scan from the fovea outwards), then the linear inverse on it
+ * (the inverse of a piecewise-linear increasing function is the
+ * piecewise-linear function through the swapped samples). */
+static double tab_inv(const double *tab, int n, double u) {
+    int k = 0;
+    while (k < n - 2 && tab[k + 1] <= u) ++k;
+    double h = 1.0 / (n - 1);
+    return (k + (u - tab[k]) / (tab[k + 1] - tab[k])) * h;
+}
+
+/* Scale of a radial map about the fovea taking distance rho to g(rho / R) R
+ * (g = the profile, inverted when inv), as the factor on (point - fovea). */
+static double tab_scale(const double *vp, int which, int inv, double rho) {
+    const double *tab = vp + (which ? ORC_PL : ORC_PC);
+    int n = (int)vp[which ? ORC_NL : ORC_NC];
+    double s = rho / orc_fovea_radius(vp);
+    return (inv ? tab_inv(tab, n, s) : tab_eval(tab, n, s)) / s;
+}
+
+/* Unfoveate (foveated NDC y -> display NDC x): radial about the fovea; with
+ * the power law display distance = R (rho/R)^alpha (alpha = 1 is the
+ * identity: constant density, common rasterization); with a tabulated p_c
+ * display distance = R p_c^{-1}(rho/R).  The display point is the panel's:
+ * a lens distortion (orc_undistort) applies after it. */
 void orc_unfoveate(const double *vp, const double y[2], double x[2]) {
     double fx = vp[ORC_FOV], fy = vp[ORC_FOV + 1];
     double dx = y[0] - fx, dy = y[1] - fy;
     double rho = sqrt(dx * dx + dy * dy);
     if (rho == 0.0) { x[0] = fx; x[1] = fy; return; }
-    double s = pow(rho / orc_fovea_radius(vp), vp[ORC_ALPHA] - 1.0);
+    double s = vp[ORC_NC] > 0 ? tab_scale(vp, 0, 1, rho) : pow(rho / orc_fovea_radius(vp), vp[ORC_ALPHA] - 1.0);
     x[0] = fx + dx * s;
     x[1] = fy + dy * s;
 }
 
-/* Foveate (display NDC x -> foveated NDC y), the inverse power law. */
+/* Foveate (display NDC x -> foveated NDC y), the inverse of orc_unfoveate:
+ * foveated distance = R (d/R)^(1/alpha), or R p_c(d/R). */
 void orc_foveate(const double *vp, const double x[2], double y[2]) {
     double fx = vp[ORC_FOV], fy = vp[ORC_FOV + 1];
     double dx = x[0] - fx, dy = x[1] - fy;
     double rho = sqrt(dx * dx + dy * dy);
     if (rho == 0.0) { y[0] = fx; y[1] = fy; return; }
-    double s = pow(rho / orc_fovea_radius(vp), 1.0 / vp[ORC_ALPHA] - 1.0);
+    double s = vp[ORC_NC] > 0 ? tab_scale(vp, 0, 0, rho) : pow(rho / orc_fovea_radius(vp), 1.0 / vp[ORC_ALPHA] - 1.0);
     y[0] = fx + dx * s;
     y[1] = fy + dy * s;
+}
+
+/* Lens distortion (Sec. 5.1 "Lens Distortion": p = p_c o p_l, p_l undone by
+ * the optics): p_l takes the undistorted distance of a view direction to
+ * its panel distance, about the same centre as p_c (the paper composes the
+ * two distance functions).  Panel point x -> undistorted point u, whose
+ * pinhole ray the pixel casts; the identity without a lens. */
+void orc_undistort(const double *vp, const double x[2], double u[2]) {
+    double fx = vp[ORC_FOV], fy = vp[ORC_FOV + 1];
+    double dx = x[0] - fx, dy = x[1] - fy;
+    double rho = sqrt(dx * dx + dy * dy);
+    if (vp[ORC_NL] <= 0 || rho == 0.0) { u[0] = x[0]; u[1] = x[1]; return; }
+    double s = tab_scale(vp, 1, 1, rho);
+    u[0] = fx + dx * s;
+    u[1] = fy + dy * s;
 }
 
 /* Rolling function: unit display position (x+1)/2 dotted with the skew
@@ -188,14 +253,18 @@ double orc_pixel_time(const double *vp, const double x[2]) {
     return t;
 }
 
-/* Per-pixel setup: foveated sample y, display point x, time t, ray r. */
+/* Per-pixel setup: foveated sample y, its panel point (unfoveated) whose
+ * scan time is t, and the undistorted point x of that panel point (x is the
+ * panel point without a lens), whose pinhole ray is r. */
 void orc_pixel_setup(const double *vp, int64_t pix, double y[2], double x[2], double *t, double r[3]) {
     int W = (int)vp[ORC_W], H = (int)vp[ORC_H];
     int64_t i = pix % W, j = pix / W;
     y[0] = 2.0 * (i + 0.5) / W - 1.0;
     y[1] = 1.0 - 2.0 * (j + 0.5) / H;
-    orc_unfoveate(vp, y, x);
-    *t = orc_pixel_time(vp, x);
+    double xp[2];
+    orc_unfoveate(vp, y, xp);
+    *t = orc_pixel_time(vp, xp);
+    orc_undistort(vp, xp, x);
     r[0] = (x[0] - vp[ORC_CX]) / vp[ORC_FX];
     r[1] = (x[1] - vp[ORC_CY]) / vp[ORC_FY];
     r[2] = 1.0;
@@ -792,8 +861,9 @@ void orc_foveate_jac(const double *vp, const double x[2], double JF[4]);
 /* Per pixel: the visible triangle's unit face normal at the pixel's time in
  * the camera frame, turned towards the eye; the barycentrics mu_1, mu_2 of
  * the ray's hit (mu_k = e_k / S); the pixel density, the square root of the
- * Jacobian determinant of the foveate map at the pixel's display point (how
- * much a short display-space length grows in the foveated image).  Misses
+ * Jacobian determinant of the foveate map at the pixel's display (panel)
+ * point (how much a short display-space length grows in the foveated image;
+ * a lens is undone optically, not by the display, so it does not enter).  Misses
  * give zero normal and barycentrics; the density is written for every pixel. */
 void orc_gbuffer(const double *vp, const double *v0, const double *v1, int nv, const int32_t *tri, int nt,
                  const int64_t *pix, int64_t npix, const int32_t *ids, double *out_normal, double *out_bary,
@@ -807,8 +877,9 @@ void orc_gbuffer(const double *vp, const double *v0, const double *v1, int nv, c
         int64_t p = pix ? pix[q] : q;
         double y[2], x[2], t, r[3];
         orc_pixel_setup(vp, p, y, x, &t, r);
-        double JF[4];
-        orc_foveate_jac(vp, x, JF);
+        double xp[2], JF[4];   /* the foveation's Jacobian at the panel point */
+        orc_unfoveate(vp, y, xp);
+        orc_foveate_jac(vp, xp, JF);
         out_density[q] = sqrt(fabs(JF[0] * JF[3] - JF[1] * JF[2]));
         double n[3] = {0, 0, 0}, mu[3] = {0, 0, 0};
         int f = ids[q];
@@ -872,6 +943,18 @@ void orc_gbuffer(const double *vp, const double *v0, const double *v1, int nv, c
 void orc_foveate_jac(const double *vp, const double x[2], double JF[4]) {
     double d[2] = {x[0] - vp[ORC_FOV], x[1] - vp[ORC_FOV + 1]};
     double rho2 = d[0] * d[0] + d[1] * d[1];
+    if (vp[ORC_NC] > 0) {
+        /* y - f = (x - f) g(s)/s, s = |x - f|/R: J = (g/s) I + (g' - g/s) n n^T
+         * with n the unit direction; at the fovea g/s -> g'(0) */
+        const double *tab = vp + ORC_PC;
+        int n = (int)vp[ORC_NC];
+        double rho = sqrt(rho2), s = rho / orc_fovea_radius(vp);
+        double gp = tab_slope(tab, n, s), gs = rho2 == 0.0 ? gp : tab_eval(tab, n, s) / s;
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c)
+                JF[2 * r + c] = (r == c ? gs : 0.0) + (rho2 == 0.0 ? 0.0 : (gp - gs) * d[r] * d[c] / rho2);
+        return;
+    }
     double e = 1.0 / vp[ORC_ALPHA];
     if (rho2 == 0.0) {
         double v = e == 1.0 ? 1.0 : INFINITY;

@@ -56,6 +56,8 @@ class View:
     alpha: float = 2.0           # power-law foveation exponent, 1 = off
     roll_dir: tuple = (1.0, 0.0)  # rolling skew direction d, (0, 0) = off
     mesh: int = 0                # index of the mesh this view renders
+    profile_c: np.ndarray = None  # float32 samples of a tabulated foveation p_c (None: the power law)
+    profile_l: np.ndarray = None  # float32 samples of a tabulated lens distortion p_l (None: no lens)
 
 
 @dataclass
@@ -418,7 +420,7 @@ def make_grad(seed: int = 5, size: int = 512, f: int = 71, noise: float = 0.01) 
 def make_moving_soup(seed: int, n_tris: int, width: int, height: int, alpha: float = 2.0,
                      roll=(1.0, 0.0), yaw_deg_s: float = 120.0, obj_speed: float = 2.0,
                      fovea=None, fx: float = 1.0, fy: float = 1.0, centre_lo=(-1.5, -1.5, 1.0),
-                     centre_hi=(1.5, 1.5, 5.0), side=(0.02, 0.3)) -> Scene:
+                     centre_hi=(1.5, 1.5, 5.0), side=(0.02, 0.3), profile_c=None, profile_l=None) -> Scene:
     """Small test workload: a triangle soup whose triangles each move with
     their own velocity (|v| <= obj_speed m/s) under a yawing, translating
     camera, foveated and rolling.  Small enough for full brute force."""
@@ -431,8 +433,24 @@ def make_moving_soup(seed: int, n_tris: int, width: int, height: int, alpha: flo
         fovea = tuple(float(np.float32(x)) for x in rng.uniform(-0.2, 0.2, size=2))
     view = View(width, height, head_pose(0.0, yaw_deg_s, (0.5, 0, 0), 0.0),
                 head_pose(FRAME_S, yaw_deg_s, (0.5, 0, 0), 0.0), fx=fx, fy=fy,
-                fovea=fovea, alpha=alpha, roll_dir=roll)
+                fovea=fovea, alpha=alpha, roll_dir=roll, profile_c=profile_c, profile_l=profile_l)
     return Scene('moving_soup', [mesh], [view])
+
+
+def foveal_table(n: int = 33, gain: float = 3.0) -> np.ndarray:
+    """n float32 samples on s = k/(n-1) of the monotone profile
+    u(s) = s (1 + gain) / (1 + gain s): u(0) = 0, u(1) = 1, slope 1 + gain at
+    the fovea and 1 / (1 + gain) at the farthest corner (an input for the
+    tabulated foveation, of a shape no power law has)."""
+    s = np.linspace(0.0, 1.0, n)
+    return (s * (1.0 + gain) / (1.0 + gain * s)).astype(np.float32)
+
+
+def barrel_table(n: int = 33, k: float = 0.2) -> np.ndarray:
+    """n float32 samples of a barrel pre-distortion u(s) = s (1 - k s^2)
+    (undistorted -> panel distance, increasing for k < 1/3)."""
+    s = np.linspace(0.0, 1.0, n)
+    return (s * (1.0 - k * s * s)).astype(np.float32)
 
 
 WORKLOADS = {

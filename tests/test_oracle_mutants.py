@@ -2,8 +2,9 @@
 
 Each case copies oracle/pr_oracle.c, plants one plausible mistake (a dropped
 term, a wrong sign or index, a swapped operand), builds the copy with gcc and
-runs tests/test_oracle_pins.py, tests/test_oracle_display_pins.py and
-tests/test_oracle_shading_pins.py against it; the pins must fail.  Runs on the
+runs tests/test_oracle_pins.py, tests/test_oracle_display_pins.py,
+tests/test_oracle_shading_pins.py and tests/test_oracle_profile_pins.py
+against it; the pins must fail.  Runs on the
 CPU only.
 """
 import os
@@ -74,8 +75,20 @@ MUTANTS = {
                                    '        }'),
     'gbuffer_density_not_sqrt': ('out_density[q] = sqrt(fabs(JF[0] * JF[3] - JF[1] * JF[2]));',
                                  'out_density[q] = fabs(JF[0] * JF[3] - JF[1] * JF[2]);'),
-    'gbuffer_density_display_distance': ('    double JF[4];\n        orc_foveate_jac(vp, x, JF);',
-                                         '    double JF[4];\n        orc_foveate_jac(vp, y, JF);'),
+    'gbuffer_density_display_distance': ('orc_foveate_jac(vp, xp, JF);\n        out_density',
+                                         'orc_foveate_jac(vp, y, JF);\n        out_density'),
+    # tabulated foveation and lens distortion
+    'tab_inverse_segment': ('while (k < n - 2 && tab[k + 1] <= u) ++k;', 'while (k < n - 2 && tab[k] <= u) ++k;'),
+    'tab_eval_segment_offset': ('return tab[k] + (s - k * h) / h * (tab[k + 1] - tab[k]);',
+                                'return tab[k] + s / h * (tab[k + 1] - tab[k]);'),
+    'tab_slope_not_scaled': ('return (tab[k + 1] - tab[k]) / h;', 'return (tab[k + 1] - tab[k]);'),
+    'tab_unfoveate_uses_power_law': ('double s = vp[ORC_NC] > 0 ? tab_scale(vp, 0, 1, rho) :',
+                                     'double s = 0 ? tab_scale(vp, 0, 1, rho) :'),
+    'lens_not_applied': ('    orc_undistort(vp, xp, x);\n    r[0]', '    x[0] = xp[0]; x[1] = xp[1];\n    r[0]'),
+    'lens_forward_not_inverse': ('double s = tab_scale(vp, 1, 1, rho);', 'double s = tab_scale(vp, 1, 0, rho);'),
+    'time_from_undistorted_point': ('*t = orc_pixel_time(vp, xp);\n    orc_undistort(vp, xp, x);',
+                                    'orc_undistort(vp, xp, x);\n    *t = orc_pixel_time(vp, x);'),
+    'tab_jacobian_radial_dropped': ('(gp - gs) * d[r] * d[c] / rho2', '0.0 * d[r] * d[c] / rho2'),
     # display unfoveation
     'mip_texel_centre_shift': ('double uk0 = (u[0] + 0.5) * sc - 0.5, uk1 = (u[1] + 0.5) * sc - 0.5;',
                                'double uk0 = u[0] * sc, uk1 = u[1] * sc;'),
@@ -104,7 +117,8 @@ def _run(name, tmp):
     r = subprocess.run([sys.executable, '-m', 'pytest', '-x', '-q', '-p', 'no:cacheprovider',
                         os.path.join(ROOT, 'tests', 'test_oracle_pins.py'),
                         os.path.join(ROOT, 'tests', 'test_oracle_display_pins.py'),
-                        os.path.join(ROOT, 'tests', 'test_oracle_shading_pins.py')],
+                        os.path.join(ROOT, 'tests', 'test_oracle_shading_pins.py'),
+                        os.path.join(ROOT, 'tests', 'test_oracle_profile_pins.py')],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode
 
