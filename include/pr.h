@@ -102,10 +102,42 @@ typedef struct pr_mesh {
     int32_t nt;
 } pr_mesh;
 
+/* Tabulated foveation and lens distortion (Sec. 3.1.1 "Domain": the
+ * density function p may be any monotone function and change every frame;
+ * Sec. 5.1 "Lens Distortion": p = p_c o p_l, with only p_c undone when the
+ * image is displayed).  Each profile is a radial function of normalised
+ * distance s = d / R about the view's fovea (R: distance from the fovea to
+ * the farthest image corner) given by n samples G(k / (n-1)), linear between
+ * samples and continued past the last one with the last segment's slope;
+ * G(0) = 0 and the samples strictly increase (finite).
+ *   p_c (n_c samples, 2..PR_PROFILE_MAX; 0 = the power law of alpha): the
+ *     foveation, panel (display) distance -> foveated distance; a pixel at
+ *     foveated distance rho has its panel point at distance R
+ *     p_c^{-1}(rho / R) (the numeric inverse: the segment bracketing rho / R,
+ *     then linear).  Requires p_c(s_k) >= s_k at every sample (the foveation
+ *     never moves a pixel's panel point outwards, as the power law does
+ *     not), else PR_ERR_INVALID.
+ *   p_l (n_l samples, 2..PR_PROFILE_MAX; 0 = no lens): the lens
+ *     pre-distortion, undistorted distance -> panel distance, about the same
+ *     centre; the pixel's ray passes through the point at undistorted
+ *     distance R p_l^{-1}(panel distance / R).
+ * A pixel's time comes from its panel point (the panel scans), its ray from
+ * the undistorted point.  With a lens the rolling bound's time window is
+ * the scan-time range of the triangle's panel image over the frame (the
+ * catch-up window assumes a straight scan in the projected image). */
+#define PR_PROFILE_MAX 64
+typedef struct pr_profile {
+    int32_t n_c, n_l;
+    float p_c[PR_PROFILE_MAX];
+    float p_l[PR_PROFILE_MAX];
+} pr_profile;
+
 /* One view (eye, frame or batch entry).  width, height in pixels
  * (1..16384); mesh indexes the pr_mesh array; pose0 / pose1 world->view at
  * the frame's start / end; fx, fy non-zero; znear > 0; fovea in NDC;
- * alpha >= 1 (1 = no foveation); roll_dir = d ((0,0) = rolling off). */
+ * alpha >= 1 (1 = no foveation); roll_dir = d ((0,0) = rolling off);
+ * profile: NULL (the power law of alpha, no lens) or a host pointer to the
+ * view's tabulated foveation / lens (read during the call only). */
 typedef struct pr_view {
     int32_t width, height, mesh, reserved;
     float pose0[6];
@@ -114,6 +146,7 @@ typedef struct pr_view {
     float fovea[2];
     float alpha;
     float roll_dir[2];
+    const pr_profile *profile;
 } pr_view;
 
 /* Directional light: dir_world points towards the light (need not be unit);

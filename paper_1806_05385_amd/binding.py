@@ -34,12 +34,20 @@ class PrMesh(ctypes.Structure):
                 ('nv', ctypes.c_int32), ('nt', ctypes.c_int32)]
 
 
+PR_PROFILE_MAX = 64
+
+
+class PrProfile(ctypes.Structure):
+    _fields_ = [('n_c', ctypes.c_int32), ('n_l', ctypes.c_int32), ('p_c', ctypes.c_float * PR_PROFILE_MAX),
+                ('p_l', ctypes.c_float * PR_PROFILE_MAX)]
+
+
 class PrView(ctypes.Structure):
     _fields_ = [('width', ctypes.c_int32), ('height', ctypes.c_int32), ('mesh', ctypes.c_int32),
                 ('reserved', ctypes.c_int32), ('pose0', ctypes.c_float * 6), ('pose1', ctypes.c_float * 6),
                 ('fx', ctypes.c_float), ('fy', ctypes.c_float), ('cx', ctypes.c_float), ('cy', ctypes.c_float),
                 ('znear', ctypes.c_float), ('fovea', ctypes.c_float * 2), ('alpha', ctypes.c_float),
-                ('roll_dir', ctypes.c_float * 2)]
+                ('roll_dir', ctypes.c_float * 2), ('profile', ctypes.POINTER(PrProfile))]
 
 
 class PrLight(ctypes.Structure):
@@ -142,7 +150,31 @@ def make_view(v, mesh_index: int = None) -> PrView:
     pv.fovea[0], pv.fovea[1] = float(v.fovea[0]), float(v.fovea[1])
     pv.alpha = float(v.alpha)
     pv.roll_dir[0], pv.roll_dir[1] = float(v.roll_dir[0]), float(v.roll_dir[1])
+    pc, pl = getattr(v, 'profile_c', None), getattr(v, 'profile_l', None)
+    if pc is not None or pl is not None:
+        prof = PrProfile()
+        for arr, n_name, field in ((pc, 'n_c', 'p_c'), (pl, 'n_l', 'p_l')):
+            if arr is None:
+                continue
+            a = [float(x) for x in arr]
+            if len(a) > PR_PROFILE_MAX:
+                raise ValueError(f'profile: at most {PR_PROFILE_MAX} samples')
+            setattr(prof, n_name, len(a))
+            dst = getattr(prof, field)
+            for k, x in enumerate(a):
+                dst[k] = x
+        # the pointer keeps prof alive as long as pv (or an array built from pv) lives
+        pv.profile = ctypes.pointer(prof)
     return pv
+
+
+def make_views(views, mesh_index: int = None):
+    """ctypes array of PrView for a list of views; the profiles the entries
+    point to stay alive with the array."""
+    pvs = [make_view(v, mesh_index) for v in views]
+    arr = (PrView * max(1, len(pvs)))(*pvs)
+    arr._keep = pvs
+    return arr
 
 
 def make_light(direction, ambient: float, specular: float = 0.0, shininess: float = 1.0) -> PrLight:

@@ -33,8 +33,30 @@ struct Layout {
     ViewDev vd[PR_MAX_VIEWS];
     int total_tiles, total_tri_blocks, total_pix_blocks, total_vtx_blocks, nparts;
     int64_t cap, total_rec4, total_tris, total_gacc;
-    size_t table, tinfo, rec, tb, bcand, bperm, boff, bpart, tcount, toff, part, pairs, lists, gacc, pacc, sched, order, bytes;
+    size_t table, tinfo, rec, tb, bcand, bperm, boff, bpart, tcount, toff, part, pairs, lists, gacc, pacc, sched, order, prof,
+        bytes;
+    ProfDev prof_host[PR_MAX_VIEWS];   // the views' tabulated profiles (used where prof_used)
+    bool prof_used[PR_MAX_VIEWS];
+    bool any_prof;                     // some view has one (the bound kernels' general form)
 };
+
+// A view's tabulated profiles are usable: sample counts in range, samples
+// finite, starting at 0 and strictly increasing; p_c(s_k) >= s_k.
+bool profile_ok(const pr_profile &P) {
+    if (P.n_c != 0 && (P.n_c < 2 || P.n_c > PR_PROFILE_MAX)) return false;
+    if (P.n_l != 0 && (P.n_l < 2 || P.n_l > PR_PROFILE_MAX)) return false;
+    for (int w = 0; w < 2; ++w) {
+        const int n = w ? P.n_l : P.n_c;
+        const float *g = w ? P.p_l : P.p_c;
+        if (n == 0) continue;
+        if (!(g[0] == 0.0f)) return false;
+        for (int k = 1; k < n; ++k) {
+            if (!isfinite(g[k]) || !(g[k] > g[k - 1])) return false;
+            if (!w && (double)g[k] < (double)k / (n - 1)) return false;
+        }
+    }
+    return true;
+}
 
 bool finite_all(const float *p, int n) {
     for (int i = 0; i < n; ++i)
@@ -63,6 +85,7 @@ int check_args(const pr_mesh *meshes, int nm, const pr_view *views, int nv, cons
         if (V.fx == 0.0f || V.fy == 0.0f || !(V.znear > 0.0f)) return PR_ERR_INVALID;
         if (!(V.alpha >= 1.0f) || V.alpha > 16.0f) return PR_ERR_INVALID;
         if (fabsf(V.fovea[0]) > 1.0f || fabsf(V.fovea[1]) > 1.0f) return PR_ERR_INVALID;
+        if (V.profile && !profile_ok(*V.profile)) return PR_ERR_INVALID;
     }
     if (tu->tile != 8 && tu->tile != 16 && tu->tile != 32) return PR_ERR_UNSUPPORTED;
     if (tu->bin_capacity < 1) return PR_ERR_INVALID;
@@ -82,6 +105,9 @@ PixelConst pixel_const(const pr_view &v) {
     pc.invR = (float)(1.0 / sqrt(ex * ex + ey * ey));
     pc.alpha = v.alpha;
     pc.mode = v.alpha == 1.0f ? 0 : (v.alpha == 2.0f ? 1 : 2);
+    if (v.profile && v.profile->n_c >= 2) pc.mode = 3;
+    pc.lens = v.profile && v.profile->n_l >= 2 ? 1 : 0;
+    pc.prof = nullptr;   // the workspace's copy, set when the views are written
     pc.roll0 = v.roll_dir[0];
     pc.roll1 = v.roll_dir[1];
     pc.cx = v.cx;
@@ -98,6 +124,7 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     int rc = check_args(meshes, nm, views, nv, tu);
     if (rc) return rc;
     L.nv = nv;
+    L.any_prof = false;
     int64_t tiles = 0, tri_blocks = 0, pix_blocks = 0, vtx_blocks = 0, rec4 = 0, tris = 0, gacc = 0;
     for (int v = 0; v < nv; ++v) {
         const pr_view &V = views[v];
@@ -121,6 +148,17 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
         d.tri_off = tris;
         d.vtx_block0 = (int32_t)vtx_blocks;
         d.gacc_off = gacc;
+        L.prof_used[v] = V.profile && (V.profile->n_c >= 2 || V.profile->n_l >= 2);
+        L.any_prof = L.any_prof || L.prof_used[v];
+        if (L.prof_used[v]) {
+            ProfDev &P = L.prof_host[v];
+            memset(&P, 0, sizeof(P));
+            P.nc = V.profile->n_c >= 2 ? V.profile->n_c : 0;
+            P.nl = V.profile->n_l >= 2 ? V.profile->n_l : 0;
+            for (int k = 0; k < P.nc; ++k) P.c[k] = V.profile->p_c[k];
+            for (int k = 0; k < P.nl; ++k) P.l[k] = V.profile->p_l[k];
+        }
+        d.view.profile = nullptr;   // a host pointer: never read on the device
         vtx_blocks += (M.nv + 255) / 256;
         gacc += 6 * (int64_t)M.nv;
         tiles += d.ntiles;
@@ -159,6 +197,7 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     L.pacc = off; off = up(off + ((size_t)pix_blocks + 1) * kPoseAcc * 8);   // per pixel block (backward)
     L.sched = off; off = up(off + sizeof(Sched));
     L.order = off; off = up(off + (size_t)tiles * 16 * kXcds);   // one tile order per XCD share
+    L.prof = off; off = up(off + (size_t)nv * sizeof(ProfDev));
     L.bytes = off;
     return PR_OK;
 }
@@ -202,6 +241,9 @@ void fill_u32(void *p, uint32_t v, int64_t n, hipStream_t s) {
 // camera geometry computed on the device); reset_status: also clear the
 // status block (the frame's first pass).
 void write_views(const Layout &L, ViewTable *T, DevStatus *st, bool reset_status, hipStream_t s) {
+    ProfDev *prof = reinterpret_cast<ProfDev *>(reinterpret_cast<char *>(T) - L.table + L.prof);
+    for (int v = 0; v < L.nv; ++v)
+        if (L.prof_used[v]) hipLaunchKernelGGL(k_write_profile, dim3(1), dim3(64), 0, s, L.prof_host[v], prof + v);
     for (int first = 0; first < L.nv; first += kViewsPerWrite) {
         ViewPack p;
         memset(&p, 0, sizeof(p));
@@ -213,7 +255,10 @@ void write_views(const Layout &L, ViewTable *T, DevStatus *st, bool reset_status
         p.total_pix_blocks = L.total_pix_blocks;
         p.total_vtx_blocks = L.total_vtx_blocks;
         p.reset_status = reset_status ? 1 : 0;
-        for (int i = 0; i < p.count; ++i) p.v[i] = L.vd[first + i];
+        for (int i = 0; i < p.count; ++i) {
+            p.v[i] = L.vd[first + i];
+            p.v[i].pc.prof = L.prof_used[first + i] ? prof + first + i : nullptr;
+        }
         hipLaunchKernelGGL(k_write_views, dim3(1), dim3(64), 0, s, p, T, st);
     }
 }
@@ -333,9 +378,14 @@ int pr_bound(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const 
              size_t ws_bytes, void *stream) {
     PR_PREP();
     write_views(L, T, st, true, s);
-    if (L.total_tri_blocks > 0)
-        hipLaunchKernelGGL(k_bound, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec),
-                           at<TriBound>(ws, L.tb), st, at<int32_t>(ws, L.bcand));
+    if (L.total_tri_blocks > 0) {
+        if (L.any_prof)
+            hipLaunchKernelGGL(k_bound<true>, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec),
+                               at<TriBound>(ws, L.tb), st, at<int32_t>(ws, L.bcand));
+        else
+            hipLaunchKernelGGL(k_bound<false>, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec),
+                               at<TriBound>(ws, L.tb), st, at<int32_t>(ws, L.bcand));
+    }
     return launched();
 }
 
@@ -346,10 +396,10 @@ int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     const int chunk_blocks = (L.total_tri_blocks + 255) / 256;
     // one block more than the tiles and chunks need: the last orders the
     // binning blocks
-    hipLaunchKernelGGL(k_tiles, dim3(std::max(tile_blocks, chunk_blocks) + 1), dim3(256), 0, s, T,
-                       at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<Sched>(ws, L.sched),
-                       at<int32_t>(ws, L.bcand), at<int64_t>(ws, L.boff), at<int64_t>(ws, L.bpart), st,
-                       at<int32_t>(ws, L.bperm));
+    hipLaunchKernelGGL(L.any_prof ? k_tiles<true> : k_tiles<false>, dim3(std::max(tile_blocks, chunk_blocks) + 1),
+                       dim3(256), 0, s, T, at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount),
+                       at<Sched>(ws, L.sched), at<int32_t>(ws, L.bcand), at<int64_t>(ws, L.boff),
+                       at<int64_t>(ws, L.bpart), st, at<int32_t>(ws, L.bperm));
     if (L.total_tri_blocks > 0)
         hipLaunchKernelGGL(k_bin, dim3(L.total_tri_blocks), dim3(kBinThreads), 0, s, T, at<TriBound>(ws, L.tb),
                            at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<int64_t>(ws, L.boff),
@@ -564,8 +614,11 @@ int pr_debug_tile_lists(const pr_mesh *meshes, int nm, const pr_view *views, int
 // ---------------------------------------------------------------------------
 int pr_host_time_interval(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, double *t) {
     if (!mesh || !view || !t || f < 0 || f >= mesh->nt || bound < 0 || bound > PR_BOUND_QUAD) return -1;
+    if (view->profile && !profile_ok(*view->profile)) return -1;
     prg::Geom g;
     prg::make_geom(*view, g);
+    if (view->profile)
+        prg::attach_profile(g, view->profile->p_c, view->profile->n_c, view->profile->p_l, view->profile->n_l);
     double Ps[3][3], Pe[3][3];
     int32_t idx[3];
     if (!prg::load_tri(mesh->v0, mesh->v1, mesh->tri, mesh->nv, f, g, Ps, Pe, idx)) return 0;
@@ -576,8 +629,11 @@ int pr_host_tile_rect(const pr_mesh *mesh, int32_t f, const pr_view *view, int32
                       int32_t *rect) {
     if (!mesh || !view || !rect || f < 0 || f >= mesh->nt || tile < 1 || bound < 0 || bound > PR_BOUND_QUAD)
         return -1;
+    if (view->profile && !profile_ok(*view->profile)) return -1;
     prg::Geom g;
     prg::make_geom(*view, g);
+    if (view->profile)
+        prg::attach_profile(g, view->profile->p_c, view->profile->n_c, view->profile->p_l, view->profile->n_l);
     double Ps[3][3], Pe[3][3], win[2], box[4];
     int32_t idx[3];
     if (!prg::load_tri(mesh->v0, mesh->v1, mesh->tri, mesh->nv, f, g, Ps, Pe, idx)) return 0;
@@ -593,8 +649,11 @@ int pr_host_tile_rect(const pr_mesh *mesh, int32_t f, const pr_view *view, int32
 int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, int32_t tile, int32_t tx,
                       int32_t ty) {
     if (!mesh || !view || f < 0 || f >= mesh->nt || tile < 1 || bound < 0 || bound > PR_BOUND_QUAD) return -1;
+    if (view->profile && !profile_ok(*view->profile)) return -1;
     prg::Geom g;
     prg::make_geom(*view, g);
+    if (view->profile)
+        prg::attach_profile(g, view->profile->p_c, view->profile->n_c, view->profile->p_l, view->profile->n_l);
     double Ps[3][3], Pe[3][3], win[2], box[4];
     int32_t idx[3];
     if (!prg::load_tri(mesh->v0, mesh->v1, mesh->tri, mesh->nv, f, g, Ps, Pe, idx)) return 0;
@@ -650,6 +709,12 @@ int disp_layout(const pr_view *views, int nv, const pr_display *disp, DispLayout
         d.e = (float)(1.0 / (double)V.alpha);
         d.invR = (float)(1.0 / prg::fovea_radius(V.fovea[0], V.fovea[1]));
         d.powmode = V.alpha == 1.0f ? 0 : (V.alpha == 2.0f ? 1 : 2);
+        if (V.profile && !profile_ok(*V.profile)) return PR_ERR_INVALID;
+        if (V.profile && V.profile->n_c >= 2) {   // tabulated p_c (a lens is undone by the optics)
+            d.powmode = 3;
+            d.ntab = V.profile->n_c;
+            for (int k = 0; k < d.ntab; ++k) d.tab[k] = V.profile->p_c[k];
+        }
         if (D.mode == PR_UNFOV_FILTER) d.inv2s2 = (float)(1.0 / (2.0 * (double)D.sigma * D.sigma));
         d.blk0 = (int32_t)blocks;
         blocks += (int64_t)((D.width + 31) / 32) * ((D.height + 7) / 8);
@@ -798,6 +863,7 @@ extern "C" int pr_frame_static(const pr_mesh *meshes, int nm, const pr_view *vie
 struct pr_batch {
     std::vector<pr_mesh> meshes;
     std::vector<pr_view> views;
+    std::vector<pr_profile> profiles;   // the views' profiles, owned (views point here)
     pr_tuning tuning;
     pr_light light;
     std::vector<const float *> albedo;
@@ -954,6 +1020,12 @@ int pr_batch_create(const pr_mesh *meshes, int nm, const pr_view *views, int nv,
     pr_batch *b = new pr_batch();
     b->meshes.assign(meshes, meshes + nm);
     b->views.assign(views, views + nv);
+    b->profiles.resize(nv);
+    for (int v = 0; v < nv; ++v)
+        if (views[v].profile) {
+            b->profiles[v] = *views[v].profile;
+            b->views[v].profile = &b->profiles[v];
+        }
     b->light = *light;
     b->albedo.assign(albedo, albedo + nm);
     b->ids.assign(tri_id, tri_id + nv);

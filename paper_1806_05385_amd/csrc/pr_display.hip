@@ -38,7 +38,7 @@ namespace prd {
 
 constexpr int kMaxLevels = 16;   // 16384 pixels halve to 1 in 15 steps
 constexpr int kTileLevels = 5;   // levels built per 32 x 32 tile
-constexpr int kDispViewsPerWrite = 8;
+constexpr int kDispViewsPerWrite = 4;
 
 // One view as the display kernels see it.
 struct DispView {
@@ -47,12 +47,13 @@ struct DispView {
     int32_t tiles_x, tiles_y;    // 32 x 32 tiles of level 0
     float fov0, fov1, e, invR;   // fovea, 1 / alpha, 1 / R
     float inv2s2, pad;           // filter form: 1 / (2 sigma^2)
-    int32_t powmode;             // 0: alpha == 1, 1: alpha == 2, 2: general
+    int32_t powmode;             // 0: alpha == 1, 1: alpha == 2, 2: general, 3: tabulated p_c
     int32_t blk0;                // first display block (32 x 8 pixels)
     int32_t tile0;               // first 32 x 32 tile (pyramid build)
-    int32_t pad2;
+    int32_t ntab;                // samples of a tabulated p_c (powmode 3)
     int32_t lw[kMaxLevels], lh[kMaxLevels];
     int64_t loff[kMaxLevels];    // float4 offset of level k >= 1 in the pyramid
+    float tab[PR_PROFILE_MAX];   // p_c samples (powmode 3; the lens is undone by the optics)
 };
 
 struct DispTable {
@@ -66,6 +67,7 @@ struct DispPack {
     int32_t first, count, nv, total_blocks, total_tiles, pad[3];
     DispView v[kDispViewsPerWrite];
 };
+static_assert(sizeof(DispPack) <= 4096, "kernel arguments are limited to 4 KiB");
 
 struct DispIO {
     const uint8_t *fov[PR_MAX_VIEWS];
@@ -255,10 +257,46 @@ __device__ __forceinline__ float fov_scale(const DispView &d, float rho, float p
     return powf(q, pw);
 }
 
+// Numeric inverse of the tabulated p_c (the segment bracketing u, found by
+// binary search over the samples, then linear).
+__device__ __forceinline__ float tab_inv(const DispView &d, float u) {
+    const int n = d.ntab;
+    int lo = 0, hi = n - 2;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d.tab[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    const float a = d.tab[lo], b = d.tab[lo + 1];
+    return ((float)lo + (u - a) / (b - a)) / (float)(n - 1);
+}
+
 // Foveated position of display NDC x, and the foveation Jacobian.
 __device__ __forceinline__ void foveate_j(const DispView &d, float x0, float x1, float &y0, float &y1, float JF[4]) {
     const float d0 = x0 - d.fov0, d1 = x1 - d.fov1;
     const float rho2 = d0 * d0 + d1 * d1;
+    if (d.powmode == 3) {
+        // tabulated p_c: y - f = (x - f) p_c(s)/s, s = |x - f|/R; Jacobian
+        // (p_c/s) I + (p_c' - p_c/s) n n^T, n the unit direction
+        const int n = d.ntab;
+        const float rho = __builtin_amdgcn_sqrtf(rho2), sp = rho * d.invR;
+        const float q = sp * (float)(n - 1);
+        const int k = q >= (float)(n - 2) ? n - 2 : (int)q;
+        const float a = d.tab[k], b = d.tab[k + 1], slope = (b - a) * (float)(n - 1);
+        if (rho2 == 0.0f) {
+            y0 = x0; y1 = x1;
+            JF[0] = slope; JF[1] = 0.f; JF[2] = 0.f; JF[3] = slope;
+            return;
+        }
+        const float s = fmaf(q - (float)k, b - a, a) / sp;
+        y0 = fmaf(d0, s, d.fov0);
+        y1 = fmaf(d1, s, d.fov1);
+        const float g = (slope - s) / rho2;
+        JF[0] = fmaf(g, d0 * d0, s);
+        JF[1] = g * d0 * d1;
+        JF[2] = JF[1];
+        JF[3] = fmaf(g, d1 * d1, s);
+        return;
+    }
     if (d.powmode == 0) {
         y0 = x0; y1 = x1;
         JF[0] = 1.f; JF[1] = 0.f; JF[2] = 0.f; JF[3] = 1.f;
@@ -286,7 +324,10 @@ __device__ __forceinline__ void unfoveate_texel(const DispView &d, int i, int j,
     const float y0 = (float)(2 * i + 1) / (float)d.W - 1.0f, y1 = 1.0f - (float)(2 * j + 1) / (float)d.H;
     const float d0 = y0 - d.fov0, d1 = y1 - d.fov1;
     float s = 1.0f;
-    if (d.powmode != 0) {
+    if (d.powmode == 3) {
+        const float rho = __builtin_amdgcn_sqrtf(d0 * d0 + d1 * d1), sf = rho * d.invR;
+        s = rho > 0.0f ? tab_inv(d, sf) / sf : 1.0f;
+    } else if (d.powmode != 0) {
         const float rho = __builtin_amdgcn_sqrtf(d0 * d0 + d1 * d1);
         s = d.powmode == 1 ? rho * d.invR : (rho > 0.0f ? fov_scale(d, rho, 1.0f / d.e - 1.0f) : 0.0f);
     }

@@ -29,10 +29,17 @@ struct Geom {
     double roll[2];
     int W, H;
     bool rolling;
+    // tabulated foveation p_c (nc >= 2; otherwise the power law of alpha)
+    // and lens distortion p_l (nl >= 2; otherwise none): float samples on
+    // normalised distance (pr_profile), attached by attach_profile
+    const float *tc, *tl;
+    int nc, nl;
 };
 
-PRG double dmin(double a, double b) { return a < b ? a : b; }
-PRG double dmax(double a, double b) { return a > b ? a : b; }
+// fmin / fmax (one instruction each on the device; the bound's values are
+// never NaN, and which zero a tie of -0 and +0 returns does not matter)
+PRG double dmin(double a, double b) { return fmin(a, b); }
+PRG double dmax(double a, double b) { return fmax(a, b); }
 PRG double clamp01(double t) { return t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t); }
 
 // Rotation matrix of a rotation vector (Rodrigues' formula).
@@ -123,6 +130,47 @@ PRG void make_geom(const pr_view &v, Geom &g) {
     g.roll[0] = v.roll_dir[0]; g.roll[1] = v.roll_dir[1];
     g.rolling = (v.roll_dir[0] != 0.0f) || (v.roll_dir[1] != 0.0f);
     g.W = v.width; g.H = v.height;
+    g.tc = g.tl = nullptr;
+    g.nc = g.nl = 0;
+}
+
+// The view's tabulated profiles (samples in memory the caller's side can
+// read: host memory for the host hooks, the workspace on the device).
+PRG void attach_profile(Geom &g, const float *tc, int nc, const float *tl, int nl) {
+    g.tc = nc >= 2 ? tc : nullptr;
+    g.nc = nc >= 2 ? nc : 0;
+    g.tl = nl >= 2 ? tl : nullptr;
+    g.nl = nl >= 2 ? nl : 0;
+}
+
+// Tabulated radial profile (Sec. 3.1.1 "Domain": p arbitrary and monotone):
+// samples tab[k] = G(k / (n-1)) of an increasing function of normalised
+// distance, G(0) = 0, linear between samples and continued past the last
+// sample with the last segment's slope.  Segment of s:
+PRG int prof_seg(int n, double s) {
+    const double q = s * (n - 1);
+    return q >= (double)(n - 2) ? n - 2 : (q > 0.0 ? (int)q : 0);
+}
+PRG double prof_eval(const float *tab, int n, double s) {
+    const int k = prof_seg(n, s);
+    const double a = tab[k], b = tab[k + 1];
+    return a + (s * (n - 1) - k) * (b - a);
+}
+PRG double prof_slope(const float *tab, int n, double s) {
+    const int k = prof_seg(n, s);
+    return ((double)tab[k + 1] - (double)tab[k]) * (n - 1);
+}
+// The numeric inverse: the segment whose samples bracket u (binary search
+// over the samples), then its linear inverse (exact: the inverse of the
+// piecewise-linear profile is piecewise linear through the swapped samples).
+PRG double prof_inv(const float *tab, int n, double u) {
+    int lo = 0, hi = n - 2;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((double)tab[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    const double a = tab[lo], b = tab[lo + 1];
+    return (lo + (u - a) / (b - a)) / (n - 1);
 }
 
 // Radial power map about the fovea: |m(x) - f| = R (|x - f| / R)^e.
@@ -164,6 +212,113 @@ PRG void radial_bbox(const Geom &g, double e, double a0, double a1, double b0, d
     x = ((b0 - g.fov[1] <= 0) == grows) ? farthest(g.fov[0], a0, a1) : nearest(g.fov[0], a0, a1);
     radial_map(g, e, x, b0, o0, o1);
     out[2] = o1;
+}
+
+// The maps below take a template flag PROF: false compiles only the power
+// law without a lens (what a view without a pr_profile uses), so kernels can
+// keep that path free of the tabulated paths' registers; true handles both.
+
+// Foveated point -> panel (display) point: display distance R p_c^{-1}(rho/R)
+// with a tabulated p_c, else the power law.
+template <bool PROF = true>
+PRG void unfoveate_pt(const Geom &g, double y0, double y1, double &x0, double &x1) {
+    if (!PROF || g.nc < 2) {
+        radial_map(g, g.alpha, y0, y1, x0, x1);
+        return;
+    }
+    const double d0 = y0 - g.fov[0], d1 = y1 - g.fov[1];
+    const double rho = sqrt(d0 * d0 + d1 * d1);
+    if (rho == 0.0) { x0 = y0; x1 = y1; return; }
+    const double s = rho * g.inv_rad, sc = prof_inv(g.tc, g.nc, s) / s;
+    x0 = g.fov[0] + d0 * sc;
+    x1 = g.fov[1] + d1 * sc;
+}
+
+// Panel point -> undistorted point (Sec. 5.1 "Lens Distortion": p = p_c o p_l
+// about the same centre; the undistorted distance is R p_l^{-1}(d/R)); the
+// identity without a lens.
+template <bool PROF = true>
+PRG void undistort_pt(const Geom &g, double x0, double x1, double &u0, double &u1) {
+    if (!PROF || g.nl < 2) { u0 = x0; u1 = x1; return; }
+    const double d0 = x0 - g.fov[0], d1 = x1 - g.fov[1];
+    const double rho = sqrt(d0 * d0 + d1 * d1);
+    if (rho == 0.0) { u0 = x0; u1 = x1; return; }
+    const double s = rho * g.inv_rad, sc = prof_inv(g.tl, g.nl, s) / s;
+    u0 = g.fov[0] + d0 * sc;
+    u1 = g.fov[1] + d1 * sc;
+}
+
+// Box of the image of box b = [b0,b1] x [b2,b3] under the radial map about
+// the fovea taking normalised distance s to G(s) (the profile tab, or its
+// inverse when inv; G increasing): the image lies in the annular sector of
+// radii R G(s_min), R G(s_max) (s_min, s_max the box's nearest and farthest
+// points) over the angles the box spans as seen from the fovea, and this is
+// the box of that sector (its corners, and its outer arc where it crosses
+// an axis direction).  Conservative for any increasing G; a box holding the
+// fovea gives the disc of the outer radius.
+PRG void sector_box(const Geom &g, const float *tab, int n, bool inv, const double b[4], double out[4]) {
+    const double f0 = g.fov[0], f1 = g.fov[1], R = g.rad;
+    const double nx = (f0 < b[0] ? b[0] : (f0 > b[1] ? b[1] : f0)) - f0;
+    const double ny = (f1 < b[2] ? b[2] : (f1 > b[3] ? b[3] : f1)) - f1;
+    const double fx = dmax(fabs(b[0] - f0), fabs(b[1] - f0)), fy = dmax(fabs(b[2] - f1), fabs(b[3] - f1));
+    const double s0 = sqrt(nx * nx + ny * ny) * g.inv_rad, s1 = sqrt(fx * fx + fy * fy) * g.inv_rad;
+    const double r0 = R * (inv ? prof_inv(tab, n, s0) : prof_eval(tab, n, s0)) * (1.0 - 1e-12);
+    const double r1 = R * (inv ? prof_inv(tab, n, s1) : prof_eval(tab, n, s1)) * (1.0 + 1e-12);
+    if (s0 == 0.0) {
+        out[0] = f0 - r1; out[1] = f0 + r1; out[2] = f1 - r1; out[3] = f1 + r1;
+        return;
+    }
+    // the angles of the corners about the direction of the nearest point
+    // (the box does not hold the fovea, so it spans less than a half turn)
+    const double c = atan2(ny, nx);
+    double lo = 0.0, hi = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        double a = atan2(b[2 + (k >> 1)] - f1, b[k & 1] - f0) - c;
+        if (a > M_PI) a -= 2.0 * M_PI;
+        if (a < -M_PI) a += 2.0 * M_PI;
+        lo = dmin(lo, a);
+        hi = dmax(hi, a);
+    }
+    lo = c + lo - 1e-12;
+    hi = c + hi + 1e-12;
+    double o[4] = {1e300, -1e300, 1e300, -1e300};
+    auto add = [&](double r, double a) {
+        const double x = f0 + r * cos(a), y = f1 + r * sin(a);
+        o[0] = dmin(o[0], x); o[1] = dmax(o[1], x);
+        o[2] = dmin(o[2], y); o[3] = dmax(o[3], y);
+    };
+    add(r0, lo); add(r0, hi); add(r1, lo); add(r1, hi);
+    for (int k = 0; k < 4; ++k) {   // axis directions inside the span: the outer arc's extreme
+        double d = k * 0.5 * M_PI - lo;
+        d -= 2.0 * M_PI * floor(d / (2.0 * M_PI));
+        if (d <= hi - lo) add(r1, k * 0.5 * M_PI);
+    }
+    for (int k = 0; k < 4; ++k) out[k] = o[k];
+}
+
+// Panel box of the foveated box b (the pixels' display points).
+template <bool PROF = true>
+PRG void box_unfoveate(const Geom &g, const double b[4], double out[4]) {
+    if (!PROF || g.nc < 2) radial_bbox(g, g.alpha, b[0], b[1], b[2], b[3], out);
+    else sector_box(g, g.tc, g.nc, true, b, out);
+}
+// Foveated box of the panel box b.
+template <bool PROF = true>
+PRG void box_foveate(const Geom &g, const double b[4], double out[4]) {
+    if (!PROF || g.nc < 2) radial_bbox(g, g.inv_alpha, b[0], b[1], b[2], b[3], out);
+    else sector_box(g, g.tc, g.nc, false, b, out);
+}
+// Panel box of the undistorted box b (the lens applied); b itself without one.
+template <bool PROF = true>
+PRG void box_distort(const Geom &g, const double b[4], double out[4]) {
+    if (!PROF || g.nl < 2) for (int k = 0; k < 4; ++k) out[k] = b[k];
+    else sector_box(g, g.tl, g.nl, false, b, out);
+}
+// Undistorted box of the panel box b (the lens inverted).
+template <bool PROF = true>
+PRG void box_undistort(const Geom &g, const double b[4], double out[4]) {
+    if (!PROF || g.nl < 2) for (int k = 0; k < 4; ++k) out[k] = b[k];
+    else sector_box(g, g.tl, g.nl, true, b, out);
 }
 
 // Camera-space start / end vertices of triangle f.  Returns false if an
@@ -256,6 +411,47 @@ enum { kCulled = 0, kWindow = 1, kClipped = 2 };
 // edges of the two end triangles (any axis separates validly).
 enum { kBoundZenon = 0, kBoundAdaptive = 1, kBoundHull = 2, kBoundQuad = 3 };
 
+// The time window of a triangle seen through a lens (kWindow or kCulled).
+PRG int lens_window(const Geom &g, const double Ps[3][3], const double Pe[3][3], double win[2]) {
+    // Through a lens the scan is no straight line of the projected
+    // (undistorted) image, so the catch-up analysis does not apply.  A
+    // pixel at time t in the window [w0, w1] sees the triangle inside
+    // the hull of its projected vertices at w0 and w1 (linear motion in
+    // front of the eye), whose box's panel image bounds the pixel's
+    // panel point, whose scan time bounds t: so t also lies in that
+    // panel box's scan-time range (clamped to the frame, as pixel times
+    // are).  Starting from the whole frame, the window is narrowed
+    // three times that way.
+    double w0 = 0.0, w1 = 1.0;
+    for (int it = 0; it < 3; ++it) {
+        double ub[4] = {1e300, -1e300, 1e300, -1e300};
+        for (int k = 0; k < 6; ++k) {
+            const double t = k < 3 ? w0 : w1;
+            const double *A = Ps[k % 3], *B = Pe[k % 3];
+            double P[3];
+            for (int r = 0; r < 3; ++r) P[r] = (1.0 - t) * A[r] + t * B[r];
+            const double x = g.fx * P[0] / P[2] + g.cx, y = g.fy * P[1] / P[2] + g.cy;
+            ub[0] = dmin(ub[0], x); ub[1] = dmax(ub[1], x);
+            ub[2] = dmin(ub[2], y); ub[3] = dmax(ub[3], y);
+        }
+        for (int k = 0; k < 4; ++k) ub[k] += ((k & 1) ? 1.0 : -1.0) * kSlackNdc * (1.0 + fabs(ub[k]));
+        double pb[4];
+        box_distort(g, ub, pb);
+        double lo = 1e300, hi = -1e300;
+        for (int c = 0; c < 4; ++c) {
+            const double u = 0.5 * (g.roll[0] * (pb[c & 1] + 1.0) + g.roll[1] * (pb[2 + (c >> 1)] + 1.0));
+            lo = dmin(lo, u);
+            hi = dmax(hi, u);
+        }
+        w0 = dmax(w0, clamp01(lo - kSlackTime));
+        w1 = dmin(w1, clamp01(hi + kSlackTime));
+        if (w0 > w1) return kCulled;
+    }
+    win[0] = w0;
+    win[1] = w1;
+    return kWindow;
+}
+
 // Frame-time window in which the triangle can affect a pixel.
 //  kCulled : never (every space-time vertex behind the near plane, or the
 //            rolling scan never meets the triangle).
@@ -274,6 +470,7 @@ enum { kBoundZenon = 0, kBoundAdaptive = 1, kBoundHull = 2, kBoundQuad = 3 };
 // t = 0 pixels with u <= 0 count, at t = 1 pixels with u >= 1.  Between the
 // roots of the h_k no sign changes, so testing each root and each gap's
 // midpoint gives the window exactly.
+template <bool PROF = true>
 PRG int time_window(const Geom &g, const double Ps[3][3], const double Pe[3][3], double win[2],
                     int mode = kBoundZenon) {
     int n_in = 0, n_pts = g.rolling ? 6 : 3;
@@ -296,6 +493,7 @@ PRG int time_window(const Geom &g, const double Ps[3][3], const double Pe[3][3],
         win[1] = 1.0;
         return kWindow;
     }
+    if (PROF && g.nl >= 2) return lens_window(g, Ps, Pe, win);
     if (mode == kBoundAdaptive) {
         // every covered display point lies in the hull of the six projected
         // vertices, and its (unclamped) scan time is linear in the point:
@@ -432,16 +630,23 @@ PRG bool pixel_range(double lo, double hi, int n, bool flip, int &i0, int &i1) {
     return i0 <= i1;
 }
 
-// Tile rectangle (inclusive tile coordinates) of a display box.  The box is
-// clipped to the display square (every pixel's display point lies in it),
-// mapped to the foveated domain with the exact box rule, and converted to
-// the pixel centres it contains.  Returns false if it covers no pixel centre.
+// Tile rectangle (inclusive tile coordinates) of a display box (of projected
+// points; through a lens first mapped to the panel).  The box is clipped to
+// the display square (every pixel's display point lies in it: the power law
+// and a tabulated p_c with p_c(s) >= s never move a pixel outwards), mapped
+// to the foveated domain (the exact box rule of the power law, the sector
+// box of a table), and converted to the pixel centres it contains.  Returns
+// false if it covers no pixel centre.
+template <bool PROF = true>
 PRG bool tile_rect(const Geom &g, const double box[4], int tile, int rect[4]) {
-    double a0 = dmax(box[0], -1.0), a1 = dmin(box[1], 1.0);
-    double b0 = dmax(box[2], -1.0), b1 = dmin(box[3], 1.0);
+    double pb[4];
+    box_distort<PROF>(g, box, pb);   // through a lens: the box's panel image
+    double a0 = dmax(pb[0], -1.0), a1 = dmin(pb[1], 1.0);
+    double b0 = dmax(pb[2], -1.0), b1 = dmin(pb[3], 1.0);
     if (!(a0 <= a1 && b0 <= b1)) return false;
     double fb[4];
-    radial_bbox(g, g.inv_alpha, a0, a1, b0, b1, fb);
+    const double cb[4] = {a0, a1, b0, b1};
+    box_foveate<PROF>(g, cb, fb);
     for (int k = 0; k < 4; ++k) {
         double m = kSlackNdc * (1.0 + fabs(fb[k]));
         fb[k] += (k & 1) ? m : -m;
@@ -459,14 +664,30 @@ PRG bool tile_rect(const Geom &g, const double box[4], int tile, int rect[4]) {
 }
 
 // Display-space box of the pixel centres of columns [i0, i1] x rows [j0, j1]
-// (clipped to the image; false if that leaves no pixel).
-PRG bool region_display(const Geom &g, int i0, int i1, int j0, int j1, double box[4]) {
+// (clipped to the image; false if that leaves no pixel): box holds their
+// rays' (undistorted) points, pbox (if given) their panel points, which set
+// their times.  Without a lens the two are the same.
+template <bool PROF = true>
+PRG bool region_display(const Geom &g, int i0, int i1, int j0, int j1, double box[4], double *pbox = nullptr) {
     if (i1 > g.W - 1) i1 = g.W - 1;
     if (j1 > g.H - 1) j1 = g.H - 1;
     if (i0 > i1 || j0 > j1) return false;
     double a0 = 2.0 * (i0 + 0.5) / g.W - 1.0, a1 = 2.0 * (i1 + 0.5) / g.W - 1.0;
     double b0 = 1.0 - 2.0 * (j1 + 0.5) / g.H, b1 = 1.0 - 2.0 * (j0 + 0.5) / g.H;
-    radial_bbox(g, g.alpha, a0, a1, b0, b1, box);
+    const double fb[4] = {a0, a1, b0, b1};
+    double pb[4];
+    box_unfoveate<PROF>(g, fb, pb);
+    for (int k = 0; k < 4; ++k) {
+        double m = kSlackNdc * (1.0 + fabs(pb[k]));
+        pb[k] += (k & 1) ? m : -m;
+    }
+    if (pbox)
+        for (int k = 0; k < 4; ++k) pbox[k] = pb[k];
+    if (!PROF || g.nl < 2) {
+        for (int k = 0; k < 4; ++k) box[k] = pb[k];
+        return true;
+    }
+    box_undistort<PROF>(g, pb, box);
     for (int k = 0; k < 4; ++k) {
         double m = kSlackNdc * (1.0 + fabs(box[k]));
         box[k] += (k & 1) ? m : -m;
@@ -474,7 +695,7 @@ PRG bool region_display(const Geom &g, int i0, int i1, int j0, int j1, double bo
     return true;
 }
 
-// Frame-time window of the display points in a box.
+// Frame-time window of the panel points in a box.
 PRG void tile_time(const Geom &g, const double box[4], double tw[2]) {
     if (!g.rolling) { tw[0] = tw[1] = 0.0; return; }
     double umin = 1e300, umax = -1e300;
@@ -489,18 +710,22 @@ PRG void tile_time(const Geom &g, const double box[4], double tw[2]) {
 }
 
 // Display box of a tile's pixel centres and its frame-time window.
+template <bool PROF = true>
 PRG void tile_display(const Geom &g, int tile, int tx, int ty, double box[4], double tw[2]) {
-    region_display(g, tx * tile, tx * tile + tile - 1, ty * tile, ty * tile + tile - 1, box);
-    tile_time(g, box, tw);
+    double pb[4];
+    region_display<PROF>(g, tx * tile, tx * tile + tile - 1, ty * tile, ty * tile + tile - 1, box, pb);
+    tile_time(g, pb, tw);
 }
 
 // Quadrant k = qx + 2 qy of a tile: the (tile/2)^2 pixels at column offset
-// qx * tile/2 and row offset qy * tile/2.  Display box of its pixel centres;
-// false if the quadrant lies outside the image.
-PRG bool quad_display(const Geom &g, int tile, int tx, int ty, int k, double box[4]) {
+// qx * tile/2 and row offset qy * tile/2.  Display box of its pixel centres
+// (and of their panel points in pbox, if given); false if the quadrant lies
+// outside the image.
+template <bool PROF = true>
+PRG bool quad_display(const Geom &g, int tile, int tx, int ty, int k, double box[4], double *pbox = nullptr) {
     const int h = tile / 2;
     const int i0 = tx * tile + (k & 1) * h, j0 = ty * tile + (k >> 1) * h;
-    return region_display(g, i0, i0 + h - 1, j0, j0 + h - 1, box);
+    return region_display<PROF>(g, i0, i0 + h - 1, j0, j0 + h - 1, box, pbox);
 }
 
 // FP32 rounding of a bound towards -inf / +inf (the stored tile boxes).
@@ -632,15 +857,20 @@ PRG int tile_mask(const Geom &g, const double Ps[3][3], const double Pe[3][3], i
     if (!split_quads(tile)) {
         tile_display(g, tile, tx, ty, tb, tw);
     } else {
+        double pb[4] = {1e300, -1e300, 1e300, -1e300};
         tb[0] = tb[2] = 1e300;
         tb[1] = tb[3] = -1e300;
-        for (int k = 0; k < 4; ++k)
-            if (quad_display(g, tile, tx, ty, k, qb[k])) {
+        for (int k = 0; k < 4; ++k) {
+            double qp[4];
+            if (quad_display(g, tile, tx, ty, k, qb[k], qp)) {
                 qvalid |= 1 << k;
                 tb[0] = dmin(tb[0], qb[k][0]); tb[1] = dmax(tb[1], qb[k][1]);
                 tb[2] = dmin(tb[2], qb[k][2]); tb[3] = dmax(tb[3], qb[k][3]);
+                pb[0] = dmin(pb[0], qp[0]); pb[1] = dmax(pb[1], qp[1]);
+                pb[2] = dmin(pb[2], qp[2]); pb[3] = dmax(pb[3], qp[3]);
             }
-        tile_time(g, tb, tw);
+        }
+        tile_time(g, pb, tw);
     }
     float ftb[4] = {f32_down(tb[0]), f32_up(tb[1]), f32_down(tb[2]), f32_up(tb[3])};
     float ftw[2] = {f32_down(tw[0]), f32_up(tw[1])};

@@ -58,6 +58,13 @@ struct TileInfo {
 constexpr int kListTriBits = 28;
 constexpr uint32_t kListTriMask = (1u << kListTriBits) - 1u;
 
+// A view's tabulated profiles in the workspace (pr_profile's samples).
+struct ProfDev {
+    int32_t nc, nl, pad[2];
+    float c[PR_PROFILE_MAX];   // p_c samples (nc >= 2: tabulated foveation)
+    float l[PR_PROFILE_MAX];   // p_l samples (nl >= 2: lens)
+};
+
 // Per-pixel constants of a view (FP32 setup in the ray cast and shading).
 struct PixelConst {
     float invW2, invH2;    // 2/W, 2/H
@@ -66,7 +73,9 @@ struct PixelConst {
     float cx, cy, invfx, invfy;
     float znear;
     int W, H;
-    int mode;              // 0: alpha == 1, 1: alpha == 2, 2: general power
+    int mode;              // 0: alpha == 1, 1: alpha == 2, 2: general power, 3: tabulated p_c
+    int lens;              // a tabulated lens p_l follows the foveation
+    const ProfDev *prof;   // the view's profiles (modes 3 and lens)
 };
 
 // One view as the kernels see it (lives in the workspace's view table).
@@ -116,6 +125,7 @@ struct ViewPack {
     int32_t reset_status;   // the frame's first launch clears the status block (pr_bound, not pr_backward)
     ViewDev v[kViewsPerWrite];
 };
+static_assert(sizeof(ViewPack) <= 4096, "kernel arguments are limited to 4 KiB");
 
 // Status block at the start of the workspace.
 struct DevStatus {

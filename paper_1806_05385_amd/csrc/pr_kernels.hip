@@ -132,6 +132,8 @@ __global__ void k_write_views(ViewPack p, ViewTable *__restrict__ T, DevStatus *
         ViewDev &d = T->v[p.first + i];
         d = v;
         prg::make_geom(v.view, d.g);
+        if (v.pc.prof)   // written by k_write_profile earlier on the stream
+            prg::attach_profile(d.g, v.pc.prof->c, v.pc.prof->nc, v.pc.prof->l, v.pc.prof->nl);
         for (int q = 0; q < 9; ++q) { d.R0f[q] = (float)d.g.R0[q]; d.R1f[q] = (float)d.g.R1[q]; }
         for (int q = 0; q < 3; ++q) { d.T0f[q] = (float)d.g.T0[q]; d.T1f[q] = (float)d.g.T1[q]; }
         T->vtx_block0[p.first + i] = v.vtx_block0;
@@ -150,6 +152,13 @@ __global__ void k_write_views(ViewPack p, ViewTable *__restrict__ T, DevStatus *
         T->tile_base[p.nv] = p.total_tiles;
         T->pix_block0[p.nv] = p.total_pix_blocks;
     }
+}
+
+// One view's tabulated profiles into the workspace (before k_write_views).
+__global__ void k_write_profile(ProfDev p, ProfDev *__restrict__ dst) {
+    const int i = threadIdx.x;
+    if (i == 0) { dst->nc = p.nc; dst->nl = p.nl; dst->pad[0] = dst->pad[1] = 0; }
+    if (i < PR_PROFILE_MAX) { dst->c[i] = p.c[i]; dst->l[i] = p.l[i]; }
 }
 
 // Camera-space light direction at each view's start and end.
@@ -205,6 +214,7 @@ __device__ __forceinline__ void wave_rows(float4 *__restrict__ base, int stride,
 // Triangle f of the view (every lane of the wave calls it; lanes with valid
 // false compute on an in-range triangle and store nothing); f0: the wave's
 // first triangle (wave-uniform; lane j's triangle is f0 + j).
+template <bool PROF>
 __device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, bool valid, int f0, float4 *__restrict__ rec,
                                          TriBound *__restrict__ tb, DevStatus *__restrict__ st, float4 *s_buf) {
     const prg::Geom &g = vd.g;
@@ -221,12 +231,12 @@ __device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, bool valid, i
         if (valid) atomicAdd(&st->nonfinite, 1);
     } else {
         double win[2];
-        int kind = prg::time_window(g, Ps, Pe, win, vd.bound);
+        int kind = prg::time_window<PROF>(g, Ps, Pe, win, vd.bound);
         if (kind != prg::kCulled) {
             double box[4];
             prg::display_box(g, Ps, Pe, win[0], win[1], kind, box);
             int rect[4];
-            if (prg::tile_rect(g, box, vd.tile, rect)) {
+            if (prg::tile_rect<PROF>(g, box, vd.tile, rect)) {
                 for (int k = 0; k < 4; ++k) b.rect[k] = rect[k];
                 b.kind = kind;
                 if (kind == prg::kWindow) { b.w[0] = win[0]; b.w[1] = win[1]; }
@@ -349,6 +359,9 @@ __device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, bool valid, i
 
 // One lane per triangle; the block's candidate total (the binning block of
 // the same 256 triangles) goes to bcand[block].
+// PROF: some view of the call has a tabulated profile or a lens (false: the
+// power-law code alone, with its own register allocation).
+template <bool PROF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_bound(const ViewTable *__restrict__ T, float4 *__restrict__ rec,
                                                TriBound *__restrict__ tb, DevStatus *__restrict__ st,
                                                int32_t *__restrict__ bcand) {
@@ -361,7 +374,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // mesh work on triangle 0 (a block exists only for nt >= 1)
     const bool valid = f < vd.mesh.nt;
     const int fw0 = (blockIdx.x - vd.tri_block0) * 256 + (int)(threadIdx.x & ~63u);
-    const int cnt = bound_tri(vd, valid ? f : 0, valid, fw0, rec, tb, st, s_rows[threadIdx.x >> 6]);
+    const int cnt = bound_tri<PROF>(vd, valid ? f : 0, valid, fw0, rec, tb, st, s_rows[threadIdx.x >> 6]);
     int total;
     block_excl_scan(cnt, s_tmp, total);
     if (threadIdx.x == 0) bcand[blockIdx.x] = total;
@@ -380,6 +393,7 @@ constexpr int kPermItems = 8;
 // kernel also clears the binning counters and scans the binning blocks'
 // candidate totals in chunks of 256; its last block (one more than the
 // tiles and chunks need) writes the binning blocks' dispatch order.
+template <bool PROF>   // as k_bound's
 __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, TileInfo *__restrict__ ti,
                                                uint32_t *__restrict__ tcount, Sched *__restrict__ S, const int32_t *__restrict__ bcand,
                                                int64_t *__restrict__ boff, int64_t *__restrict__ part,
@@ -456,9 +470,14 @@ __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, 
     const int lt = (valid ? gt : 0) - vd.tile_base;
     const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
     const bool split = prg::split_quads(vd.tile);
-    double qb[4] = {1e300, -1e300, 1e300, -1e300};
+    const bool prof = PROF && (vd.pc.mode == 3 || vd.pc.lens);
+    double qb[4] = {1e300, -1e300, 1e300, -1e300}, qp[4] = {1e300, -1e300, 1e300, -1e300};
     bool qok = false;
-    if (valid && split) qok = prg::quad_display(g, vd.tile, tx, ty, q, qb);
+    if (valid && split)
+        qok = prof ? prg::quad_display<true>(g, vd.tile, tx, ty, q, qb, qp)
+                   : prg::quad_display<false>(g, vd.tile, tx, ty, q, qb);
+    // the quadrants' ray (undistorted) boxes, and through a lens their panel
+    // boxes (which set the times)
     double box[4] = {qb[0], qb[1], qb[2], qb[3]};
     if (!qok) { box[0] = box[2] = 1e300; box[1] = box[3] = -1e300; }
 #pragma unroll
@@ -467,6 +486,17 @@ __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, 
         box[1] = prg::dmax(box[1], __shfl_xor(box[1], o, 64));
         box[2] = prg::dmin(box[2], __shfl_xor(box[2], o, 64));
         box[3] = prg::dmax(box[3], __shfl_xor(box[3], o, 64));
+    }
+    double pbox[4] = {box[0], box[1], box[2], box[3]};
+    if (PROF && vd.pc.lens) {
+        for (int k = 0; k < 4; ++k) pbox[k] = qok ? qp[k] : ((k & 1) ? -1e300 : 1e300);
+#pragma unroll
+        for (int o = 1; o < 4; o <<= 1) {
+            pbox[0] = prg::dmin(pbox[0], __shfl_xor(pbox[0], o, 64));
+            pbox[1] = prg::dmax(pbox[1], __shfl_xor(pbox[1], o, 64));
+            pbox[2] = prg::dmin(pbox[2], __shfl_xor(pbox[2], o, 64));
+            pbox[3] = prg::dmax(pbox[3], __shfl_xor(pbox[3], o, 64));
+        }
     }
     const unsigned long long okb = __ballot(qok);
     if (!valid) return;
@@ -480,10 +510,11 @@ __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, 
     if (q != 0) return;
     double tw[2];
     if (split) {
-        prg::tile_time(g, box, tw);
+        prg::tile_time(g, pbox, tw);
         t.qvalid = (int32_t)((okb >> (__lane_id() & ~3)) & 0xFull);
     } else {
-        prg::tile_display(g, vd.tile, tx, ty, box, tw);
+        if (prof) prg::tile_display<true>(g, vd.tile, tx, ty, box, tw);
+        else prg::tile_display<false>(g, vd.tile, tx, ty, box, tw);
         t.qvalid = 0;
         for (int k = 0; k < 4; ++k)
             for (int r = 0; r < 4; ++r) t.qb[k][r] = 0.0f;
@@ -911,20 +942,43 @@ __global__ __launch_bounds__(256) void k_scatter(const ViewTable *__restrict__ T
 // ---------------------------------------------------------------------------
 // ray cast
 // ---------------------------------------------------------------------------
-// Per-pixel setup: foveated sample -> display point (unfoveate) -> time ->
-// ray direction (rx, ry, 1).
+// Numeric inverse of a tabulated profile (samples tab[k] = G(k/(n-1)),
+// increasing): binary search for the segment bracketing u, then linear.
+__device__ __forceinline__ float prof_inv_f(const float *__restrict__ tab, int n, float u) {
+    int lo = 0, hi = n - 2;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    const float a = tab[lo], b = tab[lo + 1];
+    return ((float)lo + (u - a) / (b - a)) / (float)(n - 1);
+}
+
+// Per-pixel setup: foveated sample -> panel (display) point (unfoveate) ->
+// time; panel point -> undistorted point (a lens) -> ray direction (rx, ry, 1).
 __device__ __forceinline__ void pixel_setup(const PixelConst &pc, int px, int py, float &t, float &rx, float &ry) {
     float y0 = (float)(2 * px + 1) * (0.5f * pc.invW2) - 1.0f;
     float y1 = 1.0f - (float)(2 * py + 1) * (0.5f * pc.invH2);
     float d0 = y0 - pc.fov0, d1 = y1 - pc.fov1;
-    float s = 1.0f;
-    if (pc.mode != 0) {
-        float rho = __builtin_amdgcn_sqrtf(d0 * d0 + d1 * d1);   // hardware square root (1 ulp)
+    float s = 1.0f, rho = 0.0f;
+    if (pc.mode != 0 || pc.lens) rho = __builtin_amdgcn_sqrtf(d0 * d0 + d1 * d1);   // hardware square root (1 ulp)
+    if (pc.mode == 1 || pc.mode == 2) {
         s = pc.mode == 1 ? rho * pc.invR : (rho > 0.0f ? powf(rho * pc.invR, pc.alpha - 1.0f) : 0.0f);
+    } else if (pc.mode == 3) {
+        const float sf = rho * pc.invR;
+        s = rho > 0.0f ? prof_inv_f(pc.prof->c, pc.prof->nc, sf) / sf : 1.0f;
     }
     float x0 = pc.fov0 + d0 * s, x1 = pc.fov1 + d1 * s;
     float u = 0.5f * (pc.roll0 * (x0 + 1.0f) + pc.roll1 * (x1 + 1.0f));
     t = fminf(fmaxf(u, 0.0f), 1.0f);
+    if (pc.lens) {
+        // the undistorted point: the panel offset (d s) scaled by
+        // p_l^{-1}(s_p) / s_p, s_p the panel point's normalised distance
+        const float sp = rho * s * pc.invR;
+        const float k = sp > 0.0f ? prof_inv_f(pc.prof->l, pc.prof->nl, sp) / sp : 1.0f;
+        x0 = pc.fov0 + d0 * (s * k);
+        x1 = pc.fov1 + d1 * (s * k);
+    }
     rx = (x0 - pc.cx) * pc.invfx;
     ry = (x1 - pc.cy) * pc.invfy;
 }
@@ -1427,16 +1481,31 @@ __global__ __launch_bounds__(256) void k_shade(const ViewTable *__restrict__ T, 
 // ---------------------------------------------------------------------------
 // Pixel density of the foveation at pixel (px, py): the linear scale of the
 // foveate map at the pixel's display point (square root of its Jacobian
-// determinant).  With display distance d = R (rho/R)^alpha of foveated
-// distance rho, the map's radial and tangential scales are
-// (1/alpha)(rho/R)^(1-alpha) and (rho/R)^(1-alpha), so the density is
-// alpha^(-1/2) (rho/R)^(1-alpha): 1 without foveation, +inf at the fovea.
+// determinant; a lens is undone optically and does not enter).  With
+// display distance d = R (rho/R)^alpha of foveated distance rho, the map's
+// radial and tangential scales are (1/alpha)(rho/R)^(1-alpha) and
+// (rho/R)^(1-alpha), so the density is alpha^(-1/2) (rho/R)^(1-alpha): 1
+// without foveation, +inf at the fovea.  A tabulated p_c: the square root
+// of p_c'(s_p) times p_c(s_p) / s_p (the first segment's slope at the
+// fovea).
 __device__ __forceinline__ float pixel_density(const PixelConst &pc, int px, int py) {
     if (pc.mode == 0) return 1.0f;
     const float y0 = (float)(2 * px + 1) * (0.5f * pc.invW2) - 1.0f;
     const float y1 = 1.0f - (float)(2 * py + 1) * (0.5f * pc.invH2);
     const float d0 = y0 - pc.fov0, d1 = y1 - pc.fov1;
     const float rho = sqrtf(d0 * d0 + d1 * d1);
+    if (pc.mode == 3) {
+        // tabulated p_c at the panel distance s_p = p_c^{-1}(s_f): radial
+        // scale p_c'(s_p) (the slope of its segment), tangential s_f / s_p
+        const float *c = pc.prof->c;
+        const int n = pc.prof->nc;
+        const float sf = rho * pc.invR;
+        const float sp = sf > 0.0f ? prof_inv_f(c, n, sf) : 0.0f;
+        const float q = sp * (float)(n - 1);
+        const int k = q >= (float)(n - 2) ? n - 2 : (int)q;
+        const float slope = (c[k + 1] - c[k]) * (float)(n - 1);
+        return sf > 0.0f ? sqrtf(slope * (sf / sp)) : slope;
+    }
     if (!(rho > 0.0f)) return INFINITY;
     return rsqrtf(pc.alpha) * powf(rho * pc.invR, 1.0f - pc.alpha);
 }
@@ -1502,15 +1571,17 @@ __device__ __forceinline__ void cross3d(const double a[3], const double b[3], do
 }
 
 // FP64 pixel setup (the backward is per pixel, not per test, so it can
-// afford it): foveated sample -> display point -> time -> ray.
+// afford it): foveated sample -> panel point -> time; panel point ->
+// undistorted point -> ray.
 __device__ __forceinline__ void pixel_setup_d(const prg::Geom &g, int px, int py, double &t, double r[3]) {
     double y0 = (2.0 * px + 1.0) / g.W - 1.0, y1 = 1.0 - (2.0 * py + 1.0) / g.H;
-    double x0, x1;
-    prg::radial_map(g, g.alpha, y0, y1, x0, x1);
+    double x0, x1, u0, u1;
+    prg::unfoveate_pt(g, y0, y1, x0, x1);
     double u = 0.5 * (g.roll[0] * (x0 + 1.0) + g.roll[1] * (x1 + 1.0));
     t = prg::clamp01(u);
-    r[0] = (x0 - g.cx) / g.fx;
-    r[1] = (x1 - g.cy) / g.fy;
+    prg::undistort_pt(g, x0, x1, u0, u1);
+    r[0] = (u0 - g.cx) / g.fx;
+    r[1] = (u1 - g.cy) / g.fy;
     r[2] = 1.0;
 }
 

@@ -76,7 +76,7 @@ class Renderer:
     def _prepare(self):
         nm = len(self.meshes)
         self.c_meshes = (B.PrMesh * nm)(*[m.pr() for m in self.meshes])
-        self.c_views = (B.PrView * len(self.views))(*[B.make_view(v) for v in self.views])
+        self.c_views = B.make_views(self.views)
         self.tuning = B.PrTuning(self.tile, self.cap, self.flags, self.bound_mode)
         size = ctypes.c_size_t(0)
         B.check('pr_workspace_size', self.L.pr_workspace_size(self.c_meshes, nm, self.c_views, len(self.views),
@@ -240,7 +240,7 @@ class Batch:
             self.outputs.append(o)
         nm = len(self.meshes)
         self.c_meshes = (B.PrMesh * nm)(*[m.pr() for m in self.meshes])
-        self.c_views = (B.PrView * len(self.views))(*[B.make_view(v) for v in self.views])
+        self.c_views = B.make_views(self.views)
         self.light = B.make_light(light if light is not None else (0.0, 0.0, -1.0), ambient)
         tu = B.PrTuning(tile, bin_capacity, 0, 0)
         self.ptr = ctypes.c_void_p(0)
@@ -298,7 +298,7 @@ class Display:
         self.views = [copy.copy(v) for v in views]
         n = len(self.views)
         sizes = sizes or [(v.width, v.height) for v in self.views]
-        self.c_views = (B.PrView * n)(*[B.make_view(v, 0) for v in self.views])
+        self.c_views = B.make_views(self.views, 0)
         self.c_disp = (B.PrDisplay * n)(*[B.PrDisplay(int(w), int(h), int(mode), float(sigma)) for w, h in sizes])
         size = ctypes.c_size_t(0)
         B.check('pr_unfoveate_workspace_size', self.L.pr_unfoveate_workspace_size(self.c_views, n, self.c_disp,

@@ -43,7 +43,7 @@ def _frame(tile=16, cap=1000, **view_kw):
     v = sc.views[0]
     for k, val in view_kw.items():
         setattr(v, k, val)
-    views = (B.PrView * 1)(B.make_view(v))
+    views = B.make_views([v])
     tu = B.PrTuning(tile, cap, 0, 0)
     return meshes, views, tu, sc
 
@@ -74,6 +74,33 @@ def test_workspace_size_and_argument_checks():
     assert L.pr_workspace_size(meshes, 1, views, 65, ctypes.byref(tu), ctypes.byref(size)) == B.PR_ERR_INVALID
     nullmesh = (B.PrMesh * 1)(B.PrMesh(None, None, None, 5, 5))
     assert L.pr_workspace_size(nullmesh, 1, views, 1, ctypes.byref(tu), ctypes.byref(size)) == B.PR_ERR_INVALID
+
+
+def test_profile_checks():
+    """A tabulated p_c / p_l needs 2..64 finite samples from 0, strictly
+    increasing, and p_c(s_k) >= s_k."""
+    L = B.lib()
+    size = ctypes.c_size_t(0)
+    good_c, good_l = scenegen.foveal_table(9, 2.0), scenegen.barrel_table(9, 0.2)
+    for kw in (dict(profile_c=good_c), dict(profile_l=good_l), dict(profile_c=good_c, profile_l=good_l)):
+        m, v, t, _ = _frame(**kw)
+        assert L.pr_workspace_size(m, 1, v, 1, ctypes.byref(t), ctypes.byref(size)) == B.PR_OK, kw
+    bad = [
+        dict(profile_c=np.array([0.0], np.float32)),                      # one sample
+        dict(profile_c=np.array([0.1, 0.5, 1.0], np.float32)),             # not from 0
+        dict(profile_c=np.array([0.0, 0.6, 0.6, 1.0], np.float32)),        # not strictly increasing
+        dict(profile_c=np.array([0.0, 0.2, 1.0], np.float32)),             # p_c(1/2) < 1/2
+        dict(profile_c=np.array([0.0, float('nan'), 1.0], np.float32)),
+        dict(profile_l=np.array([0.0, -0.5], np.float32)),
+        dict(profile_l=np.array([0.0, float('inf')], np.float32)),
+    ]
+    for kw in bad:
+        m, v, t, _ = _frame(**kw)
+        assert L.pr_workspace_size(m, 1, v, 1, ctypes.byref(t), ctypes.byref(size)) == B.PR_ERR_INVALID, kw
+    m, v, t, _ = _frame(profile_c=good_c)
+    for n in (1, 65, -1):   # sample counts out of range (the binding refuses to build them)
+        v[0].profile.contents.n_c = n
+        assert L.pr_workspace_size(m, 1, v, 1, ctypes.byref(t), ctypes.byref(size)) == B.PR_ERR_INVALID, n
 
 
 def test_triangle_count_limit():

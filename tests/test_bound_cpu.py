@@ -78,6 +78,22 @@ def test_moving_rolling_foveated(alpha, roll, fovea):
     assert not missed, missed[:5]
 
 
+@pytest.mark.parametrize('bound', [0, 1, 3])
+@pytest.mark.parametrize('prof', ['table', 'lens', 'table_lens', 'table_lens_vertical', 'table_lens_tile8'])
+def test_tabulated_foveation_and_lens(prof, bound):
+    """Tabulated p_c (sector boxes), a barrel lens (panel-space times, the
+    lens window) and both, under the rolling bounds."""
+    pc = scenegen.foveal_table(33, 3.0) if 'table' in prof else None
+    pl = scenegen.barrel_table(33, 0.22) if 'lens' in prof else None
+    roll = (0.0, 0.9) if 'vertical' in prof else (1.0, 0.0)
+    sc = scenegen.make_moving_soup(seed=23, n_tris=300, width=80, height=72, alpha=2.0, roll=roll,
+                                   yaw_deg_s=3000.0, obj_speed=40.0, fovea=(0.12, -0.08), side=(0.05, 0.6),
+                                   profile_c=pc, profile_l=pl)
+    n, missed, _ = _check_hits(sc, 8 if 'tile8' in prof else 16, bound=bound)
+    assert n > 1000
+    assert not missed, missed[:5]
+
+
 def _quad_mesh(pts0, pts1=None):
     v0 = np.asarray(pts0, np.float32)
     v1 = v0.copy() if pts1 is None else np.asarray(pts1, np.float32)
@@ -110,14 +126,17 @@ def test_adversarial_triangles(case):
                                [[-0.5, -0.3, 2.0], [0.5, 0.3, 2.0], [0.3, -0.6, 2.0]]),
     }[case]
     mesh = _quad_mesh(*T)
+    profiles = [(None, None), (scenegen.foveal_table(17, 2.0), scenegen.barrel_table(17, 0.2))]
     for roll in [(1.0, 0.0), (0.0, 0.0)]:
         for pose in [np.zeros(6, np.float32), np.array([0.0, -0.3, 0.0, 0.01, 0.0, 0.0], np.float32)]:
-            view = scenegen.View(64, 64, np.zeros(6, np.float32), pose, fovea=(0.1, 0.05), alpha=2.0, roll_dir=roll)
-            sc = scenegen.Scene('adv', [mesh], [view])
-            n, missed, _ = _check_hits(sc, 8)
-            assert not missed, (case, roll, missed[:3])
-            if case == 'zero_area_at_start' and roll == (1.0, 0.0):
-                assert n > 20   # covered in the frame's later columns
+            for pc, pl in profiles:
+                view = scenegen.View(64, 64, np.zeros(6, np.float32), pose, fovea=(0.1, 0.05), alpha=2.0,
+                                     roll_dir=roll, profile_c=pc, profile_l=pl)
+                sc = scenegen.Scene('adv', [mesh], [view])
+                n, missed, _ = _check_hits(sc, 8)
+                assert not missed, (case, roll, pc is not None, missed[:3])
+                if case == 'zero_area_at_start' and roll == (1.0, 0.0):
+                    assert n > 20   # covered in the frame's later columns
 
 
 def test_bound_is_tight_enough_to_reject_pairs():
