@@ -1162,6 +1162,32 @@ struct ShadeArgs {
     int v;
 };
 
+// Cross-row register swaps of gfx950 (rows of 16 lanes): permlane32 swaps
+// the upper half of a with the lower half of b, permlane16 the odd rows of
+// a with the even rows of b.
+__device__ __forceinline__ void swap_rows32(uint32_t &a, uint32_t &b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+}
+__device__ __forceinline__ void swap_rows16(uint32_t &a, uint32_t &b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+}
+// Row broadcast: out[r] holds, in every row, row r of x.
+__device__ __forceinline__ void rows_broadcast(float x, float out[4]) {
+    uint32_t a = __float_as_uint(x), b = a;
+    swap_rows32(a, b);            // a = rows (0, 1, 0, 1), b = rows (2, 3, 2, 3)
+    uint32_t a2 = a, b2 = b;
+    swap_rows16(a, a2);           // a = row 0 everywhere, a2 = row 1
+    swap_rows16(b, b2);           // b = row 2, b2 = row 3
+    out[0] = __uint_as_float(a);
+    out[1] = __uint_as_float(a2);
+    out[2] = __uint_as_float(b);
+    out[3] = __uint_as_float(b2);
+}
+
 template <bool ROLL, bool COUNT, bool SHADE>
 __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0, int q, const float *__restrict__ vrec,
                                              int beg, int end, const uint32_t *__restrict__ lists, uint32_t ent0,
@@ -1178,10 +1204,14 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
     float t, rx, ry;   // lane l's own pixel l (shaded by lane l at the end)
     {
         pixel_setup(pc, cx0 + (lane & 7), cy0 + (lane >> 3), t, rx, ry);
+        // pixel 16 b + jl's values are row b's: broadcast each row to all
+        float tr[4], rxr[4], ryr[4];
+        rows_broadcast(t, tr);
+        rows_broadcast(rx, rxr);
+        rows_broadcast(ry, ryr);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int src = 16 * b + jl;
-            const float tj = __shfl(t, src, 64), rxj = __shfl(rx, src, 64), ryj = __shfl(ry, src, 64);
+            const float tj = tr[b], rxj = rxr[b], ryj = ryr[b];
             if (ROLL) {
                 // terms (rx, ry, t rx, t ry) and (t, t^2 rx, t^2 ry, t^2)
                 const float u = kq == 0 ? rxj : kq == 1 ? ryj : kq == 2 ? tj * rxj : tj * ryj;
@@ -1302,16 +1332,28 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
             nbuf = left;
         }
     }
-    // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the same pixel for different
-    // triangles of each group: take the minimum, then lane l writes pixel l
+    // Lanes l, l ^ 16, l ^ 32, l ^ 48 (the four rows) hold pixel 16 b + jl
+    // for different triangles of each group: best[b] in row kq is entry
+    // (b, kq) of a 4 x 4 table per jl.  Transposing it across the registers
+    // and the rows (permlane32 swaps of blocks (0, 2) and (1, 3), then
+    // permlane16 swaps of (0, 1) and (2, 3)) leaves in row r the four
+    // candidates of block r, i.e. of the lane's own pixel 16 r + jl = l.
+    uint32_t klo[4], khi[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        unsigned long long o = __shfl_xor(best[b], 16, 64);
-        best[b] = o < best[b] ? o : best[b];
-        o = __shfl_xor(best[b], 32, 64);
-        best[b] = o < best[b] ? o : best[b];
+        klo[b] = (uint32_t)best[b];
+        khi[b] = (uint32_t)(best[b] >> 32);
     }
-    const unsigned long long mine = kq == 0 ? best[0] : kq == 1 ? best[1] : kq == 2 ? best[2] : best[3];
+    swap_rows32(klo[0], klo[2]); swap_rows32(khi[0], khi[2]);
+    swap_rows32(klo[1], klo[3]); swap_rows32(khi[1], khi[3]);
+    swap_rows16(klo[0], klo[1]); swap_rows16(khi[0], khi[1]);
+    swap_rows16(klo[2], klo[3]); swap_rows16(khi[2], khi[3]);
+    unsigned long long mine = ((unsigned long long)khi[0] << 32) | klo[0];
+#pragma unroll
+    for (int b = 1; b < 4; ++b) {
+        const unsigned long long o = ((unsigned long long)khi[b] << 32) | klo[b];
+        mine = o < mine ? o : mine;
+    }
     const int px = cx0 + (lane & 7), py = cy0 + (lane >> 3);
     if (px < pc.W && py < pc.H) {
         const int64_t p = (int64_t)py * pc.W + px;
