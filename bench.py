@@ -242,11 +242,58 @@ def shading_leg(sc, args, stream, n):
     return out
 
 
+def profile_leg(sc, args, stream, n):
+    """The HMD frame with a tabulated foveation (64 samples of the alpha = 2
+    power law's p_c(s) = sqrt(s)) and with that table composed with a barrel
+    lens pre-distortion (33 samples of s (1 - 0.2 s^2)): frame ms, listed
+    pairs and ray-triangle tests, against the analytic power law."""
+    import copy as _copy
+
+    import numpy as np
+    import scenegen
+    import torch
+
+    from paper_1806_05385_amd import binding as B
+    from paper_1806_05385_amd.render import Renderer
+    out = {}
+    table = np.sqrt(np.linspace(0.0, 1.0, 64)).astype(np.float32)
+    for name, pc, pl in (('power_law', None, None), ('table', table, None),
+                         ('table_lens', table, scenegen.barrel_table(33, 0.2))):
+        views = []
+        for v in sc.views:
+            vv = _copy.copy(v)
+            vv.profile_c, vv.profile_l = pc, pl
+            views.append(vv)
+        rr = Renderer(sc.meshes, views, tile=args.tile, light=sc.light_dir, ambient=sc.ambient)
+        rr.frame(check=True, rgb32=False)
+        rr.flags = B.PR_FLAG_COUNT | B.PR_FLAG_PERSISTENT
+        rr._prepare()
+        rr.frame(check=True, rgb32=False)
+        st = rr.status()
+        rr.flags = B.PR_FLAG_PERSISTENT
+        rr._prepare()
+        for _ in range(3):
+            rr.frame(check=False, rgb32=False)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(n):
+            rr.bound()
+            rr.bin()
+            rr.raycast_shade(rgba8=True, rgb32=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = {'frame_ms': round(e0.elapsed_time(e1) / n, 4), 'pairs': int(st.pairs_total),
+                     'tests': int(st.tests)}
+        del rr
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
     ap.add_argument('--steps', type=int, default=50)
-    ap.add_argument('--warmup', type=int, default=5)
+    ap.add_argument('--warmup', type=int, default=100)
     ap.add_argument('--tile', type=int, default=16)
     ap.add_argument('--no-persistent', dest='persistent', action='store_false',
                     help='one block per tile item instead of the longest-first persistent ray cast')
@@ -339,10 +386,11 @@ def main():
     if args.only == 'hmd':
         args.no_cpu_baseline = True
     fwd_med = bwd_med = float('nan')
-    batch_out = large_out = seq_eyes_ms = display_out = ablation_out = shading_out = None
+    batch_out = large_out = seq_eyes_ms = display_out = ablation_out = shading_out = profile_out = None
     if args.only == 'all':
         seq_eyes_ms = sequential_eyes(sc, args, stream, 50)
         shading_out = shading_leg(sc, args, stream, 50)
+        profile_out = profile_leg(sc, args, stream, 20)
         display_out = display_leg(sc, r, stream, 50)
         ablation_out = bound_ablation(sc, args, stream, 20)
         fwd_med, bwd_med = grad_leg(args, stream)
@@ -483,6 +531,7 @@ def main():
         'display': display_out,
         'bound_ablation': ablation_out,
         'shading': shading_out,
+        'profiles': profile_out,
         'raycast_shade_ms': round(ray_ms_avg, 4),
         'tests_per_frame': tests,
         'tests_per_s': round(tests / (ray_ms_avg * 1e-3), 1),
