@@ -159,6 +159,10 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
             for (int k = 0; k < P.nl; ++k) P.l[k] = V.profile->p_l[k];
         }
         d.view.profile = nullptr;   // a host pointer: never read on the device
+        // FP64 camera geometry (host; the same code the host test hooks use)
+        prg::make_geom(V, d.g);
+        for (int q = 0; q < 9; ++q) { d.R0f[q] = (float)d.g.R0[q]; d.R1f[q] = (float)d.g.R1[q]; }
+        for (int q = 0; q < 3; ++q) { d.T0f[q] = (float)d.g.T0[q]; d.T1f[q] = (float)d.g.T1[q]; }
         vtx_blocks += (M.nv + 255) / 256;
         gacc += 6 * (int64_t)M.nv;
         tiles += d.ntiles;
@@ -190,7 +194,7 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     L.bpart = off; off = up(off + ((size_t)tri_blocks / 256 + 1) * 8);
     L.tcount = off; off = up(off + ((size_t)tiles + 1) * 4);
     L.toff = off; off = up(off + ((size_t)tiles + 1) * 4);
-    L.part = off; off = up(off + (size_t)L.nparts * 4);
+    L.part = off; off = up(off + (size_t)L.nparts * 8);   // the tile scan's block flags
     L.pairs = off; off = up(off + (size_t)L.cap * 12);   // Pairs: tile, slot, entry arrays
     L.lists = off; off = up(off + (size_t)L.cap * 4);
     L.gacc = off; off = up(off + (size_t)gacc * 4);
@@ -238,7 +242,7 @@ void fill_u32(void *p, uint32_t v, int64_t n, hipStream_t s) {
     ViewTable *T = at<ViewTable>(ws, L.table);
 
 // The workspace's view table from the call's own meshes and views (FP64
-// camera geometry computed on the device); reset_status: also clear the
+// camera geometry computed on the host); reset_status: also clear the
 // status block (the frame's first pass).
 void write_views(const Layout &L, ViewTable *T, DevStatus *st, bool reset_status, hipStream_t s) {
     ProfDev *prof = reinterpret_cast<ProfDev *>(reinterpret_cast<char *>(T) - L.table + L.prof);
@@ -256,8 +260,15 @@ void write_views(const Layout &L, ViewTable *T, DevStatus *st, bool reset_status
         p.total_vtx_blocks = L.total_vtx_blocks;
         p.reset_status = reset_status ? 1 : 0;
         for (int i = 0; i < p.count; ++i) {
-            p.v[i] = L.vd[first + i];
-            p.v[i].pc.prof = L.prof_used[first + i] ? prof + first + i : nullptr;
+            ViewDev &d = p.v[i];
+            d = L.vd[first + i];
+            d.pc.prof = L.prof_used[first + i] ? prof + first + i : nullptr;
+            if (d.pc.prof) {
+                // the workspace's copy (k_write_profile, earlier on the stream):
+                // device addresses, counts from the host copy
+                const ProfDev &H = L.prof_host[first + i];
+                prg::attach_profile(d.g, d.pc.prof->c, H.nc, d.pc.prof->l, H.nl);
+            }
         }
         hipLaunchKernelGGL(k_write_views, dim3(1), dim3(64), 0, s, p, T, st);
     }
@@ -399,16 +410,15 @@ int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     hipLaunchKernelGGL(L.any_prof ? k_tiles<true> : k_tiles<false>, dim3(std::max(tile_blocks, chunk_blocks) + 1),
                        dim3(256), 0, s, T, at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount),
                        at<Sched>(ws, L.sched), at<int32_t>(ws, L.bcand), at<int64_t>(ws, L.boff),
-                       at<int64_t>(ws, L.bpart), st, at<int32_t>(ws, L.bperm));
+                       at<int64_t>(ws, L.bpart), st, at<int32_t>(ws, L.bperm),
+                       at<unsigned long long>(ws, L.part), L.nparts);
     if (L.total_tri_blocks > 0)
         hipLaunchKernelGGL(k_bin, dim3(L.total_tri_blocks), dim3(kBinThreads), 0, s, T, at<TriBound>(ws, L.tb),
                            at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<int64_t>(ws, L.boff),
                            at<int64_t>(ws, L.bpart), pairs_at(L, ws), L.cap, at<int32_t>(ws, L.bperm), st);
     int n = L.total_tiles + 1;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(L.nparts), dim3(256), 0, s, at<uint32_t>(ws, L.tcount), n,
-                       at<uint32_t>(ws, L.part));
-    hipLaunchKernelGGL(k_scan_apply, dim3(L.nparts), dim3(256), 0, s, T, at<uint32_t>(ws, L.tcount), n,
-                       L.total_tiles, at<uint32_t>(ws, L.part), at<uint32_t>(ws, L.toff), at<Sched>(ws, L.sched));
+    hipLaunchKernelGGL(k_scan, dim3(L.nparts), dim3(256), 0, s, T, at<uint32_t>(ws, L.tcount), n, L.total_tiles,
+                       at<unsigned long long>(ws, L.part), at<uint32_t>(ws, L.toff), at<Sched>(ws, L.sched));
     // pairs (grid-stride) and the persistent ray cast's tile order (one
     // block per 256 tiles)
     int sb = (int)std::min<int64_t>(std::max<int64_t>((L.cap + 255) / 256, 1), 2048);

@@ -728,14 +728,20 @@ PRG bool quad_display(const Geom &g, int tile, int tx, int ty, int k, double box
     return region_display<PROF>(g, i0, i0 + h - 1, j0, j0 + h - 1, box, pbox);
 }
 
-// FP32 rounding of a bound towards -inf / +inf (the stored tile boxes).
+// FP32 bounds of x rounded outwards (the stored tile boxes and test
+// records): x's nearest float moved out by 2^-22 of its magnitude and by
+// 1e-30.  The conversion is off by at most 2^-24 of the magnitude and the
+// move's own rounding by as much again, so the bound is on the right side of
+// x with a margin (the 1e-30 covers floats near zero).  Magnitudes beyond
+// 3e38 are taken as 3e38 (the callers clamp their bounds to 1e30 or hold
+// values far smaller).
 PRG float f32_down(double x) {
-    float f = (float)x;
-    return (double)f > x ? nextafterf(f, -INFINITY) : f;
+    const float f = (float)dmin(dmax(x, -3e38), 3e38);
+    return fmaf(-fabsf(f), 2.384185791015625e-7f, f) - 1e-30f;
 }
 PRG float f32_up(double x) {
-    float f = (float)x;
-    return (double)f < x ? nextafterf(f, INFINITY) : f;
+    const float f = (float)dmin(dmax(x, -3e38), 3e38);
+    return fmaf(fabsf(f), 2.384185791015625e-7f, f) + 1e-30f;
 }
 // The triangle's image over its whole time window as the per-tile test
 // sees it, built once per triangle: the projected window-end vertices'
@@ -751,7 +757,7 @@ struct SatRec {
     float ax[6][4];    // axis n0, n1 and the interval lo, hi
 };
 
-PRG float f32_clamp(float x) { return x < -1e30f ? -1e30f : (x > 1e30f ? 1e30f : x); }
+PRG float f32_clamp(float x) { return fminf(fmaxf(x, -1e30f), 1e30f); }
 
 PRG void sat_build(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double w[4],
                    SatRec &R, int mode = kBoundZenon) {

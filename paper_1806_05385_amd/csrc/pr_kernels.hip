@@ -121,21 +121,22 @@ __device__ __forceinline__ int find_view(const int32_t *base, int nv, int key) {
     return lo;
 }
 
+// The views arrive complete (geometry included, computed on the host): the
+// block copies them word by word into the view table.
 __global__ void k_write_views(ViewPack p, ViewTable *__restrict__ T, DevStatus *__restrict__ st) {
     int i = threadIdx.x;
     if (p.first == 0 && p.reset_status) {   // the frame's first launch resets the status block
         uint32_t *w = reinterpret_cast<uint32_t *>(st);
         for (int k = i; k < (int)(sizeof(DevStatus) / 4); k += blockDim.x) w[k] = 0u;
     }
+    static_assert(sizeof(ViewDev) % 4 == 0, "ViewDev is whole words");
+    constexpr int kWords = (int)(sizeof(ViewDev) / 4);
+    for (int k = i; k < p.count * kWords; k += blockDim.x) {
+        const int v = k / kWords, wd = k - v * kWords;
+        reinterpret_cast<uint32_t *>(&T->v[p.first + v])[wd] = reinterpret_cast<const uint32_t *>(&p.v[v])[wd];
+    }
     if (i < p.count) {
         const ViewDev &v = p.v[i];
-        ViewDev &d = T->v[p.first + i];
-        d = v;
-        prg::make_geom(v.view, d.g);
-        if (v.pc.prof)   // written by k_write_profile earlier on the stream
-            prg::attach_profile(d.g, v.pc.prof->c, v.pc.prof->nc, v.pc.prof->l, v.pc.prof->nl);
-        for (int q = 0; q < 9; ++q) { d.R0f[q] = (float)d.g.R0[q]; d.R1f[q] = (float)d.g.R1[q]; }
-        for (int q = 0; q < 3; ++q) { d.T0f[q] = (float)d.g.T0[q]; d.T1f[q] = (float)d.g.T1[q]; }
         T->vtx_block0[p.first + i] = v.vtx_block0;
         T->tri_block0[p.first + i] = v.tri_block0;
         T->tile_base[p.first + i] = v.tile_base;
@@ -187,7 +188,7 @@ __device__ inline double ddot(const double a[3], const double b[3]) { return a[0
 // number of (triangle, tile) candidates of its tile rectangle.
 // Coalesced stores of per-lane rows: lane j holds rows [r0, r0 + n) (n <= 4)
 // of item j of the wave, item j's rows at base + j * stride + r0.  The rows
-// pass through the wave's 256-float4 LDS buffer so that each store
+// pass through the wave's 320-float4 LDS buffer so that each store
 // instruction writes 64-byte runs (four rows of one item) instead of one
 // row per lane; items whose bit of `valid` is clear are not written.
 __device__ __forceinline__ void wave_fence() {
@@ -196,17 +197,20 @@ __device__ __forceinline__ void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Row q of item j sits in the buffer at 5 j + q: the sixteen-byte writes of
+// eight consecutive lanes (80 bytes apart) hit eight different 16-byte bank
+// groups.
 template <int N>
 __device__ __forceinline__ void wave_rows(float4 *__restrict__ base, int stride, int r0, const float4 *v,
                                           unsigned long long valid, float4 *s_buf) {
     const int lane = __lane_id();
 #pragma unroll
-    for (int q = 0; q < N; ++q) s_buf[4 * lane + q] = v[q];
+    for (int q = 0; q < N; ++q) s_buf[5 * lane + q] = v[q];
     wave_fence();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int k = 64 * i + lane, j = k >> 2, q = k & 3;
-        if (q < N && ((valid >> j) & 1ull)) base[(int64_t)j * stride + r0 + q] = s_buf[k];
+        if (q < N && ((valid >> j) & 1ull)) base[(int64_t)j * stride + r0 + q] = s_buf[5 * j + q];
     }
     wave_fence();
 }
@@ -366,7 +370,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                TriBound *__restrict__ tb, DevStatus *__restrict__ st,
                                                int32_t *__restrict__ bcand) {
     __shared__ int s_tmp[72];
-    __shared__ float4 s_rows[4][256];   // per-wave store staging
+    __shared__ float4 s_rows[4][320];   // per-wave store staging (rows padded to 5 per item)
     const int v = find_view(T->tri_block0, T->nv, blockIdx.x);
     const ViewDev &vd = T->v[v];
     const int f = (blockIdx.x - vd.tri_block0) * 256 + threadIdx.x;
@@ -397,15 +401,18 @@ template <bool PROF>   // as k_bound's
 __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, TileInfo *__restrict__ ti,
                                                uint32_t *__restrict__ tcount, Sched *__restrict__ S, const int32_t *__restrict__ bcand,
                                                int64_t *__restrict__ boff, int64_t *__restrict__ part,
-                                               DevStatus *__restrict__ st, int32_t *__restrict__ bperm) {
+                                               DevStatus *__restrict__ st, int32_t *__restrict__ bperm,
+                                               unsigned long long *__restrict__ scan_flags, int nscan) {
     __shared__ int s_tmp[72];
     __shared__ long long s_tmp64[72];
     const int gid = blockIdx.x * 256 + threadIdx.x;
     const int gt = gid >> 2, q = gid & 3;
     const bool valid = gt < T->total_tiles;
-    // clear the counters the binning pass accumulates into
+    // clear the counters the binning pass accumulates into, and the tile
+    // scan's block flags
     if (q == 0 && gt <= T->total_tiles) tcount[gt] = 0u;
     for (int e = gid; e < kSchedCounters; e += (int)gridDim.x * 256) reinterpret_cast<uint32_t *>(S)[e] = 0u;
+    for (int e = gid; e < nscan; e += (int)gridDim.x * 256) scan_flags[e] = 0ull;
     if (blockIdx.x < (T->total_tri_blocks + 255) / 256) {
         // the binning blocks' candidate slots: local exclusive scan of 256
         // block totals here; k_bin adds the totals of the chunks before.
@@ -808,17 +815,6 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewTable *__restrict
 constexpr int kScanItems = 8;
 constexpr int kScanBlock = 256 * kScanItems;
 
-__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict__ in, int n, uint32_t *__restrict__ part) {
-    __shared__ int s_tmp[72];
-    int base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
-    int s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) s += (int)in[base + k];
-    int total;
-    block_excl_scan(s, s_tmp, total);
-    if (threadIdx.x == 0) part[blockIdx.x] = (uint32_t)total;
-}
 
 // Exclusive scan of the per-tile counts: the block's offset is the sum of
 // the partial sums of the blocks before it (few: one per 2048 tiles).  The
@@ -836,18 +832,33 @@ __device__ __forceinline__ int tile_xcd(const ViewTable *__restrict__ T, int gt)
     return (tx / per + 3 * (ty / per) + 5 * v) & (kXcds - 1);
 }
 
-__global__ __launch_bounds__(256) void k_scan_apply(const ViewTable *__restrict__ T, const uint32_t *__restrict__ in,
-                                                    int n, int ntiles, const uint32_t *__restrict__ part,
-                                                    uint32_t *__restrict__ out, Sched *__restrict__ S) {
+// Single-pass exclusive scan of the tile counts (decoupled look-back):
+// blocks take their place in the scan in the order they start (a ticket),
+// publish their sum, and wave 0 finds the exclusive prefix from the flags
+// of the blocks before: 64 at a time, each a 64-bit word (value << 32 |
+// state), state 1 = the block's own sum, 2 = the inclusive prefix through
+// it; the nearest inclusive flag ends the walk.  A block before has taken
+// its ticket earlier and publishes its sum before it looks back itself, so
+// every wait ends; a wait beyond kScanSpin polls (never expected) makes the
+// block sum the counts before it directly instead.  The kernel also builds
+// the tile-order histogram (XCD share x length bucket) of the ray cast.
+constexpr int kScanSpin = 1 << 16;
+
+__global__ __launch_bounds__(256) void k_scan(const ViewTable *__restrict__ T, const uint32_t *__restrict__ in,
+                                              int n, int ntiles, unsigned long long *__restrict__ flags,
+                                              uint32_t *__restrict__ out, Sched *__restrict__ S) {
     __shared__ int s_tmp[72];
     __shared__ uint32_t h[kXcds * kBuckets];
+    __shared__ int s_bid, s_fallback;
+    __shared__ uint32_t s_pre;
+    if (threadIdx.x == 0) {
+        s_bid = (int)atomicAdd(&S->ticket, 1u);
+        s_fallback = 0;
+    }
     for (int e = threadIdx.x; e < kXcds * kBuckets; e += 256) h[e] = 0u;
-    int pre = 0;
-    for (int i = threadIdx.x; i < (int)blockIdx.x; i += 256) pre += (int)part[i];
-    int total;
-    block_excl_scan(pre, s_tmp, total);
-    pre = total;
-    const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    __syncthreads();
+    const int bid = s_bid;
+    const int base = bid * kScanBlock + threadIdx.x * kScanItems;
     int v[kScanItems];
     int sum = 0;
 #pragma unroll
@@ -855,7 +866,55 @@ __global__ __launch_bounds__(256) void k_scan_apply(const ViewTable *__restrict_
         v[k] = base + k < n ? (int)in[base + k] : 0;
         sum += v[k];
     }
-    int ex = block_excl_scan(sum, s_tmp, total) + pre;
+    int total;
+    int ex = block_excl_scan(sum, s_tmp, total);
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        constexpr unsigned long long kAgg = 1ull, kIncl = 2ull;
+        if (lane == 0 && bid > 0)
+            __hip_atomic_store(&flags[bid], ((unsigned long long)(uint32_t)total << 32) | kAgg, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t pre = 0;
+        bool late = false;
+        for (int end = bid; end > 0 && !late;) {
+            const int i = end - 1 - lane;
+            unsigned long long w = 0ull;
+            if (i >= 0) {
+                int spin = 0;
+                do {
+                    w = __hip_atomic_load(&flags[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } while ((w & 3ull) == 0ull && ++spin < kScanSpin);
+            }
+            late = __ballot(i >= 0 && (w & 3ull) == 0ull) != 0ull;
+            const unsigned long long incl = __ballot(i < 0 || (w & 3ull) == kIncl);
+            const int first = incl ? __ffsll((long long)incl) - 1 : 64;
+            uint32_t val = (lane <= first && i >= 0) ? (uint32_t)(w >> 32) : 0u;
+            for (int o = 32; o > 0; o >>= 1) val += __shfl_xor(val, o, 64);
+            pre += val;
+            end = first < 64 ? 0 : end - 64;
+        }
+        if (lane == 0) {
+            s_pre = pre;
+            s_fallback = late ? 1 : 0;
+            if (!late)
+                __hip_atomic_store(&flags[bid], ((unsigned long long)(pre + (uint32_t)total) << 32) | kIncl,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    __syncthreads();
+    uint32_t pre = s_pre;
+    if (s_fallback) {
+        // the prefix from the counts themselves (correct whatever the flags)
+        uint32_t acc = 0;
+        for (int i = threadIdx.x; i < bid * kScanBlock && i < n; i += 256) acc += in[i];
+        int tot2;
+        block_excl_scan((int)acc, s_tmp, tot2);
+        pre = (uint32_t)tot2;
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&flags[bid], ((unsigned long long)(pre + (uint32_t)total) << 32) | 2ull,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    ex += (int)pre;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n) out[base + k] = (uint32_t)ex;
@@ -889,7 +948,7 @@ __host__ __device__ __forceinline__ int share_items(int tile, int n) {
 // Pairs -> lists.  Blocks below ceil(ntiles / 256) also write the tile
 // orders of the persistent ray cast: XCD share x's tiles at order[x ntiles
 // ...], longest lists first by power-of-two length bucket (counting sort on
-// the histogram k_scan_apply built; S->cursor cleared by k_tiles).
+// the histogram k_scan built; S->cursor cleared by k_tiles).
 __global__ __launch_bounds__(256) void k_scatter(const ViewTable *__restrict__ T, Pairs pairs,
                                                  const uint32_t *__restrict__ toff, int32_t *__restrict__ lists,
                                                  int64_t cap, int ntiles, DevStatus *__restrict__ st,
