@@ -267,7 +267,7 @@ void write_views(const Layout &L, ViewTable *T, DevStatus *st, bool reset_status
                 // the workspace's copy (k_write_profile, earlier on the stream):
                 // device addresses, counts from the host copy
                 const ProfDev &H = L.prof_host[first + i];
-                prg::attach_profile(d.g, d.pc.prof->c, H.nc, d.pc.prof->l, H.nl);
+                prg::attach_profile(d.g, d.pc.prof->c, H.nc, d.pc.prof->l, H.nl, H.c, H.l);
             }
         }
         hipLaunchKernelGGL(k_write_views, dim3(1), dim3(64), 0, s, p, T, st);

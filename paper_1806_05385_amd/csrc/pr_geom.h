@@ -34,6 +34,10 @@ struct Geom {
     // normalised distance (pr_profile), attached by attach_profile
     const float *tc, *tl;
     int nc, nl;
+    // trend of each table's scale G(s)/s (+1 non-decreasing, -1
+    // non-increasing, 0 neither), which decides where the image of a box
+    // takes its extremes
+    int tc_trend, tl_trend;
 };
 
 // fmin / fmax (one instruction each on the device; the bound's values are
@@ -132,15 +136,38 @@ PRG void make_geom(const pr_view &v, Geom &g) {
     g.W = v.width; g.H = v.height;
     g.tc = g.tl = nullptr;
     g.nc = g.nl = 0;
+    g.tc_trend = g.tl_trend = 0;
 }
 
 // The view's tabulated profiles (samples in memory the caller's side can
 // read: host memory for the host hooks, the workspace on the device).
-PRG void attach_profile(Geom &g, const float *tc, int nc, const float *tl, int nl) {
+// Trend of the scale G(s)/s of the piecewise-linear profile through the
+// samples t[k] = G(k/(n-1)) (G(0) = 0, increasing): on segment k the
+// profile is the line a_k + m_k s, so its scale a_k / s + m_k falls where
+// the intercept a_k = (k+1) t[k] - k t[k+1] is positive and rises where it
+// is negative; the scale is continuous, so it is monotone when all
+// intercepts share a sign.  -1: non-increasing (a concave profile), +1:
+// non-decreasing (a convex one), 0: neither.
+PRG int scale_trend(const float *t, int n) {
+    bool down = true, up = true;
+    for (int k = 0; k + 1 < n; ++k) {
+        const double a = (k + 1.0) * (double)t[k] - (double)k * (double)t[k + 1];
+        if (a > 0.0) up = false;
+        if (a < 0.0) down = false;
+    }
+    return down ? -1 : (up ? 1 : 0);
+}
+
+// ht / hl: host-readable copies of the samples (the table pointers may be
+// device addresses), from which the scale trends are taken.
+PRG void attach_profile(Geom &g, const float *tc, int nc, const float *tl, int nl, const float *hc = nullptr,
+                        const float *hl = nullptr) {
     g.tc = nc >= 2 ? tc : nullptr;
     g.nc = nc >= 2 ? nc : 0;
     g.tl = nl >= 2 ? tl : nullptr;
     g.nl = nl >= 2 ? nl : 0;
+    g.tc_trend = g.nc ? scale_trend(hc ? hc : tc, nc) : 0;
+    g.tl_trend = g.nl ? scale_trend(hl ? hl : tl, nl) : 0;
 }
 
 // Tabulated radial profile (Sec. 3.1.1 "Domain": p arbitrary and monotone):
@@ -186,32 +213,54 @@ PRG void radial_map(const Geom &g, double e, double x0, double x1, double &o0, d
     o1 = g.fov[1] + d1 * s;
 }
 
-// Exact bounding box of a radial map of the rectangle [a0,a1] x [b0,b1].
-// Component k of the map is increasing in coordinate k; in the other
-// coordinate it depends only on the distance to the fovea: for e > 1 the
-// scale (rho/R)^(e-1) grows with distance, for e < 1 it shrinks.  So each
-// extreme sits on the matching rectangle side at the point nearest to or
-// farthest from the fovea's coordinate.
-PRG void radial_bbox(const Geom &g, double e, double a0, double a1, double b0, double b1, double out[4]) {
-    bool grows = e > 1.0;
+// Exact bounding box of the image of the rectangle [a0,a1] x [b0,b1] under
+// a radial map about the fovea, x -> f + (x - f) sigma(|x - f|), whose
+// distance map rho sigma(rho) is increasing and whose scale sigma is
+// monotone (grows: non-decreasing).  Component k of the map is increasing
+// in coordinate k (its derivative sigma + d_k^2 sigma' / rho is at least
+// the distance map's slope); in the other coordinate it depends only on
+// the distance to the fovea through sigma.  So each extreme sits on the
+// matching rectangle side at the point nearest to or farthest from the
+// fovea's coordinate.
+template <class Map>
+PRG void radial_bbox_map(const Geom &g, bool grows, double a0, double a1, double b0, double b1, double out[4],
+                         Map &&map) {
     auto nearest = [](double c, double lo, double hi) { return c < lo ? lo : (c > hi ? hi : c); };
     auto farthest = [](double c, double lo, double hi) { return (c - lo) > (hi - c) ? lo : hi; };
     double o0, o1, y;
     // max of component 0: at x = a1
     y = ((a1 - g.fov[0] >= 0) == grows) ? farthest(g.fov[1], b0, b1) : nearest(g.fov[1], b0, b1);
-    radial_map(g, e, a1, y, o0, o1);
+    map(a1, y, o0, o1);
     out[1] = o0;
     // min of component 0: at x = a0
     y = ((a0 - g.fov[0] <= 0) == grows) ? farthest(g.fov[1], b0, b1) : nearest(g.fov[1], b0, b1);
-    radial_map(g, e, a0, y, o0, o1);
+    map(a0, y, o0, o1);
     out[0] = o0;
     // max of component 1: at y = b1
     double x = ((b1 - g.fov[1] >= 0) == grows) ? farthest(g.fov[0], a0, a1) : nearest(g.fov[0], a0, a1);
-    radial_map(g, e, x, b1, o0, o1);
+    map(x, b1, o0, o1);
     out[3] = o1;
     x = ((b0 - g.fov[1] <= 0) == grows) ? farthest(g.fov[0], a0, a1) : nearest(g.fov[0], a0, a1);
-    radial_map(g, e, x, b0, o0, o1);
+    map(x, b0, o0, o1);
     out[2] = o1;
+}
+
+// The power law: sigma = (rho/R)^(e-1) grows for e > 1, shrinks for e < 1.
+PRG void radial_bbox(const Geom &g, double e, double a0, double a1, double b0, double b1, double out[4]) {
+    radial_bbox_map(g, e > 1.0, a0, a1, b0, b1, out,
+                    [&](double x0, double x1, double &o0, double &o1) { radial_map(g, e, x0, x1, o0, o1); });
+}
+
+// The tabulated radial map: distance rho -> R G(rho / R), G the profile tab
+// (its inverse when inv).
+PRG void table_map(const Geom &g, const float *tab, int n, bool inv, double x0, double x1, double &o0,
+                   double &o1) {
+    const double d0 = x0 - g.fov[0], d1 = x1 - g.fov[1];
+    const double rho = sqrt(d0 * d0 + d1 * d1);
+    if (rho == 0.0) { o0 = x0; o1 = x1; return; }
+    const double s = rho * g.inv_rad, sc = (inv ? prof_inv(tab, n, s) : prof_eval(tab, n, s)) / s;
+    o0 = g.fov[0] + d0 * sc;
+    o1 = g.fov[1] + d1 * sc;
 }
 
 // The maps below take a template flag PROF: false compiles only the power
@@ -226,12 +275,7 @@ PRG void unfoveate_pt(const Geom &g, double y0, double y1, double &x0, double &x
         radial_map(g, g.alpha, y0, y1, x0, x1);
         return;
     }
-    const double d0 = y0 - g.fov[0], d1 = y1 - g.fov[1];
-    const double rho = sqrt(d0 * d0 + d1 * d1);
-    if (rho == 0.0) { x0 = y0; x1 = y1; return; }
-    const double s = rho * g.inv_rad, sc = prof_inv(g.tc, g.nc, s) / s;
-    x0 = g.fov[0] + d0 * sc;
-    x1 = g.fov[1] + d1 * sc;
+    table_map(g, g.tc, g.nc, true, y0, y1, x0, x1);
 }
 
 // Panel point -> undistorted point (Sec. 5.1 "Lens Distortion": p = p_c o p_l
@@ -240,12 +284,7 @@ PRG void unfoveate_pt(const Geom &g, double y0, double y1, double &x0, double &x
 template <bool PROF = true>
 PRG void undistort_pt(const Geom &g, double x0, double x1, double &u0, double &u1) {
     if (!PROF || g.nl < 2) { u0 = x0; u1 = x1; return; }
-    const double d0 = x0 - g.fov[0], d1 = x1 - g.fov[1];
-    const double rho = sqrt(d0 * d0 + d1 * d1);
-    if (rho == 0.0) { u0 = x0; u1 = x1; return; }
-    const double s = rho * g.inv_rad, sc = prof_inv(g.tl, g.nl, s) / s;
-    u0 = g.fov[0] + d0 * sc;
-    u1 = g.fov[1] + d1 * sc;
+    table_map(g, g.tl, g.nl, true, x0, x1, u0, u1);
 }
 
 // Box of the image of box b = [b0,b1] x [b2,b3] under the radial map about
@@ -296,29 +335,43 @@ PRG void sector_box(const Geom &g, const float *tab, int n, bool inv, const doub
     for (int k = 0; k < 4; ++k) out[k] = o[k];
 }
 
+// Box of the image of box b under a tabulated radial map (G = tab, or its
+// inverse when inv; trend: the trend of tab's scale): exact when the map's
+// scale is monotone (the inverse's scale runs the other way), else the
+// sector box.
+PRG void table_box(const Geom &g, const float *tab, int n, int trend, bool inv, const double b[4], double out[4]) {
+    const int t = inv ? -trend : trend;
+    if (t == 0) {
+        sector_box(g, tab, n, inv, b, out);
+        return;
+    }
+    radial_bbox_map(g, t > 0, b[0], b[1], b[2], b[3], out,
+                    [&](double x0, double x1, double &o0, double &o1) { table_map(g, tab, n, inv, x0, x1, o0, o1); });
+}
+
 // Panel box of the foveated box b (the pixels' display points).
 template <bool PROF = true>
 PRG void box_unfoveate(const Geom &g, const double b[4], double out[4]) {
     if (!PROF || g.nc < 2) radial_bbox(g, g.alpha, b[0], b[1], b[2], b[3], out);
-    else sector_box(g, g.tc, g.nc, true, b, out);
+    else table_box(g, g.tc, g.nc, g.tc_trend, true, b, out);
 }
 // Foveated box of the panel box b.
 template <bool PROF = true>
 PRG void box_foveate(const Geom &g, const double b[4], double out[4]) {
     if (!PROF || g.nc < 2) radial_bbox(g, g.inv_alpha, b[0], b[1], b[2], b[3], out);
-    else sector_box(g, g.tc, g.nc, false, b, out);
+    else table_box(g, g.tc, g.nc, g.tc_trend, false, b, out);
 }
 // Panel box of the undistorted box b (the lens applied); b itself without one.
 template <bool PROF = true>
 PRG void box_distort(const Geom &g, const double b[4], double out[4]) {
     if (!PROF || g.nl < 2) for (int k = 0; k < 4; ++k) out[k] = b[k];
-    else sector_box(g, g.tl, g.nl, false, b, out);
+    else table_box(g, g.tl, g.nl, g.tl_trend, false, b, out);
 }
 // Undistorted box of the panel box b (the lens inverted).
 template <bool PROF = true>
 PRG void box_undistort(const Geom &g, const double b[4], double out[4]) {
     if (!PROF || g.nl < 2) for (int k = 0; k < 4; ++k) out[k] = b[k];
-    else sector_box(g, g.tl, g.nl, true, b, out);
+    else table_box(g, g.tl, g.nl, g.tl_trend, true, b, out);
 }
 
 // Camera-space start / end vertices of triangle f.  Returns false if an

@@ -146,12 +146,11 @@ struct DevStatus {
 // length bucket).
 constexpr int kBuckets = 33;
 constexpr int kXcds = 8;
-constexpr int kSchedCounters = 2 * kXcds * kBuckets + kXcds + 2;   // cleared by k_tiles
+constexpr int kSchedCounters = 2 * kXcds * kBuckets + kXcds + 1;   // cleared by k_tiles
 struct Sched {
     uint32_t count[kXcds][kBuckets];    // tiles per (XCD share, bucket)
     uint32_t cursor[kXcds][kBuckets];
     uint32_t ntile[kXcds];              // tiles of each share
-    uint32_t nitems;                    // items of the persistent grid (8 x the largest share's)
     uint32_t ticket;                    // k_scan's block order
 };
 static_assert(sizeof(Sched) == 4 * kSchedCounters, "Sched is kSchedCounters words");

@@ -958,14 +958,11 @@ __global__ __launch_bounds__(256) void k_scatter(const ViewTable *__restrict__ T
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->pairs_total = toff[ntiles];
         if (ovf) st->overflow = 1;
-        int most = 0;
         for (int x = 0; x < kXcds; ++x) {
             uint32_t nt = 0;
             for (int b = 0; b < kBuckets; ++b) nt += S->count[x][b];
             S->ntile[x] = nt;
-            most = max(most, share_items(T->v[0].tile, (int)nt));
         }
-        S->nitems = (uint32_t)(kXcds * most);
     }
     if (blockIdx.x < (ntiles + 255) / 256) {
         __shared__ uint32_t h[kXcds * kBuckets], base[kXcds * kBuckets], first[kXcds * kBuckets];
@@ -1510,48 +1507,51 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
 // persistent ray cast over a longest-list-first tile queue
 // ---------------------------------------------------------------------------
 // A grid sized to the device's resident blocks walks the longest-first tile
-// order (written by k_scatter) with a static stride, so the longest lists
-// start first.
+// order (written by k_scatter) in rounds, so the longest lists start first.
 template <int TILE, bool COUNT, bool SHADE>
 __global__ __launch_bounds__((RayCfg<TILE>::NT)) __attribute__((amdgpu_waves_per_eu(6))) void k_raycast_queue(
     const ViewTable *__restrict__ T, const float4 *__restrict__ rec, const uint32_t *__restrict__ lists, RayOut out,
     DevStatus *__restrict__ st, const int4 *__restrict__ order, const Sched *__restrict__ S, ShadeIO sio,
     pr_light light) {
     __shared__ int32_t s_sel[4 * kSelCap];
-    // Block b takes items b, b + grid, b + 2 grid, ... (no queue atomics).
     // Blocks are dispatched to the XCDs in turn and the grid is a multiple
-    // of their count, so item i runs on XCD i % 8: it is position i / 8 of
-    // that XCD's share, walked longest list first (the first round holds
-    // the longest lists).  While an item is cast, the tile record two items
-    // ahead and the first list entries of the next item are loaded.
+    // of their count, so block b runs on XCD x = b % 8 and walks that XCD's
+    // share of the items, longest list first.  Its k = b / 8 of the K = grid
+    // / 8 blocks of the share takes one item per round, in serpentine order
+    // (round r: position r K + k for even r, r K + K - 1 - k for odd), which
+    // evens out the blocks' summed list lengths.  (Shared queues drawing
+    // each cell with a device-scope atomic ran several times slower.)
+    // While an item is cast, the tile record two rounds ahead and the first
+    // list entries of the next round are loaded.
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ntiles = T->total_tiles;
-    const int G = gridDim.x;
-    const int nitems = (int)S->nitems;
-    auto fetch = [&](int it, int &quad) {
-        const int x = it & (kXcds - 1), j = it >> 3;
+    const int x = (int)blockIdx.x & (kXcds - 1), k = (int)blockIdx.x >> 3, K = (int)gridDim.x >> 3;
+    const int share = (int)S->ntile[x];
+    const int nitems = share_items(TILE, share);
+    const int rounds = (nitems + K - 1) / K;
+    const int4 *ord = order + (int64_t)x * ntiles;
+    auto fetch = [&](int r, int &quad) {
+        const int j = r * K + ((r & 1) ? K - 1 - k : k);
         const int pos = TILE == 8 ? 4 * j + wv : (TILE == 16 ? j : j >> 2);
         quad = j & 3;
-        return it < nitems && pos < (int)S->ntile[x] ? order[(int64_t)x * ntiles + pos] : make_int4(-1, 0, 0, 0);
+        return j < nitems && pos < share ? ord[pos] : make_int4(-1, 0, 0, 0);
     };
-    int item = blockIdx.x;
     int qcur, qn1, qn2;
-    int4 cur = fetch(item, qcur), nx1 = fetch(item + G, qn1);
+    int4 cur = fetch(0, qcur), nx1 = fetch(1, qn1);
     uint32_t ecur = first_entries(lists, cur);
-    while (item < nitems) {
-        const int4 nx2 = fetch(item + 2 * G, qn2);
+    for (int r = 0; r < rounds; ++r) {
+        const int4 nx2 = fetch(r + 2, qn2);
         const uint32_t enx = first_entries(lists, nx1);
         // Waves of equal priority issue oldest first, so the blocks
         // dispatched last fall behind and end up running alone; a wave in
-        // the first quarter of its items runs at priority 3, in the last at
+        // the first quarter of its rounds runs at priority 3, in the last at
         // 0, so lagging waves are issued first and the grid drains evenly.
-        const int quarter = 4 * ((item - (int)blockIdx.x) / G) / ((nitems - 1 - (int)blockIdx.x) / G + 1);
+        const int quarter = 4 * r / rounds;
         if (quarter == 0) __builtin_amdgcn_s_setprio(3);
         else if (quarter == 1) __builtin_amdgcn_s_setprio(2);
         else if (quarter == 2) __builtin_amdgcn_s_setprio(1);
         else __builtin_amdgcn_s_setprio(0);
         raycast_item<TILE, COUNT, SHADE>(T, rec, lists, out, st, qcur, cur, ecur, s_sel, &sio, &light);
-        item += G;
         cur = nx1;
         qcur = qn1;
         nx1 = nx2;

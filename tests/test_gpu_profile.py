@@ -32,6 +32,9 @@ PROFILES = {
     'table': (lambda: scenegen.foveal_table(33, 3.0), lambda: None),
     'lens': (lambda: None, lambda: scenegen.barrel_table(33, 0.22)),
     'table_lens': (lambda: scenegen.foveal_table(17, 2.0), lambda: scenegen.barrel_table(25, 0.2)),
+    # scales G(s)/s that are not monotone (the bound's sector-box fallback)
+    'kinked': (lambda: np.array([0.0, 0.4, 0.5, 0.8, 1.0], np.float32),
+               lambda: np.array([0.0, 0.2, 0.6, 0.7, 1.0], np.float32)),
 }
 
 
@@ -76,7 +79,8 @@ def test_profile_full_frame(prof, tile, flags):
 
 
 @pytest.mark.parametrize('prof,alpha,roll', [('table', 2.0, (1.0, 0.0)), ('lens', 1.0, (0.0, 0.9)),
-                                             ('lens', 3.0, (1.0, 0.5)), ('table_lens', 2.0, (1.0, 0.0))])
+                                             ('lens', 3.0, (1.0, 0.5)), ('table_lens', 2.0, (1.0, 0.0)),
+                                             ('kinked', 2.0, (0.0, 0.9))])
 def test_profile_bound_invariant_on_device_lists(prof, alpha, roll):
     """Every oracle hit (occluded or not) lies in a tile whose device-built
     list holds the triangle, with the pixel's quadrant in the mask."""
