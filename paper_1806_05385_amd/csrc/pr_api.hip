@@ -33,7 +33,7 @@ struct Layout {
     ViewDev vd[PR_MAX_VIEWS];
     int total_tiles, total_tri_blocks, total_pix_blocks, total_vtx_blocks, nparts;
     int64_t cap, total_rec4, total_tris, total_gacc;
-    size_t table, tinfo, rec, tb, bcand, bperm, boff, bpart, tcount, toff, part, pairs, lists, gacc, pacc, sched, order, prof,
+    size_t table, tinfo, rec, tb, bcand, bnf, bperm, boff, bpart, tcount, toff, part, pairs, lists, gacc, pacc, sched, order, prof,
         bytes;
     ProfDev prof_host[PR_MAX_VIEWS];   // the views' tabulated profiles (used where prof_used)
     bool prof_used[PR_MAX_VIEWS];
@@ -189,6 +189,7 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     L.rec = off; off = up(off + (size_t)rec4 * sizeof(float4));
     L.tb = off; off = up(off + (size_t)tris * sizeof(TriBound));
     L.bcand = off; off = up(off + ((size_t)tri_blocks + 1) * 4);
+    L.bnf = off; off = up(off + ((size_t)tri_blocks + 1) * 4);
     L.bperm = off; off = up(off + ((size_t)tri_blocks + 1) * 4);
     L.boff = off; off = up(off + ((size_t)tri_blocks + 1) * 8);
     L.bpart = off; off = up(off + ((size_t)tri_blocks / 256 + 1) * 8);
@@ -241,37 +242,50 @@ void fill_u32(void *p, uint32_t v, int64_t n, hipStream_t s) {
     DevStatus *st = at<DevStatus>(ws, 0);                                 \
     ViewTable *T = at<ViewTable>(ws, L.table);
 
+// The views' tabulated profiles into the workspace (before the view table,
+// whose geometry points at them).
+ProfDev *write_profiles(const Layout &L, ViewTable *T, hipStream_t s) {
+    ProfDev *prof = reinterpret_cast<ProfDev *>(reinterpret_cast<char *>(T) - L.table + L.prof);
+    for (int v = 0; v < L.nv; ++v)
+        if (L.prof_used[v]) hipLaunchKernelGGL(k_write_profile, dim3(1), dim3(64), 0, s, L.prof_host[v], prof + v);
+    return prof;
+}
+
+// Views first .. first + kViewsPerWrite - 1 of the call as one pack of
+// kernel arguments; reset_status: the launch that takes it also clears the
+// status block (the frame's first pass).
+ViewPack make_pack(const Layout &L, ProfDev *prof, int first, bool reset_status) {
+    ViewPack p;
+    memset(&p, 0, sizeof(p));
+    p.first = first;
+    p.count = std::min(kViewsPerWrite, L.nv - first);
+    p.nv = L.nv;
+    p.total_tiles = L.total_tiles;
+    p.total_tri_blocks = L.total_tri_blocks;
+    p.total_pix_blocks = L.total_pix_blocks;
+    p.total_vtx_blocks = L.total_vtx_blocks;
+    p.reset_status = reset_status ? 1 : 0;
+    for (int i = 0; i < p.count; ++i) {
+        ViewDev &d = p.v[i];
+        d = L.vd[first + i];
+        d.pc.prof = L.prof_used[first + i] ? prof + first + i : nullptr;
+        if (d.pc.prof) {
+            // the workspace's copy (k_write_profile, earlier on the stream):
+            // device addresses, counts from the host copy
+            const ProfDev &H = L.prof_host[first + i];
+            prg::attach_profile(d.g, d.pc.prof->c, H.nc, d.pc.prof->l, H.nl, H.c, H.l);
+        }
+    }
+    return p;
+}
+
 // The workspace's view table from the call's own meshes and views (FP64
 // camera geometry computed on the host); reset_status: also clear the
 // status block (the frame's first pass).
 void write_views(const Layout &L, ViewTable *T, DevStatus *st, bool reset_status, hipStream_t s) {
-    ProfDev *prof = reinterpret_cast<ProfDev *>(reinterpret_cast<char *>(T) - L.table + L.prof);
-    for (int v = 0; v < L.nv; ++v)
-        if (L.prof_used[v]) hipLaunchKernelGGL(k_write_profile, dim3(1), dim3(64), 0, s, L.prof_host[v], prof + v);
-    for (int first = 0; first < L.nv; first += kViewsPerWrite) {
-        ViewPack p;
-        memset(&p, 0, sizeof(p));
-        p.first = first;
-        p.count = std::min(kViewsPerWrite, L.nv - first);
-        p.nv = L.nv;
-        p.total_tiles = L.total_tiles;
-        p.total_tri_blocks = L.total_tri_blocks;
-        p.total_pix_blocks = L.total_pix_blocks;
-        p.total_vtx_blocks = L.total_vtx_blocks;
-        p.reset_status = reset_status ? 1 : 0;
-        for (int i = 0; i < p.count; ++i) {
-            ViewDev &d = p.v[i];
-            d = L.vd[first + i];
-            d.pc.prof = L.prof_used[first + i] ? prof + first + i : nullptr;
-            if (d.pc.prof) {
-                // the workspace's copy (k_write_profile, earlier on the stream):
-                // device addresses, counts from the host copy
-                const ProfDev &H = L.prof_host[first + i];
-                prg::attach_profile(d.g, d.pc.prof->c, H.nc, d.pc.prof->l, H.nl, H.c, H.l);
-            }
-        }
-        hipLaunchKernelGGL(k_write_views, dim3(1), dim3(64), 0, s, p, T, st);
-    }
+    ProfDev *prof = write_profiles(L, T, s);
+    for (int first = 0; first < L.nv; first += kViewsPerWrite)
+        hipLaunchKernelGGL(k_write_views, dim3(1), dim3(64), 0, s, make_pack(L, prof, first, reset_status), T, st);
 }
 
 // Blocks of a kernel the whole device keeps resident (persistent grids).
@@ -388,14 +402,20 @@ int pr_workspace_size(const pr_mesh *meshes, int nm, const pr_view *views, int n
 int pr_bound(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr_tuning *tuning, void *ws,
              size_t ws_bytes, void *stream) {
     PR_PREP();
-    write_views(L, T, st, true, s);
+    // up to kViewsPerWrite views travel in k_bound's arguments (its block 0
+    // writes the view table), more need the table written first
+    const bool pack = L.nv <= kViewsPerWrite && L.total_tri_blocks > 0;
+    ViewPack p;
+    if (pack) p = make_pack(L, write_profiles(L, T, s), 0, true);
+    else {
+        write_views(L, T, st, true, s);
+        memset(&p, 0, sizeof(p));
+    }
     if (L.total_tri_blocks > 0) {
-        if (L.any_prof)
-            hipLaunchKernelGGL(k_bound<true>, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec),
-                               at<TriBound>(ws, L.tb), st, at<int32_t>(ws, L.bcand));
-        else
-            hipLaunchKernelGGL(k_bound<false>, dim3(L.total_tri_blocks), dim3(256), 0, s, T, at<float4>(ws, L.rec),
-                               at<TriBound>(ws, L.tb), st, at<int32_t>(ws, L.bcand));
+        auto k = L.any_prof ? (pack ? k_bound<true, true> : k_bound<true, false>)
+                            : (pack ? k_bound<false, true> : k_bound<false, false>);
+        hipLaunchKernelGGL(k, dim3(L.total_tri_blocks), dim3(256), 0, s, p, T, at<float4>(ws, L.rec),
+                           at<TriBound>(ws, L.tb), st, at<int32_t>(ws, L.bcand), at<int32_t>(ws, L.bnf));
     }
     return launched();
 }
@@ -409,7 +429,8 @@ int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     // binning blocks
     hipLaunchKernelGGL(L.any_prof ? k_tiles<true> : k_tiles<false>, dim3(std::max(tile_blocks, chunk_blocks) + 1),
                        dim3(256), 0, s, T, at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount),
-                       at<Sched>(ws, L.sched), at<int32_t>(ws, L.bcand), at<int64_t>(ws, L.boff),
+                       at<Sched>(ws, L.sched), at<int32_t>(ws, L.bcand), at<int32_t>(ws, L.bnf),
+                       at<int64_t>(ws, L.boff),
                        at<int64_t>(ws, L.bpart), st, at<int32_t>(ws, L.bperm),
                        at<unsigned long long>(ws, L.part), L.nparts);
     if (L.total_tri_blocks > 0)

@@ -123,15 +123,17 @@ __device__ __forceinline__ int find_view(const int32_t *base, int nv, int key) {
 
 // The views arrive complete (geometry included, computed on the host): the
 // block copies them word by word into the view table.
-__global__ void k_write_views(ViewPack p, ViewTable *__restrict__ T, DevStatus *__restrict__ st) {
-    int i = threadIdx.x;
+// Thread i of n threads: its share of writing pack p into the view table
+// (and of clearing the status block when p asks for it).
+__device__ __forceinline__ void write_pack(const ViewPack &p, ViewTable *__restrict__ T, DevStatus *__restrict__ st,
+                                           int i, int n) {
     if (p.first == 0 && p.reset_status) {   // the frame's first launch resets the status block
         uint32_t *w = reinterpret_cast<uint32_t *>(st);
-        for (int k = i; k < (int)(sizeof(DevStatus) / 4); k += blockDim.x) w[k] = 0u;
+        for (int k = i; k < (int)(sizeof(DevStatus) / 4); k += n) w[k] = 0u;
     }
     static_assert(sizeof(ViewDev) % 4 == 0, "ViewDev is whole words");
     constexpr int kWords = (int)(sizeof(ViewDev) / 4);
-    for (int k = i; k < p.count * kWords; k += blockDim.x) {
+    for (int k = i; k < p.count * kWords; k += n) {
         const int v = k / kWords, wd = k - v * kWords;
         reinterpret_cast<uint32_t *>(&T->v[p.first + v])[wd] = reinterpret_cast<const uint32_t *>(&p.v[v])[wd];
     }
@@ -153,6 +155,10 @@ __global__ void k_write_views(ViewPack p, ViewTable *__restrict__ T, DevStatus *
         T->tile_base[p.nv] = p.total_tiles;
         T->pix_block0[p.nv] = p.total_pix_blocks;
     }
+}
+
+__global__ void k_write_views(ViewPack p, ViewTable *__restrict__ T, DevStatus *__restrict__ st) {
+    write_pack(p, T, st, threadIdx.x, blockDim.x);
 }
 
 // One view's tabulated profiles into the workspace (before k_write_views).
@@ -217,10 +223,11 @@ __device__ __forceinline__ void wave_rows(float4 *__restrict__ base, int stride,
 
 // Triangle f of the view (every lane of the wave calls it; lanes with valid
 // false compute on an in-range triangle and store nothing); f0: the wave's
-// first triangle (wave-uniform; lane j's triangle is f0 + j).
+// first triangle (wave-uniform; lane j's triangle is f0 + j).  nonfinite:
+// the (valid) triangle has an index out of range or a non-finite vertex.
 template <bool PROF>
 __device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, bool valid, int f0, float4 *__restrict__ rec,
-                                         TriBound *__restrict__ tb, DevStatus *__restrict__ st, float4 *s_buf) {
+                                         TriBound *__restrict__ tb, bool &nonfinite, float4 *s_buf) {
     const prg::Geom &g = vd.g;
     double Ps[3][3], Pe[3][3];
     int32_t idx[3];
@@ -231,9 +238,8 @@ __device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, bool valid, i
     b.pad = 0;
     b.pad2[0] = b.pad2[1] = 0;
     for (int k = 0; k < 4; ++k) b.w[k] = 0.0;
-    if (!ok) {
-        if (valid) atomicAdd(&st->nonfinite, 1);
-    } else {
+    nonfinite = valid && !ok;
+    if (ok) {
         double win[2];
         int kind = prg::time_window<PROF>(g, Ps, Pe, win, vd.bound);
         if (kind != prg::kCulled) {
@@ -362,26 +368,47 @@ __device__ __forceinline__ int bound_tri(const ViewDev &vd, int f, bool valid, i
 }
 
 // One lane per triangle; the block's candidate total (the binning block of
-// the same 256 triangles) goes to bcand[block].
+// the same 256 triangles) goes to bcand[block], its count of triangles with
+// bad data to bnf[block] (k_tiles adds them to the status block).
 // PROF: some view of the call has a tabulated profile or a lens (false: the
-// power-law code alone, with its own register allocation).
-template <bool PROF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_bound(const ViewTable *__restrict__ T, float4 *__restrict__ rec,
-                                               TriBound *__restrict__ tb, DevStatus *__restrict__ st,
-                                               int32_t *__restrict__ bcand) {
+// power-law code alone, with its own register allocation).  PACK: the
+// call's views come in the kernel arguments (all of them: at most
+// kViewsPerWrite), and block 0 also writes them into the view table and
+// clears the status block for the kernels after (none of this kernel's
+// blocks reads either); otherwise the view table was written before.
+static_assert(kViewsPerWrite == 2, "k_bound takes a packed view by constant index 0 or 1");
+template <bool PROF, bool PACK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_bound(
+    ViewPack P, ViewTable *__restrict__ T, float4 *__restrict__ rec, TriBound *__restrict__ tb,
+    DevStatus *__restrict__ st, int32_t *__restrict__ bcand, int32_t *__restrict__ bnf) {
     __shared__ int s_tmp[72];
     __shared__ float4 s_rows[4][320];   // per-wave store staging (rows padded to 5 per item)
-    const int v = find_view(T->tri_block0, T->nv, blockIdx.x);
-    const ViewDev &vd = T->v[v];
-    const int f = (blockIdx.x - vd.tri_block0) * 256 + threadIdx.x;
-    // every lane takes part in the wave's coalesced stores; lanes past the
-    // mesh work on triangle 0 (a block exists only for nt >= 1)
-    const bool valid = f < vd.mesh.nt;
-    const int fw0 = (blockIdx.x - vd.tri_block0) * 256 + (int)(threadIdx.x & ~63u);
-    const int cnt = bound_tri<PROF>(vd, valid ? f : 0, valid, fw0, rec, tb, st, s_rows[threadIdx.x >> 6]);
+    __shared__ int s_nf;
+    if (PACK && blockIdx.x == 0) write_pack(P, T, st, threadIdx.x, 256);
+    if (threadIdx.x == 0) s_nf = 0;
+    __syncthreads();
+    int v;
+    if (PACK) v = P.count > 1 && (int)blockIdx.x >= P.v[1].tri_block0 ? 1 : 0;
+    else v = find_view(T->tri_block0, T->nv, blockIdx.x);
+    auto run = [&](const ViewDev &vd, bool &nonfinite) {
+        const int f = (blockIdx.x - vd.tri_block0) * 256 + threadIdx.x;
+        // every lane takes part in the wave's coalesced stores; lanes past
+        // the mesh work on triangle 0 (a block exists only for nt >= 1)
+        const bool valid = f < vd.mesh.nt;
+        const int fw0 = (blockIdx.x - vd.tri_block0) * 256 + (int)(threadIdx.x & ~63u);
+        return bound_tri<PROF>(vd, valid ? f : 0, valid, fw0, rec, tb, nonfinite, s_rows[threadIdx.x >> 6]);
+    };
+    bool nonfinite = false;
+    // (the packed views by constant index: a dynamic one into the kernel
+    // arguments costs the bound spilled registers)
+    const int cnt = !PACK ? run(T->v[v], nonfinite) : (v == 0 ? run(P.v[0], nonfinite) : run(P.v[1], nonfinite));
+    if (nonfinite) atomicAdd(&s_nf, 1);
     int total;
-    block_excl_scan(cnt, s_tmp, total);
-    if (threadIdx.x == 0) bcand[blockIdx.x] = total;
+    block_excl_scan(cnt, s_tmp, total);   // (its barriers also order the count above)
+    if (threadIdx.x == 0) {
+        bcand[blockIdx.x] = total;
+        bnf[blockIdx.x] = s_nf;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -400,6 +427,7 @@ constexpr int kPermItems = 8;
 template <bool PROF>   // as k_bound's
 __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, TileInfo *__restrict__ ti,
                                                uint32_t *__restrict__ tcount, Sched *__restrict__ S, const int32_t *__restrict__ bcand,
+                                               const int32_t *__restrict__ bnf,
                                                int64_t *__restrict__ boff, int64_t *__restrict__ part,
                                                DevStatus *__restrict__ st, int32_t *__restrict__ bperm,
                                                unsigned long long *__restrict__ scan_flags, int nscan) {
@@ -424,9 +452,12 @@ __global__ __launch_bounds__(256) void k_tiles(const ViewTable *__restrict__ T, 
         long long tot;
         const long long ex = block_excl_scan64(c, s_tmp64, tot);
         if (b < nb) boff[b] = ex;
+        long long nf;   // the chunk's triangles with bad data
+        block_excl_scan64(b < nb ? bnf[b] : 0, s_tmp64, nf);
         if (threadIdx.x == 0) {
             part[blockIdx.x] = tot;
             atomicAdd(&st->pairs_required, (unsigned long long)tot);
+            if (nf) atomicAdd(&st->nonfinite, (int)nf);
         }
     }
     if (blockIdx.x == gridDim.x - 1) {

@@ -246,6 +246,11 @@ def test_nonfinite_vertex_and_empty_mesh():
     r, out = _render(sc2, 16)
     assert r.status().nonfinite == 1
     assert not (out[0]['id'] == 1).any()
+    # counted once per view: three views take the launch form that writes
+    # the view table first (two or fewer travel in the bound's arguments)
+    r3, out3 = _render(scenegen.Scene('nan3', sc2.meshes, sc.views * 3), 16)
+    assert r3.status().nonfinite == 3
+    assert all(np.array_equal(o['id'], out[0]['id']) for o in out3)
     keep = (ref[0]['id'] != 1)
     # pixels not showing triangle 1 are unchanged
     assert np.array_equal(out[0]['id'][keep], ref[0]['id'][keep])
