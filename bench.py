@@ -163,40 +163,68 @@ def display_leg(sc, r, stream, n):
     return out
 
 
-def bound_ablation(sc, args, stream, n):
-    """The HMD frame under each rolling bound of Sec. 4.2 (Zenon, Adaptive,
-    Hull, Quad): listed pairs, ray-triangle tests, sample test efficiency
-    (hits / tests, counted in a separate frame) and the mean frame time."""
+def _ablation_run(sc, args, stream, n, **kw):
+    """One bound setting on scene sc: listed pairs, candidates, ray-triangle
+    tests, sample test efficiency (hits / tests, counted in a separate
+    frame) and the mean frame time."""
     import torch
 
     from paper_1806_05385_amd import binding as B
     from paper_1806_05385_amd.render import Renderer
+    rr = Renderer(sc.meshes, sc.views, tile=args.tile, light=sc.light_dir, ambient=sc.ambient, **kw)
+    rr.frame(check=True, rgb32=False)
+    rr.flags = B.PR_FLAG_COUNT | B.PR_FLAG_PERSISTENT
+    rr._prepare()
+    rr.frame(check=True, rgb32=False)
+    st = rr.status()
+    rr.flags = B.PR_FLAG_PERSISTENT
+    rr._prepare()
+    for _ in range(3):
+        rr.frame(check=False, rgb32=False)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(n):
+        rr.bound()
+        rr.bin()
+        rr.raycast_shade(rgba8=True, rgb32=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    out = {'frame_ms': round(e0.elapsed_time(e1) / n, 4), 'pairs': int(st.pairs_total),
+           'candidates': int(st.pairs_required), 'tests': int(st.tests),
+           'ste': round(int(st.hits) / max(int(st.tests), 1), 4)}
+    del rr
+    return out
+
+
+def bound_ablation(sc, args, stream, n):
+    """The HMD frame under each rolling bound of Sec. 4.2 (Zenon, Adaptive,
+    Hull, Quad), and under each foveated per-tile test (Sec. 4.1: exact
+    display-space test, box only, Simple and Recursive support lines) on
+    the same frame and on its static form (no rolling, no motion)."""
+    import copy as _copy
+
+    import numpy as np
+
+    from paper_1806_05385_amd import binding as B
     out = {}
     for name, mode in (('zenon', B.PR_BOUND_ZENON), ('adaptive', B.PR_BOUND_ADAPTIVE), ('hull', B.PR_BOUND_HULL),
                        ('quad', B.PR_BOUND_QUAD)):
-        rr = Renderer(sc.meshes, sc.views, tile=args.tile, light=sc.light_dir, ambient=sc.ambient, bound=mode)
-        rr.frame(check=True, rgb32=False)
-        rr.flags = B.PR_FLAG_COUNT | B.PR_FLAG_PERSISTENT
-        rr._prepare()
-        rr.frame(check=True, rgb32=False)
-        st = rr.status()
-        rr.flags = B.PR_FLAG_PERSISTENT
-        rr._prepare()
-        for _ in range(3):
-            rr.frame(check=False, rgb32=False)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(n):
-            rr.bound()
-            rr.bin()
-            rr.raycast_shade(rgba8=True, rgb32=False)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        out[name] = {'frame_ms': round(e0.elapsed_time(e1) / n, 4), 'pairs': int(st.pairs_total),
-                     'candidates': int(st.pairs_required), 'tests': int(st.tests),
-                     'ste': round(int(st.hits) / max(int(st.tests), 1), 4)}
-        del rr
+        out[name] = _ablation_run(sc, args, stream, n, bound=mode)
+    static = _copy.copy(sc)
+    static.views = []
+    for v in sc.views:
+        vv = _copy.copy(v)
+        vv.roll_dir = (0.0, 0.0)
+        vv.pose1 = np.array(vv.pose0, copy=True)
+        static.views.append(vv)
+    static.meshes = [_copy.copy(m) for m in sc.meshes]
+    for m in static.meshes:
+        m.v1 = m.v0
+    fovs = (('exact', B.PR_FOV_EXACT), ('box', B.PR_FOV_QUAD), ('simple', B.PR_FOV_SIMPLE),
+            ('recursive', B.PR_FOV_RECURSIVE))
+    out['foveated'] = {name: _ablation_run(sc, args, stream, n, fov_bound=mode) for name, mode in fovs}
+    out['foveated_static'] = {name: _ablation_run(static, args, stream, n, fov_bound=mode) for name, mode in fovs}
     return out
 
 

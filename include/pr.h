@@ -177,6 +177,15 @@ typedef struct pr_light {
  * bin_capacity: (triangle, tile) candidate pairs a frame can hold (all
  *   views; each candidate of a triangle's tile rectangle takes one slot,
  *   and the tile lists hold the candidates that survive the tile test).
+ * fov_bound: how the binning tests a triangle against a tile of a foveated
+ *   view (an ablation of Sec. 4.1's foveated bounds; all conservative, same
+ *   images): PR_FOV_EXACT (default, 0) in display space, the tile's pixel
+ *   centres unfoveated to an exact box; PR_FOV_QUAD no spatial test, every
+ *   tile of the triangle's foveated bounding box; PR_FOV_SIMPLE /
+ *   PR_FOV_RECURSIVE in foveated space against lines supporting the
+ *   foveated triangle, normal to its display-space edges (Simple) or to
+ *   the chords between its edges' foveated end points (Recursive), their
+ *   offsets bounded from exact image boxes of pieces of the edges.
  * flags: PR_FLAG_COUNT makes pr_raycast count ray-triangle tests and hits
  * (sample test efficiency) into the status block: a test is one triangle at
  * one pixel the ray cast evaluates; PR_FLAG_PERSISTENT makes it order the
@@ -187,6 +196,7 @@ typedef struct pr_tuning {
     int32_t bin_capacity;
     int32_t flags;
     int32_t bound;
+    int32_t fov_bound;
 } pr_tuning;
 
 #define PR_FLAG_COUNT 1
@@ -196,6 +206,11 @@ typedef struct pr_tuning {
 #define PR_BOUND_ADAPTIVE 1
 #define PR_BOUND_HULL 2
 #define PR_BOUND_QUAD 3
+
+#define PR_FOV_EXACT 0
+#define PR_FOV_QUAD 1
+#define PR_FOV_SIMPLE 2
+#define PR_FOV_RECURSIVE 3
 
 /* Device-side conditions of the last frame (all views). */
 typedef struct pr_status {
@@ -437,12 +452,16 @@ int pr_debug_tile_lists(const pr_mesh *meshes, int nm, const pr_view *views, int
  *   rect = {x0, y0, x1, y1}; returns 0 if culled, 1 otherwise.
  * pr_host_tile_test: the quadrant mask binning gives the pair (triangle f,
  *   tile (tx, ty)) (as in pr_debug_tile_lists); 0 if the pair is rejected
- *   (or the triangle is culled). */
+ *   (or the triangle is culled).
+ * pr_host_tile_test_fov: the same under foveated bound fov (a PR_FOV_*
+ *   mode; -1 for another value). */
 int pr_host_time_interval(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, double *t);
 int pr_host_tile_rect(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, int32_t tile,
                       int32_t *rect);
 int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, int32_t tile,
                       int32_t tx, int32_t ty);
+int pr_host_tile_test_fov(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, int32_t fov,
+                          int32_t tile, int32_t tx, int32_t ty);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,7 @@ PR_BOUND_ZENON = 0
 PR_BOUND_ADAPTIVE = 1
 PR_BOUND_HULL = 2
 PR_BOUND_QUAD = 3
+PR_FOV_EXACT, PR_FOV_QUAD, PR_FOV_SIMPLE, PR_FOV_RECURSIVE = 0, 1, 2, 3
 PR_UNFOV_MIP = 0
 PR_UNFOV_FILTER = 1
 
@@ -57,7 +58,7 @@ class PrLight(ctypes.Structure):
 
 class PrTuning(ctypes.Structure):
     _fields_ = [('tile', ctypes.c_int32), ('bin_capacity', ctypes.c_int32), ('flags', ctypes.c_int32),
-                ('bound', ctypes.c_int32)]
+                ('bound', ctypes.c_int32), ('fov_bound', ctypes.c_int32)]
 
 
 class PrDisplay(ctypes.Structure):
@@ -109,6 +110,8 @@ SIGNATURES = {
     'pr_batch_destroy': (ctypes.c_int, [ctypes.c_void_p]),
     'pr_host_time_interval': (ctypes.c_int, [_MP, ctypes.c_int32, _VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     'pr_host_tile_rect': (ctypes.c_int, [_MP, ctypes.c_int32, _VP, ctypes.c_int32, ctypes.c_int32, c_int32_p]),
+    'pr_host_tile_test_fov': (ctypes.c_int, [_MP, ctypes.c_int32, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.c_int32]),
     'pr_host_tile_test': (ctypes.c_int, [_MP, ctypes.c_int32, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int32]),
 }

@@ -38,6 +38,7 @@ struct Layout {
     ProfDev prof_host[PR_MAX_VIEWS];   // the views' tabulated profiles (used where prof_used)
     bool prof_used[PR_MAX_VIEWS];
     bool any_prof;                     // some view has one (the bound kernels' general form)
+    bool any_fov;                      // a foveated bound other than the exact one (the binning's general form)
 };
 
 // A view's tabulated profiles are usable: sample counts in range, samples
@@ -90,6 +91,7 @@ int check_args(const pr_mesh *meshes, int nm, const pr_view *views, int nv, cons
     if (tu->tile != 8 && tu->tile != 16 && tu->tile != 32) return PR_ERR_UNSUPPORTED;
     if (tu->bin_capacity < 1) return PR_ERR_INVALID;
     if (tu->bound < PR_BOUND_ZENON || tu->bound > PR_BOUND_QUAD) return PR_ERR_INVALID;
+    if (tu->fov_bound < PR_FOV_EXACT || tu->fov_bound > PR_FOV_RECURSIVE) return PR_ERR_INVALID;
     return PR_OK;
 }
 
@@ -125,6 +127,7 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
     if (rc) return rc;
     L.nv = nv;
     L.any_prof = false;
+    L.any_fov = false;
     int64_t tiles = 0, tri_blocks = 0, pix_blocks = 0, vtx_blocks = 0, rec4 = 0, tris = 0, gacc = 0;
     for (int v = 0; v < nv; ++v) {
         const pr_view &V = views[v];
@@ -143,6 +146,8 @@ int layout(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
         d.pix_block0 = (int32_t)pix_blocks;
         d.rolling = rolling(V) ? 1 : 0;
         d.bound = tu->bound;
+        d.fov_bound = tu->fov_bound;
+        L.any_fov = L.any_fov || tu->fov_bound != PR_FOV_EXACT;
         d.rec_w = d.rolling ? kRecRoll : kRecStatic;
         d.rec_off = rec4;
         d.tri_off = tris;
@@ -434,7 +439,8 @@ int pr_bin(const pr_mesh *meshes, int nm, const pr_view *views, int nv, const pr
                        at<int64_t>(ws, L.bpart), st, at<int32_t>(ws, L.bperm),
                        at<unsigned long long>(ws, L.part), L.nparts);
     if (L.total_tri_blocks > 0)
-        hipLaunchKernelGGL(k_bin, dim3(L.total_tri_blocks), dim3(kBinThreads), 0, s, T, at<TriBound>(ws, L.tb),
+        hipLaunchKernelGGL(L.any_fov ? k_bin<true> : k_bin<false>, dim3(L.total_tri_blocks), dim3(kBinThreads), 0, s,
+                           T, at<TriBound>(ws, L.tb),
                            at<TileInfo>(ws, L.tinfo), at<uint32_t>(ws, L.tcount), at<int64_t>(ws, L.boff),
                            at<int64_t>(ws, L.bpart), pairs_at(L, ws), L.cap, at<int32_t>(ws, L.bperm), st);
     int n = L.total_tiles + 1;
@@ -677,8 +683,9 @@ int pr_host_tile_rect(const pr_mesh *mesh, int32_t f, const pr_view *view, int32
     return 1;
 }
 
-int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, int32_t tile, int32_t tx,
-                      int32_t ty) {
+int pr_host_tile_test_fov(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, int32_t fov,
+                          int32_t tile, int32_t tx, int32_t ty) {
+    if (fov < PR_FOV_EXACT || fov > PR_FOV_RECURSIVE) return -1;
     if (!mesh || !view || f < 0 || f >= mesh->nt || tile < 1 || bound < 0 || bound > PR_BOUND_QUAD) return -1;
     if (view->profile && !profile_ok(*view->profile)) return -1;
     prg::Geom g;
@@ -697,7 +704,12 @@ int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32
     double w[4];
     if (kind == prg::kWindow) { w[0] = win[0]; w[1] = win[1]; w[2] = w[3] = 0.0; }
     else for (int k = 0; k < 4; ++k) w[k] = box[k];
-    return prg::tile_mask(g, Ps, Pe, kind, w, tile, tx, ty, bound);
+    return prg::tile_mask(g, Ps, Pe, kind, w, tile, tx, ty, bound, fov);
+}
+
+int pr_host_tile_test(const pr_mesh *mesh, int32_t f, const pr_view *view, int32_t bound, int32_t tile, int32_t tx,
+                      int32_t ty) {
+    return pr_host_tile_test_fov(mesh, f, view, bound, PR_FOV_EXACT, tile, tx, ty);
 }
 
 }  // extern "C"

@@ -464,6 +464,15 @@ enum { kCulled = 0, kWindow = 1, kClipped = 2 };
 // edges of the two end triangles (any axis separates validly).
 enum { kBoundZenon = 0, kBoundAdaptive = 1, kBoundHull = 2, kBoundQuad = 3 };
 
+// Foveated per-tile tests (an ablation of Sec. 4.1's bounds): kFovExact
+// tests in display space against the tile's unfoveated box (the default);
+// kFovQuad keeps every tile of the triangle's foveated box (no spatial
+// test); kFovSimple / kFovRecursive test in foveated space against support
+// lines of the foveated triangle whose normals are those of the display-
+// space edges (Simple) or of the chords between the edges' foveated end
+// points (Recursive).
+enum { kFovExact = 0, kFovQuad = 1, kFovSimple = 2, kFovRecursive = 3 };
+
 // The time window of a triangle seen through a lens (kWindow or kCulled).
 PRG int lens_window(const Geom &g, const double Ps[3][3], const double Pe[3][3], double win[2]) {
     // Through a lens the scan is no straight line of the projected
@@ -875,6 +884,153 @@ PRG void sat_build(const Geom &g, const double Ps[3][3], const double Pe[3][3], 
     }
 }
 
+// Panel point -> foveated point (the inverse of unfoveate_pt), and
+// undistorted point -> panel point (the lens applied; the identity without
+// one).
+template <bool PROF = true>
+PRG void foveate_pt(const Geom &g, double x0, double x1, double &y0, double &y1) {
+    if (!PROF || g.nc < 2) radial_map(g, g.inv_alpha, x0, x1, y0, y1);
+    else table_map(g, g.tc, g.nc, false, x0, x1, y0, y1);
+}
+template <bool PROF = true>
+PRG void distort_pt(const Geom &g, double u0, double u1, double &x0, double &x1) {
+    if (!PROF || g.nl < 2) { x0 = u0; x1 = u1; return; }
+    table_map(g, g.tl, g.nl, false, u0, u1, x0, x1);
+}
+
+// Pieces per segment of the foveated record's boundary sampling.
+constexpr int kFovPieces = 8;
+
+// The per-tile test record in foveated space (kFovSimple, kFovRecursive).
+// The space-time triangle's display points over its window lie in the hull
+// H of its six projected window-end vertices; the foveated image of H is
+// bounded by the image of H's boundary, whose edges are among the 15
+// segments joining the six points.  Each segment is cut into kFovPieces
+// pieces whose boxes are carried to foveated space as exact image boxes
+// (lens, then foveation): every corner of those boxes together bounds the
+// image, so the box of the corners and, for any direction, the range of
+// the corners' projections are conservative.  The directions: the normals
+// of the six window-end edges (Simple) or of the chords between their
+// foveated end points (Recursive).  A triangle the near plane cuts keeps
+// the foveated box of its display box alone.
+template <bool PROF = true>
+PRG void sat_build_fov(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double w[4],
+                       SatRec &R, int fov) {
+    R.kind = kind;
+    R.pad = 0;
+    for (int a = 0; a < 6; ++a) { R.ax[a][0] = R.ax[a][1] = 0.0f; R.ax[a][2] = -1.0f; R.ax[a][3] = 1.0f; }
+    if (kind != kWindow) {
+        double pb[4], fb[4];
+        box_distort<PROF>(g, w, pb);
+        box_foveate<PROF>(g, pb, fb);
+        R.ext[0] = f32_clamp(f32_down(fb[0])); R.ext[1] = f32_clamp(f32_up(fb[1]));
+        R.ext[2] = f32_clamp(f32_down(fb[2])); R.ext[3] = f32_clamp(f32_up(fb[3]));
+        R.win[0] = 0.0f; R.win[1] = 1.0f;
+        return;
+    }
+    const double w0 = w[0], w1 = w[1];
+    R.win[0] = f32_down(w0);
+    R.win[1] = f32_up(w1);
+    double q[6][2];
+    for (int k = 0; k < 3; ++k)
+        for (int e = 0; e < 2; ++e) {
+            const double t = e ? w1 : w0;
+            double P[3];
+            for (int r = 0; r < 3; ++r) P[r] = (1.0 - t) * Ps[k][r] + t * Pe[k][r];
+            const double iz = 1.0 / P[2];
+            q[3 * e + k][0] = g.fx * P[0] * iz + g.cx;
+            q[3 * e + k][1] = g.fy * P[1] * iz + g.cy;
+        }
+    // the six axes
+    double n[6][2];
+    for (int a = 0; a < 6; ++a) {
+        const int e = a / 3, k = a % 3;
+        const double *p = q[3 * e + k], *r = q[3 * e + (k + 1) % 3];
+        if (fov == kFovRecursive) {
+            double u0, u1, v0, v1, fp0, fp1, fr0, fr1;
+            distort_pt<PROF>(g, p[0], p[1], u0, u1);
+            foveate_pt<PROF>(g, u0, u1, fp0, fp1);
+            distort_pt<PROF>(g, r[0], r[1], v0, v1);
+            foveate_pt<PROF>(g, v0, v1, fr0, fr1);
+            n[a][0] = -(fr1 - fp1);
+            n[a][1] = fr0 - fp0;
+        } else {
+            n[a][0] = -(r[1] - p[1]);
+            n[a][1] = r[0] - p[0];
+        }
+        const double l = fabs(n[a][0]) + fabs(n[a][1]);
+        if (!(l > 0.0)) { n[a][0] = 1.0; n[a][1] = 0.0; }   // a degenerate edge: any direction bounds
+        else { n[a][0] /= l; n[a][1] /= l; }
+        n[a][0] = (double)(float)n[a][0];   // the stored (FP32) direction
+        n[a][1] = (double)(float)n[a][1];
+    }
+    double ext[4] = {1e300, -1e300, 1e300, -1e300}, lo[6], hi[6];
+    for (int a = 0; a < 6; ++a) { lo[a] = 1e300; hi[a] = -1e300; }
+    for (int i = 0; i < 6; ++i)
+        for (int j = i + 1; j < 6; ++j)
+            for (int c = 0; c < kFovPieces; ++c) {
+                const double s0 = (double)c / kFovPieces, s1 = (double)(c + 1) / kFovPieces;
+                const double x0 = q[i][0] + s0 * (q[j][0] - q[i][0]), x1 = q[i][0] + s1 * (q[j][0] - q[i][0]);
+                const double y0 = q[i][1] + s0 * (q[j][1] - q[i][1]), y1 = q[i][1] + s1 * (q[j][1] - q[i][1]);
+                const double b[4] = {dmin(x0, x1), dmax(x0, x1), dmin(y0, y1), dmax(y0, y1)};
+                double pb[4], fb[4];
+                box_distort<PROF>(g, b, pb);
+                box_foveate<PROF>(g, pb, fb);
+                ext[0] = dmin(ext[0], fb[0]); ext[1] = dmax(ext[1], fb[1]);
+                ext[2] = dmin(ext[2], fb[2]); ext[3] = dmax(ext[3], fb[3]);
+                for (int a = 0; a < 6; ++a) {
+                    const double cx0 = n[a][0] * fb[0], cx1 = n[a][0] * fb[1];
+                    const double cy0 = n[a][1] * fb[2], cy1 = n[a][1] * fb[3];
+                    lo[a] = dmin(lo[a], dmin(cx0, cx1) + dmin(cy0, cy1));
+                    hi[a] = dmax(hi[a], dmax(cx0, cx1) + dmax(cy0, cy1));
+                }
+            }
+    double big = 1.0;
+    for (int k = 0; k < 4; ++k) big = dmax(big, fabs(ext[k]));
+    const double mxy = 1e-12 * big;
+    R.ext[0] = f32_clamp(f32_down(ext[0] - mxy)); R.ext[1] = f32_clamp(f32_up(ext[1] + mxy));
+    R.ext[2] = f32_clamp(f32_down(ext[2] - mxy)); R.ext[3] = f32_clamp(f32_up(ext[3] + mxy));
+    for (int a = 0; a < 6; ++a) {
+        const double m = 1e-12 * (fabs(n[a][0]) + fabs(n[a][1])) * big;
+        R.ax[a][0] = (float)n[a][0];
+        R.ax[a][1] = (float)n[a][1];
+        R.ax[a][2] = f32_clamp(f32_down(lo[a] - m));
+        R.ax[a][3] = f32_clamp(f32_up(hi[a] + m));
+    }
+}
+
+// Pixel-centre box in foveated NDC of pixels [i0, i1] x [j0, j1] (clipped to
+// the image; false if empty), widened by kSlackNdc.
+PRG bool region_foveated(const Geom &g, int i0, int i1, int j0, int j1, double box[4]) {
+    if (i1 > g.W - 1) i1 = g.W - 1;
+    if (j1 > g.H - 1) j1 = g.H - 1;
+    if (i0 > i1 || j0 > j1) return false;
+    box[0] = 2.0 * (i0 + 0.5) / g.W - 1.0;
+    box[1] = 2.0 * (i1 + 0.5) / g.W - 1.0;
+    box[2] = 1.0 - 2.0 * (j1 + 0.5) / g.H;
+    box[3] = 1.0 - 2.0 * (j0 + 0.5) / g.H;
+    for (int k = 0; k < 4; ++k) box[k] += ((k & 1) ? 1.0 : -1.0) * kSlackNdc * (1.0 + fabs(box[k]));
+    return true;
+}
+
+// A tile's foveated box and its quadrants' (outward-rounded FP32; qvalid:
+// the quadrants inside the image), for the foveated-space tests.
+PRG void tile_foveated(const Geom &g, int tile, int tx, int ty, float tb[4], float qb[4][4], int &qvalid) {
+    double b[4];
+    region_foveated(g, tx * tile, tx * tile + tile - 1, ty * tile, ty * tile + tile - 1, b);
+    tb[0] = f32_down(b[0]); tb[1] = f32_up(b[1]); tb[2] = f32_down(b[2]); tb[3] = f32_up(b[3]);
+    qvalid = 0;
+    const int h = tile / 2;
+    for (int k = 0; k < 4; ++k) {
+        const int i0 = tx * tile + (k & 1) * h, j0 = ty * tile + (k >> 1) * h;
+        double c[4];
+        const bool ok = region_foveated(g, i0, i0 + h - 1, j0, j0 + h - 1, c);
+        qvalid |= ok ? 1 << k : 0;
+        qb[k][0] = ok ? f32_down(c[0]) : 0.0f; qb[k][1] = ok ? f32_up(c[1]) : 0.0f;
+        qb[k][2] = ok ? f32_down(c[2]) : 0.0f; qb[k][3] = ok ? f32_up(c[3]) : 0.0f;
+    }
+}
+
 PRG bool fbox_meets(const float a[4], const float b[4]) {
     return !(a[1] < b[0] || a[0] > b[1] || a[3] < b[2] || a[2] > b[3]);
 }
@@ -910,7 +1066,7 @@ PRG bool split_quads(int tile) { return tile >= 16; }
 // and window built and rounded as the device builds them: a split tile's
 // box is the union of its quadrants' boxes.
 PRG int tile_mask(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double w[4],
-                  int tile, int tx, int ty, int mode = kBoundZenon) {
+                  int tile, int tx, int ty, int mode = kBoundZenon, int fov = kFovExact) {
     double tb[4], tw[2], qb[4][4];
     int qvalid = 0;
     if (!split_quads(tile)) {
@@ -941,6 +1097,19 @@ PRG int tile_mask(const Geom &g, const double Ps[3][3], const double Pe[3][3], i
     }
     SatRec R;
     sat_build(g, Ps, Pe, kind, w, R, mode);
+    if (fov == kFovQuad) {   // the time window alone
+        if (R.win[1] < ftw[0] || R.win[0] > ftw[1]) return 0;
+        return split_quads(tile) ? qvalid : 0xF;
+    }
+    if (fov == kFovSimple || fov == kFovRecursive) {
+        SatRec F;
+        sat_build_fov(g, Ps, Pe, kind, w, F, fov);
+        F.win[0] = R.win[0];
+        F.win[1] = R.win[1];
+        int fq;
+        tile_foveated(g, tile, tx, ty, ftb, fqb, fq);
+        return sat_mask(F, ftb, ftw, split_quads(tile) ? fqb : nullptr, fq);
+    }
     return sat_mask(R, ftb, ftw, split_quads(tile) ? fqb : nullptr, qvalid);
 }
 

@@ -93,7 +93,7 @@ struct ViewDev {
     int64_t rec_off;       // float4 offset of the view's first record
     int64_t tri_off;       // TriBound index of the view's first triangle
     int32_t vtx_block0;    // first 256-vertex block (backward vertex pass)
-    int32_t pad2;
+    int32_t fov_bound;     // foveated per-tile test (prg::kFov*; pr_tuning.fov_bound)
     int64_t gacc_off;      // float offset of the view's backward accumulators [2][nv][3]
     float light0[3];       // R0 * light direction (written by pr_shade / pr_backward)
     float light1[3];       // R1 * light direction

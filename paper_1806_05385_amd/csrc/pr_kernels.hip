@@ -637,6 +637,9 @@ constexpr int kBinTris = 256;
 // first kBinTris, the candidates are shared by all
 constexpr int kBinThreads = 512;
 
+// FOV: some view of the call uses a foveated per-tile test other than the
+// exact one (its general form; false keeps that code out).
+template <bool FOV>
 __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewTable *__restrict__ T, const TriBound *__restrict__ tb,
                                              const TileInfo *__restrict__ ti, uint32_t *__restrict__ tcount,
                                              const int64_t *__restrict__ boff, const int64_t *__restrict__ bpart,
@@ -680,7 +683,10 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewTable *__restrict
                     int32_t idx[3];
                     prg::load_tri(vd.mesh.v0, vd.mesh.v1, vd.mesh.tri, vd.mesh.nv, f, g, Ps, Pe, idx);
                     prg::SatRec R;
-                    prg::sat_build(g, Ps, Pe, b.kind, b.w, R, vd.bound);
+                    if (FOV && (vd.fov_bound == prg::kFovSimple || vd.fov_bound == prg::kFovRecursive))
+                        prg::sat_build_fov(g, Ps, Pe, b.kind, b.w, R, vd.fov_bound);
+                    else
+                        prg::sat_build(g, Ps, Pe, b.kind, b.w, R, vd.bound);
                     uint32_t rw[32];   // the record's words (memcpy: no type punning)
                     static_assert(sizeof(R) == sizeof(rw), "SatRec is 32 words");
                     __builtin_memcpy(rw, &R, sizeof(rw));
@@ -730,7 +736,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewTable *__restrict
                     float4 tt[6];
 #pragma unroll
                     for (int i = 0; i < 6; ++i) tt[i] = nt[i];
-                    const int cq = cur.q;
+                    const int cq = cur.q, cgt = cur.gt;
                     if (k + 1 < myn) {
                         bin_step(cur, vd, s_rect, s_pref);
 #pragma unroll
@@ -746,7 +752,17 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewTable *__restrict
                     // TileInfo words: box 0..3, tw 4..5, qvalid 6, pad 7, qb 8..23
                     const float tbx[4] = {tt[0].x, tt[0].y, tt[0].z, tt[0].w}, tw[2] = {tt[1].x, tt[1].y};
                     int mask;
-                    if (split) {
+                    if (FOV && vd.fov_bound == prg::kFovQuad) {
+                        // the time window alone
+                        mask = (R.win[1] < tw[0] || R.win[0] > tw[1]) ? 0 : (split ? __float_as_int(tt[1].z) : 0xF);
+                    } else if (FOV && vd.fov_bound != prg::kFovExact) {
+                        // foveated space: the tile's own pixel-centre boxes
+                        const int lt = cgt - vd.tile_base;
+                        float fb[4], fqb[4][4];
+                        int fq;
+                        prg::tile_foveated(g, vd.tile, lt % vd.tiles_x, lt / vd.tiles_x, fb, fqb, fq);
+                        mask = prg::sat_mask(R, fb, tw, split ? fqb : nullptr, fq);
+                    } else if (split) {
                         const float qb[4][4] = {{tt[2].x, tt[2].y, tt[2].z, tt[2].w}, {tt[3].x, tt[3].y, tt[3].z, tt[3].w},
                                                 {tt[4].x, tt[4].y, tt[4].z, tt[4].w}, {tt[5].x, tt[5].y, tt[5].z, tt[5].w}};
                         mask = prg::sat_mask(R, tbx, tw, qb, __float_as_int(tt[1].z));

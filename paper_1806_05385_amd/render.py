@@ -51,9 +51,10 @@ class Renderer:
 
     def __init__(self, meshes, views, tile: int = 16, bin_capacity: int = 0, light=None, ambient: float = 0.1,
                  flags: int = B.PR_FLAG_PERSISTENT, device='cuda', bound: int = B.PR_BOUND_ZENON,
-                 specular: float = 0.0, shininess: float = 1.0):
+                 specular: float = 0.0, shininess: float = 1.0, fov_bound: int = B.PR_FOV_EXACT):
         self.L = B.lib()
         self.bound_mode = int(bound)
+        self.fov_bound = int(fov_bound)
         self.device = torch.device(device)
         self.meshes = [m if isinstance(m, DeviceMesh) else DeviceMesh.from_numpy(m, device) for m in meshes]
         self.views = [copy.copy(v) for v in views]
@@ -77,7 +78,7 @@ class Renderer:
         nm = len(self.meshes)
         self.c_meshes = (B.PrMesh * nm)(*[m.pr() for m in self.meshes])
         self.c_views = B.make_views(self.views)
-        self.tuning = B.PrTuning(self.tile, self.cap, self.flags, self.bound_mode)
+        self.tuning = B.PrTuning(self.tile, self.cap, self.flags, self.bound_mode, self.fov_bound)
         size = ctypes.c_size_t(0)
         B.check('pr_workspace_size', self.L.pr_workspace_size(self.c_meshes, nm, self.c_views, len(self.views),
                                                               ctypes.byref(self.tuning), ctypes.byref(size)))

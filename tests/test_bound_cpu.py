@@ -20,7 +20,7 @@ import scenegen
 from paper_1806_05385_amd import binding as B
 
 
-def _check_hits(scene, tile, max_pix=None, seed=0, bound=0):
+def _check_hits(scene, tile, max_pix=None, seed=0, bound=0, fov=0):
     L = B.lib()
     mesh, view = scene.meshes[0], scene.views[0]
     W, H = view.width, view.height
@@ -47,7 +47,7 @@ def _check_hits(scene, tile, max_pix=None, seed=0, bound=0):
         t = oracle.pixel_setup(view, p)[2]
         ok = kind in (1, 2) and r is not None and r[0] <= tx <= r[2] and r[1] <= ty <= r[3]
         ok = ok and (kind == 2 or w[0] <= t <= w[1])
-        mask = L.pr_host_tile_test(ctypes.byref(hm), f, ctypes.byref(pv), bound, tile, tx, ty)
+        mask = L.pr_host_tile_test_fov(ctypes.byref(hm), f, ctypes.byref(pv), bound, fov, tile, tx, ty)
         if tile >= 16:   # the pixel's quadrant of its tile must be in the pair's mask
             h = tile // 2
             quad = int(i % tile >= h) + 2 * int(j % tile >= h)
@@ -99,6 +99,49 @@ def test_tabulated_foveation_and_lens(prof, bound):
     n, missed, _ = _check_hits(sc, 8 if 'tile8' in prof else 16, bound=bound)
     assert n > 1000
     assert not missed, missed[:5]
+
+
+@pytest.mark.parametrize('fov', [B.PR_FOV_QUAD, B.PR_FOV_SIMPLE, B.PR_FOV_RECURSIVE])
+@pytest.mark.parametrize('case', ['static', 'rolling', 'table_lens', 'tile8'])
+def test_foveated_bound_modes_are_conservative(fov, case):
+    """The foveated per-tile tests (Sec. 4.1 ablation): every oracle hit
+    survives the box-only test and the Simple / Recursive support-line tests
+    in foveated space, static and rolling, power law and table + lens."""
+    roll = (0.0, 0.0) if case == 'static' else (1.0, 0.0)
+    pc = scenegen.foveal_table(33, 3.0) if case == 'table_lens' else None
+    pl = scenegen.barrel_table(33, 0.22) if case == 'table_lens' else None
+    sc = scenegen.make_moving_soup(seed=26, n_tris=300, width=80, height=72, alpha=2.0, roll=roll,
+                                   yaw_deg_s=3000.0, obj_speed=40.0, fovea=(0.12, -0.08), side=(0.05, 0.6),
+                                   profile_c=pc, profile_l=pl)
+    n, missed, _ = _check_hits(sc, 8 if case == 'tile8' else 16, fov=fov)
+    assert n > 1000
+    assert not missed, missed[:5]
+
+
+def test_foveated_bound_modes_keep_fewer_pairs_than_the_box():
+    """On a static foveated soup every spatial test rejects pairs the box
+    keeps; the Recursive lines (normal to the foveated chords) keep no more
+    than the Simple ones (normal to the display-space edges)."""
+    L = B.lib()
+    sc = scenegen.make_moving_soup(seed=27, n_tris=200, width=128, height=128, alpha=2.0, roll=(0.0, 0.0),
+                                   side=(0.05, 0.4), fovea=(0.1, 0.05))
+    mesh, view = sc.meshes[0], sc.views[0]
+    hm = B.host_mesh(mesh.v0, mesh.v1, mesh.tri)
+    pv = B.make_view(view)
+    rect = (ctypes.c_int32 * 4)()
+    kept = {m: 0 for m in range(4)}
+    for f in range(mesh.nt):
+        if L.pr_host_tile_rect(ctypes.byref(hm), f, ctypes.byref(pv), 0, 16, rect) != 1:
+            continue
+        for ty in range(rect[1], rect[3] + 1):
+            for tx in range(rect[0], rect[2] + 1):
+                for m in range(4):
+                    kept[m] += bin(L.pr_host_tile_test_fov(ctypes.byref(hm), f, ctypes.byref(pv), 0, m, 16, tx,
+                                                           ty)).count('1')
+    print(kept)
+    assert max(kept[B.PR_FOV_EXACT], kept[B.PR_FOV_SIMPLE], kept[B.PR_FOV_RECURSIVE]) < kept[B.PR_FOV_QUAD]
+    assert kept[B.PR_FOV_RECURSIVE] <= kept[B.PR_FOV_SIMPLE]
+    assert L.pr_host_tile_test_fov(ctypes.byref(hm), 0, ctypes.byref(pv), 0, 4, 16, 0, 0) == -1
 
 
 def test_tabulated_boxes_match_the_power_law():

@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 import scenegen
+from paper_1806_05385_amd import binding as B
 from parity import assert_parity, compare
 
 pytestmark = pytest.mark.gpu
@@ -313,3 +314,28 @@ def test_shading_matches_oracle():
     same = (out[0]['id'].ravel() == oid) & hit
     own8 = out[0]['rgba8'].reshape(-1, 4).astype(int)
     assert np.abs(own8[same, :3] - ref8[same]).max() <= 1
+
+
+@pytest.mark.parametrize('fov', [B.PR_FOV_QUAD, B.PR_FOV_SIMPLE, B.PR_FOV_RECURSIVE])
+@pytest.mark.parametrize('case', ['rolling', 'static_table_lens'])
+def test_foveated_bound_modes_give_the_same_image(fov, case):
+    """The foveated per-tile tests (box only, Simple and Recursive support
+    lines in foveated space) change what is listed and tested, never the
+    image: ids and depths bitwise equal to the default display-space test,
+    and the box alone lists the most pairs."""
+    if case == 'rolling':
+        sc = scenegen.make_moving_soup(seed=61, n_tris=1500, width=203, height=171, alpha=2.0, roll=(1.0, 0.0),
+                                       yaw_deg_s=2000.0, obj_speed=20.0, fovea=(0.1, -0.15), side=(0.03, 0.5))
+    else:
+        sc = scenegen.make_moving_soup(seed=62, n_tris=1500, width=190, height=160, alpha=2.0, roll=(0.0, 0.0),
+                                       yaw_deg_s=0.0, obj_speed=0.0, fovea=(-0.05, 0.1), side=(0.03, 0.5),
+                                       profile_c=scenegen.foveal_table(33, 3.0),
+                                       profile_l=scenegen.barrel_table(33, 0.2))
+    r0, ref = _render(sc, 16)
+    r1, out = _render(sc, 16, fov_bound=fov)
+    for a, b in zip(ref, out):
+        assert np.array_equal(a['id'], b['id'])
+        assert np.array_equal(a['depth'], b['depth'])
+    assert (ref[0]['id'] >= 0).sum() > 5000
+    if fov == B.PR_FOV_QUAD:
+        assert r1.status().pairs_total > r0.status().pairs_total
