@@ -190,7 +190,7 @@ typedef struct pr_light {
  * (sample test efficiency) into the status block: a test is one triangle at
  * one pixel the ray cast evaluates; PR_FLAG_PERSISTENT makes it order the
  * tiles longest list first and run one resident grid that walks that order
- * with a fixed stride. */
+ * in rounds, a fixed set of items per block. */
 typedef struct pr_tuning {
     int32_t tile;
     int32_t bin_capacity;
