@@ -898,21 +898,21 @@ PRG void distort_pt(const Geom &g, double u0, double u1, double &x0, double &x1)
     table_map(g, g.tl, g.nl, false, u0, u1, x0, x1);
 }
 
-// Pieces per segment of the foveated record's boundary sampling.
+// Pieces per hull edge of the foveated record's boundary sampling.
 constexpr int kFovPieces = 8;
 
 // The per-tile test record in foveated space (kFovSimple, kFovRecursive).
 // The space-time triangle's display points over its window lie in the hull
 // H of its six projected window-end vertices; the foveated image of H is
-// bounded by the image of H's boundary, whose edges are among the 15
-// segments joining the six points.  Each segment is cut into kFovPieces
-// pieces whose boxes are carried to foveated space as exact image boxes
-// (lens, then foveation): every corner of those boxes together bounds the
-// image, so the box of the corners and, for any direction, the range of
-// the corners' projections are conservative.  The directions: the normals
-// of the six window-end edges (Simple) or of the chords between their
-// foveated end points (Recursive).  A triangle the near plane cuts keeps
-// the foveated box of its display box alone.
+// bounded by the image of H's boundary.  Each hull edge is cut into
+// kFovPieces pieces whose boxes (padded by 1e-12 of the coordinates' scale,
+// which covers the hull's rounding) are carried to foveated space as exact
+// image boxes (lens, then foveation): every corner of those boxes together
+// bounds the image, so the box of the corners and, for any direction, the
+// range of the corners' projections are conservative.  The directions: the
+// normals of the six window-end edges (Simple) or of the chords between
+// their foveated end points (Recursive).  A triangle the near plane cuts
+// keeps the foveated box of its display box alone.
 template <bool PROF = true>
 PRG void sat_build_fov(const Geom &g, const double Ps[3][3], const double Pe[3][3], int kind, const double w[4],
                        SatRec &R, int fov) {
@@ -964,27 +964,52 @@ PRG void sat_build_fov(const Geom &g, const double Ps[3][3], const double Pe[3][
         n[a][0] = (double)(float)n[a][0];   // the stored (FP32) direction
         n[a][1] = (double)(float)n[a][1];
     }
+    // the hull of the six points (monotone chain over the points sorted by
+    // x, then y; collinear points dropped): h[0..m)
+    int o[6] = {0, 1, 2, 3, 4, 5};
+    for (int i = 1; i < 6; ++i)
+        for (int j = i; j > 0 && (q[o[j]][0] < q[o[j - 1]][0] ||
+                                  (q[o[j]][0] == q[o[j - 1]][0] && q[o[j]][1] < q[o[j - 1]][1])); --j) {
+            const int tmp = o[j]; o[j] = o[j - 1]; o[j - 1] = tmp;
+        }
+    auto cross = [&](int a, int b, int c) {
+        return (q[b][0] - q[a][0]) * (q[c][1] - q[a][1]) - (q[b][1] - q[a][1]) * (q[c][0] - q[a][0]);
+    };
+    int h[12], m = 0;
+    for (int i = 0; i < 6; ++i) {   // lower hull
+        while (m >= 2 && cross(h[m - 2], h[m - 1], o[i]) <= 0.0) --m;
+        h[m++] = o[i];
+    }
+    for (int i = 4, m0 = m + 1; i >= 0; --i) {   // upper hull
+        while (m >= m0 && cross(h[m - 2], h[m - 1], o[i]) <= 0.0) --m;
+        h[m++] = o[i];
+    }
+    if (m > 1) --m;   // the last point repeats the first
+    double scale = 1.0;
+    for (int i = 0; i < 6; ++i) scale = dmax(scale, dmax(fabs(q[i][0]), fabs(q[i][1])));
+    const double pad = 1e-12 * scale;
     double ext[4] = {1e300, -1e300, 1e300, -1e300}, lo[6], hi[6];
     for (int a = 0; a < 6; ++a) { lo[a] = 1e300; hi[a] = -1e300; }
-    for (int i = 0; i < 6; ++i)
-        for (int j = i + 1; j < 6; ++j)
-            for (int c = 0; c < kFovPieces; ++c) {
-                const double s0 = (double)c / kFovPieces, s1 = (double)(c + 1) / kFovPieces;
-                const double x0 = q[i][0] + s0 * (q[j][0] - q[i][0]), x1 = q[i][0] + s1 * (q[j][0] - q[i][0]);
-                const double y0 = q[i][1] + s0 * (q[j][1] - q[i][1]), y1 = q[i][1] + s1 * (q[j][1] - q[i][1]);
-                const double b[4] = {dmin(x0, x1), dmax(x0, x1), dmin(y0, y1), dmax(y0, y1)};
-                double pb[4], fb[4];
-                box_distort<PROF>(g, b, pb);
-                box_foveate<PROF>(g, pb, fb);
-                ext[0] = dmin(ext[0], fb[0]); ext[1] = dmax(ext[1], fb[1]);
-                ext[2] = dmin(ext[2], fb[2]); ext[3] = dmax(ext[3], fb[3]);
-                for (int a = 0; a < 6; ++a) {
-                    const double cx0 = n[a][0] * fb[0], cx1 = n[a][0] * fb[1];
-                    const double cy0 = n[a][1] * fb[2], cy1 = n[a][1] * fb[3];
-                    lo[a] = dmin(lo[a], dmin(cx0, cx1) + dmin(cy0, cy1));
-                    hi[a] = dmax(hi[a], dmax(cx0, cx1) + dmax(cy0, cy1));
-                }
+    for (int i = 0; i < m; ++i) {
+        const double *P0 = q[h[i]], *P1 = q[h[(i + 1) % m]];
+        for (int c = 0; c < kFovPieces; ++c) {
+            const double s0 = (double)c / kFovPieces, s1 = (double)(c + 1) / kFovPieces;
+            const double x0 = P0[0] + s0 * (P1[0] - P0[0]), x1 = P0[0] + s1 * (P1[0] - P0[0]);
+            const double y0 = P0[1] + s0 * (P1[1] - P0[1]), y1 = P0[1] + s1 * (P1[1] - P0[1]);
+            const double b[4] = {dmin(x0, x1) - pad, dmax(x0, x1) + pad, dmin(y0, y1) - pad, dmax(y0, y1) + pad};
+            double pb[4], fb[4];
+            box_distort<PROF>(g, b, pb);
+            box_foveate<PROF>(g, pb, fb);
+            ext[0] = dmin(ext[0], fb[0]); ext[1] = dmax(ext[1], fb[1]);
+            ext[2] = dmin(ext[2], fb[2]); ext[3] = dmax(ext[3], fb[3]);
+            for (int a = 0; a < 6; ++a) {
+                const double cx0 = n[a][0] * fb[0], cx1 = n[a][0] * fb[1];
+                const double cy0 = n[a][1] * fb[2], cy1 = n[a][1] * fb[3];
+                lo[a] = dmin(lo[a], dmin(cx0, cx1) + dmin(cy0, cy1));
+                hi[a] = dmax(hi[a], dmax(cx0, cx1) + dmax(cy0, cy1));
             }
+        }
+    }
     double big = 1.0;
     for (int k = 0; k < 4; ++k) big = dmax(big, fabs(ext[k]));
     const double mxy = 1e-12 * big;
