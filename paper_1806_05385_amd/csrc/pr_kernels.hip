@@ -1130,9 +1130,21 @@ __device__ __forceinline__ float specular_at(const pr_light &light, const float 
 
 // Rolling colour of triangle id (0 <= id < nt) at a pixel whose time and
 // ray pixel_setup gave as (t, rx, ry): Lambert plus the rolling highlight.
+// The light direction in the camera frame at the view's start and end.
+__device__ __forceinline__ void view_light(const ViewDev &vd, const pr_light &light, float l0[3], float l1[3]) {
+    for (int r = 0; r < 3; ++r) {
+        l0[r] = vd.R0f[3 * r] * light.dir_world[0] + vd.R0f[3 * r + 1] * light.dir_world[1] +
+                vd.R0f[3 * r + 2] * light.dir_world[2];
+        l1[r] = vd.R1f[3 * r] * light.dir_world[0] + vd.R1f[3 * r + 1] * light.dir_world[1] +
+                vd.R1f[3 * r + 2] * light.dir_world[2];
+    }
+}
+
+// l0, l1: view_light's directions (computed once per view by the caller).
 __device__ __forceinline__ void shade_pixel_at(const ViewDev &vd, const float4 *__restrict__ rec,
-                                               const float *__restrict__ alb, const pr_light &light, float t,
-                                               float rx, float ry, int id, float c[3]) {
+                                               const float *__restrict__ alb, const pr_light &light,
+                                               const float l0[3], const float l1[3], float t, float rx, float ry,
+                                               int id, float c[3]) {
     const float ambient = light.ambient;
     // gathers first (vertex indices, then all nine albedo values), so their
     // latencies overlap each other and the arithmetic below
@@ -1150,19 +1162,13 @@ __device__ __forceinline__ void shade_pixel_at(const ViewDev &vd, const float4 *
     float sg = (N[0] * rx + N[1] * ry + N[2]) > 0.0f ? -inn : inn;
     // light direction in camera space at the pixel's time
     float L[3];
-    for (int r = 0; r < 3; ++r) {
-        const float l0 = vd.R0f[3 * r] * light.dir_world[0] + vd.R0f[3 * r + 1] * light.dir_world[1] +
-                         vd.R0f[3 * r + 2] * light.dir_world[2];
-        const float l1 = vd.R1f[3 * r] * light.dir_world[0] + vd.R1f[3 * r + 1] * light.dir_world[1] +
-                         vd.R1f[3 * r + 2] * light.dir_world[2];
-        L[r] = fmaf(t, l1 - l0, l0);
-    }
+    for (int r = 0; r < 3; ++r) L[r] = fmaf(t, l1[r] - l0[r], l0[r]);
     float inl = rsqrtf(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
     float ndl = sg * inl * (N[0] * L[0] + N[1] * L[1] + N[2] * L[2]);
     float s = ambient + (1.0f - ambient) * fmaxf(ndl, 0.0f);
     const float nu[3] = {sg * N[0], sg * N[1], sg * N[2]}, lu[3] = {inl * L[0], inl * L[1], inl * L[2]};
     const float sp = specular_at(light, nu, lu, ndl, rx, ry);
-    float invS = 1.0f / S;
+    const float invS = __builtin_amdgcn_rcpf(S);   // (1 ulp)
     c[0] = c[1] = c[2] = 0.0f;
     for (int k = 0; k < 3; ++k) {
         float mu = e[k] * invS;
@@ -1175,9 +1181,10 @@ __device__ __forceinline__ void shade_pixel_at(const ViewDev &vd, const float4 *
 __device__ __forceinline__ void shade_pixel(const ViewDev &vd, const float4 *__restrict__ rec,
                                             const float *__restrict__ alb, const pr_light &light, int px, int py,
                                             int id, float c[3]) {
-    float t, rx, ry;
+    float t, rx, ry, l0[3], l1[3];
     pixel_setup(vd.pc, px, py, t, rx, ry);
-    shade_pixel_at(vd, rec, alb, light, t, rx, ry, id, c);
+    view_light(vd, light, l0, l1);
+    shade_pixel_at(vd, rec, alb, light, l0, l1, t, rx, ry, id, c);
 }
 
 // The shaded outputs of pixel p of view v (id < 0: a miss, colour 0).
@@ -1261,6 +1268,7 @@ struct RecLayout {
 struct ShadeArgs {
     const ShadeIO *io;
     const pr_light *light;
+    const float *l01;   // the view's light directions at its start (0..2) and end (3..5)
     const float4 *rec;
     int v;
 };
@@ -1316,11 +1324,12 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
         for (int b = 0; b < 4; ++b) {
             const float tj = tr[b], rxj = rxr[b], ryj = ryr[b];
             if (ROLL) {
-                // terms (rx, ry, t rx, t ry) and (t, t^2 rx, t^2 ry, t^2)
-                const float u = kq == 0 ? rxj : kq == 1 ? ryj : kq == 2 ? tj * rxj : tj * ryj;
+                // terms (rx, ry, t rx, t ry) and (t, t^2 rx, t^2 ry, t^2),
+                // from the lane's selections of rx / ry (the same products)
+                const float r0 = (kq & 1) ? ryj : rxj, r1 = kq == 1 ? rxj : ryj;
                 const float t2 = tj * tj;
-                bt0[b] = u;
-                bt1[b] = kq == 0 ? tj : kq == 1 ? t2 * rxj : kq == 2 ? t2 * ryj : t2;
+                bt0[b] = kq < 2 ? r0 : tj * r0;
+                bt1[b] = kq == 0 ? tj : (kq == 3 ? t2 : t2 * r1);
             } else {
                 bt0[b] = kq == 0 ? rxj : kq == 1 ? ryj : 0.0f;
                 bt1[b] = 0.0f;
@@ -1466,7 +1475,8 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
         out_depth[p] = miss ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(mine >> 32));
         if (SHADE) {
             float c[3] = {0.0f, 0.0f, 0.0f};
-            if (id >= 0) shade_pixel_at(vd, sa.rec, sa.io->albedo[sa.v], *sa.light, t, rx, ry, id, c);
+            if (id >= 0)
+                shade_pixel_at(vd, sa.rec, sa.io->albedo[sa.v], *sa.light, sa.l01, sa.l01 + 3, t, rx, ry, id, c);
             store_shade(*sa.io, sa.v, p, c, id);
         }
     }
@@ -1499,7 +1509,8 @@ template <int TILE, bool COUNT, bool SHADE>
 __device__ __forceinline__ void raycast_item(const ViewTable *__restrict__ T, const float4 *__restrict__ rec,
                                              const uint32_t *__restrict__ lists, const RayOut &out,
                                              DevStatus *__restrict__ st, int quad, int4 tr, uint32_t ent0,
-                                             int32_t *s_sel_block, const ShadeIO *sio, const pr_light *light) {
+                                             int32_t *s_sel_block, const ShadeIO *sio, const pr_light *light,
+                                             const float *l01) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (tr.x < 0) return;
     const int v = tr.y;
@@ -1519,7 +1530,7 @@ __device__ __forceinline__ void raycast_item(const ViewTable *__restrict__ T, co
     const float *vrec = reinterpret_cast<const float *>(rec + vd.rec_off);
     unsigned long long *cnt = &st->cnt[blockIdx.x & (kCountSlots - 1)][0];
     int32_t *s_sel = s_sel_block + wv * kSelCap;
-    const ShadeArgs sa{sio, light, rec, v};
+    const ShadeArgs sa{sio, light, l01 ? l01 + 6 * v : nullptr, rec, v};
     if (vd.rolling)
         raycast_cell<true, COUNT, SHADE>(vd, cx0, cy0, q, vrec, tr.z, tr.w, lists, ent0, out.id[v], out.depth[v], cnt,
                                          s_sel, sa);
@@ -1547,7 +1558,7 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
     const int k = item_tile<TILE>(item, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
     const int4 tr = k < T->total_tiles ? tile_rec(T, toff, k, st->overflow != 0) : make_int4(-1, 0, 0, 0);
     raycast_item<TILE, COUNT, false>(T, rec, lists, out, st, item & 3, tr, first_entries(lists, tr), s_sel, nullptr,
-                                     nullptr);
+                                     nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1577,6 +1588,13 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) __attribute__((amdgpu_waves_per
     const int nitems = share_items(TILE, share);
     const int rounds = (nitems + K - 1) / K;
     const int4 *ord = order + (int64_t)x * ntiles;
+    // the views' light directions (the fused shading's), once per block
+    __shared__ float s_l01[PR_MAX_VIEWS][6];
+    if (SHADE) {
+        for (int v = threadIdx.x; v < T->nv; v += RayCfg<TILE>::NT)
+            view_light(T->v[v], light, &s_l01[v][0], &s_l01[v][3]);
+        __syncthreads();
+    }
     auto fetch = [&](int r, int &quad) {
         const int j = r * K + ((r & 1) ? K - 1 - k : k);
         const int pos = TILE == 8 ? 4 * j + wv : (TILE == 16 ? j : j >> 2);
@@ -1598,7 +1616,7 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) __attribute__((amdgpu_waves_per
         else if (quarter == 1) __builtin_amdgcn_s_setprio(2);
         else if (quarter == 2) __builtin_amdgcn_s_setprio(1);
         else __builtin_amdgcn_s_setprio(0);
-        raycast_item<TILE, COUNT, SHADE>(T, rec, lists, out, st, qcur, cur, ecur, s_sel, &sio, &light);
+        raycast_item<TILE, COUNT, SHADE>(T, rec, lists, out, st, qcur, cur, ecur, s_sel, &sio, &light, &s_l01[0][0]);
         cur = nx1;
         qcur = qn1;
         nx1 = nx2;
