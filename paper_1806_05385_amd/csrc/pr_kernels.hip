@@ -1165,7 +1165,9 @@ __device__ __forceinline__ void shade_pixel_at(const ViewDev &vd, const float4 *
     for (int r = 0; r < 3; ++r) L[r] = fmaf(t, l1[r] - l0[r], l0[r]);
     float inl = rsqrtf(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
     float ndl = sg * inl * (N[0] * L[0] + N[1] * L[1] + N[2] * L[2]);
-    float s = ambient + (1.0f - ambient) * fmaxf(ndl, 0.0f);
+    // (1 - ambient is uniform: kept in a scalar register, not a vector one)
+    const float amb1 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(1.0f - ambient)));
+    float s = ambient + amb1 * fmaxf(ndl, 0.0f);
     const float nu[3] = {sg * N[0], sg * N[1], sg * N[2]}, lu[3] = {inl * L[0], inl * L[1], inl * L[2]};
     const float sp = specular_at(light, nu, lu, ndl, rx, ry);
     const float invS = __builtin_amdgcn_rcpf(S);   // (1 ulp)
@@ -1299,6 +1301,14 @@ __device__ __forceinline__ void rows_broadcast(float x, float out[4]) {
     out[3] = __uint_as_float(b2);
 }
 
+// The lane index, computed where it is used (an opaque mbcnt pair the
+// compiler cannot move out of loops).
+__device__ __forceinline__ int lane_fresh() {
+    int l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+    return l;
+}
+
 template <bool ROLL, bool COUNT, bool SHADE>
 __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0, int q, const float *__restrict__ vrec,
                                              int beg, int end, const uint32_t *__restrict__ lists, uint32_t ent0,
@@ -1309,12 +1319,16 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
     const PixelConst &pc = vd.pc;
     const int lane = __lane_id();
     const int kq = lane >> 4, jl = lane & 15;
+    // the pixel's coordinates from a lane index read per cell: they are not
+    // hoisted out of the caller's loop over items (where they would hold
+    // registers through every cell, or be spilled)
+    const int pl = lane_fresh();
     // B operands: ray terms kq and kq + 4 of pixel 16 b + jl of the cell.
     // Lane l sets up pixel l; the others fetch its (t, rx, ry).
     float bt0[4], bt1[4], tb[4];
     float t, rx, ry;   // lane l's own pixel l (shaded by lane l at the end)
     {
-        pixel_setup(pc, cx0 + (lane & 7), cy0 + (lane >> 3), t, rx, ry);
+        pixel_setup(pc, cx0 + (pl & 7), cy0 + (pl >> 3), t, rx, ry);
         // pixel 16 b + jl's values are row b's: broadcast each row to all
         float tr[4], rxr[4], ryr[4];
         rows_broadcast(t, tr);
@@ -1346,12 +1360,14 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
     unsigned long long tests = 0;
     int nvc = 0;   // valid pixels of the cell (PR_FLAG_COUNT)
     if (COUNT) {
-        const int px = cx0 + (lane & 7), py = cy0 + (lane >> 3);
+        const int px = cx0 + (pl & 7), py = cy0 + (pl >> 3);
         nvc = __popcll(__ballot(px < pc.W && py < pc.H));
     }
     // A operand of lane l: triangle (l >> 2) & 3 of the group, output l & 3,
     // term kq (+ 4)
-    const int ga = (lane >> 2) & 3, aoff = 4 * kq + (lane & 3);
+    // (aoff4: that term's byte offset in the record)
+    const int ga = (lane >> 2) & 3;
+    const uint32_t aoff4 = 4u * (uint32_t)(4 * kq + (lane & 3));
     int nbuf = 0;
     uint32_t ent_next = ent0;   // lists[beg + lane], loaded by the caller
     for (int c = beg; c < end; c += 64) {
@@ -1381,10 +1397,11 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
         const char *vbase = reinterpret_cast<const char *>(vrec);
         auto load_group = [&](Group &G, int g) {
             const int ia = 4 * g + ga, ic = 4 * g + kq;
-            const uint32_t oa = (uint32_t)s_sel[ia < nbuf ? ia : 0] << 4;
+            // (32-bit offsets from the uniform base: one VGPR per address)
+            const uint32_t oa = ((uint32_t)s_sel[ia < nbuf ? ia : 0] << 4) + aoff4;
             const uint32_t oc = (uint32_t)s_sel[ic < nbuf ? ic : 0] << 4;
-            G.a0 = *reinterpret_cast<const float *>(vbase + oa + 4 * aoff);
-            G.a1 = ROLL ? *reinterpret_cast<const float *>(vbase + oa + 4 * (16 + aoff)) : 0.0f;
+            G.a0 = *reinterpret_cast<const float *>(vbase + oa);
+            G.a1 = ROLL ? *reinterpret_cast<const float *>(vbase + oa + 64) : 0.0f;
             G.valid = ic < nbuf;
             const float4 c4 = *reinterpret_cast<const float4 *>(vbase + oc + 4 * RL::C);
             G.c = v4f{c4.x, c4.y, c4.z, c4.w};
@@ -1466,7 +1483,8 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
         const unsigned long long o = ((unsigned long long)khi[b] << 32) | klo[b];
         mine = o < mine ? o : mine;
     }
-    const int px = cx0 + (lane & 7), py = cy0 + (lane >> 3);
+    const int pl2 = lane_fresh();
+    const int px = cx0 + (pl2 & 7), py = cy0 + (pl2 >> 3);
     if (px < pc.W && py < pc.H) {
         const int64_t p = (int64_t)py * pc.W + px;
         const bool miss = mine == kFar;
