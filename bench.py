@@ -399,8 +399,19 @@ def main():
     st = r.status()
     assert not st.overflow
     ms_step = t0.elapsed_time(t1) / args.steps
-    ray_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    ray_ms_avg = float(ray_ms.mean())
+    # the ray cast bracketed by an event pair inside each frame (each pair
+    # adds the event's own wait to the span)
+    ray_ms_bracketed = float(np.array([a.elapsed_time(b) for a, b in ev]).mean())
+    # its average launch duration (the roofline's): the same launch, on the
+    # same lists, issued `steps` times back to back between one event pair
+    b0 = torch.cuda.Event(enable_timing=True)
+    b1 = torch.cuda.Event(enable_timing=True)
+    b0.record(stream)
+    for _ in range(args.steps):
+        r.raycast_shade(rgba8=True, rgb32=False)
+    b1.record(stream)
+    torch.cuda.synchronize()
+    ray_ms_avg = b0.elapsed_time(b1) / args.steps
     # the frame's distribution, timed frame by frame (not the headline)
     dist = frame_distribution(r, stream, max(200, args.steps))
     px_total = sum(v.width * v.height for v in sc.views)
@@ -561,6 +572,7 @@ def main():
         'shading': shading_out,
         'profiles': profile_out,
         'raycast_shade_ms': round(ray_ms_avg, 4),
+        'raycast_shade_bracketed_ms': round(ray_ms_bracketed, 4),
         'tests_per_frame': tests,
         'tests_per_s': round(tests / (ray_ms_avg * 1e-3), 1),
         'ste': round(hits / max(tests, 1), 4),
