@@ -381,7 +381,6 @@ def main():
     for _ in range(args.warmup):
         r.frame(check=False, rgb32=False)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -390,17 +389,23 @@ def main():
     for k in range(args.steps):
         r.bound()
         r.bin()
-        ev[k][0].record(stream)
         r.raycast_shade(rgba8=True, rgb32=False)   # ray cast with the shading fused in
-        ev[k][1].record(stream)
     t1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     st = r.status()
     assert not st.overflow
     ms_step = t0.elapsed_time(t1) / args.steps
-    # the ray cast bracketed by an event pair inside each frame (each pair
-    # adds the event's own wait to the span)
+    # (after the timed frames) the ray cast bracketed by an event pair inside
+    # each frame: each pair adds the event's own wait to the span
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for k in range(args.steps):
+        r.bound()
+        r.bin()
+        ev[k][0].record(stream)
+        r.raycast_shade(rgba8=True, rgb32=False)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
     ray_ms_bracketed = float(np.array([a.elapsed_time(b) for a, b in ev]).mean())
     # its average launch duration (the roofline's): the same launch, on the
     # same lists, issued `steps` times back to back between one event pair
