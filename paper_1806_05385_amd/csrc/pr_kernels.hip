@@ -1354,7 +1354,13 @@ __device__ __forceinline__ void raycast_cell(const ViewDev &vd, int cx0, int cy0
     // packed (depth bits, id) keys; kFar (depth +inf) is above every finite
     // positive depth's key, so a key below it is a finite hit
     constexpr unsigned long long kFar = 0x7f80000000000000ull;
-    unsigned long long best[4] = {kFar, kFar, kFar, kFar};
+    // (the initial keys from a scalar register written per cell: a constant
+    // held in vector registers through the caller's item loop would be
+    // spilled)
+    uint32_t far_hi;
+    asm volatile("s_mov_b32 %0, 0x7f800000" : "=s"(far_hi));
+    const unsigned long long far_key = (unsigned long long)far_hi << 32;
+    unsigned long long best[4] = {far_key, far_key, far_key, far_key};
     const float znear = pc.znear;
     unsigned hits = 0;
     unsigned long long tests = 0;
@@ -1526,10 +1532,9 @@ __device__ __forceinline__ uint32_t first_entries(const uint32_t *__restrict__ l
 template <int TILE, bool COUNT, bool SHADE>
 __device__ __forceinline__ void raycast_item(const ViewTable *__restrict__ T, const float4 *__restrict__ rec,
                                              const uint32_t *__restrict__ lists, const RayOut &out,
-                                             DevStatus *__restrict__ st, int quad, int4 tr, uint32_t ent0,
+                                             DevStatus *__restrict__ st, int wv, int quad, int4 tr, uint32_t ent0,
                                              int32_t *s_sel_block, const ShadeIO *sio, const pr_light *light,
                                              const float *l01) {
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (tr.x < 0) return;
     const int v = tr.y;
     const ViewDev &vd = T->v[v];
@@ -1573,9 +1578,10 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
                                                                DevStatus *__restrict__ st) {
     __shared__ int32_t s_sel[4 * kSelCap];
     const int item = xcd_item(blockIdx.x, gridDim.x);
-    const int k = item_tile<TILE>(item, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int k = item_tile<TILE>(item, wv);
     const int4 tr = k < T->total_tiles ? tile_rec(T, toff, k, st->overflow != 0) : make_int4(-1, 0, 0, 0);
-    raycast_item<TILE, COUNT, false>(T, rec, lists, out, st, item & 3, tr, first_entries(lists, tr), s_sel, nullptr,
+    raycast_item<TILE, COUNT, false>(T, rec, lists, out, st, wv, item & 3, tr, first_entries(lists, tr), s_sel, nullptr,
                                      nullptr, nullptr);
 }
 
@@ -1585,7 +1591,7 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) void k_raycast(const ViewTable 
 // A grid sized to the device's resident blocks walks the longest-first tile
 // order (written by k_scatter) in rounds, so the longest lists start first.
 template <int TILE, bool COUNT, bool SHADE>
-__global__ __launch_bounds__((RayCfg<TILE>::NT)) __attribute__((amdgpu_waves_per_eu(6))) void k_raycast_queue(
+__global__ __launch_bounds__((RayCfg<TILE>::NT)) __attribute__((amdgpu_waves_per_eu(7))) void k_raycast_queue(
     const ViewTable *__restrict__ T, const float4 *__restrict__ rec, const uint32_t *__restrict__ lists, RayOut out,
     DevStatus *__restrict__ st, const int4 *__restrict__ order, const Sched *__restrict__ S, ShadeIO sio,
     pr_light light) {
@@ -1634,7 +1640,7 @@ __global__ __launch_bounds__((RayCfg<TILE>::NT)) __attribute__((amdgpu_waves_per
         else if (quarter == 1) __builtin_amdgcn_s_setprio(2);
         else if (quarter == 2) __builtin_amdgcn_s_setprio(1);
         else __builtin_amdgcn_s_setprio(0);
-        raycast_item<TILE, COUNT, SHADE>(T, rec, lists, out, st, qcur, cur, ecur, s_sel, &sio, &light, &s_l01[0][0]);
+        raycast_item<TILE, COUNT, SHADE>(T, rec, lists, out, st, wv, qcur, cur, ecur, s_sel, &sio, &light, &s_l01[0][0]);
         cur = nx1;
         qcur = qn1;
         nx1 = nx2;
