@@ -584,7 +584,7 @@ struct Pairs {
 // LDS and reserve their places in the tiles' lists with one global atomic
 // per tile.  A survivor's list entry carries its quadrant mask above the
 // triangle index.
-constexpr int kBinPer = 8;
+constexpr int kBinPer = 4;
 // LDS table of a round's survivors per tile: 2^kBinHashBits entries,
 // kBinProbe linear probes.
 constexpr int kBinHashBits = 10;
