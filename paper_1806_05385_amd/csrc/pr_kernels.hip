@@ -859,12 +859,12 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const ViewTable *__restrict
 // ---------------------------------------------------------------------------
 // exclusive scan of n uint32 counts (n < 2^31; totals fit in 32 bits)
 // ---------------------------------------------------------------------------
-constexpr int kScanItems = 8;
+constexpr int kScanItems = 1;
 constexpr int kScanBlock = 256 * kScanItems;
 
 
 // Exclusive scan of the per-tile counts: the block's offset is the sum of
-// the partial sums of the blocks before it (few: one per 2048 tiles).  The
+// the partial sums of the blocks before it (one per 256 tiles: many short blocks finish sooner than few long ones).  The
 // block also adds its tiles' (XCD share, list-length bucket) pairs to the
 // persistent ray cast's histogram (S->count, cleared by k_tiles).
 __device__ __forceinline__ int len_bucket(uint32_t len) { return len == 0u ? 0 : 32 - __clz(len); }
