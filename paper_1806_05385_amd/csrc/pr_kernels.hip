@@ -865,8 +865,9 @@ constexpr int kScanBlock = 256 * kScanItems;
 
 // Exclusive scan of the per-tile counts: the block's offset is the sum of
 // the partial sums of the blocks before it (one per 256 tiles: many short
-// blocks finish sooner than few long ones).  The block also adds its tiles' (XCD share, list-length bucket) pairs to the
-// persistent ray cast's histogram (S->count, cleared by k_tiles).
+// blocks finish sooner than few long ones).  The block also adds its
+// tiles' (XCD share, list-length bucket) pairs to the persistent ray
+// cast's histogram (S->count, cleared by k_tiles).
 __device__ __forceinline__ int len_bucket(uint32_t len) { return len == 0u ? 0 : 32 - __clz(len); }
 
 // The XCD share of global tile gt: its view's 64 x 64-pixel super-tile
