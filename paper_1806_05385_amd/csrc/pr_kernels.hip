@@ -870,13 +870,13 @@ constexpr int kScanBlock = 256 * kScanItems;
 // cast's histogram (S->count, cleared by k_tiles).
 __device__ __forceinline__ int len_bucket(uint32_t len) { return len == 0u ? 0 : 32 - __clz(len); }
 
-// The XCD share of global tile gt: its view's 64 x 64-pixel super-tile
-// (tile / 64 is a power of two) on a diagonal pattern over the XCDs.
+// The XCD share of global tile gt: its view's 32 x 32-pixel super-tile
+// (32 / tile is a power of two) on a diagonal pattern over the XCDs.
 __device__ __forceinline__ int tile_xcd(const ViewTable *__restrict__ T, int gt) {
     const int v = find_view(T->tile_base, T->nv, gt);
     const ViewDev &vd = T->v[v];
     const int lt = gt - vd.tile_base, tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
-    const int per = vd.tile >= 64 ? 1 : 64 / vd.tile;
+    const int per = vd.tile >= 32 ? 1 : 32 / vd.tile;
     return (tx / per + 3 * (ty / per) + 5 * v) & (kXcds - 1);
 }
 
