@@ -13,7 +13,7 @@
 //              of the block's rectangles tested conservatively; the round's
 //              survivors counted per tile in LDS take their list places with
 //              one global atomic per tile
-//   k_scan_*   exclusive scan of per-tile counts
+//   k_scan     exclusive scan of per-tile counts (single pass, look-back)
 //   k_scatter  pairs -> per-tile triangle lists
 //   k_raycast  one wave per 8x8 cell: every pixel's ray (foveated position,
 //   (_queue)   rolling time) tested against the cell's triangles of the tile
